@@ -1,0 +1,258 @@
+"""ctypes loader for the FP64 C oracle ``pic_oracle.c``.
+
+TEST INFRASTRUCTURE ONLY: only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may use it.  Every function here is
+argument marshalling around the C routine of the same name; the arithmetic
+lives in ``pic_oracle.c`` (which cites the dissertation's Ch. 3 passages).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pic_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, no FMA contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Grid(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32),
+        ("nx", C.c_int32 * 3),
+        ("dx", C.c_double * 3),
+        ("xmin", C.c_double * 3),
+        ("dt", C.c_double),
+        ("order", C.c_int32),
+        ("e0", C.c_double * 3),
+        ("b0", C.c_double * 3),
+    ]
+
+
+@dataclass
+class Grid:
+    """Grid, time step and shape order of one periodic simulation box."""
+
+    dim: int
+    nx: tuple
+    dx: tuple
+    dt: float
+    order: int
+    xmin: tuple = (0.0, 0.0, 0.0)
+    e0: tuple = (0.0, 0.0, 0.0)
+    b0: tuple = (0.0, 0.0, 0.0)
+
+    def c(self) -> _Grid:
+        g = _Grid()
+        g.dim = self.dim
+        nx = list(self.nx) + [1] * (3 - len(self.nx))
+        dx = list(self.dx) + [1.0] * (3 - len(self.dx))
+        xm = list(self.xmin) + [0.0] * (3 - len(self.xmin))
+        for i in range(3):
+            g.nx[i] = int(nx[i]) if i < self.dim else 1
+            g.dx[i] = float(dx[i])
+            g.xmin[i] = float(xm[i])
+            g.e0[i] = float(self.e0[i])
+            g.b0[i] = float(self.b0[i])
+        g.dt = float(self.dt)
+        g.order = int(self.order)
+        return g
+
+    @property
+    def ncell(self) -> int:
+        n = 1
+        for i in range(self.dim):
+            n *= int(self.nx[i])
+        return n
+
+    @property
+    def shape(self) -> tuple:
+        """numpy shape of one grid component, slowest axis first."""
+        return tuple(int(self.nx[i]) for i in reversed(range(self.dim)))
+
+
+_lib = None
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = C.CDLL(_LIB)
+        P = C.POINTER(C.c_double)
+        G = C.POINTER(_Grid)
+        lib.orc_shape.argtypes = [C.c_int, C.c_double]
+        lib.orc_shape.restype = C.c_double
+        lib.orc_gather.argtypes = [G, C.c_int64, P, P, P, P, P]
+        lib.orc_boris.argtypes = [C.c_int64, P, P, P, P, C.c_double]
+        lib.orc_deposit_cells.argtypes = [G, C.c_int64, P, P, P, P, P]
+        lib.orc_rho.argtypes = [G, C.c_int64, P, P, P]
+        lib.orc_yee_b.argtypes = [G, P, P, C.c_double]
+        lib.orc_yee_e.argtypes = [G, P, P, P, C.c_double]
+        lib.orc_step.argtypes = [G, C.c_int64, P, P, P, P, P, P, P]
+        lib.orc_step.restype = C.c_int
+        lib.orc_gauss_residual.argtypes = [G, P, P, P]
+        lib.orc_charge_residual.argtypes = [G, P, P, P, P]
+        lib.orc_field_energy.argtypes = [G, P, P, P]
+        lib.orc_particle_moments.argtypes = [G, C.c_int64, P, P, P, P]
+        _lib = lib
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"], (a.dtype, a.flags)
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def shape(order: int, t: float) -> float:
+    return _L().orc_shape(int(order), float(t))
+
+
+def gather(g: Grid, x, E, B):
+    """E, B (each [3, ncell]) at absolute positions x[n, dim] -> (Ep, Bp) [n, 3]."""
+    x = _f64(x).reshape(-1, g.dim)
+    n = x.shape[0]
+    E = _f64(E).reshape(3, g.ncell)
+    B = _f64(B).reshape(3, g.ncell)
+    Ep = np.zeros((n, 3))
+    Bp = np.zeros((n, 3))
+    gc = g.c()
+    _L().orc_gather(C.byref(gc), n, _p(x), _p(E), _p(B), _p(Ep), _p(Bp))
+    return Ep, Bp
+
+
+def boris(u, Ep, Bp, qm, dt):
+    """Return u^{n+1/2} from u^{n-1/2} [n, 3] and fields at the particles."""
+    u = _f64(u).reshape(-1, 3).copy()
+    n = u.shape[0]
+    Ep = _f64(Ep).reshape(n, 3)
+    Bp = _f64(Bp).reshape(n, 3)
+    qm = _f64(np.broadcast_to(qm, (n,)))
+    _L().orc_boris(n, _p(u), _p(Ep), _p(Bp), _p(qm), float(dt))
+    return u
+
+
+def deposit_cells(g: Grid, a, b, w, v3=None, J=None):
+    """ISIS current of particles moving a -> b (cell units, unwrapped) -> J [3, ncell]."""
+    a = _f64(a).reshape(-1, g.dim)
+    n = a.shape[0]
+    b = _f64(b).reshape(n, g.dim)
+    w = _f64(np.broadcast_to(w, (n,)))
+    v3 = _f64(np.zeros(n) if v3 is None else np.broadcast_to(v3, (n,)))
+    J = np.zeros((3, g.ncell)) if J is None else J
+    gc = g.c()
+    _L().orc_deposit_cells(C.byref(gc), n, _p(a), _p(b), _p(w), _p(v3), _p(J))
+    return J
+
+
+def rho(g: Grid, x, w, out=None):
+    x = _f64(x).reshape(-1, g.dim)
+    n = x.shape[0]
+    w = _f64(np.broadcast_to(w, (n,)))
+    out = np.zeros(g.ncell) if out is None else out
+    gc = g.c()
+    _L().orc_rho(C.byref(gc), n, _p(x), _p(w), _p(out))
+    return out
+
+
+def yee_b(g: Grid, E, B, h):
+    """B - h curl E (returns a new array)."""
+    E = _f64(E).reshape(3, g.ncell)
+    B = _f64(B).reshape(3, g.ncell).copy()
+    gc = g.c()
+    _L().orc_yee_b(C.byref(gc), _p(E), _p(B), float(h))
+    return B
+
+
+def yee_e(g: Grid, E, B, J, dt):
+    """E + dt (curl B - J) (returns a new array)."""
+    E = _f64(E).reshape(3, g.ncell).copy()
+    B = _f64(B).reshape(3, g.ncell)
+    J = _f64(J).reshape(3, g.ncell)
+    gc = g.c()
+    _L().orc_yee_e(C.byref(gc), _p(E), _p(B), _p(J), float(dt))
+    return E
+
+
+@dataclass
+class StepResult:
+    x: np.ndarray
+    u: np.ndarray
+    E: np.ndarray
+    B: np.ndarray
+    J: np.ndarray = field(default=None)
+
+
+def step(g: Grid, x, u, w, qm, E, B) -> StepResult:
+    """One full PIC step; inputs are not modified."""
+    x = _f64(x).reshape(-1, g.dim).copy()
+    n = x.shape[0]
+    u = _f64(u).reshape(n, 3).copy()
+    w = _f64(np.broadcast_to(w, (n,)))
+    qm = _f64(np.broadcast_to(qm, (n,)))
+    E = _f64(E).reshape(3, g.ncell).copy()
+    B = _f64(B).reshape(3, g.ncell).copy()
+    J = np.zeros((3, g.ncell))
+    gc = g.c()
+    rc = _L().orc_step(C.byref(gc), n, _p(x), _p(u), _p(w), _p(qm), _p(E), _p(B), _p(J))
+    if rc != 0:
+        raise MemoryError("oracle step failed to allocate")
+    return StepResult(x=x, u=u, E=E, B=B, J=J)
+
+
+def gauss_residual(g: Grid, E, rho_):
+    E = _f64(E).reshape(3, g.ncell)
+    rho_ = _f64(rho_).reshape(g.ncell)
+    G = np.zeros(g.ncell)
+    gc = g.c()
+    _L().orc_gauss_residual(C.byref(gc), _p(E), _p(rho_), _p(G))
+    return G
+
+
+def charge_residual(g: Grid, rho0, rho1, J):
+    rho0 = _f64(rho0).reshape(g.ncell)
+    rho1 = _f64(rho1).reshape(g.ncell)
+    J = _f64(J).reshape(3, g.ncell)
+    Cc = np.zeros(g.ncell)
+    gc = g.c()
+    _L().orc_charge_residual(C.byref(gc), _p(rho0), _p(rho1), _p(J), _p(Cc))
+    return Cc
+
+
+def field_energy(g: Grid, E, B):
+    E = _f64(E).reshape(3, g.ncell)
+    B = _f64(B).reshape(3, g.ncell)
+    out = np.zeros(2)
+    gc = g.c()
+    _L().orc_field_energy(C.byref(gc), _p(E), _p(B), _p(out))
+    return out
+
+
+def particle_moments(g: Grid, u, w, qm):
+    u = _f64(u).reshape(-1, 3)
+    n = u.shape[0]
+    w = _f64(np.broadcast_to(w, (n,)))
+    qm = _f64(np.broadcast_to(qm, (n,)))
+    out = np.zeros(4)
+    gc = g.c()
+    _L().orc_particle_moments(C.byref(gc), n, _p(u), _p(w), _p(qm), _p(out))
+    return out

@@ -1,0 +1,561 @@
+"""Pins of the FP64 oracle against what the dissertation and the mathematics fix.
+
+None of these re-types the oracle's own formulas: each checks the oracle
+against a closed form, an invariant, a special case that reduces to a textbook
+result, a hand-derived worked example (tests/golden/) or an independent
+evaluation (numerical quadrature, a published closed-form decomposition).
+Citations are to Hemker (2000), Ch. 3.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _closed_forms():
+    vals = {}
+    with open(os.path.join(GOLD, "closed_forms.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                k, v = line.split()
+                vals[k] = float(v)
+    return vals
+
+
+CF = _closed_forms()
+
+# --------------------------------------------------------------------------
+# shapes (Sec. 3.2 field weighting, generalised to B-splines)
+# --------------------------------------------------------------------------
+
+
+def _box_convolve(f, t):
+    """int_{t-1/2}^{t+1/2} f(s) ds by adaptive quadrature with breakpoints at
+    the knots (independent of the piecewise polynomial forms)."""
+    from scipy.integrate import quad
+
+    knots = [k / 2 for k in range(-8, 9) if t - 0.5 < k / 2 < t + 0.5]
+    val, _ = quad(f, t - 0.5, t + 0.5, points=knots or None, epsabs=1e-13, epsrel=1e-13, limit=200)
+    return val
+
+
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_shape_is_box_convolution(orc, order):
+    """S_m = S_{m-1} * box, S_0 = box: the B-spline recursion, evaluated numerically."""
+    prev = (lambda s: 1.0 if abs(s) < 0.5 else (0.5 if abs(s) == 0.5 else 0.0)) if order == 1 else (
+        lambda s: orc.shape(order - 1, s))
+    for t in np.linspace(-2.3, 2.3, 47):
+        ref = _box_convolve(prev, t)
+        assert abs(orc.shape(order, t) - ref) < 1e-12, (order, t)
+
+
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_shape_partition_and_moment(orc, order):
+    """sum_i S(x - i) = 1 and sum_i i S(x - i) = x for every B-spline order."""
+    rng = np.random.default_rng(1)
+    for x in rng.uniform(-3, 3, 50):
+        nodes = np.arange(math.floor(x) - 3, math.floor(x) + 4)
+        s = np.array([orc.shape(order, x - i) for i in nodes])
+        assert abs(s.sum() - 1.0) < 1e-14
+        assert abs((s * nodes).sum() - x) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# gather (Sec. 3.2, Eq. 2d-field-weighting-e3)
+# --------------------------------------------------------------------------
+
+E_OFF = [(0.5, 0.0, 0.0), (0.0, 0.5, 0.0), (0.0, 0.0, 0.5)]
+B_OFF = [(0.0, 0.5, 0.5), (0.5, 0.0, 0.5), (0.5, 0.5, 0.0)]
+
+
+def _node_coords(g, off):
+    """Physical coordinates of every node of a component with staggering 'off'."""
+    idx = np.indices(g.shape)[::-1]  # i0, i1, (i2)
+    return [g.xmin[d] + (idx[d] + off[d]) * g.dx[d] for d in range(g.dim)]
+
+
+@pytest.mark.parametrize("dim,order", [(2, 1), (2, 2), (2, 3), (3, 1), (3, 2), (3, 3)])
+def test_gather_reproduces_linear_fields(orc, dim, order):
+    """B-splines of every order reproduce linear functions, so a field that is
+    linear in the physical coordinate of each component's own staggered
+    location must be gathered exactly.  A wrong staggering offset or weight
+    fails this (Sec. 3.2: each component uses the points where it is known)."""
+    nx = (12, 10, 9)[:dim]
+    dx = (0.2, 0.3, 0.25)[:dim]
+    g = orc.Grid(dim=dim, nx=nx, dx=dx, dt=0.05, order=order, xmin=(0.5, -1.0, 2.0))
+    rng = np.random.default_rng(2 + dim * 10 + order)
+    E = np.zeros((3, g.ncell))
+    B = np.zeros((3, g.ncell))
+    coefs = rng.normal(size=(6, 4))
+    for c in range(3):
+        for arr, off, row in ((E, E_OFF[c], c), (B, B_OFF[c], 3 + c)):
+            X = _node_coords(g, off)
+            val = coefs[row, 0] + sum(coefs[row, 1 + d] * X[d] for d in range(dim))
+            arr[c] = val.reshape(-1)
+    # particles well inside (linear field is not periodic, keep away from wrap)
+    n = 40
+    lo = np.array([g.xmin[d] + 4 * dx[d] for d in range(dim)])
+    hi = np.array([g.xmin[d] + (nx[d] - 4) * dx[d] for d in range(dim)])
+    x = rng.uniform(lo, hi, size=(n, dim))
+    Ep, Bp = orc.gather(g, x, E, B)
+    for c in range(3):
+        refE = coefs[c, 0] + sum(coefs[c, 1 + d] * x[:, d] for d in range(dim))
+        refB = coefs[3 + c, 0] + sum(coefs[3 + c, 1 + d] * x[:, d] for d in range(dim))
+        np.testing.assert_allclose(Ep[:, c], refE, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(Bp[:, c], refB, rtol=0, atol=1e-12)
+
+
+def test_gather_matches_paper_bilinear_e3(orc):
+    """Order 1 in 2D is the paper's bilinear formula for E3 at
+    (eps1 dx1, eps2 dx2) inside cell (i1, i2) (Eq. 2d-field-weighting-e3)."""
+    g = orc.Grid(dim=2, nx=(7, 6), dx=(0.3, 0.2), dt=0.05, order=1)
+    rng = np.random.default_rng(3)
+    E = np.zeros((3, g.ncell))
+    E[2] = rng.normal(size=g.ncell)
+    F = E[2].reshape(6, 7)  # [i2][i1]
+    for _ in range(30):
+        i1, i2 = rng.integers(0, 7), rng.integers(0, 6)
+        e1, e2 = rng.uniform(0, 1, 2)
+        x = np.array([[(i1 + e1) * 0.3, (i2 + e2) * 0.2]])
+        Ep, _ = orc.gather(g, x, E, np.zeros((3, g.ncell)))
+        j1, j2 = (i1 + 1) % 7, (i2 + 1) % 6
+        ref = (1 - e1) * ((1 - e2) * F[i2, i1] + e2 * F[j2, i1]) + e1 * (
+            (1 - e2) * F[i2, j1] + e2 * F[j2, j1])
+        assert abs(Ep[0, 2] - ref) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# Boris push (Sec. 3.2, Eq. momentum-update)
+# --------------------------------------------------------------------------
+
+
+def test_boris_pure_electric_kick(orc):
+    """With B = 0 the push is u + (q/m) dt E exactly (both half kicks present)."""
+    rng = np.random.default_rng(4)
+    u = rng.normal(size=(20, 3))
+    E = rng.normal(size=(20, 3))
+    qm = rng.choice([-1.0, 0.5, 1836.0 ** -1], 20)
+    out = orc.boris(u, E, np.zeros((20, 3)), qm, 0.07)
+    np.testing.assert_allclose(out, u + (qm * 0.07)[:, None] * E, rtol=0, atol=1e-14)
+
+
+def test_boris_rotation_closed_form(orc):
+    """E = 0: |u| and u.B are invariant; the angle per step is
+    2 atan(|q/m| |B| dt / (2 gamma)) and electrons turn counter-clockwise about +z."""
+    u0 = np.array([[0.1, 0.0, 0.0]])
+    out = orc.boris(u0, np.zeros((1, 3)), np.array([[0.0, 0.0, 1.0]]), -1.0, 0.1)
+    ang = math.atan2(out[0, 1], out[0, 0])
+    assert abs(ang - CF["boris_theta"]) < 1e-14
+    assert abs(np.linalg.norm(out) - 0.1) < 1e-16
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        u = rng.normal(size=(1, 3)) * rng.uniform(0.01, 30)
+        Bv = rng.normal(size=(1, 3))
+        qm, dt = rng.choice([-1.0, 1.0, 0.01]), rng.uniform(0.01, 0.5)
+        v = orc.boris(u, np.zeros((1, 3)), Bv, qm, dt)
+        gam = math.sqrt(1 + (u ** 2).sum())
+        assert abs(np.linalg.norm(v) / np.linalg.norm(u) - 1) < 1e-14
+        bh = Bv[0] / np.linalg.norm(Bv)
+        assert abs(v[0] @ bh - u[0] @ bh) < 1e-12 * np.linalg.norm(u)
+        up, vp = u[0] - (u[0] @ bh) * bh, v[0] - (v[0] @ bh) * bh
+        cosang = up @ vp / (np.linalg.norm(up) * np.linalg.norm(vp))
+        theta = 2 * math.atan(abs(qm) * np.linalg.norm(Bv) * dt / (2 * gam))
+        assert abs(math.acos(min(1.0, cosang)) - theta) < 1e-7
+        # sense: d(u_perp)/dt is along (q/m) u x B
+        turn = np.cross(up, vp) @ bh
+        assert np.sign(turn) == -np.sign(qm)
+
+
+def test_boris_time_reversible(orc):
+    rng = np.random.default_rng(6)
+    u = rng.normal(size=(30, 3)) * 3
+    E, Bv = rng.normal(size=(30, 3)), rng.normal(size=(30, 3))
+    v = orc.boris(u, E, Bv, -1.0, 0.1)
+    back = orc.boris(v, E, Bv, -1.0, -0.1)
+    np.testing.assert_allclose(back, u, rtol=0, atol=1e-13)
+
+
+def test_boris_exb_drift(orc):
+    """Crossed uniform E = 0.01 y and B = z: the gyro-averaged velocity of a
+    particle started at rest is E x B / B^2 = 0.01 x."""
+    u = np.zeros((1, 3))
+    E = np.array([[0.0, 0.01, 0.0]])
+    Bv = np.array([[0.0, 0.0, 1.0]])
+    dt = 0.05
+    theta = 2 * math.atan(dt / 2)       # rotation per step (gamma ~ 1 + 5e-5)
+    steps_per_turn = 2 * math.pi / theta
+    nsteps = int(round(200 * steps_per_turn))
+    vs = []
+    for _ in range(nsteps):
+        u = orc.boris(u, E, Bv, -1.0, dt)
+        vs.append(u[0] / math.sqrt(1 + (u ** 2).sum()))
+    vmean = np.mean(vs, axis=0)
+    assert abs(vmean[0] - 0.01) < 2e-5
+    assert abs(vmean[1]) < 2e-5 and abs(vmean[2]) < 1e-15
+
+
+def test_gyro_orbit_full_step(orc):
+    """A zero-weight particle in a uniform external B (full oracle step, no
+    self-field): positions are the vertices of a regular polygon on a circle of
+    radius (|u| dt / gamma) / (2 sin(theta/2)) and gamma is conserved exactly."""
+    g = orc.Grid(dim=2, nx=(16, 16), dx=(0.2, 0.2), dt=0.1, order=2, b0=(0.0, 0.0, 1.0))
+    x = np.array([[1.6, 1.6]])
+    u = np.array([[0.1, 0.0, 0.0]])
+    E = np.zeros((3, g.ncell))
+    B = np.zeros((3, g.ncell))
+    pts = []
+    for _ in range(150):
+        r = orc.step(g, x, u, 0.0, -1.0, E, B)
+        x, u = r.x, r.u
+        pts.append(x[0].copy())
+        assert abs(math.sqrt(1 + (u ** 2).sum()) - CF["boris_gamma"]) < 1e-14
+    pts = np.array(pts)
+    # circle through the points: least squares for centre
+    A = np.c_[2 * pts, np.ones(len(pts))]
+    bvec = (pts ** 2).sum(1)
+    cx, cy, c0 = np.linalg.lstsq(A, bvec, rcond=None)[0]
+    rad = np.sqrt(((pts - [cx, cy]) ** 2).sum(1))
+    assert np.abs(rad - CF["boris_radius"]).max() < 1e-12
+
+
+# --------------------------------------------------------------------------
+# ISIS deposit (Sec. 3.2, Eq. continuity and the ordering average)
+# --------------------------------------------------------------------------
+
+
+def _moves(rng, dim, n, maxstep=0.95):
+    a = rng.uniform(3, 5, size=(n, dim))
+    d = rng.uniform(-maxstep, maxstep, size=(n, dim)) / math.sqrt(dim)
+    # include exact cell-face and node crossings
+    a[0, 0] = 3.999999
+    d[0, 0] = 2e-6
+    a[1, 0] = 3.5
+    d[1, 0] = -0.25
+    return a, a + d
+
+
+@pytest.mark.parametrize("dim,order", [(2, 1), (2, 2), (2, 3), (3, 1), (3, 2), (3, 3)])
+def test_deposit_continuity(orc, dim, order):
+    """Eq. continuity holds to roundoff for every single particle, shape order
+    and crossing case: (rho1 - rho0)/dt + div J = 0."""
+    nx = (9, 9, 9)[:dim]
+    dx = (0.2, 0.25, 0.3)[:dim]
+    g = orc.Grid(dim=dim, nx=nx, dx=dx, dt=0.1, order=order)
+    rng = np.random.default_rng(7 + dim + 10 * order)
+    a, b = _moves(rng, dim, 12)
+    w = rng.uniform(-2, 2, len(a))
+    for p in range(len(a)):
+        J = orc.deposit_cells(g, a[p:p + 1], b[p:p + 1], w[p:p + 1], v3=0.3)
+        r0 = orc.rho(g, a[p:p + 1] * dx, w[p:p + 1])
+        r1 = orc.rho(g, b[p:p + 1] * dx, w[p:p + 1])
+        Cres = orc.charge_residual(g, r0, r1, J)
+        assert np.abs(Cres).max() < 1e-13 * np.abs(r0).max() / g.dt
+
+
+@pytest.mark.parametrize("dim,order", [(2, 1), (2, 3), (3, 2)])
+def test_deposit_sum_rule(orc, dim, order):
+    """sum_i J_d(i) = w * delta_d * dx_d / dt (total current = charge x velocity)."""
+    nx = (10, 9, 8)[:dim]
+    dx = (0.2, 0.25, 0.3)[:dim]
+    g = orc.Grid(dim=dim, nx=nx, dx=dx, dt=0.1, order=order)
+    rng = np.random.default_rng(8)
+    a, b = _moves(rng, dim, 6)
+    for p in range(len(a)):
+        J = orc.deposit_cells(g, a[p:p + 1], b[p:p + 1], 1.7, v3=0.4)
+        for d in range(dim):
+            assert abs(J[d].sum() - 1.7 * (b[p, d] - a[p, d]) * dx[d] / g.dt) < 1e-12
+        if dim == 2:
+            assert abs(J[2].sum() - 1.7 * 0.4) < 1e-12
+
+
+def _parse_golden(path):
+    cases, cur = [], None
+    with open(path) as f:
+        for line in f:
+            t = line.split()
+            if not t or t[0].startswith("#"):
+                continue
+            if t[0] == "case":
+                cur = {"J": []}
+            elif t[0] == "move":
+                cur["a"] = [float(t[1]), float(t[2])]
+                cur["b"] = [float(t[3]), float(t[4])]
+            elif t[0] == "v3":
+                cur["v3"] = float(t[1])
+            elif t[0].startswith("J"):
+                cur["J"].append((int(t[0][1]) - 1, int(t[1]), int(t[2]), float(t[3])))
+            elif t[0] == "end":
+                cases.append(cur)
+    return cases
+
+
+def test_deposit_golden_cic2d(orc):
+    """Hand-derived single-particle CIC currents (tests/golden/cic2d_deposit.txt)."""
+    g = orc.Grid(dim=2, nx=(8, 8), dx=(0.2, 0.2), dt=0.1, order=1)
+    for case in _parse_golden(os.path.join(GOLD, "cic2d_deposit.txt")):
+        J = orc.deposit_cells(g, [case["a"]], [case["b"]], 1.0, v3=case["v3"])
+        ref = np.zeros((3, 8, 8))
+        for comp, i0, i1, v in case["J"]:
+            ref[comp, i1, i0] = v
+        np.testing.assert_allclose(J.reshape(3, 8, 8), ref, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_deposit_cic_in_cell_equals_straight_path(orc, dim):
+    """Particle staying in its cell: ISIS equals the exact current of the CIC
+    cloud moving on the straight path (Sec. 3.2: the two schemes agree then).
+    The reference integrates w v_d prod_{k!=d} S(x_k(t) - i_k) over the step by
+    Gauss-Legendre quadrature; along d the face current is w v_d because the
+    face stays inside the cloud."""
+    nx = (8, 8, 8)[:dim]
+    dx = (0.2, 0.3, 0.25)[:dim]
+    g = orc.Grid(dim=dim, nx=nx, dx=dx, dt=0.1, order=1)
+    rng = np.random.default_rng(9)
+    tq, wq = np.polynomial.legendre.leggauss(8)
+    tq, wq = 0.5 * (tq + 1), 0.5 * wq
+    for _ in range(10):
+        cell = rng.integers(2, 5, dim)
+        e0 = rng.uniform(0.05, 0.95, dim)
+        e1 = np.clip(e0 + rng.uniform(-0.04, 0.04, dim), 0.001, 0.999)
+        a, b = cell + e0, cell + e1
+        J = orc.deposit_cells(g, [a], [b], 0.9).reshape((3,) + g.shape)
+        for d in range(dim):
+            v = 0.9 * (b[d] - a[d]) * dx[d] / g.dt
+            others = [k for k in range(dim) if k != d]
+            for offs in itertools.product([0, 1], repeat=dim - 1):
+                wt = 0.0
+                for t, ww in zip(tq, wq):
+                    pos = a + t * (b - a)
+                    wt += ww * np.prod([orc.shape(1, pos[k] - (cell[k] + o)) for k, o in zip(others, offs)])
+                idx = [0] * dim
+                idx[d] = cell[d]
+                for k, o in zip(others, offs):
+                    idx[k] = cell[k] + o
+                assert abs(J[(d,) + tuple(idx[::-1])] - v * wt) < 1e-14
+
+
+def _esirkepov(orc, g, a, b, w, v3):
+    """Published closed-form density decomposition (Esirkepov, CPC 135, 2001):
+    W_1 = dS1 (S2^0 + S2^1)/2 in 2D, W_1 = dS1 [(S2^0 S3^0 + S2^1 S3^1)/3 +
+    (S2^0 S3^1 + S2^1 S3^0)/6] in 3D, J_d = -w dx_d/dt cumsum_d W_d; 2D J3 =
+    w v3 [S1^0 S2^0/3 + (S1^0 S2^1 + S1^1 S2^0)/6 + S1^1 S2^1/3]."""
+    dim = g.dim
+    base = [int(math.floor(min(a[d], b[d]))) - 3 for d in range(dim)]
+    L = 8
+    S0, S1 = [], []
+    for d in range(dim):
+        nodes = base[d] + np.arange(L)
+        S0.append(np.array([orc.shape(g.order, a[d] - i) for i in nodes]))
+        S1.append(np.array([orc.shape(g.order, b[d] - i) for i in nodes]))
+    J = np.zeros((3,) + (L,) * dim)
+    if dim == 2:
+        W1 = np.outer(S1[1] + S0[1], S1[0] - S0[0]) / 2   # [i1, i0]
+        W2 = np.outer(S1[1] - S0[1], S1[0] + S0[0]) / 2
+        J[0] = -w * g.dx[0] / g.dt * np.cumsum(W1, axis=1)
+        J[1] = -w * g.dx[1] / g.dt * np.cumsum(W2, axis=0)
+        J[2] = w * v3 * (np.outer(S0[1], S0[0]) / 3 + (np.outer(S1[1], S0[0]) + np.outer(S0[1], S1[0])) / 6
+                         + np.outer(S1[1], S1[0]) / 3)
+    else:
+        def t3(x2, x1, x0):
+            return np.einsum("k,j,i->kji", x2, x1, x0)
+        D = [S1[d] - S0[d] for d in range(3)]
+        W = [
+            t3(S0[2], S0[1], D[0]) / 3 + t3(S1[2], S1[1], D[0]) / 3 + t3(S1[2], S0[1], D[0]) / 6 + t3(S0[2], S1[1], D[0]) / 6,
+            t3(S0[2], D[1], S0[0]) / 3 + t3(S1[2], D[1], S1[0]) / 3 + t3(S1[2], D[1], S0[0]) / 6 + t3(S0[2], D[1], S1[0]) / 6,
+            t3(D[2], S0[1], S0[0]) / 3 + t3(D[2], S1[1], S1[0]) / 3 + t3(D[2], S1[1], S0[0]) / 6 + t3(D[2], S0[1], S1[0]) / 6,
+        ]
+        for d in range(3):
+            J[d] = -w * g.dx[d] / g.dt * np.cumsum(W[d], axis=2 - d)
+    return J, base
+
+
+@pytest.mark.parametrize("dim,order", [(2, 1), (2, 2), (2, 3), (3, 1), (3, 2), (3, 3)])
+def test_deposit_equals_published_closed_form(orc, dim, order):
+    """The ordering-average deposit equals Esirkepov's closed form."""
+    nx = (16, 16, 16)[:dim]
+    dx = (0.2, 0.25, 0.3)[:dim]
+    g = orc.Grid(dim=dim, nx=nx, dx=dx, dt=0.1, order=order)
+    rng = np.random.default_rng(11 + order)
+    a, b = _moves(rng, dim, 8)
+    a += 3
+    b += 3
+    for p in range(len(a)):
+        J = orc.deposit_cells(g, a[p:p + 1], b[p:p + 1], -0.7, v3=0.2).reshape((3,) + g.shape)
+        Jc, base = _esirkepov(orc, g, a[p], b[p], -0.7, 0.2)
+        sl = tuple(slice(base[d], base[d] + 8) for d in reversed(range(dim)))
+        ncomp = 3
+        for c in range(ncomp):
+            np.testing.assert_allclose(J[c][sl], Jc[c], rtol=0, atol=2e-14)
+            # nothing outside the window
+            outside = J[c].copy()
+            outside[sl] = 0
+            assert np.abs(outside).max() < 1e-15
+
+
+def test_deposit_one_dimensional_move(orc):
+    """A move along x1 only is the 1D charge-conserving current spread over
+    the rows with the particle's fixed transverse shape."""
+    g = orc.Grid(dim=2, nx=(12, 12), dx=(0.2, 0.2), dt=0.1, order=2)
+    a = np.array([[5.3, 6.7]])
+    b = np.array([[5.9, 6.7]])
+    J = orc.deposit_cells(g, a, b, 1.0).reshape(3, 12, 12)
+    rows = np.array([orc.shape(2, 6.7 - j) for j in range(12)])
+    # 1D: flux through face i+1/2 = w dx/dt * [C(b) - C(a)], C(x) = sum_{k>i} S(x-k)
+    for i in range(12):
+        Ca = sum(orc.shape(2, 5.3 - k) for k in range(i + 1, 20))
+        Cb = sum(orc.shape(2, 5.9 - k) for k in range(i + 1, 20))
+        ref = (Cb - Ca) * 0.2 / 0.1 * rows
+        np.testing.assert_allclose(J[0][:, i], ref, atol=1e-14)
+    assert np.abs(J[1]).max() == 0
+
+
+# --------------------------------------------------------------------------
+# Yee solver (Sec. 3.2 Eqs. 2d-field-solve-*, Sec. 3.3)
+# --------------------------------------------------------------------------
+
+
+def _yee_run(orc, g, E, B, J, nsteps):
+    for _ in range(nsteps):
+        B = orc.yee_b(g, E, B, g.dt / 2)
+        E = orc.yee_e(g, E, B, J, g.dt)
+        B = orc.yee_b(g, E, B, g.dt / 2)
+    return E, B
+
+
+@pytest.mark.parametrize("dim,axis,pol", [(2, 0, 1), (2, 0, 2), (2, 1, 0), (2, 1, 2), (3, 2, 0), (3, 0, 2)])
+def test_yee_plane_wave_exact(orc, dim, axis, pol):
+    """A plane wave with the Yee numerical dispersion sin(w dt/2)/dt =
+    sin(k dx/2)/dx is an exact solution of the discrete scheme; B^n is the mean
+    of B^{n-1/2} and B^{n+1/2}, hence the cos(w dt/2) factor."""
+    nx = [8, 8, 8][:dim]
+    nx[axis] = 64
+    dx = [0.3, 0.25, 0.35][:dim]
+    dx[axis] = 0.2
+    dt = 0.1
+    g = orc.Grid(dim=dim, nx=tuple(nx), dx=tuple(dx), dt=dt, order=1)
+    k = 2 * math.pi / (64 * 0.2)
+    w = 2 / dt * math.asin(dt / dx[axis] * math.sin(k * dx[axis] / 2))
+    if (dim, axis, pol) == (2, 0, 1):
+        assert abs(w - CF["yee_omega"]) < 1e-15 and abs(k - CF["yee_k"]) < 1e-15
+    # E along pol, B along the third axis making (pol, bcomp, axis) right handed
+    bcomp = 3 - axis - pol
+    sign = 1.0 if (pol, bcomp, axis) in [(0, 1, 2), (1, 2, 0), (2, 0, 1)] else -1.0
+    # a wave moving in +axis has E x B along +axis:  B_b = s * E_pol with s such that
+    # e_pol x e_b = +e_axis  <=>  (pol, b, axis) is cyclic
+    E = np.zeros((3, g.ncell))
+    B = np.zeros((3, g.ncell))
+    XE = _node_coords(g, E_OFF[pol])[axis].reshape(-1)
+    XB = _node_coords(g, B_OFF[bcomp])[axis].reshape(-1)
+    E[pol] = np.cos(k * XE)
+    B[bcomp] = sign * math.cos(w * dt / 2) * np.cos(k * XB)
+    n = 37
+    E2, B2 = _yee_run(orc, g, E, B, np.zeros((3, g.ncell)), n)
+    np.testing.assert_allclose(E2[pol], np.cos(k * XE - w * n * dt), atol=1e-12)
+    np.testing.assert_allclose(B2[bcomp], sign * math.cos(w * dt / 2) * np.cos(k * XB - w * n * dt), atol=1e-12)
+    others = [c for c in range(3) if c != pol]
+    assert np.abs(E2[others]).max() < 1e-13
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_yee_div_b_and_uniform_current(orc, dim):
+    """div B stays at its initial zero (B from a vector potential) and a uniform
+    current drains the uniform field mode by dt J per step."""
+    nx = (10, 8, 6)[:dim]
+    dx = (0.2, 0.25, 0.3)[:dim]
+    g = orc.Grid(dim=dim, nx=nx, dx=dx, dt=0.05, order=1)
+    rng = np.random.default_rng(12)
+    A = rng.normal(size=(3, g.ncell))
+    B = orc.yee_b(g, A, np.zeros((3, g.ncell)), -1.0)   # B = curl A on the B mesh
+    E = rng.normal(size=(3, g.ncell))
+
+    def divB(B):
+        Bs = B.reshape((3,) + g.shape)
+        d = sum((np.roll(Bs[c], -1, axis=dim - 1 - c) - Bs[c]) / dx[c] for c in range(dim))
+        return np.abs(d).max()
+
+    assert divB(B) < 1e-12
+    Jc = np.zeros((3, g.ncell))
+    Jc[0] = 0.3
+    Jc[1] = -0.2
+    E2, B2 = _yee_run(orc, g, E, B, Jc, 9)
+    assert divB(B2) < 1e-11
+    np.testing.assert_allclose(E2.mean(axis=1) - E.mean(axis=1), -9 * 0.05 * Jc.mean(axis=1), atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# whole loop (Sec. 3.1)
+# --------------------------------------------------------------------------
+
+
+def _thermal(orc, dim, nx, dx, ppc, uth, seed):
+    rng = np.random.default_rng(seed)
+    ncell = int(np.prod(nx))
+    cells = np.repeat(np.arange(ncell), ppc)
+    idx = np.stack(np.unravel_index(cells, nx[::-1])[::-1], axis=1)
+    x = (idx + rng.uniform(0, 1, size=(len(cells), dim))) * np.array(dx)
+    u = rng.normal(0, uth, size=(len(cells), 3))
+    return x, u
+
+
+@pytest.mark.parametrize("dim,order", [(2, 1), (2, 3), (3, 2)])
+def test_gauss_law_drift_zero(orc, dim, order):
+    """Charge conservation plus div curl = 0: the Gauss residual does not
+    change over full steps (the initial residual need not vanish: the
+    neutralising background is assumed, no initial field solve)."""
+    nx = (8, 6, 4)[:dim]
+    dx = (0.2, 0.25, 0.3)[:dim]
+    g = orc.Grid(dim=dim, nx=nx, dx=dx, dt=0.08, order=order)
+    x, u = _thermal(orc, dim, nx, dx, 3, 0.1, 13)
+    w = -1.0 / 3
+    E = np.zeros((3, g.ncell))
+    B = np.zeros((3, g.ncell))
+    G0 = orc.gauss_residual(g, E, orc.rho(g, x, w) + 1.0)
+    scale = np.abs(G0).max()
+    for _ in range(6):
+        r = orc.step(g, x, u, w, -1.0, E, B)
+        x, u, E, B = r.x, r.u, r.E, r.B
+        G = orc.gauss_residual(g, E, orc.rho(g, x, w) + 1.0)
+        assert np.abs(G - G0).max() < 1e-12 * scale
+
+
+@pytest.mark.slow
+def test_cold_plasma_frequency(orc):
+    """A cold plasma displaced by a long-wavelength sinusoid oscillates at the
+    leapfrog plasma frequency (2/dt) asin(w_p dt / 2), w_p = 1 for unit density
+    and q/m = -1 (normalised units of App. A)."""
+    nx, ppc_x = (256, 2), 2
+    dx, dt = (0.2, 0.2), 0.1
+    g = orc.Grid(dim=2, nx=nx, dx=dx, dt=dt, order=1)
+    L = nx[0] * dx[0]
+    ii, jj = np.meshgrid(np.arange(nx[0] * ppc_x), np.arange(nx[1] * ppc_x), indexing="ij")
+    x = np.stack([(ii.ravel() + 0.5) * dx[0] / ppc_x, (jj.ravel() + 0.5) * dx[1] / ppc_x], axis=1)
+    k = 2 * math.pi / L
+    amp = 1e-4
+    x[:, 0] += amp * np.sin(k * x[:, 0])
+    u = np.zeros((len(x), 3))
+    w = -1.0 / (ppc_x * ppc_x)
+    E = np.zeros((3, g.ncell))
+    B = np.zeros((3, g.ncell))
+    # consistent initial E1 from Gauss's law in 1D: E1 at (i+1/2) = cumulative charge
+    rho = orc.rho(g, x, w).reshape(nx[1], nx[0]) + 1.0
+    e1 = np.cumsum(rho.mean(axis=0)) * dx[0]
+    e1 -= e1.mean()
+    E[0] = np.tile(e1, nx[1])
+    sig = []
+    nsteps = 330
+    for _ in range(nsteps):
+        r = orc.step(g, x, u, w, -1.0, E, B)
+        x, u, E, B = r.x, r.u, r.E, r.B
+        sig.append(E[0].reshape(nx[1], nx[0]).mean(axis=0) @ np.sin(k * (np.arange(nx[0]) + 0.5) * dx[0]))
+    sig = np.array(sig)
+    # zero crossings by linear interpolation
+    zc = [i + sig[i] / (sig[i] - sig[i + 1]) for i in range(len(sig) - 1) if sig[i] * sig[i + 1] < 0]
+    half_periods = np.diff(zc)
+    omega = math.pi / (np.mean(half_periods) * dt)
+    assert len(zc) >= 8
+    assert abs(omega / CF["plasma_omega"] - 1) < 1e-4, omega
