@@ -1,0 +1,201 @@
+/*
+ * pic.h -- C ABI of the MI355X particle-in-cell step library (libpic.so).
+ *
+ * The library advances a fully relativistic, electromagnetic particle-in-cell
+ * (PIC) plasma on one GPU.  One step is the loop of R. G. Hemker, "Particle-
+ * In-Cell Modeling of Plasma-Based Accelerators in Two and Three Dimensions"
+ * (2000), Ch. 3, Sec. 3.1: interpolate the Yee-staggered E and B to every
+ * particle, advance momentum (relativistic Boris push, Sec. 3.2 Eq.
+ * momentum-update) and position (Eq. 2d-position-update), deposit a
+ * charge-conserving current (the ISIS ordering average, Sec. 3.2, Eq.
+ * continuity), and advance the fields by the Yee scheme (Sec. 3.2 Eqs.
+ * 2d-field-solve-b-part1, -e, -b-part2; Sec. 3.3 for 3D).
+ *
+ * Units are the normalised units of App. A: time 1/omega_n, length
+ * c/omega_n, momentum u = p/(m c) = gamma*beta, fields m c omega_n / e,
+ * density n_n.  The Gaussian 4*pi is absorbed: dE/dt = curl B - J,
+ * div E = rho.
+ *
+ * Conventions shared by every call:
+ *  - Every function returns a pic_status; PIC_OK (0) on success, a negative
+ *    code otherwise.  The message of the last failure on a context is
+ *    available from pic_last_error().  No C++ exception crosses the ABI.
+ *  - FP64 at the ABI, FP32 inside (particles, fields, current); the
+ *    diagnostics reduce in FP64 with compensated sums.
+ *  - Buffers passed in are copied; the caller keeps ownership.  Outputs go
+ *    into caller buffers whose size in bytes is checked: when out_bytes is
+ *    too small the call fails with PIC_E_RANGE and *written holds the size
+ *    required.
+ *  - Grid arrays are [component][cell], cell = i0 + nx0*(i1 + nx1*i2), with
+ *    the staggering E1 (1/2,0,0), E2 (0,1/2,0), E3 (0,0,1/2),
+ *    B1 (0,1/2,1/2), B2 (1/2,0,1/2), B3 (1/2,1/2,0), J_d at E_d and rho at
+ *    the node (offsets in cells from node i; 2D drops the third offset).
+ *    This is the only layout consistent with the difference stencils of
+ *    Sec. 3.2 (the grid figure itself is not reproduced in the text).
+ *  - A context owns all device memory it allocates and works on one HIP
+ *    stream (the one given at creation, or the null stream).  Calls are
+ *    asynchronous with respect to the host unless stated; a context is not
+ *    safe for concurrent calls from several threads.
+ *  - All boundaries are periodic; on one device a periodic boundary is the
+ *    exchange of a domain with its own opposite face (App. A, node
+ *    configuration).
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pic_ctx pic_ctx;     /* opaque: one simulation instance */
+typedef struct pic_batch pic_batch; /* opaque: many independent instances */
+
+typedef enum {
+  PIC_OK = 0,
+  PIC_E_INVALID = -1,     /* bad argument or configuration */
+  PIC_E_NOMEM = -2,       /* device or host allocation failed, or capacity exceeded */
+  PIC_E_HIP = -3,         /* a HIP runtime call failed */
+  PIC_E_STATE = -4,       /* call not valid in the current state */
+  PIC_E_RANGE = -5,       /* non-finite input, or output buffer too small */
+  PIC_E_UNSUPPORTED = -6  /* valid request this build does not implement */
+} pic_status;
+
+/* Accumulator used for the current in the deposit. */
+enum {
+  PIC_ACC_FP32 = 0,        /* FP32 LDS and global atomic adds */
+  PIC_ACC_COMPENSATED = 1, /* FP32 pair: an exactly summed coarse part plus a
+                              rounded fine remainder (error-free split) */
+  PIC_ACC_FIXED64 = 2      /* int64 fixed point: exact and order independent */
+};
+
+/* Simulation configuration (the deck's grid, space, time and EM-field
+ * sections of App. A, restricted to periodic boxes). */
+typedef struct {
+  int32_t ndim;          /* 2 (2D3V) or 3 (3D3V) */
+  int32_t nx[3];         /* cells per axis; nx[2] ignored in 2D */
+  double dx[3];          /* cell size per axis */
+  double xmin[3];        /* lower corner of the box */
+  double dt;             /* time step; needs dt * sqrt(sum_d dx_d^-2) < 1
+                            (Courant condition, Sec. 4.5, generalised to
+                            several dimensions) */
+  int32_t shape_order;   /* particle shape: 1 linear (CIC), 2 quadratic, 3 cubic */
+  double e0[3];          /* uniform external E felt by the particles */
+  double b0[3];          /* uniform external B felt by the particles */
+  double ion_density;    /* immobile neutralising background charge density,
+                            used only by the rho and Gauss diagnostics */
+  int64_t capacity;      /* maximum particles per species (num_par_max) */
+  int32_t tile[3];       /* tile extent in cells; 0 = choose automatically */
+  int32_t sort_interval; /* steps between rebin checks; 0 = choose automatically */
+  int32_t chunk;         /* maximum particles one workgroup takes from a tile; 0 = auto */
+  int32_t accumulator;   /* PIC_ACC_* */
+} pic_config;
+
+/* Flags for the load calls. */
+#define PIC_DEVICE_PTRS 1u /* input pointers are device memory */
+
+/* Create a context.  cfg is copied.  hip_stream may be NULL (null stream).
+ * Fails with PIC_E_INVALID on a bad configuration, PIC_E_NOMEM when the
+ * device memory for the fields cannot be allocated.  *out is NULL on failure. */
+pic_status pic_create(const pic_config* cfg, void* hip_stream, pic_ctx** out);
+
+/* Release every resource of a context; NULL is accepted and ignored. */
+pic_status pic_destroy(pic_ctx* ctx);
+
+/* Append n particles to a species (0 <= species < 8).
+ * x: n*ndim absolute positions (FP64, row-major per particle), wrapped into
+ *    the periodic box;
+ * u: n*3 momenta u = p/(m c) at time n-1/2;
+ * w: n signed charge weights (charge density each macro-particle carries,
+ *    q * n / (n_n * particles per cell); electrons negative);
+ * rqm: mass-to-charge ratio of the species (App. A species section,
+ *    electrons -1); fixed by the first load of a species.
+ * The species' particles are re-binned by tile after the append.  Fails with
+ * PIC_E_RANGE on a non-finite value, PIC_E_NOMEM beyond the capacity. */
+pic_status pic_load_particles(pic_ctx* ctx, int32_t species, double rqm, int64_t n,
+                              const double* x, const double* u, const double* w,
+                              uint32_t flags);
+
+/* Overwrite E and B (each 3*ncell FP64 in the grid layout above) at the
+ * current time level n. */
+pic_status pic_load_fields(pic_ctx* ctx, const double* e, const double* b, uint32_t flags);
+
+/* Advance nsteps steps (asynchronous on the context's stream).  Fails with
+ * PIC_E_STATE when an earlier step found a particle outside the region
+ * staged for its tile (an internal invariant), PIC_E_INVALID for nsteps < 0. */
+pic_status pic_step(pic_ctx* ctx, int64_t nsteps);
+
+/* Block until all work queued on the context's stream has finished. */
+pic_status pic_sync(pic_ctx* ctx);
+
+typedef enum {
+  PIC_DIAG_ENERGY = 0,          /* double[4]: field E energy, field B energy,
+                                   kinetic energy (at u^{n-1/2}), their sum;
+                                   (V/2) sum |E|^2, (V/2) sum |B|^2,
+                                   V sum_p w rqm (gamma-1) */
+  PIC_DIAG_MOMENTUM = 1,        /* double[3]: V sum_p w rqm u */
+  PIC_DIAG_RHO = 2,             /* double[ncell]: rho at the nodes from the stored
+                                   positions, plus ion_density */
+  PIC_DIAG_GAUSS_RESIDUAL = 3,  /* double[ncell]: div E - rho (Sec. 3.1, Gauss law) */
+  PIC_DIAG_GAUSS_NORM = 4,      /* double[2]: max |div E - rho|, rms */
+  PIC_DIAG_RHO_SNAPSHOT = 5,    /* no output: keep rho for CHARGE_RESIDUAL */
+  PIC_DIAG_CHARGE_RESIDUAL = 6, /* double[ncell]: (rho_now - rho_snapshot)/dt + div J
+                                   with J of the last step (Eq. continuity); meaningful
+                                   when exactly one step ran since the snapshot */
+  PIC_DIAG_EXPORT_STATE = 7,    /* double[n*(ndim+4)]: per particle x[ndim], u[3], w,
+                                   species by species, each in load order */
+  PIC_DIAG_EXPORT_FIELDS = 8,   /* double[6*ncell]: E1 E2 E3 B1 B2 B3 at time n */
+  PIC_DIAG_EXPORT_CURRENT = 9,  /* double[3*ncell]: J^{n+1/2} of the last step */
+  PIC_DIAG_COUNTS = 10          /* double[4]: steps done, particles, rebins done,
+                                   rebin checks done */
+} pic_diag_kind;
+
+/* Compute or export a diagnostic into a host buffer (synchronous). */
+pic_status pic_diag(pic_ctx* ctx, pic_diag_kind kind, void* out, size_t out_bytes,
+                    size_t* written);
+
+/* Tuning and layout the context settled on. */
+typedef struct {
+  int32_t tile[3];
+  int32_t sort_interval;
+  int32_t chunk;
+  int32_t slack;       /* cells a particle may stray outside its tile between rebins */
+  int32_t accumulator;
+  int32_t nspecies;
+  int64_t nparticles[8];
+  double rqm[8];
+  int64_t lds_bytes;   /* LDS per workgroup of the fused particle kernel */
+} pic_info;
+
+pic_status pic_get_info(const pic_ctx* ctx, pic_info* out);
+
+/* Message of the last failure on ctx (never NULL; "" when none). */
+const char* pic_last_error(const pic_ctx* ctx);
+
+/* ---------------------------------------------------------------------
+ * Batched instances: n independent periodic boxes (parameter scans) with
+ * their own grids, shapes and particles, advanced together.  Each step of
+ * every instance runs in the same kernel launches (one per phase and shape
+ * order), and pic_batch_step replays them as one captured HIP graph.
+ * Per-instance results equal those of the same instance run alone.
+ * ------------------------------------------------------------------- */
+pic_status pic_batch_create(const pic_config* cfgs, int32_t n, void* hip_stream,
+                            pic_batch** out);
+pic_status pic_batch_destroy(pic_batch* b);
+pic_status pic_batch_load_particles(pic_batch* b, int32_t inst, int32_t species, double rqm,
+                                    int64_t n, const double* x, const double* u,
+                                    const double* w, uint32_t flags);
+pic_status pic_batch_load_fields(pic_batch* b, int32_t inst, const double* e, const double* bf,
+                                 uint32_t flags);
+pic_status pic_batch_step(pic_batch* b, int64_t nsteps);
+pic_status pic_batch_diag(pic_batch* b, int32_t inst, pic_diag_kind kind, void* out,
+                          size_t out_bytes, size_t* written);
+pic_status pic_batch_sync(pic_batch* b);
+const char* pic_batch_last_error(const pic_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIC_H */

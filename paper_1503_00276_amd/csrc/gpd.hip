@@ -1,0 +1,596 @@
+// gpd.hip -- the fused particle kernel: field gather, relativistic Boris push,
+// position advance and charge-conserving current deposit, one tile of particles
+// per work item (Hemker 2000, Ch. 3, Sec. 3.1 loop; Sec. 3.2 equations).
+//
+// Per work item (a run of particles that belong to one tile):
+//  1. stage E and B of the tile plus guard nodes from HBM into LDS
+//     (periodic wrap applied here, so the global planes carry no guards);
+//  2. clear an LDS current tile (tile plus deposit guards);
+//  3. for each particle: shape weights at the six staggered offsets, gather,
+//     Boris push, advance, re-cell, and the ISIS current in Esirkepov's closed
+//     form added to the LDS tile with LDS atomics;
+//  4. add the LDS current tile into the global current with atomics
+//     (overlapping guards of neighbouring tiles fold in here).
+//
+// Positions are stored as a packed integer cell plus an FP32 offset in [0,1)
+// per axis; all arithmetic is FP32.
+#include "pic_dev.h"
+#include "pic_kernels.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMaxGroup = 256;
+
+// ---------------------------------------------------------------------------
+// shape weights
+// ---------------------------------------------------------------------------
+
+// Weights of a B-spline of order ORDER for the staggered component whose
+// nodes sit at offset 0 (half=false) or 1/2 (half=true) from the cell's node
+// along one axis; eps is the particle's in-cell offset.  base is the first
+// node, relative to the particle's cell.
+template <int ORDER>
+__device__ __forceinline__ void gather_weights(float eps, bool half, int& base, float w[ORDER + 1]) {
+  if constexpr (ORDER == 1) {
+    float f;
+    if (!half) {
+      base = 0;
+      f = eps;
+    } else {
+      bool hi = eps >= 0.5f;
+      base = hi ? 0 : -1;
+      f = hi ? eps - 0.5f : eps + 0.5f;
+    }
+    w[0] = 1.0f - f;
+    w[1] = f;
+  } else if constexpr (ORDER == 2) {
+    float t;
+    if (!half) {
+      int n = eps >= 0.5f ? 1 : 0;
+      t = eps - (float)n;
+      base = n - 1;
+    } else {
+      t = eps - 0.5f;
+      base = -1;
+    }
+    float a = 0.5f - t, b = 0.5f + t;
+    w[0] = 0.5f * a * a;
+    w[1] = 0.75f - t * t;
+    w[2] = 0.5f * b * b;
+  } else {
+    float f;
+    if (!half) {
+      base = -1;
+      f = eps;
+    } else {
+      bool hi = eps >= 0.5f;
+      base = hi ? -1 : -2;
+      f = hi ? eps - 0.5f : eps + 0.5f;
+    }
+    float g = 1.0f - f, f2 = f * f, f3 = f2 * f;
+    const float s6 = 1.0f / 6.0f;
+    w[0] = g * g * g * s6;
+    w[1] = (4.0f - 6.0f * f2 + 3.0f * f3) * s6;
+    w[2] = (1.0f + 3.0f * f + 3.0f * f2 - 3.0f * f3) * s6;
+    w[3] = f3 * s6;
+  }
+}
+
+// Old shape S0 on a window of ORDER+2 nodes starting at node 'base' (relative
+// to the particle's old cell) and the change D = S1 - S0 on that window, for
+// a move from offset e0 in the old cell to offset e1 in the cell c (-1,0,1)
+// cells away.  When no knot of the shape is crossed D is formed from factored
+// differences (proportional to the displacement), keeping full FP32 relative
+// accuracy for small moves; otherwise D = S1 - S0 directly.
+template <int ORDER>
+__device__ __forceinline__ void deposit_shape(float e0, float e1, int c, int& base,
+                                              float S0[ORDER + 2], float D[ORDER + 2]) {
+  constexpr int W = ORDER + 2;
+#pragma unroll
+  for (int k = 0; k < W; k++) {
+    S0[k] = 0.0f;
+    D[k] = 0.0f;
+  }
+  if constexpr (ORDER == 1) {
+    // old nodes 0,1; new nodes c, c+1
+    base = c < 0 ? -1 : 0;
+    int p0 = -base;  // window position of old node 0
+    float a0 = 1.0f - e0;
+    if (p0 == 0) {
+      S0[0] = a0;
+      S0[1] = e0;
+    } else {
+      S0[1] = a0;
+      S0[2] = e0;
+    }
+    if (c == 0) {
+      float d = e1 - e0;
+      D[0] = -d;
+      D[1] = d;
+    } else if (c > 0) {
+      D[0] = -a0;
+      D[1] = a0 - e1;
+      D[2] = e1;
+    } else {
+      float a1 = 1.0f - e1;
+      D[0] = a1;
+      D[1] = e0 - a1;
+      D[2] = -e0;
+    }
+  } else if constexpr (ORDER == 2) {
+    int h0 = e0 >= 0.5f ? 1 : 0;
+    int h1 = e1 >= 0.5f ? 1 : 0;
+    int n0 = h0, n1 = c + h1;           // nearest nodes, relative to the old cell
+    float t0 = e0 - (float)h0, t1 = e1 - (float)h1;
+    int nlo = n0 < n1 ? n0 : n1;
+    base = nlo - 1;
+    int p0 = n0 - 1 - base;  // 0 or 1
+    float a = 0.5f - t0, b = 0.5f + t0;
+    float w0 = 0.5f * a * a, w1 = 0.75f - t0 * t0, w2 = 0.5f * b * b;
+    if (p0 == 0) {
+      S0[0] = w0; S0[1] = w1; S0[2] = w2;
+    } else {
+      S0[1] = w0; S0[2] = w1; S0[3] = w2;
+    }
+    if (n1 == n0) {
+      float d = t1 - t0, s = t0 + t1;
+      float v0 = 0.5f * d * (s - 1.0f), v1 = -d * s, v2 = 0.5f * d * (1.0f + s);
+      if (p0 == 0) {
+        D[0] = v0; D[1] = v1; D[2] = v2;
+      } else {
+        D[1] = v0; D[2] = v1; D[3] = v2;
+      }
+    } else {
+      int p1 = n1 - 1 - base;
+      float a1 = 0.5f - t1, b1 = 0.5f + t1;
+      float u0 = 0.5f * a1 * a1, u1 = 0.75f - t1 * t1, u2 = 0.5f * b1 * b1;
+      float S1[W] = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (p1 == 0) {
+        S1[0] = u0; S1[1] = u1; S1[2] = u2;
+      } else {
+        S1[1] = u0; S1[2] = u1; S1[3] = u2;
+      }
+#pragma unroll
+      for (int k = 0; k < W; k++) D[k] = S1[k] - S0[k];
+    }
+  } else {
+    // old nodes -1..2 (floor = 0), new nodes c-1..c+2
+    base = (c < 0 ? c : 0) - 1;
+    int p0 = -1 - base;  // 0 or 1
+    const float s6 = 1.0f / 6.0f;
+    float g0 = 1.0f - e0, f2 = e0 * e0, f3 = f2 * e0;
+    float w0 = g0 * g0 * g0 * s6, w1 = (4.0f - 6.0f * f2 + 3.0f * f3) * s6;
+    float w2 = (1.0f + 3.0f * e0 + 3.0f * f2 - 3.0f * f3) * s6, w3 = f3 * s6;
+    if (p0 == 0) {
+      S0[0] = w0; S0[1] = w1; S0[2] = w2; S0[3] = w3;
+    } else {
+      S0[1] = w0; S0[2] = w1; S0[3] = w2; S0[4] = w3;
+    }
+    if (c == 0) {
+      float d = e1 - e0;
+      float s = e1 + e0, q = e1 * e1 + e1 * e0 + e0 * e0;
+      float g1 = 1.0f - e1;
+      float a = g1 * g1 + g1 * g0 + g0 * g0;
+      D[0] = -(d * s6) * a;
+      D[1] = d * (0.5f * q - s);
+      D[2] = (0.5f * d) * (1.0f + s - q);
+      D[3] = (d * s6) * q;
+    } else {
+      int p1 = c - 1 - base;
+      float g1 = 1.0f - e1, h2 = e1 * e1, h3 = h2 * e1;
+      float u0 = g1 * g1 * g1 * s6, u1 = (4.0f - 6.0f * h2 + 3.0f * h3) * s6;
+      float u2 = (1.0f + 3.0f * e1 + 3.0f * h2 - 3.0f * h3) * s6, u3 = h3 * s6;
+      float S1[W] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+      if (p1 == 0) {
+        S1[0] = u0; S1[1] = u1; S1[2] = u2; S1[3] = u3;
+      } else {
+        S1[1] = u0; S1[2] = u1; S1[3] = u2; S1[4] = u3;
+      }
+#pragma unroll
+      for (int k = 0; k < W; k++) D[k] = S1[k] - S0[k];
+    }
+  }
+}
+
+__device__ __forceinline__ void lds_add(float* p, float v) {
+  if (v != 0.0f) __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// ---------------------------------------------------------------------------
+// one work item
+// ---------------------------------------------------------------------------
+
+template <int DIM, int ORDER>
+__device__ void process_item(const StoreDesc& S, int cur, const Item it, float* smem) {
+  constexpr int NG = ORDER + 1;  // gather taps per axis
+  constexpr int W = ORDER + 2;   // deposit window per axis
+  const GridDesc& g = S.g;
+  const int tid = threadIdx.x;
+
+  int tc[3];
+  pic_tile_coords(g, it.tile, tc);
+  int org[3], ext[3], FR[3], JR[3], flo[3], jlo[3];
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    if (d < DIM) {
+      org[d] = tc[d] * g.tile[d];
+      ext[d] = min(g.tile[d], g.nx[d] - org[d]);
+      flo[d] = g.slack + g.fa;  // region-relative index of tile node 0
+      jlo[d] = g.slack + g.ja;
+      FR[d] = ext[d] + 2 * g.slack + g.fa + g.fb;
+      JR[d] = ext[d] + 2 * g.slack + g.ja + g.jb;
+    } else {
+      org[d] = 0; ext[d] = 1; flo[d] = 0; jlo[d] = 0; FR[d] = 1; JR[d] = 1;
+    }
+  }
+  const int fn = FR[0] * FR[1] * FR[2];
+  const int jn = JR[0] * JR[1] * JR[2];
+  float* sF = smem;            // [6][fn]
+  float* sJ = smem + 6 * fn;   // [3][jn]
+
+  // 1. stage E, B with periodic wrap
+  const int ncell = g.ncell;
+  for (int idx = tid; idx < fn; idx += blockDim.x) {
+    int rx = idx % FR[0];
+    int rr = idx / FR[0];
+    int ry = rr % FR[1];
+    int rz = rr / FR[1];
+    int gx = pic_wrap(org[0] - flo[0] + rx, g.nx[0]);
+    int gy = pic_wrap(org[1] - flo[1] + ry, g.nx[1]);
+    int gz = DIM == 3 ? pic_wrap(org[2] - flo[2] + rz, g.nx[2]) : 0;
+    int gi = gx + g.nx[0] * (gy + g.nx[1] * gz);
+#pragma unroll
+    for (int c = 0; c < 6; c++) sF[c * fn + idx] = S.F[(size_t)c * ncell + gi];
+  }
+  // 2. clear the current tile
+  for (int idx = tid; idx < 3 * jn; idx += blockDim.x) sJ[idx] = 0.0f;
+  __syncthreads();
+
+  const int set = cur;
+  int* __restrict__ cellp = S.cell[set];
+  float* __restrict__ ep0 = S.eps[set][0];
+  float* __restrict__ ep1 = S.eps[set][1];
+  float* __restrict__ ep2 = S.eps[set][2];
+  float* __restrict__ up0 = S.u[set][0];
+  float* __restrict__ up1 = S.u[set][1];
+  float* __restrict__ up2 = S.u[set][2];
+  const float* __restrict__ wp = S.w[set];
+  const float h = 0.5f * S.qm * g.dt;
+  bool strayed = false, bad = false;
+
+  // 3. particles
+  for (int p = it.begin + tid; p < it.end; p += blockDim.x) {
+    int cell = cellp[p];
+    float e[3];
+    e[0] = ep0[p];
+    e[1] = ep1[p];
+    e[2] = DIM == 3 ? ep2[p] : 0.0f;
+    float ux = up0[p], uy = up1[p], uz = up2[p];
+    float wq = wp[p];
+    int cc[3];
+    pic_unpack(g, cell, cc);
+    int l[3] = {0, 0, 0};
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < DIM; d++) {
+      l[d] = pic_local(cc[d], org[d], ext[d], g.nx[d]);
+      ok = ok && (l[d] >= -g.slack) && (l[d] < ext[d] + g.slack);
+    }
+    if (!ok) {
+      bad = true;
+      continue;
+    }
+
+    // ---- gather: weights at offset 0 and 1/2 per axis
+    int b0[3], bh[3];
+    float w0[3][NG], wh[3][NG];
+#pragma unroll
+    for (int d = 0; d < DIM; d++) {
+      gather_weights<ORDER>(e[d], false, b0[d], w0[d]);
+      gather_weights<ORDER>(e[d], true, bh[d], wh[d]);
+    }
+    float Fp[6];
+#pragma unroll
+    for (int c = 0; c < 6; c++) {
+      // component c: E_c staggered half along axis c, B_c half along the others
+      bool hx = (c < 3) ? (c == 0) : (c != 3);
+      bool hy = (c < 3) ? (c == 1) : (c != 4);
+      bool hz = (c < 3) ? (c == 2) : (c != 5);
+      const float* wx = hx ? wh[0] : w0[0];
+      const float* wy = hy ? wh[1] : w0[1];
+      int sx = flo[0] + l[0] + (hx ? bh[0] : b0[0]);
+      int sy = flo[1] + l[1] + (hy ? bh[1] : b0[1]);
+      const float* Fc = sF + c * fn;
+      float acc = 0.0f;
+      if constexpr (DIM == 2) {
+#pragma unroll
+        for (int j = 0; j < NG; j++) {
+          const float* row = Fc + (sy + j) * FR[0] + sx;
+          float r = 0.0f;
+#pragma unroll
+          for (int i = 0; i < NG; i++) r += wx[i] * row[i];
+          acc += wy[j] * r;
+        }
+      } else {
+        const float* wz = hz ? wh[2] : w0[2];
+        int sz = flo[2] + l[2] + (hz ? bh[2] : b0[2]);
+#pragma unroll
+        for (int k = 0; k < NG; k++) {
+          float pl = 0.0f;
+#pragma unroll
+          for (int j = 0; j < NG; j++) {
+            const float* row = Fc + ((sz + k) * FR[1] + (sy + j)) * FR[0] + sx;
+            float r = 0.0f;
+#pragma unroll
+            for (int i = 0; i < NG; i++) r += wx[i] * row[i];
+            pl += wy[j] * r;
+          }
+          acc += wz[k] * pl;
+        }
+      }
+      Fp[c] = acc;
+    }
+    float Ex = Fp[0] + g.e0[0], Ey = Fp[1] + g.e0[1], Ez = Fp[2] + g.e0[2];
+    float Bx = Fp[3] + g.b0[0], By = Fp[4] + g.b0[1], Bz = Fp[5] + g.b0[2];
+
+    // ---- Boris push (Sec. 3.2, Eq. momentum-update)
+    float mx = ux + h * Ex, my = uy + h * Ey, mz = uz + h * Ez;
+    float gim = rsqrtf(1.0f + mx * mx + my * my + mz * mz);
+    float tx = h * Bx * gim, ty = h * By * gim, tz = h * Bz * gim;
+    float sfac = 2.0f / (1.0f + tx * tx + ty * ty + tz * tz);
+    float px = mx + (my * tz - mz * ty);
+    float py = my + (mz * tx - mx * tz);
+    float pz = mz + (mx * ty - my * tx);
+    float sx_ = sfac * tx, sy_ = sfac * ty, sz_ = sfac * tz;
+    ux = mx + (py * sz_ - pz * sy_) + h * Ex;
+    uy = my + (pz * sx_ - px * sz_) + h * Ey;
+    uz = mz + (px * sy_ - py * sx_) + h * Ez;
+
+    // ---- advance (Eq. 2d-position-update; in-plane only in 2D)
+    float gi = rsqrtf(1.0f + ux * ux + uy * uy + uz * uz);
+    float uu[3] = {ux, uy, uz};
+    float en[3];
+    int mv[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < DIM; d++) {
+      float x = e[d] + g.dt * g.rdx[d] * (uu[d] * gi);
+      float f = floorf(x);
+      int c = (int)f;
+      float r = x - f;
+      if (r >= 1.0f) {  // rounding edge: keep the offset in [0,1)
+        r = 0.0f;
+        c += 1;
+      }
+      // the Courant condition keeps |move| below one cell; clamp so a
+      // rounding of a move at the limit never leaves the deposit window
+      if (c > 1) {
+        c = 1;
+        r = 0.99999994f;
+      } else if (c < -1) {
+        c = -1;
+        r = 0.0f;
+      }
+      en[d] = r;
+      mv[d] = c;
+    }
+
+    // ---- deposit (ISIS ordering average in Esirkepov's closed form)
+    int wb[3];
+    float S0[3][W], D[3][W];
+#pragma unroll
+    for (int d = 0; d < DIM; d++) deposit_shape<ORDER>(e[d], en[d], mv[d], wb[d], S0[d], D[d]);
+    int jx = jlo[0] + l[0] + wb[0];
+    int jy = jlo[1] + l[1] + wb[1];
+    float* J1 = sJ;
+    float* J2 = sJ + jn;
+    float* J3 = sJ + 2 * jn;
+    float q1 = -wq * g.cdt[0], q2 = -wq * g.cdt[1];
+    float P1[W - 1], P2[W - 1];
+    {
+      float a = 0.0f, b = 0.0f;
+#pragma unroll
+      for (int k = 0; k < W - 1; k++) {
+        a += D[0][k];
+        b += D[1][k];
+        P1[k] = q1 * a;
+        P2[k] = q2 * b;
+      }
+    }
+    if constexpr (DIM == 2) {
+      float v3 = wq * uz * gi;
+#pragma unroll
+      for (int j = 0; j < W; j++) {
+        float T1 = S0[1][j] + 0.5f * D[1][j];
+        float U2 = 0.5f * S0[1][j] + (1.0f / 3.0f) * D[1][j];
+        float* r1 = J1 + (jy + j) * JR[0] + jx;
+        float* r3 = J3 + (jy + j) * JR[0] + jx;
+#pragma unroll
+        for (int i = 0; i < W - 1; i++) lds_add(r1 + i, P1[i] * T1);
+#pragma unroll
+        for (int i = 0; i < W; i++) lds_add(r3 + i, v3 * (S0[0][i] * T1 + D[0][i] * U2));
+      }
+#pragma unroll
+      for (int j = 0; j < W - 1; j++) {
+        float* r2 = J2 + (jy + j) * JR[0] + jx;
+#pragma unroll
+        for (int i = 0; i < W; i++) lds_add(r2 + i, P2[j] * (S0[0][i] + 0.5f * D[0][i]));
+      }
+    } else {
+      int jz = jlo[2] + l[2] + wb[2];
+      float q3 = -wq * g.cdt[2];
+      float P3[W - 1];
+      {
+        float a = 0.0f;
+#pragma unroll
+        for (int k = 0; k < W - 1; k++) {
+          a += D[2][k];
+          P3[k] = q3 * a;
+        }
+      }
+      const float th = 1.0f / 3.0f;
+      // J1: P1[i] * T1[k][j]
+#pragma unroll
+      for (int k = 0; k < W; k++) {
+#pragma unroll
+        for (int j = 0; j < W; j++) {
+          float T = S0[1][j] * S0[2][k] + 0.5f * (D[1][j] * S0[2][k] + S0[1][j] * D[2][k]) +
+                    th * D[1][j] * D[2][k];
+          float* r = J1 + ((jz + k) * JR[1] + (jy + j)) * JR[0] + jx;
+#pragma unroll
+          for (int i = 0; i < W - 1; i++) lds_add(r + i, P1[i] * T);
+        }
+      }
+      // J2: P2[j] * T2[k][i]
+#pragma unroll
+      for (int k = 0; k < W; k++) {
+        float Tk[W];
+#pragma unroll
+        for (int i = 0; i < W; i++)
+          Tk[i] = S0[0][i] * S0[2][k] + 0.5f * (D[0][i] * S0[2][k] + S0[0][i] * D[2][k]) +
+                  th * D[0][i] * D[2][k];
+#pragma unroll
+        for (int j = 0; j < W - 1; j++) {
+          float* r = J2 + ((jz + k) * JR[1] + (jy + j)) * JR[0] + jx;
+#pragma unroll
+          for (int i = 0; i < W; i++) lds_add(r + i, P2[j] * Tk[i]);
+        }
+      }
+      // J3: P3[k] * T3[j][i]
+#pragma unroll
+      for (int j = 0; j < W; j++) {
+        float Tj[W];
+#pragma unroll
+        for (int i = 0; i < W; i++)
+          Tj[i] = S0[0][i] * S0[1][j] + 0.5f * (D[0][i] * S0[1][j] + S0[0][i] * D[1][j]) +
+                  th * D[0][i] * D[1][j];
+#pragma unroll
+        for (int k = 0; k < W - 1; k++) {
+          float* r = J3 + ((jz + k) * JR[1] + (jy + j)) * JR[0] + jx;
+#pragma unroll
+          for (int i = 0; i < W; i++) lds_add(r + i, P3[k] * Tj[i]);
+        }
+      }
+    }
+
+    // ---- store the new state
+    int nc[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < DIM; d++) {
+      nc[d] = cc[d] + mv[d];
+      if (nc[d] < 0) nc[d] += g.nx[d];
+      if (nc[d] >= g.nx[d]) nc[d] -= g.nx[d];
+      int ln = pic_local(nc[d], org[d], ext[d], g.nx[d]);
+      strayed = strayed || ln < -g.flag_slack || ln >= ext[d] + g.flag_slack;
+    }
+    cellp[p] = pic_pack(g, nc[0], nc[1], DIM == 3 ? nc[2] : 0);
+    ep0[p] = en[0];
+    ep1[p] = en[1];
+    if (DIM == 3) ep2[p] = en[2];
+    up0[p] = ux;
+    up1[p] = uy;
+    up2[p] = uz;
+  }
+  if (strayed) atomicOr(&S.ctl->flag, 1);
+  if (bad) atomicOr(&S.ctl->bad, 1);
+  __syncthreads();
+
+  // 4. fold the LDS current into the global current (periodic wrap)
+  for (int idx = tid; idx < jn; idx += blockDim.x) {
+    int rx = idx % JR[0];
+    int rr = idx / JR[0];
+    int ry = rr % JR[1];
+    int rz = rr / JR[1];
+    int gx = pic_wrap(org[0] - jlo[0] + rx, g.nx[0]);
+    int gy = pic_wrap(org[1] - jlo[1] + ry, g.nx[1]);
+    int gz = DIM == 3 ? pic_wrap(org[2] - jlo[2] + rz, g.nx[2]) : 0;
+    int gi = gx + g.nx[0] * (gy + g.nx[1] * gz);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      float v = sJ[c * jn + idx];
+      if (v != 0.0f) unsafeAtomicAdd(S.J + (size_t)c * ncell + gi, v);
+    }
+  }
+  __syncthreads();
+}
+
+template <int DIM, int ORDER>
+__global__ void __launch_bounds__(kBlock) gpd_kernel(const StoreDesc* __restrict__ stores, int nstores) {
+  extern __shared__ float smem[];
+  __shared__ int s_pref[kMaxGroup + 1];
+  __shared__ int s_cur[kMaxGroup];
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int s = 0; s < nstores; s++) {
+      int cur = stores[s].ctl->cur;
+      s_cur[s] = cur;
+      s_pref[s] = acc;
+      acc += stores[s].ctl->n_items[cur];
+    }
+    s_pref[nstores] = acc;
+  }
+  __syncthreads();
+  const int total = s_pref[nstores];
+  int s = 0;
+  for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
+    while (gi >= s_pref[s + 1]) s++;
+    const StoreDesc& S = stores[s];
+    const int cur = s_cur[s];
+    const Item it = S.items[cur][gi - s_pref[s]];
+    process_item<DIM, ORDER>(S, cur, it, smem);
+  }
+}
+
+template <int DIM, int ORDER>
+hipError_t prepare_one(size_t lds) {
+  return hipFuncSetAttribute((const void*)gpd_kernel<DIM, ORDER>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds);
+}
+
+template <int DIM, int ORDER>
+hipError_t launch_one(const StoreDesc* stores, int nstores, int grid, size_t lds, hipStream_t st) {
+  gpd_kernel<DIM, ORDER><<<dim3(grid), dim3(kBlock), lds, st>>>(stores, nstores);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// LDS bytes one workgroup of the fused kernel needs for a grid.
+size_t pic_gpd_lds_bytes(const GridDesc& g) {
+  size_t fn = 1, jn = 1;
+  for (int d = 0; d < g.dim; d++) {
+    fn *= (size_t)(g.tile[d] + 2 * g.slack + g.fa + g.fb);
+    jn *= (size_t)(g.tile[d] + 2 * g.slack + g.ja + g.jb);
+  }
+  return (6 * fn + 3 * jn) * sizeof(float);
+}
+
+int pic_gpd_block() { return kBlock; }
+int pic_gpd_max_group() { return kMaxGroup; }
+
+hipError_t pic_gpd_prepare(int dim, int order, size_t lds) {
+  if (dim == 2) {
+    if (order == 1) return prepare_one<2, 1>(lds);
+    if (order == 2) return prepare_one<2, 2>(lds);
+    if (order == 3) return prepare_one<2, 3>(lds);
+  } else if (dim == 3) {
+    if (order == 1) return prepare_one<3, 1>(lds);
+    if (order == 2) return prepare_one<3, 2>(lds);
+    if (order == 3) return prepare_one<3, 3>(lds);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t pic_launch_gpd(int dim, int order, const StoreDesc* d_stores, int nstores, int grid,
+                          size_t lds, hipStream_t st) {
+  if (dim == 2) {
+    if (order == 1) return launch_one<2, 1>(d_stores, nstores, grid, lds, st);
+    if (order == 2) return launch_one<2, 2>(d_stores, nstores, grid, lds, st);
+    if (order == 3) return launch_one<2, 3>(d_stores, nstores, grid, lds, st);
+  } else if (dim == 3) {
+    if (order == 1) return launch_one<3, 1>(d_stores, nstores, grid, lds, st);
+    if (order == 2) return launch_one<3, 2>(d_stores, nstores, grid, lds, st);
+    if (order == 3) return launch_one<3, 3>(d_stores, nstores, grid, lds, st);
+  }
+  return hipErrorInvalidValue;
+}

@@ -1,0 +1,129 @@
+// pic_dev.h -- device-side data layout shared by the HIP kernels and the host
+// runtime of libpic.so.  Plain structs, copied to device memory once and read
+// by the kernels through a pointer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define PIC_MAX_SPECIES 8
+#define PIC_NSLOT 27  // neighbour slots (-1,0,+1)^3 for the rebin
+
+// One periodic box: grid, time step, shape order and tiling.
+struct GridDesc {
+  int dim;            // 2 or 3
+  int order;          // 1, 2, 3
+  int nx[3];          // cells per axis (1 on unused axes)
+  int tile[3];        // tile extent (cells)
+  int ntile[3];       // tiles per axis
+  int ntiles;         // product of ntile
+  int sh1, sh2;       // bit shifts of the packed cell index (c0 | c1<<sh1 | c2<<sh2)
+  int m0, m1;         // masks of c0 and c1
+  int slack;          // cells a particle may stray outside its tile at a step start
+  int flag_slack;     // stray distance (cells) beyond which a rebin is requested
+  int ncell;          // product of nx
+  float dx[3];        // cell size
+  float rdx[3];       // 1 / dx
+  float cdt[3];       // dx / dt (current per unit charge density per cell moved)
+  float dt;
+  float e0[3], b0[3]; // uniform external fields
+  double dxd[3];      // cell size in FP64 (diagnostics)
+  double dtd;         // time step in FP64 (diagnostics)
+  // LDS region geometry (nodes relative to the tile origin):
+  // field region [-(slack+fa), e+slack+fb), current region [-(slack+ja), e+slack+jb)
+  int fa, fb, ja, jb;
+};
+
+// Control words of one particle store, written by the kernels.
+struct StoreCtl {
+  int cur;          // which ping-pong buffer set holds the particles
+  int flag;         // a particle strayed beyond flag_slack: rebin at the next check
+  int n_items[2];   // work items of each buffer set
+  int bad;          // a particle was found outside its staged region (skipped)
+  int nsorts;       // rebins performed
+  int nchecks;      // rebin checks performed
+  int pad;
+};
+
+// Work item: a contiguous run of particles that all belong to one tile.
+struct Item {
+  int tile, begin, end, pad;
+};
+
+// One particle species of one instance: SoA particles in two ping-pong sets.
+struct StoreDesc {
+  GridDesc g;
+  float qm;                  // charge-to-mass ratio q/m = 1/rqm
+  int np;                    // particles stored
+  int chunk;                 // maximum particles per work item
+  int max_items;
+  float* F;                  // instance fields: E1 E2 E3 B1 B2 B3 planes of ncell floats
+  float* J;                  // instance current: J1 J2 J3 planes
+  int* cell[2];              // packed cell index
+  float* eps[2][3];          // in-cell offset in [0,1)
+  float* u[2][3];            // u = gamma v
+  float* w[2];               // charge weight
+  int* id[2];                // load order
+  int* toff[2];              // tile offsets [ntiles+1]
+  int* ioff[2];              // first item of each tile [ntiles+1]
+  Item* items[2];
+  int* cnt;                  // [max_items][27] slot counts of the current items
+  int* pre;                  // [max_items][27] prefix of cnt over earlier items of the tile
+  int* tot;                  // [ntiles][27]
+  int* dbase;                // [ntiles][27] slot base inside the destination tile
+  int* dcount;               // [ntiles]
+  StoreCtl* ctl;
+};
+
+// One instance (for the field kernels).
+struct InstDesc {
+  GridDesc g;
+  float* F;
+  float* J;
+};
+
+// ---------------------------------------------------------------------------
+// small helpers used by several kernels
+// ---------------------------------------------------------------------------
+
+__host__ __device__ inline int pic_wrap(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+// Position of cell coordinate c relative to a tile starting at o with extent
+// e on a periodic axis of n cells.  Cells inside the tile map to [0, e);
+// outside, the nearer side wins (ties go above), giving a value in (-n, n).
+__host__ __device__ inline int pic_local(int c, int o, int e, int n) {
+  int r = c - o;
+  if (r < 0) r += n;
+  if (r < e) return r;
+  int dh = r - e + 1;
+  int dl = n - r;
+  return (dh <= dl) ? r : r - n;
+}
+
+__host__ __device__ inline void pic_unpack(const GridDesc& g, int cell, int c[3]) {
+  c[0] = cell & g.m0;
+  c[1] = (cell >> g.sh1) & g.m1;
+  c[2] = cell >> g.sh2;
+}
+
+__host__ __device__ inline int pic_pack(const GridDesc& g, int c0, int c1, int c2) {
+  return c0 | (c1 << g.sh1) | (c2 << g.sh2);
+}
+
+__host__ __device__ inline void pic_tile_coords(const GridDesc& g, int t, int tc[3]) {
+  tc[0] = t % g.ntile[0];
+  int r = t / g.ntile[0];
+  tc[1] = r % g.ntile[1];
+  tc[2] = r / g.ntile[1];
+}
+
+__host__ __device__ inline int pic_tile_index(const GridDesc& g, int t0, int t1, int t2) {
+  return t0 + g.ntile[0] * (t1 + g.ntile[1] * t2);
+}
+
+// Slot (0..26) of a displacement d in {-1,0,1}^3.
+__host__ __device__ inline int pic_slot(int d0, int d1, int d2) {
+  return (d0 + 1) + 3 * (d1 + 1) + 9 * (d2 + 1);
+}

@@ -1,0 +1,43 @@
+// pic_kernels.h -- host-side launchers of the HIP kernels (one translation
+// unit per kernel family; the runtime calls only these).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include "pic_dev.h"
+
+// fused gather + push + deposit (gpd.hip)
+size_t pic_gpd_lds_bytes(const GridDesc& g);
+int pic_gpd_block();
+int pic_gpd_max_group();
+// allow the LDS size a group needs (call before launching or capturing)
+hipError_t pic_gpd_prepare(int dim, int order, size_t lds);
+hipError_t pic_launch_gpd(int dim, int order, const StoreDesc* d_stores, int nstores, int grid,
+                          size_t lds, hipStream_t st);
+
+// Yee field solve and current reset (field.hip); instances in d_inst[0..ninst)
+hipError_t pic_launch_zero_current(const InstDesc* d_inst, int ninst, int max_ncell, hipStream_t st);
+hipError_t pic_launch_yee_b(const InstDesc* d_inst, int ninst, int max_ncell, int dim, float hfrac,
+                            hipStream_t st);
+hipError_t pic_launch_yee_e(const InstDesc* d_inst, int ninst, int max_ncell, int dim, hipStream_t st);
+
+// tile rebin (sort.hip); stores in d_stores[0..nstores)
+hipError_t pic_launch_rebin(const StoreDesc* d_stores, int nstores, int max_items, int max_tiles,
+                            hipStream_t st);
+
+// diagnostics (diag.hip)
+hipError_t pic_launch_rho64(const StoreDesc* d_store, int np_max, double* rho, hipStream_t st);
+hipError_t pic_launch_fill64(double* p, double v, size_t n, hipStream_t st);
+hipError_t pic_launch_gauss64(const InstDesc* d_inst, const double* rho, double* G, int ncell,
+                              int dim, hipStream_t st);
+hipError_t pic_launch_charge64(const InstDesc* d_inst, const double* rho0, const double* rho1,
+                               double* C, int ncell, int dim, hipStream_t st);
+// compensated FP64 sums: out[0..nout) with partial scratch (>= 2*nout*pic_reduce_blocks() doubles)
+int pic_reduce_blocks();
+hipError_t pic_launch_field_sums(const InstDesc* d_inst, int ncell, double* scratch, double* out,
+                                 hipStream_t st);
+hipError_t pic_launch_particle_sums(const StoreDesc* d_store, int np, double rqm, double* scratch,
+                                    double* out, hipStream_t st);
+hipError_t pic_launch_sq_sums(const double* v, int n, double* scratch, double* out, hipStream_t st);
+hipError_t pic_launch_export_state(const StoreDesc* d_store, int np, double* out, hipStream_t st);
+hipError_t pic_launch_f32_to_f64(const float* in, double* out, size_t n, hipStream_t st);
+hipError_t pic_launch_f64_to_f32(const double* in, float* out, size_t n, hipStream_t st);

@@ -1,0 +1,1002 @@
+// runtime.hip -- host runtime and C ABI of libpic.so (declared in include/pic.h).
+//
+// A Sim holds one or more independent periodic instances.  A plain context is
+// a Sim of one instance; a batch is a Sim of many.  Each step launches, for
+// all instances together: current reset, the fused particle kernel (one
+// launch per dimension/shape-order group), the three Yee kernels, and every
+// sort_interval steps the conditional tile rebin.  pic_step replays captured
+// HIP graphs of whole rebin cycles.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pic.h"
+#include "pic_dev.h"
+#include "pic_kernels.h"
+
+namespace {
+
+constexpr int kLdsMax = 160 * 1024;
+constexpr int kNumCU = 256;
+
+struct Species {
+  bool used = false;
+  double rqm = 0.0;
+  int64_t np = 0;
+  int64_t cap = 0;
+  int max_items = 0;
+  std::vector<void*> allocs;
+  StoreDesc desc{};
+  StoreCtl* ctl = nullptr;
+};
+
+struct Instance {
+  pic_config cfg{};
+  GridDesc g{};
+  float* F = nullptr;
+  float* J = nullptr;
+  double* rho_snap = nullptr;
+  bool have_snap = false;
+  Species sp[PIC_MAX_SPECIES];
+  int64_t steps = 0;
+};
+
+struct Group {
+  int dim, order, first, count, max_ncell, max_items, max_tiles;
+  size_t lds;
+};
+
+struct Sim {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<Instance> inst;
+  int sort_interval = 1;
+  int64_t steps = 0;
+  StoreDesc* d_stores = nullptr;
+  int d_stores_cap = 0;
+  InstDesc* d_inst = nullptr;
+  std::vector<Group> sgroups, igroups;
+  std::vector<int> store_inst, store_species;  // d_stores index -> (instance, species)
+  bool dirty = true;
+  double* d_scratch = nullptr;  // reductions
+  double* d_out = nullptr;      // reduction outputs
+  std::string err;
+  // captured graphs: one rebin cycle (sort_interval steps ending with the check)
+  hipGraphExec_t cycle_exec = nullptr;
+  bool use_graph = true;
+
+  pic_status fail(pic_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    err = buf;
+    return code;
+  }
+};
+
+#define HIPCHK(S, expr)                                                                      \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return (S).fail(PIC_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+int bits_for(int n) {
+  int b = 0;
+  while ((1 << b) < n) b++;
+  return b;
+}
+
+// Region guards (nodes) of the gather (fa below, fb above) and of the deposit
+// window (ja, jb) for a shape order, relative to a particle's cell.
+void region_guards(int order, int& fa, int& fb, int& ja, int& jb) {
+  if (order == 1) { fa = 1; fb = 2; ja = 1; jb = 3; }
+  else if (order == 2) { fa = 1; fb = 3; ja = 2; jb = 4; }
+  else { fa = 2; fb = 3; ja = 2; jb = 4; }
+}
+
+// Largest tile extent <= target along an axis of n cells that divides n and
+// leaves room for a particle to stray 'need' cells; the whole axis otherwise.
+int pick_tile(int n, int target, int need) {
+  if (n <= target) return n;
+  for (int t = target; t >= need; t--)
+    if (n % t == 0) return t;
+  return n;
+}
+
+bool tile_ok(int n, int t, int need) {
+  if (t <= 0 || t > n) return false;
+  if (t == n) return true;
+  if (t < need) return false;
+  int r = n % t;
+  return r == 0 || r >= need;
+}
+
+// Fill g from a validated configuration, tile and sort interval.
+pic_status setup_grid(Sim& S, const pic_config& c, int sort_interval, GridDesc& g) {
+  memset(&g, 0, sizeof g);
+  g.dim = c.ndim;
+  g.order = c.shape_order;
+  double vmax = 0.0;
+  for (int d = 0; d < 3; d++) {
+    g.nx[d] = d < c.ndim ? c.nx[d] : 1;
+    g.dxd[d] = d < c.ndim ? c.dx[d] : 1.0;
+    g.dx[d] = (float)g.dxd[d];
+    g.rdx[d] = (float)(1.0 / g.dxd[d]);
+    g.cdt[d] = (float)(g.dxd[d] / c.dt);
+    g.e0[d] = (float)c.e0[d];
+    g.b0[d] = (float)c.b0[d];
+    if (d < c.ndim) vmax = std::max(vmax, c.dt / c.dx[d]);
+  }
+  g.dt = (float)c.dt;
+  g.dtd = c.dt;
+  g.flag_slack = 1;
+  int extra = (int)std::ceil((sort_interval - 1) * vmax - 1e-12);
+  g.slack = g.flag_slack + std::max(0, extra);
+  region_guards(g.order, g.fa, g.fb, g.ja, g.jb);
+  const int need = g.slack + 2;
+  g.ntiles = 1;
+  for (int d = 0; d < 3; d++) {
+    if (d >= c.ndim) {
+      g.tile[d] = 1;
+      g.ntile[d] = 1;
+      continue;
+    }
+    int t = c.tile[d];
+    if (t == 0) t = pick_tile(g.nx[d], c.ndim == 2 ? 16 : 8, need);
+    if (!tile_ok(g.nx[d], t, need))
+      return S.fail(PIC_E_INVALID, "tile[%d]=%d does not suit nx=%d (needs >= %d cells per tile and per remainder)",
+                    d, t, g.nx[d], need);
+    g.tile[d] = t;
+    g.ntile[d] = (g.nx[d] + t - 1) / t;
+    g.ntiles *= g.ntile[d];
+  }
+  int b0 = bits_for(g.nx[0]), b1 = bits_for(g.nx[1]), b2 = bits_for(g.nx[2]);
+  if (b0 + b1 + b2 > 31) return S.fail(PIC_E_INVALID, "grid too large for a 31-bit packed cell index");
+  g.sh1 = b0;
+  g.sh2 = b0 + b1;
+  g.m0 = (1 << b0) - 1;
+  g.m1 = (1 << b1) - 1;
+  g.ncell = g.nx[0] * g.nx[1] * g.nx[2];
+  // 3D tiles shrink until the fused kernel's LDS fits one workgroup
+  while (pic_gpd_lds_bytes(g) > (size_t)kLdsMax) {
+    int dmax = 0;
+    for (int d = 1; d < c.ndim; d++)
+      if (g.tile[d] > g.tile[dmax]) dmax = d;
+    int t = g.tile[dmax] / 2;
+    if (c.tile[dmax] != 0 || t < need) return S.fail(PIC_E_INVALID, "tile needs more LDS than a workgroup has");
+    while (t >= need && !tile_ok(g.nx[dmax], t, need)) t--;
+    if (t < need) return S.fail(PIC_E_INVALID, "no tile fits the LDS");
+    g.ntiles /= g.ntile[dmax];
+    g.tile[dmax] = t;
+    g.ntile[dmax] = (g.nx[dmax] + t - 1) / t;
+    g.ntiles *= g.ntile[dmax];
+  }
+  return PIC_OK;
+}
+
+pic_status validate(Sim& S, const pic_config& c) {
+  if (c.ndim != 2 && c.ndim != 3) return S.fail(PIC_E_INVALID, "ndim must be 2 or 3");
+  if (c.shape_order < 1 || c.shape_order > 3) return S.fail(PIC_E_INVALID, "shape_order must be 1, 2 or 3");
+  double inv = 0.0;
+  for (int d = 0; d < c.ndim; d++) {
+    if (c.nx[d] < 1) return S.fail(PIC_E_INVALID, "nx[%d] must be positive", d);
+    if (!(c.dx[d] > 0.0) || !std::isfinite(c.dx[d])) return S.fail(PIC_E_INVALID, "dx[%d] must be positive", d);
+    if (!std::isfinite(c.xmin[d])) return S.fail(PIC_E_INVALID, "xmin[%d] not finite", d);
+    inv += 1.0 / (c.dx[d] * c.dx[d]);
+  }
+  if (!(c.dt > 0.0) || !std::isfinite(c.dt)) return S.fail(PIC_E_INVALID, "dt must be positive");
+  if (c.dt * std::sqrt(inv) >= 1.0)
+    return S.fail(PIC_E_INVALID, "dt=%g violates the Courant condition dt*sqrt(sum 1/dx^2) < 1", c.dt);
+  if (c.capacity < 0 || c.capacity > (int64_t)0x7fffff00) return S.fail(PIC_E_INVALID, "capacity out of range");
+  if (c.accumulator != PIC_ACC_FP32)
+    return S.fail(PIC_E_UNSUPPORTED, "accumulator %d not available in this build", c.accumulator);
+  if (c.sort_interval < 0 || c.chunk < 0) return S.fail(PIC_E_INVALID, "negative sort_interval or chunk");
+  for (int d = 0; d < 3; d++)
+    if (!std::isfinite(c.e0[d]) || !std::isfinite(c.b0[d])) return S.fail(PIC_E_INVALID, "external field not finite");
+  return PIC_OK;
+}
+
+int default_interval(const pic_config& c) {
+  double vmax = 0.0;
+  for (int d = 0; d < c.ndim; d++) vmax = std::max(vmax, c.dt / c.dx[d]);
+  // largest interval whose slack stays at 2 cells
+  int s = 1 + (int)std::floor(1.0 / vmax + 1e-12);
+  return std::max(1, std::min(s, 8));
+}
+
+template <typename T>
+pic_status dalloc(Sim& S, std::vector<void*>& list, T** p, size_t n) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T));
+  if (e != hipSuccess) return S.fail(PIC_E_NOMEM, "hipMalloc of %zu bytes failed: %s", n * sizeof(T), hipGetErrorString(e));
+  list.push_back(q);
+  *p = (T*)q;
+  return PIC_OK;
+}
+
+void free_species(Species& sp) {
+  for (void* p : sp.allocs) (void)hipFree(p);
+  sp.allocs.clear();
+  sp.cap = 0;
+  sp.np = 0;
+  sp.ctl = nullptr;
+  memset(&sp.desc, 0, sizeof sp.desc);
+}
+
+// Allocate (or grow) a species store for 'cap' particles.
+pic_status alloc_species(Sim& S, Instance& I, Species& sp, int64_t cap, int chunk) {
+  free_species(sp);
+  const GridDesc& g = I.g;
+  StoreDesc& d = sp.desc;
+  memset(&d, 0, sizeof d);
+  d.g = g;
+  d.chunk = chunk;
+  d.max_items = (int)std::min<int64_t>((int64_t)g.ntiles + cap / chunk + 1, 0x7fffffff);
+  sp.max_items = d.max_items;
+  pic_status st;
+#define AL(ptr, n) \
+  if ((st = dalloc(S, sp.allocs, &(ptr), (size_t)(n))) != PIC_OK) return st
+  for (int s = 0; s < 2; s++) {
+    AL(d.cell[s], cap);
+    for (int k = 0; k < g.dim; k++) AL(d.eps[s][k], cap);
+    for (int k = 0; k < 3; k++) AL(d.u[s][k], cap);
+    AL(d.w[s], cap);
+    AL(d.id[s], cap);
+    AL(d.toff[s], g.ntiles + 1);
+    AL(d.ioff[s], g.ntiles + 1);
+    AL(d.items[s], d.max_items);
+  }
+  AL(d.cnt, (size_t)d.max_items * PIC_NSLOT);
+  AL(d.pre, (size_t)d.max_items * PIC_NSLOT);
+  AL(d.tot, (size_t)g.ntiles * PIC_NSLOT);
+  AL(d.dbase, (size_t)g.ntiles * PIC_NSLOT);
+  AL(d.dcount, g.ntiles);
+  AL(sp.ctl, 1);
+#undef AL
+  d.ctl = sp.ctl;
+  d.F = I.F;
+  d.J = I.J;
+  StoreCtl z{};
+  HIPCHK(S, hipMemcpy(sp.ctl, &z, sizeof z, hipMemcpyHostToDevice));
+  sp.cap = cap;
+  return PIC_OK;
+}
+
+// Rebuild the device descriptor arrays (stores grouped by dimension and shape
+// order, instances grouped by dimension).
+pic_status refresh_descriptors(Sim& S) {
+  if (!S.dirty) return PIC_OK;
+  std::vector<StoreDesc> stores;
+  S.store_inst.clear();
+  S.store_species.clear();
+  S.sgroups.clear();
+  S.igroups.clear();
+  for (int dim = 2; dim <= 3; dim++)
+    for (int order = 1; order <= 3; order++) {
+      Group gr{dim, order, (int)stores.size(), 0, 0, 0, 0, 0};
+      for (size_t i = 0; i < S.inst.size(); i++) {
+        Instance& I = S.inst[i];
+        if (I.g.dim != dim || I.g.order != order) continue;
+        for (int s = 0; s < PIC_MAX_SPECIES; s++) {
+          Species& sp = I.sp[s];
+          if (!sp.used || sp.np == 0) continue;
+          sp.desc.np = (int)sp.np;
+          stores.push_back(sp.desc);
+          S.store_inst.push_back((int)i);
+          S.store_species.push_back(s);
+          gr.count++;
+          gr.max_items += sp.max_items;
+          gr.max_tiles += I.g.ntiles;
+          gr.lds = std::max(gr.lds, pic_gpd_lds_bytes(I.g));
+        }
+      }
+          if (gr.count > 0) {
+        if (gr.count > pic_gpd_max_group()) return S.fail(PIC_E_INVALID, "too many stores in one group");
+        HIPCHK(S, pic_gpd_prepare(dim, order, gr.lds));
+        S.sgroups.push_back(gr);
+      }
+    }
+  std::vector<InstDesc> insts;
+  for (int dim = 2; dim <= 3; dim++) {
+    Group gr{dim, 0, (int)insts.size(), 0, 0, 0, 0, 0};
+    for (size_t i = 0; i < S.inst.size(); i++) {
+      Instance& I = S.inst[i];
+      if (I.g.dim != dim) continue;
+      insts.push_back(InstDesc{I.g, I.F, I.J});
+      gr.count++;
+      gr.max_ncell = std::max(gr.max_ncell, I.g.ncell);
+    }
+    if (gr.count > 0) S.igroups.push_back(gr);
+  }
+  if ((int)stores.size() > S.d_stores_cap) {
+    if (S.d_stores) (void)hipFree(S.d_stores);
+    S.d_stores = nullptr;
+    int cap = std::max<int>((int)stores.size(), 4);
+    HIPCHK(S, hipMalloc(&S.d_stores, cap * sizeof(StoreDesc)));
+    S.d_stores_cap = cap;
+  }
+  if (!stores.empty())
+    HIPCHK(S, hipMemcpy(S.d_stores, stores.data(), stores.size() * sizeof(StoreDesc), hipMemcpyHostToDevice));
+  if (S.d_inst) (void)hipFree(S.d_inst);
+  S.d_inst = nullptr;
+  HIPCHK(S, hipMalloc(&S.d_inst, std::max<size_t>(insts.size(), 1) * sizeof(InstDesc)));
+  HIPCHK(S, hipMemcpy(S.d_inst, insts.data(), insts.size() * sizeof(InstDesc), hipMemcpyHostToDevice));
+  if (S.cycle_exec) {
+    (void)hipGraphExecDestroy(S.cycle_exec);
+    S.cycle_exec = nullptr;
+  }
+  S.dirty = false;
+  return PIC_OK;
+}
+
+int inst_desc_index(const Sim& S, int i) {
+  // position of instance i in the dimension-grouped InstDesc array
+  int pos = 0;
+  for (int dim = 2; dim <= 3; dim++)
+    for (size_t k = 0; k < S.inst.size(); k++) {
+      if (S.inst[k].g.dim != dim) continue;
+      if ((int)k == i) return pos;
+      pos++;
+    }
+  return -1;
+}
+
+int store_desc_index(const Sim& S, int i, int s) {
+  for (size_t k = 0; k < S.store_inst.size(); k++)
+    if (S.store_inst[k] == i && S.store_species[k] == s) return (int)k;
+  return -1;
+}
+
+pic_status launch_steps(Sim& S, int nsteps, bool end_with_check) {
+  for (int k = 0; k < nsteps; k++) {
+    for (const Group& gr : S.igroups)
+      HIPCHK(S, pic_launch_zero_current(S.d_inst + gr.first, gr.count, gr.max_ncell, S.stream));
+    for (const Group& gr : S.sgroups) {
+      int per_cu = std::max(1, std::min(8, (int)(kLdsMax / std::max<size_t>(gr.lds, 1))));
+      int grid = std::max(1, std::min(gr.max_items, kNumCU * per_cu));
+      HIPCHK(S, pic_launch_gpd(gr.dim, gr.order, S.d_stores + gr.first, gr.count, grid, gr.lds, S.stream));
+    }
+    for (const Group& gr : S.igroups) {
+      HIPCHK(S, pic_launch_yee_b(S.d_inst + gr.first, gr.count, gr.max_ncell, gr.dim, 0.5f, S.stream));
+      HIPCHK(S, pic_launch_yee_e(S.d_inst + gr.first, gr.count, gr.max_ncell, gr.dim, S.stream));
+      HIPCHK(S, pic_launch_yee_b(S.d_inst + gr.first, gr.count, gr.max_ncell, gr.dim, 0.5f, S.stream));
+    }
+    if (end_with_check && k == nsteps - 1) {
+      for (const Group& gr : S.sgroups)
+        HIPCHK(S, pic_launch_rebin(S.d_stores + gr.first, gr.count, gr.max_items, gr.max_tiles, S.stream));
+    }
+  }
+  return PIC_OK;
+}
+
+pic_status capture_cycle(Sim& S) {
+  if (S.cycle_exec) return PIC_OK;
+  hipGraph_t graph = nullptr;
+  HIPCHK(S, hipStreamBeginCapture(S.stream, hipStreamCaptureModeThreadLocal));
+  pic_status st = launch_steps(S, S.sort_interval, true);
+  hipError_t e = hipStreamEndCapture(S.stream, &graph);
+  if (st != PIC_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return S.fail(PIC_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&S.cycle_exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    S.cycle_exec = nullptr;
+    return S.fail(PIC_E_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
+  }
+  return PIC_OK;
+}
+
+pic_status sim_step(Sim& S, int64_t nsteps) {
+  if (nsteps < 0) return S.fail(PIC_E_INVALID, "nsteps < 0");
+  if (nsteps == 0) return PIC_OK;
+  pic_status st = refresh_descriptors(S);
+  if (st != PIC_OK) return st;
+  if (S.sgroups.empty() && S.igroups.empty()) return PIC_OK;
+  const int SI = S.sort_interval;
+  int64_t done = 0;
+  while (done < nsteps) {
+    int64_t phase = S.steps % SI;  // steps already done in the current cycle
+    int64_t left = nsteps - done;
+    if (phase == 0 && left >= SI && S.use_graph) {
+      st = capture_cycle(S);
+      if (st != PIC_OK) return st;
+      HIPCHK(S, hipGraphLaunch(S.cycle_exec, S.stream));
+      S.steps += SI;
+      done += SI;
+      continue;
+    }
+    int64_t run = std::min<int64_t>(left, SI - phase);
+    bool check = (phase + run == SI);
+    st = launch_steps(S, (int)run, check);
+    if (st != PIC_OK) return st;
+    S.steps += run;
+    done += run;
+  }
+  for (Instance& I : S.inst) I.steps = S.steps;
+  return PIC_OK;
+}
+
+pic_status sim_sync(Sim& S) {
+  HIPCHK(S, hipStreamSynchronize(S.stream));
+  for (Instance& I : S.inst)
+    for (Species& sp : I.sp) {
+      if (!sp.used || !sp.ctl) continue;
+      StoreCtl c{};
+      HIPCHK(S, hipMemcpy(&c, sp.ctl, sizeof c, hipMemcpyDeviceToHost));
+      if (c.bad) return S.fail(PIC_E_STATE, "a particle left the region staged for its tile");
+    }
+  return PIC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// loading
+// ---------------------------------------------------------------------------
+
+struct HostParticles {
+  std::vector<int> cell, id;
+  std::vector<float> eps[3], u[3], w;
+  void resize(size_t n) {
+    cell.resize(n);
+    id.resize(n);
+    for (auto& v : eps) v.resize(n);
+    for (auto& v : u) v.resize(n);
+    w.resize(n);
+  }
+};
+
+pic_status read_back(Sim& S, Species& sp, int dim, HostParticles& h) {
+  h.resize(sp.np);
+  if (sp.np == 0) return PIC_OK;
+  StoreCtl c{};
+  HIPCHK(S, hipMemcpy(&c, sp.ctl, sizeof c, hipMemcpyDeviceToHost));
+  const int s = c.cur;
+  const StoreDesc& d = sp.desc;
+  size_t n = sp.np;
+  HIPCHK(S, hipMemcpy(h.cell.data(), d.cell[s], n * 4, hipMemcpyDeviceToHost));
+  HIPCHK(S, hipMemcpy(h.id.data(), d.id[s], n * 4, hipMemcpyDeviceToHost));
+  for (int k = 0; k < dim; k++) HIPCHK(S, hipMemcpy(h.eps[k].data(), d.eps[s][k], n * 4, hipMemcpyDeviceToHost));
+  for (int k = 0; k < 3; k++) HIPCHK(S, hipMemcpy(h.u[k].data(), d.u[s][k], n * 4, hipMemcpyDeviceToHost));
+  HIPCHK(S, hipMemcpy(h.w.data(), d.w[s], n * 4, hipMemcpyDeviceToHost));
+  return PIC_OK;
+}
+
+// Bin host particles by tile (stable) and upload them as buffer set 0.
+pic_status upload_binned(Sim& S, Instance& I, Species& sp, const HostParticles& h) {
+  const GridDesc& g = I.g;
+  const size_t n = h.cell.size();
+  std::vector<int> tile(n), count(g.ntiles + 1, 0);
+  for (size_t p = 0; p < n; p++) {
+    int c[3];
+    pic_unpack(g, h.cell[p], c);
+    int t = pic_tile_index(g, c[0] / g.tile[0], c[1] / g.tile[1], g.dim == 3 ? c[2] / g.tile[2] : 0);
+    tile[p] = t;
+    count[t + 1]++;
+  }
+  std::vector<int> toff(g.ntiles + 1, 0);
+  for (int t = 0; t < g.ntiles; t++) toff[t + 1] = toff[t] + count[t + 1];
+  std::vector<int> pos(toff.begin(), toff.end() - 1);
+  HostParticles o;
+  o.resize(n);
+  for (size_t p = 0; p < n; p++) {
+    int q = pos[tile[p]]++;
+    o.cell[q] = h.cell[p];
+    o.id[q] = h.id[p];
+    for (int k = 0; k < 3; k++) {
+      o.eps[k][q] = h.eps[k][p];
+      o.u[k][q] = h.u[k][p];
+    }
+    o.w[q] = h.w[p];
+  }
+  const int chunk = sp.desc.chunk;
+  std::vector<int> ioff(g.ntiles + 1, 0);
+  std::vector<Item> items;
+  for (int t = 0; t < g.ntiles; t++) {
+    int c = toff[t + 1] - toff[t];
+    ioff[t] = (int)items.size();
+    for (int b = 0; b < c; b += chunk) items.push_back(Item{t, toff[t] + b, toff[t] + std::min(c, b + chunk), 0});
+  }
+  ioff[g.ntiles] = (int)items.size();
+  if ((int)items.size() > sp.max_items) return S.fail(PIC_E_NOMEM, "work item list overflow");
+  const StoreDesc& d = sp.desc;
+  if (n > 0) {
+    HIPCHK(S, hipMemcpy(d.cell[0], o.cell.data(), n * 4, hipMemcpyHostToDevice));
+    HIPCHK(S, hipMemcpy(d.id[0], o.id.data(), n * 4, hipMemcpyHostToDevice));
+    for (int k = 0; k < g.dim; k++) HIPCHK(S, hipMemcpy(d.eps[0][k], o.eps[k].data(), n * 4, hipMemcpyHostToDevice));
+    for (int k = 0; k < 3; k++) HIPCHK(S, hipMemcpy(d.u[0][k], o.u[k].data(), n * 4, hipMemcpyHostToDevice));
+    HIPCHK(S, hipMemcpy(d.w[0], o.w.data(), n * 4, hipMemcpyHostToDevice));
+  }
+  HIPCHK(S, hipMemcpy(d.toff[0], toff.data(), toff.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(S, hipMemcpy(d.ioff[0], ioff.data(), ioff.size() * 4, hipMemcpyHostToDevice));
+  if (!items.empty()) HIPCHK(S, hipMemcpy(d.items[0], items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
+  StoreCtl c{};
+  HIPCHK(S, hipMemcpy(&c, sp.ctl, sizeof c, hipMemcpyDeviceToHost));
+  c.cur = 0;
+  c.flag = 0;
+  c.bad = 0;
+  c.n_items[0] = (int)items.size();
+  c.n_items[1] = 0;
+  HIPCHK(S, hipMemcpy(sp.ctl, &c, sizeof c, hipMemcpyHostToDevice));
+  sp.np = (int64_t)n;
+  sp.desc.np = (int)n;
+  S.dirty = true;
+  return PIC_OK;
+}
+
+pic_status copy_in(Sim& S, std::vector<double>& dst, const double* src, size_t n, uint32_t flags) {
+  dst.resize(n);
+  if (n == 0) return PIC_OK;
+  if (flags & PIC_DEVICE_PTRS)
+    HIPCHK(S, hipMemcpy(dst.data(), src, n * sizeof(double), hipMemcpyDeviceToHost));
+  else
+    memcpy(dst.data(), src, n * sizeof(double));
+  return PIC_OK;
+}
+
+pic_status sim_load(Sim& S, int inst, int32_t species, double rqm, int64_t n, const double* x,
+                    const double* u, const double* w, uint32_t flags) {
+  if (inst < 0 || inst >= (int)S.inst.size()) return S.fail(PIC_E_INVALID, "instance %d out of range", inst);
+  if (species < 0 || species >= PIC_MAX_SPECIES) return S.fail(PIC_E_INVALID, "species %d out of range", species);
+  if (n < 0) return S.fail(PIC_E_INVALID, "n < 0");
+  if (n > 0 && (!x || !u || !w)) return S.fail(PIC_E_INVALID, "null particle array");
+  if (!std::isfinite(rqm) || rqm == 0.0) return S.fail(PIC_E_INVALID, "rqm must be finite and nonzero");
+  Instance& I = S.inst[inst];
+  Species& sp = I.sp[species];
+  HIPCHK(S, hipStreamSynchronize(S.stream));
+  if (sp.used && sp.rqm != rqm) return S.fail(PIC_E_INVALID, "rqm differs from the species' first load");
+  const int dim = I.g.dim;
+  std::vector<double> hx, hu, hw;
+  pic_status st;
+  if ((st = copy_in(S, hx, x, (size_t)n * dim, flags)) != PIC_OK) return st;
+  if ((st = copy_in(S, hu, u, (size_t)n * 3, flags)) != PIC_OK) return st;
+  if ((st = copy_in(S, hw, w, (size_t)n, flags)) != PIC_OK) return st;
+  for (double v : hx)
+    if (!std::isfinite(v)) return S.fail(PIC_E_RANGE, "non-finite position");
+  for (double v : hu)
+    if (!std::isfinite(v)) return S.fail(PIC_E_RANGE, "non-finite momentum");
+  for (double v : hw)
+    if (!std::isfinite(v)) return S.fail(PIC_E_RANGE, "non-finite weight");
+  const int64_t total = sp.np + n;
+  if (I.cfg.capacity > 0 && total > I.cfg.capacity)
+    return S.fail(PIC_E_NOMEM, "species %d would hold %lld particles, capacity %lld", species, (long long)total,
+                  (long long)I.cfg.capacity);
+  if (total > 0x7fffff00LL) return S.fail(PIC_E_NOMEM, "too many particles");
+  HostParticles h;
+  if ((st = read_back(S, sp, dim, h)) != PIC_OK) return st;
+  const size_t old = h.cell.size();
+  h.resize(old + n);
+  for (int64_t p = 0; p < n; p++) {
+    int c[3] = {0, 0, 0};
+    for (int d = 0; d < dim; d++) {
+      double L = (double)I.g.nx[d];
+      double xi = (hx[p * dim + d] - I.cfg.xmin[d]) / I.cfg.dx[d];
+      xi = std::fmod(xi, L);
+      if (xi < 0.0) xi += L;
+      if (xi >= L) xi -= L;
+      double f = std::floor(xi);
+      int ci = (int)f;
+      float e = (float)(xi - f);
+      if (e >= 1.0f) {
+        e = 0.0f;
+        ci += 1;
+      }
+      if (ci >= I.g.nx[d]) ci -= I.g.nx[d];
+      c[d] = ci;
+      h.eps[d][old + p] = e;
+    }
+    h.cell[old + p] = pic_pack(I.g, c[0], c[1], c[2]);
+    h.id[old + p] = (int)(old + p);
+    for (int k = 0; k < 3; k++) h.u[k][old + p] = (float)hu[p * 3 + k];
+    h.w[old + p] = (float)hw[p];
+  }
+  if (!sp.used || total > sp.cap) {
+    int64_t cap = I.cfg.capacity > 0 ? I.cfg.capacity : total;
+    int chunk = I.cfg.chunk > 0 ? I.cfg.chunk : 2048;
+    if ((st = alloc_species(S, I, sp, std::max<int64_t>(cap, 1), chunk)) != PIC_OK) return st;
+    sp.used = true;
+    sp.rqm = rqm;
+    sp.desc.qm = (float)(1.0 / rqm);
+  }
+  return upload_binned(S, I, sp, h);
+}
+
+pic_status sim_load_fields(Sim& S, int inst, const double* e, const double* b, uint32_t flags) {
+  if (inst < 0 || inst >= (int)S.inst.size()) return S.fail(PIC_E_INVALID, "instance out of range");
+  if (!e || !b) return S.fail(PIC_E_INVALID, "null field array");
+  Instance& I = S.inst[inst];
+  size_t n = (size_t)3 * I.g.ncell;
+  std::vector<double> he, hb;
+  pic_status st;
+  if ((st = copy_in(S, he, e, n, flags)) != PIC_OK) return st;
+  if ((st = copy_in(S, hb, b, n, flags)) != PIC_OK) return st;
+  std::vector<float> f(2 * n);
+  for (size_t i = 0; i < n; i++) {
+    if (!std::isfinite(he[i]) || !std::isfinite(hb[i])) return S.fail(PIC_E_RANGE, "non-finite field value");
+    f[i] = (float)he[i];
+    f[n + i] = (float)hb[i];
+  }
+  HIPCHK(S, hipStreamSynchronize(S.stream));
+  HIPCHK(S, hipMemcpy(I.F, f.data(), 2 * n * sizeof(float), hipMemcpyHostToDevice));
+  return PIC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// diagnostics
+// ---------------------------------------------------------------------------
+
+pic_status need(Sim& S, size_t want, size_t out_bytes, size_t* written) {
+  if (written) *written = want;
+  if (out_bytes < want) return S.fail(PIC_E_RANGE, "output buffer of %zu bytes, %zu needed", out_bytes, want);
+  return PIC_OK;
+}
+
+pic_status compute_rho(Sim& S, int i, double* d_rho) {
+  Instance& I = S.inst[i];
+  HIPCHK(S, pic_launch_fill64(d_rho, I.cfg.ion_density, (size_t)I.g.ncell, S.stream));
+  for (int s = 0; s < PIC_MAX_SPECIES; s++) {
+    if (!I.sp[s].used || I.sp[s].np == 0) continue;
+    int k = store_desc_index(S, i, s);
+    if (k < 0) return S.fail(PIC_E_STATE, "species descriptor missing");
+    HIPCHK(S, pic_launch_rho64(S.d_stores + k, (int)I.sp[s].np, d_rho, S.stream));
+  }
+  return PIC_OK;
+}
+
+pic_status sim_diag(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_bytes, size_t* written) {
+  if (i < 0 || i >= (int)S.inst.size()) return S.fail(PIC_E_INVALID, "instance out of range");
+  if (written) *written = 0;
+  pic_status st = refresh_descriptors(S);
+  if (st != PIC_OK) return st;
+  if ((st = sim_sync(S)) != PIC_OK) return st;
+  Instance& I = S.inst[i];
+  const GridDesc& g = I.g;
+  const size_t nc = (size_t)g.ncell;
+  const int ii = inst_desc_index(S, i);
+  const double V = g.dxd[0] * g.dxd[1] * (g.dim == 3 ? g.dxd[2] : 1.0);
+  if (kind != PIC_DIAG_RHO_SNAPSHOT && !out) return S.fail(PIC_E_INVALID, "null output buffer");
+  std::vector<void*> tmp;
+  struct Free {
+    std::vector<void*>& v;
+    ~Free() {
+      for (void* p : v) (void)hipFree(p);
+    }
+  } fr{tmp};
+  switch (kind) {
+    case PIC_DIAG_ENERGY:
+    case PIC_DIAG_MOMENTUM: {
+      size_t want = (kind == PIC_DIAG_ENERGY ? 4 : 3) * sizeof(double);
+      if ((st = need(S, want, out_bytes, written)) != PIC_OK) return st;
+      double fe[2] = {0, 0}, pm[4] = {0, 0, 0, 0};
+      HIPCHK(S, pic_launch_field_sums(S.d_inst + ii, g.ncell, S.d_scratch, S.d_out, S.stream));
+      HIPCHK(S, hipMemcpyAsync(fe, S.d_out, 2 * sizeof(double), hipMemcpyDeviceToHost, S.stream));
+      HIPCHK(S, hipStreamSynchronize(S.stream));
+      for (int s = 0; s < PIC_MAX_SPECIES; s++) {
+        Species& sp = I.sp[s];
+        if (!sp.used || sp.np == 0) continue;
+        int k = store_desc_index(S, i, s);
+        double r[4];
+        HIPCHK(S, pic_launch_particle_sums(S.d_stores + k, (int)sp.np, sp.rqm, S.d_scratch, S.d_out, S.stream));
+        HIPCHK(S, hipMemcpyAsync(r, S.d_out, 4 * sizeof(double), hipMemcpyDeviceToHost, S.stream));
+        HIPCHK(S, hipStreamSynchronize(S.stream));
+        for (int q = 0; q < 4; q++) pm[q] += r[q];
+      }
+      double* o = (double*)out;
+      if (kind == PIC_DIAG_ENERGY) {
+        o[0] = 0.5 * V * fe[0];
+        o[1] = 0.5 * V * fe[1];
+        o[2] = V * pm[0];
+        o[3] = o[0] + o[1] + o[2];
+      } else {
+        o[0] = V * pm[1];
+        o[1] = V * pm[2];
+        o[2] = V * pm[3];
+      }
+      return PIC_OK;
+    }
+    case PIC_DIAG_RHO:
+    case PIC_DIAG_GAUSS_RESIDUAL:
+    case PIC_DIAG_GAUSS_NORM:
+    case PIC_DIAG_CHARGE_RESIDUAL: {
+      size_t want = (kind == PIC_DIAG_GAUSS_NORM ? 2 : nc) * sizeof(double);
+      if ((st = need(S, want, out_bytes, written)) != PIC_OK) return st;
+      if (kind == PIC_DIAG_CHARGE_RESIDUAL && !I.have_snap)
+        return S.fail(PIC_E_STATE, "CHARGE_RESIDUAL needs an earlier RHO_SNAPSHOT");
+      double *rho = nullptr, *res = nullptr;
+      HIPCHK(S, hipMalloc(&rho, nc * sizeof(double)));
+      tmp.push_back(rho);
+      if ((st = compute_rho(S, i, rho)) != PIC_OK) return st;
+      double* src = rho;
+      if (kind != PIC_DIAG_RHO) {
+        HIPCHK(S, hipMalloc(&res, nc * sizeof(double)));
+        tmp.push_back(res);
+        if (kind == PIC_DIAG_CHARGE_RESIDUAL)
+          HIPCHK(S, pic_launch_charge64(S.d_inst + ii, I.rho_snap, rho, res, g.ncell, g.dim, S.stream));
+        else
+          HIPCHK(S, pic_launch_gauss64(S.d_inst + ii, rho, res, g.ncell, g.dim, S.stream));
+        src = res;
+      }
+      if (kind == PIC_DIAG_GAUSS_NORM) {
+        double ss = 0.0;
+        HIPCHK(S, pic_launch_sq_sums(res, g.ncell, S.d_scratch, S.d_out, S.stream));
+        HIPCHK(S, hipMemcpyAsync(&ss, S.d_out, sizeof(double), hipMemcpyDeviceToHost, S.stream));
+        std::vector<double> h(nc);
+        HIPCHK(S, hipMemcpyAsync(h.data(), res, nc * sizeof(double), hipMemcpyDeviceToHost, S.stream));
+        HIPCHK(S, hipStreamSynchronize(S.stream));
+        double mx = 0.0;
+        for (double v : h) mx = std::max(mx, std::fabs(v));
+        ((double*)out)[0] = mx;
+        ((double*)out)[1] = std::sqrt(ss / (double)nc);
+        return PIC_OK;
+      }
+      HIPCHK(S, hipMemcpyAsync(out, src, nc * sizeof(double), hipMemcpyDeviceToHost, S.stream));
+      HIPCHK(S, hipStreamSynchronize(S.stream));
+      return PIC_OK;
+    }
+    case PIC_DIAG_RHO_SNAPSHOT: {
+      if (!I.rho_snap) HIPCHK(S, hipMalloc(&I.rho_snap, nc * sizeof(double)));
+      if ((st = compute_rho(S, i, I.rho_snap)) != PIC_OK) return st;
+      HIPCHK(S, hipStreamSynchronize(S.stream));
+      I.have_snap = true;
+      return PIC_OK;
+    }
+    case PIC_DIAG_EXPORT_STATE: {
+      int64_t ntot = 0;
+      for (Species& sp : I.sp)
+        if (sp.used) ntot += sp.np;
+      const int stride = g.dim + 4;
+      if ((st = need(S, (size_t)ntot * stride * sizeof(double), out_bytes, written)) != PIC_OK) return st;
+      double* o = (double*)out;
+      for (int s = 0; s < PIC_MAX_SPECIES; s++) {
+        Species& sp = I.sp[s];
+        if (!sp.used || sp.np == 0) continue;
+        int k = store_desc_index(S, i, s);
+        double* dbuf = nullptr;
+        HIPCHK(S, hipMalloc(&dbuf, (size_t)sp.np * stride * sizeof(double)));
+        tmp.push_back(dbuf);
+        HIPCHK(S, pic_launch_export_state(S.d_stores + k, (int)sp.np, dbuf, S.stream));
+        HIPCHK(S, hipMemcpyAsync(o, dbuf, (size_t)sp.np * stride * sizeof(double), hipMemcpyDeviceToHost, S.stream));
+        HIPCHK(S, hipStreamSynchronize(S.stream));
+        for (int64_t p = 0; p < sp.np; p++)
+          for (int d = 0; d < g.dim; d++) o[p * stride + d] = I.cfg.xmin[d] + o[p * stride + d] * I.cfg.dx[d];
+        o += (size_t)sp.np * stride;
+      }
+      return PIC_OK;
+    }
+    case PIC_DIAG_EXPORT_FIELDS:
+    case PIC_DIAG_EXPORT_CURRENT: {
+      size_t ncomp = kind == PIC_DIAG_EXPORT_FIELDS ? 6 : 3;
+      if ((st = need(S, ncomp * nc * sizeof(double), out_bytes, written)) != PIC_OK) return st;
+      double* dbuf = nullptr;
+      HIPCHK(S, hipMalloc(&dbuf, ncomp * nc * sizeof(double)));
+      tmp.push_back(dbuf);
+      HIPCHK(S, pic_launch_f32_to_f64(kind == PIC_DIAG_EXPORT_FIELDS ? I.F : I.J, dbuf, ncomp * nc, S.stream));
+      HIPCHK(S, hipMemcpyAsync(out, dbuf, ncomp * nc * sizeof(double), hipMemcpyDeviceToHost, S.stream));
+      HIPCHK(S, hipStreamSynchronize(S.stream));
+      return PIC_OK;
+    }
+    case PIC_DIAG_COUNTS: {
+      if ((st = need(S, 4 * sizeof(double), out_bytes, written)) != PIC_OK) return st;
+      double* o = (double*)out;
+      o[0] = (double)I.steps;
+      o[1] = 0;
+      o[2] = 0;
+      o[3] = 0;
+      for (Species& sp : I.sp) {
+        if (!sp.used || !sp.ctl) continue;
+        StoreCtl c{};
+        HIPCHK(S, hipMemcpy(&c, sp.ctl, sizeof c, hipMemcpyDeviceToHost));
+        o[1] += (double)sp.np;
+        o[2] = std::max(o[2], (double)c.nsorts);
+        o[3] = std::max(o[3], (double)c.nchecks);
+      }
+      return PIC_OK;
+    }
+  }
+  return S.fail(PIC_E_INVALID, "unknown diagnostic kind %d", (int)kind);
+}
+
+pic_status sim_create(Sim& S, const pic_config* cfgs, int n, void* stream) {
+  if (!cfgs || n < 1) return S.fail(PIC_E_INVALID, "no configuration");
+  S.stream = (hipStream_t)stream;
+  if (!S.stream) {
+    // graph capture needs a stream of our own when the caller gives none
+    HIPCHK(S, hipStreamCreateWithFlags(&S.stream, hipStreamNonBlocking));
+    S.own_stream = true;
+  }
+  int SI = 0;
+  for (int i = 0; i < n; i++) {
+    pic_status st = validate(S, cfgs[i]);
+    if (st != PIC_OK) return st;
+    int si = cfgs[i].sort_interval > 0 ? cfgs[i].sort_interval : default_interval(cfgs[i]);
+    SI = (i == 0) ? si : std::min(SI, si);
+  }
+  S.sort_interval = SI;
+  const char* env = getenv("PIC_NO_GRAPH");
+  S.use_graph = !(env && env[0] == '1');
+  S.inst.resize(n);
+  for (int i = 0; i < n; i++) {
+    Instance& I = S.inst[i];
+    I.cfg = cfgs[i];
+    pic_status st = setup_grid(S, cfgs[i], SI, I.g);
+    if (st != PIC_OK) return st;
+    size_t nc = (size_t)I.g.ncell;
+    if (hipMalloc(&I.F, 6 * nc * sizeof(float)) != hipSuccess) return S.fail(PIC_E_NOMEM, "field allocation failed");
+    if (hipMalloc(&I.J, 3 * nc * sizeof(float)) != hipSuccess) return S.fail(PIC_E_NOMEM, "current allocation failed");
+    HIPCHK(S, hipMemset(I.F, 0, 6 * nc * sizeof(float)));
+    HIPCHK(S, hipMemset(I.J, 0, 3 * nc * sizeof(float)));
+  }
+  HIPCHK(S, hipMalloc(&S.d_scratch, (size_t)2 * 4 * pic_reduce_blocks() * sizeof(double)));
+  HIPCHK(S, hipMalloc(&S.d_out, 8 * sizeof(double)));
+  S.dirty = true;
+  return PIC_OK;
+}
+
+void sim_destroy(Sim& S) {
+  if (S.cycle_exec) (void)hipGraphExecDestroy(S.cycle_exec);
+  for (Instance& I : S.inst) {
+    for (Species& sp : I.sp) free_species(sp);
+    if (I.F) (void)hipFree(I.F);
+    if (I.J) (void)hipFree(I.J);
+    if (I.rho_snap) (void)hipFree(I.rho_snap);
+  }
+  if (S.d_stores) (void)hipFree(S.d_stores);
+  if (S.d_inst) (void)hipFree(S.d_inst);
+  if (S.d_scratch) (void)hipFree(S.d_scratch);
+  if (S.d_out) (void)hipFree(S.d_out);
+  if (S.own_stream && S.stream) (void)hipStreamDestroy(S.stream);
+}
+
+pic_status sim_info(const Sim& S, int i, pic_info* out) {
+  if (!out || i < 0 || i >= (int)S.inst.size()) return PIC_E_INVALID;
+  memset(out, 0, sizeof *out);
+  const Instance& I = S.inst[i];
+  for (int d = 0; d < 3; d++) out->tile[d] = I.g.tile[d];
+  out->sort_interval = S.sort_interval;
+  out->slack = I.g.slack;
+  out->accumulator = I.cfg.accumulator;
+  out->lds_bytes = (int64_t)pic_gpd_lds_bytes(I.g);
+  for (int s = 0; s < PIC_MAX_SPECIES; s++) {
+    if (!I.sp[s].used) continue;
+    out->nspecies = s + 1;
+    out->nparticles[s] = I.sp[s].np;
+    out->rqm[s] = I.sp[s].rqm;
+    out->chunk = I.sp[s].desc.chunk;
+  }
+  if (out->chunk == 0) out->chunk = I.cfg.chunk > 0 ? I.cfg.chunk : 2048;
+  return PIC_OK;
+}
+
+}  // namespace
+
+struct pic_ctx {
+  Sim s;
+};
+struct pic_batch {
+  Sim s;
+};
+
+extern "C" {
+
+pic_status pic_create(const pic_config* cfg, void* hip_stream, pic_ctx** out) {
+  if (!out) return PIC_E_INVALID;
+  *out = nullptr;
+  pic_ctx* c = new (std::nothrow) pic_ctx();
+  if (!c) return PIC_E_NOMEM;
+  pic_status st = sim_create(c->s, cfg, 1, hip_stream);
+  if (st != PIC_OK) {
+    fprintf(stderr, "pic_create: %s\n", c->s.err.c_str());
+    sim_destroy(c->s);
+    delete c;
+    return st;
+  }
+  *out = c;
+  return PIC_OK;
+}
+
+pic_status pic_destroy(pic_ctx* ctx) {
+  if (!ctx) return PIC_OK;
+  (void)hipStreamSynchronize(ctx->s.stream);
+  sim_destroy(ctx->s);
+  delete ctx;
+  return PIC_OK;
+}
+
+pic_status pic_load_particles(pic_ctx* ctx, int32_t species, double rqm, int64_t n, const double* x,
+                              const double* u, const double* w, uint32_t flags) {
+  if (!ctx) return PIC_E_INVALID;
+  return sim_load(ctx->s, 0, species, rqm, n, x, u, w, flags);
+}
+
+pic_status pic_load_fields(pic_ctx* ctx, const double* e, const double* b, uint32_t flags) {
+  if (!ctx) return PIC_E_INVALID;
+  return sim_load_fields(ctx->s, 0, e, b, flags);
+}
+
+pic_status pic_step(pic_ctx* ctx, int64_t nsteps) {
+  if (!ctx) return PIC_E_INVALID;
+  return sim_step(ctx->s, nsteps);
+}
+
+pic_status pic_sync(pic_ctx* ctx) {
+  if (!ctx) return PIC_E_INVALID;
+  return sim_sync(ctx->s);
+}
+
+pic_status pic_diag(pic_ctx* ctx, pic_diag_kind kind, void* out, size_t out_bytes, size_t* written) {
+  if (!ctx) return PIC_E_INVALID;
+  return sim_diag(ctx->s, 0, kind, out, out_bytes, written);
+}
+
+pic_status pic_get_info(const pic_ctx* ctx, pic_info* out) {
+  if (!ctx) return PIC_E_INVALID;
+  return sim_info(ctx->s, 0, out);
+}
+
+const char* pic_last_error(const pic_ctx* ctx) { return ctx ? ctx->s.err.c_str() : "null context"; }
+
+pic_status pic_batch_create(const pic_config* cfgs, int32_t n, void* hip_stream, pic_batch** out) {
+  if (!out) return PIC_E_INVALID;
+  *out = nullptr;
+  pic_batch* b = new (std::nothrow) pic_batch();
+  if (!b) return PIC_E_NOMEM;
+  pic_status st = sim_create(b->s, cfgs, n, hip_stream);
+  if (st != PIC_OK) {
+    fprintf(stderr, "pic_batch_create: %s\n", b->s.err.c_str());
+    sim_destroy(b->s);
+    delete b;
+    return st;
+  }
+  *out = b;
+  return PIC_OK;
+}
+
+pic_status pic_batch_destroy(pic_batch* b) {
+  if (!b) return PIC_OK;
+  (void)hipStreamSynchronize(b->s.stream);
+  sim_destroy(b->s);
+  delete b;
+  return PIC_OK;
+}
+
+pic_status pic_batch_load_particles(pic_batch* b, int32_t inst, int32_t species, double rqm, int64_t n,
+                                    const double* x, const double* u, const double* w, uint32_t flags) {
+  if (!b) return PIC_E_INVALID;
+  return sim_load(b->s, inst, species, rqm, n, x, u, w, flags);
+}
+
+pic_status pic_batch_load_fields(pic_batch* b, int32_t inst, const double* e, const double* bf, uint32_t flags) {
+  if (!b) return PIC_E_INVALID;
+  return sim_load_fields(b->s, inst, e, bf, flags);
+}
+
+pic_status pic_batch_step(pic_batch* b, int64_t nsteps) {
+  if (!b) return PIC_E_INVALID;
+  return sim_step(b->s, nsteps);
+}
+
+pic_status pic_batch_diag(pic_batch* b, int32_t inst, pic_diag_kind kind, void* out, size_t out_bytes,
+                          size_t* written) {
+  if (!b) return PIC_E_INVALID;
+  return sim_diag(b->s, inst, kind, out, out_bytes, written);
+}
+
+pic_status pic_batch_sync(pic_batch* b) {
+  if (!b) return PIC_E_INVALID;
+  return sim_sync(b->s);
+}
+
+const char* pic_batch_last_error(const pic_batch* b) { return b ? b->s.err.c_str() : "null batch"; }
+
+}  // extern "C"
