@@ -63,12 +63,18 @@ typedef enum {
   PIC_E_UNSUPPORTED = -6  /* valid request this build does not implement */
 } pic_status;
 
-/* Accumulator used for the current in the deposit. */
+/* Accumulation of the current.  Every particle's FP32 contribution is
+ * rounded to an integer multiple of a power-of-two unit (2^-30 of the largest
+ * possible single contribution, max|w| * max(dx/dt, 1)) and the contributions
+ * of a tile are summed exactly in int64 in LDS. */
 enum {
-  PIC_ACC_FP32 = 0,        /* FP32 LDS and global atomic adds */
-  PIC_ACC_COMPENSATED = 1, /* FP32 pair: an exactly summed coarse part plus a
-                              rounded fine remainder (error-free split) */
-  PIC_ACC_FIXED64 = 2      /* int64 fixed point: exact and order independent */
+  PIC_ACC_FP32 = 0,        /* exact tile sums, folded into the FP32 current
+                              with FP32 global atomic adds */
+  PIC_ACC_COMPENSATED = 1, /* same as PIC_ACC_FP32: the exact int64 tile sum
+                              is the compensated accumulation */
+  PIC_ACC_FIXED64 = 2      /* tiles folded in int64 too: the current is
+                              independent of the order of the adds (bitwise
+                              reproducible), converted to FP32 once per step */
 };
 
 /* Simulation configuration (the deck's grid, space, time and EM-field
@@ -148,13 +154,24 @@ typedef enum {
                                    species by species, each in load order */
   PIC_DIAG_EXPORT_FIELDS = 8,   /* double[6*ncell]: E1 E2 E3 B1 B2 B3 at time n */
   PIC_DIAG_EXPORT_CURRENT = 9,  /* double[3*ncell]: J^{n+1/2} of the last step */
-  PIC_DIAG_COUNTS = 10          /* double[4]: steps done, particles, rebins done,
+  PIC_DIAG_COUNTS = 10,         /* double[4]: steps done, particles, rebins done,
                                    rebin checks done */
+  PIC_DIAG_KERNEL_TIMES = 11    /* double[6]: milliseconds and launches of the fused
+                                   particle kernel, of the field kernels (current reset
+                                   and Yee), and of the rebin checks, summed over the
+                                   steps run while profiling was on (HIP events on the
+                                   context's stream) */
 } pic_diag_kind;
 
 /* Compute or export a diagnostic into a host buffer (synchronous). */
 pic_status pic_diag(pic_ctx* ctx, pic_diag_kind kind, void* out, size_t out_bytes,
                     size_t* written);
+
+/* Profiling: while enabled, pic_step launches every kernel individually
+ * (no graph replay) and brackets each kernel family with HIP events on the
+ * context's stream; PIC_DIAG_KERNEL_TIMES reads the sums.  enable = 0 turns it
+ * off, 1 turns it on, 2 turns it on and clears the sums. */
+pic_status pic_profile(pic_ctx* ctx, int32_t enable);
 
 /* Tuning and layout the context settled on. */
 typedef struct {
@@ -193,6 +210,7 @@ pic_status pic_batch_step(pic_batch* b, int64_t nsteps);
 pic_status pic_batch_diag(pic_batch* b, int32_t inst, pic_diag_kind kind, void* out,
                           size_t out_bytes, size_t* written);
 pic_status pic_batch_sync(pic_batch* b);
+pic_status pic_batch_profile(pic_batch* b, int32_t enable);
 const char* pic_batch_last_error(const pic_batch* b);
 
 #ifdef __cplusplus

@@ -25,7 +25,21 @@ __device__ __forceinline__ void cell_coords(const GridDesc& g, int c, int& i, in
 __global__ void __launch_bounds__(kBlock) zero_current(const InstDesc* __restrict__ inst) {
   const InstDesc& I = inst[blockIdx.y];
   const int n = 3 * I.g.ncell;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) I.J[c] = 0.0f;
+  if (I.g.acc_mode == 2) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) I.J64[c] = 0ull;
+  } else {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) I.J[c] = 0.0f;
+  }
+}
+
+// Deterministic mode: the int64 fixed-point current becomes the FP32 current.
+__global__ void __launch_bounds__(kBlock) fold_current(const InstDesc* __restrict__ inst) {
+  const InstDesc& I = inst[blockIdx.y];
+  if (I.g.acc_mode != 2) return;
+  const int n = 3 * I.g.ncell;
+  const double inv = (double)I.g.jinv;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
+    I.J[c] = (float)((double)(long long)I.J64[c] * inv);
 }
 
 template <int DIM>
@@ -111,6 +125,11 @@ int grid_for(int max_n) {
 
 hipError_t pic_launch_zero_current(const InstDesc* d_inst, int ninst, int max_ncell, hipStream_t st) {
   hipLaunchKernelGGL(zero_current, dim3(grid_for(3 * max_ncell), ninst), dim3(kBlock), 0, st, d_inst);
+  return hipGetLastError();
+}
+
+hipError_t pic_launch_fold_current(const InstDesc* d_inst, int ninst, int max_ncell, hipStream_t st) {
+  hipLaunchKernelGGL(fold_current, dim3(grid_for(3 * max_ncell), ninst), dim3(kBlock), 0, st, d_inst);
   return hipGetLastError();
 }
 

@@ -19,6 +19,11 @@
 
 namespace {
 
+// Global-address-space views: pointers read from the descriptor are generic;
+// casting them lets the compiler emit global (not flat) memory instructions.
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) int gint;
+
 constexpr int kBlock = 256;
 constexpr int kMaxGroup = 256;
 
@@ -193,8 +198,16 @@ __device__ __forceinline__ void deposit_shape(float e0, float e1, int c, int& ba
   }
 }
 
-__device__ __forceinline__ void lds_add(float* p, float v) {
-  if (v != 0.0f) __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+// LDS current accumulator.  FP32 atomic adds to LDS are slow on gfx950
+// (about 0.3 lane-ops per cycle per CU against 5-10 for integer adds), so each
+// FP32 contribution v, bounded by |w| max(dx/dt, 1), is rounded to an integer
+// in units of 1/scale (|v*scale| < 2^30) and summed exactly in int64.
+typedef unsigned long long acc_t;
+
+__device__ __forceinline__ void lds_add(acc_t* p, float v, float scale) {
+  int q = __float2int_rn(v * scale);
+  if (q != 0)
+    __hip_atomic_fetch_add(p, (acc_t)(long long)q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // ---------------------------------------------------------------------------
@@ -226,8 +239,8 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, float* 
   }
   const int fn = FR[0] * FR[1] * FR[2];
   const int jn = JR[0] * JR[1] * JR[2];
-  float* sF = smem;            // [6][fn]
-  float* sJ = smem + 6 * fn;   // [3][jn]
+  float* sF = smem;                                     // [6][fn]
+  acc_t* sJ = (acc_t*)(smem + ((6 * fn + 1) & ~1));     // [3][jn], 8-byte aligned
 
   // 1. stage E, B with periodic wrap
   const int ncell = g.ncell;
@@ -240,22 +253,23 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, float* 
     int gy = pic_wrap(org[1] - flo[1] + ry, g.nx[1]);
     int gz = DIM == 3 ? pic_wrap(org[2] - flo[2] + rz, g.nx[2]) : 0;
     int gi = gx + g.nx[0] * (gy + g.nx[1] * gz);
+    const gfloat* Fg = (const gfloat*)S.F;
 #pragma unroll
-    for (int c = 0; c < 6; c++) sF[c * fn + idx] = S.F[(size_t)c * ncell + gi];
+    for (int c = 0; c < 6; c++) sF[c * fn + idx] = Fg[(size_t)c * ncell + gi];
   }
   // 2. clear the current tile
-  for (int idx = tid; idx < 3 * jn; idx += blockDim.x) sJ[idx] = 0.0f;
+  for (int idx = tid; idx < 3 * jn; idx += blockDim.x) sJ[idx] = 0ull;
   __syncthreads();
 
   const int set = cur;
-  int* __restrict__ cellp = S.cell[set];
-  float* __restrict__ ep0 = S.eps[set][0];
-  float* __restrict__ ep1 = S.eps[set][1];
-  float* __restrict__ ep2 = S.eps[set][2];
-  float* __restrict__ up0 = S.u[set][0];
-  float* __restrict__ up1 = S.u[set][1];
-  float* __restrict__ up2 = S.u[set][2];
-  const float* __restrict__ wp = S.w[set];
+  gint* __restrict__ cellp = (gint*)S.cell[set];
+  gfloat* __restrict__ ep0 = (gfloat*)S.eps[set][0];
+  gfloat* __restrict__ ep1 = (gfloat*)S.eps[set][1];
+  gfloat* __restrict__ ep2 = (gfloat*)S.eps[set][2];
+  gfloat* __restrict__ up0 = (gfloat*)S.u[set][0];
+  gfloat* __restrict__ up1 = (gfloat*)S.u[set][1];
+  gfloat* __restrict__ up2 = (gfloat*)S.u[set][2];
+  const gfloat* __restrict__ wp = (const gfloat*)S.w[set];
   const float h = 0.5f * S.qm * g.dt;
   bool strayed = false, bad = false;
 
@@ -382,9 +396,10 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, float* 
     for (int d = 0; d < DIM; d++) deposit_shape<ORDER>(e[d], en[d], mv[d], wb[d], S0[d], D[d]);
     int jx = jlo[0] + l[0] + wb[0];
     int jy = jlo[1] + l[1] + wb[1];
-    float* J1 = sJ;
-    float* J2 = sJ + jn;
-    float* J3 = sJ + 2 * jn;
+    acc_t* J1 = sJ;
+    acc_t* J2 = sJ + jn;
+    acc_t* J3 = sJ + 2 * jn;
+    const float js = g.jscale;
     float q1 = -wq * g.cdt[0], q2 = -wq * g.cdt[1];
     float P1[W - 1], P2[W - 1];
     {
@@ -403,18 +418,18 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, float* 
       for (int j = 0; j < W; j++) {
         float T1 = S0[1][j] + 0.5f * D[1][j];
         float U2 = 0.5f * S0[1][j] + (1.0f / 3.0f) * D[1][j];
-        float* r1 = J1 + (jy + j) * JR[0] + jx;
-        float* r3 = J3 + (jy + j) * JR[0] + jx;
+        acc_t* r1 = J1 + (jy + j) * JR[0] + jx;
+        acc_t* r3 = J3 + (jy + j) * JR[0] + jx;
 #pragma unroll
-        for (int i = 0; i < W - 1; i++) lds_add(r1 + i, P1[i] * T1);
+        for (int i = 0; i < W - 1; i++) lds_add(r1 + i, P1[i] * T1, js);
 #pragma unroll
-        for (int i = 0; i < W; i++) lds_add(r3 + i, v3 * (S0[0][i] * T1 + D[0][i] * U2));
+        for (int i = 0; i < W; i++) lds_add(r3 + i, v3 * (S0[0][i] * T1 + D[0][i] * U2), js);
       }
 #pragma unroll
       for (int j = 0; j < W - 1; j++) {
-        float* r2 = J2 + (jy + j) * JR[0] + jx;
+        acc_t* r2 = J2 + (jy + j) * JR[0] + jx;
 #pragma unroll
-        for (int i = 0; i < W; i++) lds_add(r2 + i, P2[j] * (S0[0][i] + 0.5f * D[0][i]));
+        for (int i = 0; i < W; i++) lds_add(r2 + i, P2[j] * (S0[0][i] + 0.5f * D[0][i]), js);
       }
     } else {
       int jz = jlo[2] + l[2] + wb[2];
@@ -436,9 +451,9 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, float* 
         for (int j = 0; j < W; j++) {
           float T = S0[1][j] * S0[2][k] + 0.5f * (D[1][j] * S0[2][k] + S0[1][j] * D[2][k]) +
                     th * D[1][j] * D[2][k];
-          float* r = J1 + ((jz + k) * JR[1] + (jy + j)) * JR[0] + jx;
+          acc_t* r = J1 + ((jz + k) * JR[1] + (jy + j)) * JR[0] + jx;
 #pragma unroll
-          for (int i = 0; i < W - 1; i++) lds_add(r + i, P1[i] * T);
+          for (int i = 0; i < W - 1; i++) lds_add(r + i, P1[i] * T, js);
         }
       }
       // J2: P2[j] * T2[k][i]
@@ -451,9 +466,9 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, float* 
                   th * D[0][i] * D[2][k];
 #pragma unroll
         for (int j = 0; j < W - 1; j++) {
-          float* r = J2 + ((jz + k) * JR[1] + (jy + j)) * JR[0] + jx;
+          acc_t* r = J2 + ((jz + k) * JR[1] + (jy + j)) * JR[0] + jx;
 #pragma unroll
-          for (int i = 0; i < W; i++) lds_add(r + i, P2[j] * Tk[i]);
+          for (int i = 0; i < W; i++) lds_add(r + i, P2[j] * Tk[i], js);
         }
       }
       // J3: P3[k] * T3[j][i]
@@ -466,9 +481,9 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, float* 
                   th * D[0][i] * D[1][j];
 #pragma unroll
         for (int k = 0; k < W - 1; k++) {
-          float* r = J3 + ((jz + k) * JR[1] + (jy + j)) * JR[0] + jx;
+          acc_t* r = J3 + ((jz + k) * JR[1] + (jy + j)) * JR[0] + jx;
 #pragma unroll
-          for (int i = 0; i < W; i++) lds_add(r + i, P3[k] * Tj[i]);
+          for (int i = 0; i < W; i++) lds_add(r + i, P3[k] * Tj[i], js);
         }
       }
     }
@@ -507,8 +522,14 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, float* 
     int gi = gx + g.nx[0] * (gy + g.nx[1] * gz);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-      float v = sJ[c * jn + idx];
-      if (v != 0.0f) unsafeAtomicAdd(S.J + (size_t)c * ncell + gi, v);
+      long long q = (long long)sJ[c * jn + idx];
+      if (q != 0) {
+        if (g.acc_mode == 2)
+          atomicAdd(S.J64 + (size_t)c * ncell + gi, (acc_t)q);
+        else
+          __builtin_amdgcn_global_atomic_fadd_f32((gfloat*)S.J + (size_t)c * ncell + gi,
+                                                  (float)((double)q * (double)g.jinv));
+      }
     }
   }
   __syncthreads();
@@ -562,7 +583,7 @@ size_t pic_gpd_lds_bytes(const GridDesc& g) {
     fn *= (size_t)(g.tile[d] + 2 * g.slack + g.fa + g.fb);
     jn *= (size_t)(g.tile[d] + 2 * g.slack + g.ja + g.jb);
   }
-  return (6 * fn + 3 * jn) * sizeof(float);
+  return ((6 * fn + 1) & ~(size_t)1) * sizeof(float) + 3 * jn * sizeof(unsigned long long);
 }
 
 int pic_gpd_block() { return kBlock; }

@@ -28,6 +28,10 @@ struct GridDesc {
   float e0[3], b0[3]; // uniform external fields
   double dxd[3];      // cell size in FP64 (diagnostics)
   double dtd;         // time step in FP64 (diagnostics)
+  // current accumulation: contributions are rounded to integers in units of
+  // jinv = 1/jscale (a power of two) and summed exactly in int64
+  float jscale, jinv;
+  int acc_mode;       // 0/1: FP32 fold of the tile sums, 2: int64 fold (deterministic)
   // LDS region geometry (nodes relative to the tile origin):
   // field region [-(slack+fa), e+slack+fb), current region [-(slack+ja), e+slack+jb)
   int fa, fb, ja, jb;
@@ -58,6 +62,7 @@ struct StoreDesc {
   int max_items;
   float* F;                  // instance fields: E1 E2 E3 B1 B2 B3 planes of ncell floats
   float* J;                  // instance current: J1 J2 J3 planes
+  unsigned long long* J64;   // int64 fixed-point current (deterministic mode only)
   int* cell[2];              // packed cell index
   float* eps[2][3];          // in-cell offset in [0,1)
   float* u[2][3];            // u = gamma v
@@ -79,6 +84,7 @@ struct InstDesc {
   GridDesc g;
   float* F;
   float* J;
+  unsigned long long* J64;
 };
 
 // ---------------------------------------------------------------------------

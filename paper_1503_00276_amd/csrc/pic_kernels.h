@@ -16,6 +16,7 @@ hipError_t pic_launch_gpd(int dim, int order, const StoreDesc* d_stores, int nst
 
 // Yee field solve and current reset (field.hip); instances in d_inst[0..ninst)
 hipError_t pic_launch_zero_current(const InstDesc* d_inst, int ninst, int max_ncell, hipStream_t st);
+hipError_t pic_launch_fold_current(const InstDesc* d_inst, int ninst, int max_ncell, hipStream_t st);
 hipError_t pic_launch_yee_b(const InstDesc* d_inst, int ninst, int max_ncell, int dim, float hfrac,
                             hipStream_t st);
 hipError_t pic_launch_yee_e(const InstDesc* d_inst, int ninst, int max_ncell, int dim, hipStream_t st);

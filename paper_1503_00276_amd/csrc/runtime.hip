@@ -43,6 +43,8 @@ struct Instance {
   GridDesc g{};
   float* F = nullptr;
   float* J = nullptr;
+  unsigned long long* J64 = nullptr;
+  double wmax[PIC_MAX_SPECIES] = {0, 0, 0, 0, 0, 0, 0, 0};
   double* rho_snap = nullptr;
   bool have_snap = false;
   Species sp[PIC_MAX_SPECIES];
@@ -52,6 +54,7 @@ struct Instance {
 struct Group {
   int dim, order, first, count, max_ncell, max_items, max_tiles;
   size_t lds;
+  bool fixed64;
 };
 
 struct Sim {
@@ -72,6 +75,12 @@ struct Sim {
   // captured graphs: one rebin cycle (sort_interval steps ending with the check)
   hipGraphExec_t cycle_exec = nullptr;
   bool use_graph = true;
+  // profiling: event pairs around each kernel family, summed at read time
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[3];
+  double prof_ms[3] = {0, 0, 0};
+  double prof_n[3] = {0, 0, 0};
 
   pic_status fail(pic_status code, const char* fmt, ...) {
     char buf[512];
@@ -139,6 +148,9 @@ pic_status setup_grid(Sim& S, const pic_config& c, int sort_interval, GridDesc& 
   }
   g.dt = (float)c.dt;
   g.dtd = c.dt;
+  g.acc_mode = c.accumulator;
+  g.jscale = 1.0f;
+  g.jinv = 1.0f;
   g.flag_slack = 1;
   int extra = (int)std::ceil((sort_interval - 1) * vmax - 1e-12);
   g.slack = g.flag_slack + std::max(0, extra);
@@ -198,8 +210,8 @@ pic_status validate(Sim& S, const pic_config& c) {
   if (c.dt * std::sqrt(inv) >= 1.0)
     return S.fail(PIC_E_INVALID, "dt=%g violates the Courant condition dt*sqrt(sum 1/dx^2) < 1", c.dt);
   if (c.capacity < 0 || c.capacity > (int64_t)0x7fffff00) return S.fail(PIC_E_INVALID, "capacity out of range");
-  if (c.accumulator != PIC_ACC_FP32)
-    return S.fail(PIC_E_UNSUPPORTED, "accumulator %d not available in this build", c.accumulator);
+  if (c.accumulator < PIC_ACC_FP32 || c.accumulator > PIC_ACC_FIXED64)
+    return S.fail(PIC_E_INVALID, "unknown accumulator %d", c.accumulator);
   if (c.sort_interval < 0 || c.chunk < 0) return S.fail(PIC_E_INVALID, "negative sort_interval or chunk");
   for (int d = 0; d < 3; d++)
     if (!std::isfinite(c.e0[d]) || !std::isfinite(c.b0[d])) return S.fail(PIC_E_INVALID, "external field not finite");
@@ -207,6 +219,8 @@ pic_status validate(Sim& S, const pic_config& c) {
 }
 
 int default_interval(const pic_config& c) {
+  // 3D tiles are LDS-bound: keep the slack at one cell and check every step
+  if (c.ndim == 3) return 1;
   double vmax = 0.0;
   for (int d = 0; d < c.ndim; d++) vmax = std::max(vmax, c.dt / c.dx[d]);
   // largest interval whose slack stays at 2 cells
@@ -231,6 +245,23 @@ void free_species(Species& sp) {
   sp.np = 0;
   sp.ctl = nullptr;
   memset(&sp.desc, 0, sizeof sp.desc);
+}
+
+// Fixed-point unit of the current: every single contribution is bounded by
+// max|w| * max(dx/dt, 1), which must stay below 2^30 units.
+void set_current_scale(Instance& I) {
+  double wmax = 0.0;
+  for (int s = 0; s < PIC_MAX_SPECIES; s++) wmax = std::max(wmax, I.wmax[s]);
+  double c = 1.0;
+  for (int d = 0; d < I.g.dim; d++) c = std::max(c, I.g.dxd[d] / I.g.dtd);
+  double V = wmax * c;
+  int e = 30;
+  if (V > 0.0) e = (int)std::floor(30.0 - std::log2(V * 1.0001));
+  e = std::max(-60, std::min(60, e));
+  I.g.jscale = std::ldexp(1.0f, e);
+  I.g.jinv = std::ldexp(1.0f, -e);
+  for (Species& sp : I.sp)
+    if (sp.used) sp.desc.g = I.g;
 }
 
 // Allocate (or grow) a species store for 'cap' particles.
@@ -266,6 +297,7 @@ pic_status alloc_species(Sim& S, Instance& I, Species& sp, int64_t cap, int chun
   d.ctl = sp.ctl;
   d.F = I.F;
   d.J = I.J;
+  d.J64 = I.J64;
   StoreCtl z{};
   HIPCHK(S, hipMemcpy(sp.ctl, &z, sizeof z, hipMemcpyHostToDevice));
   sp.cap = cap;
@@ -283,7 +315,7 @@ pic_status refresh_descriptors(Sim& S) {
   S.igroups.clear();
   for (int dim = 2; dim <= 3; dim++)
     for (int order = 1; order <= 3; order++) {
-      Group gr{dim, order, (int)stores.size(), 0, 0, 0, 0, 0};
+      Group gr{dim, order, (int)stores.size(), 0, 0, 0, 0, 0, false};
       for (size_t i = 0; i < S.inst.size(); i++) {
         Instance& I = S.inst[i];
         if (I.g.dim != dim || I.g.order != order) continue;
@@ -308,11 +340,12 @@ pic_status refresh_descriptors(Sim& S) {
     }
   std::vector<InstDesc> insts;
   for (int dim = 2; dim <= 3; dim++) {
-    Group gr{dim, 0, (int)insts.size(), 0, 0, 0, 0, 0};
+    Group gr{dim, 0, (int)insts.size(), 0, 0, 0, 0, 0, false};
     for (size_t i = 0; i < S.inst.size(); i++) {
       Instance& I = S.inst[i];
       if (I.g.dim != dim) continue;
-      insts.push_back(InstDesc{I.g, I.F, I.J});
+      insts.push_back(InstDesc{I.g, I.F, I.J, I.J64});
+      if (I.g.acc_mode == PIC_ACC_FIXED64) gr.fixed64 = true;
       gr.count++;
       gr.max_ncell = std::max(gr.max_ncell, I.g.ncell);
     }
@@ -357,23 +390,76 @@ int store_desc_index(const Sim& S, int i, int s) {
   return -1;
 }
 
+hipEvent_t take_event(Sim& S) {
+  if (!S.ev_free.empty()) {
+    hipEvent_t e = S.ev_free.back();
+    S.ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Record a start event for kernel family f (profiling only); returns it.
+hipEvent_t prof_begin(Sim& S) {
+  if (!S.profiling) return nullptr;
+  hipEvent_t e = take_event(S);
+  if (e) (void)hipEventRecord(e, S.stream);
+  return e;
+}
+
+void prof_end(Sim& S, int f, hipEvent_t start) {
+  if (!S.profiling || !start) return;
+  hipEvent_t e = take_event(S);
+  if (!e) return;
+  (void)hipEventRecord(e, S.stream);
+  S.ev_pending[f].push_back({start, e});
+}
+
+pic_status prof_collect(Sim& S) {
+  HIPCHK(S, hipStreamSynchronize(S.stream));
+  for (int f = 0; f < 3; f++) {
+    for (auto& pr : S.ev_pending[f]) {
+      float ms = 0.0f;
+      HIPCHK(S, hipEventElapsedTime(&ms, pr.first, pr.second));
+      S.prof_ms[f] += ms;
+      S.prof_n[f] += 1.0;
+      S.ev_free.push_back(pr.first);
+      S.ev_free.push_back(pr.second);
+    }
+    S.ev_pending[f].clear();
+  }
+  return PIC_OK;
+}
+
 pic_status launch_steps(Sim& S, int nsteps, bool end_with_check) {
   for (int k = 0; k < nsteps; k++) {
+    hipEvent_t e0 = prof_begin(S);
     for (const Group& gr : S.igroups)
       HIPCHK(S, pic_launch_zero_current(S.d_inst + gr.first, gr.count, gr.max_ncell, S.stream));
+    prof_end(S, 1, e0);
+    e0 = prof_begin(S);
     for (const Group& gr : S.sgroups) {
       int per_cu = std::max(1, std::min(8, (int)(kLdsMax / std::max<size_t>(gr.lds, 1))));
       int grid = std::max(1, std::min(gr.max_items, kNumCU * per_cu));
       HIPCHK(S, pic_launch_gpd(gr.dim, gr.order, S.d_stores + gr.first, gr.count, grid, gr.lds, S.stream));
     }
+    prof_end(S, 0, e0);
+    for (const Group& gr : S.igroups)
+      if (gr.fixed64) HIPCHK(S, pic_launch_fold_current(S.d_inst + gr.first, gr.count, gr.max_ncell, S.stream));
+    e0 = prof_begin(S);
     for (const Group& gr : S.igroups) {
       HIPCHK(S, pic_launch_yee_b(S.d_inst + gr.first, gr.count, gr.max_ncell, gr.dim, 0.5f, S.stream));
       HIPCHK(S, pic_launch_yee_e(S.d_inst + gr.first, gr.count, gr.max_ncell, gr.dim, S.stream));
       HIPCHK(S, pic_launch_yee_b(S.d_inst + gr.first, gr.count, gr.max_ncell, gr.dim, 0.5f, S.stream));
     }
+    prof_end(S, 1, e0);
     if (end_with_check && k == nsteps - 1) {
+      e0 = prof_begin(S);
       for (const Group& gr : S.sgroups)
         HIPCHK(S, pic_launch_rebin(S.d_stores + gr.first, gr.count, gr.max_items, gr.max_tiles, S.stream));
+      prof_end(S, 2, e0);
     }
   }
   return PIC_OK;
@@ -410,7 +496,7 @@ pic_status sim_step(Sim& S, int64_t nsteps) {
   while (done < nsteps) {
     int64_t phase = S.steps % SI;  // steps already done in the current cycle
     int64_t left = nsteps - done;
-    if (phase == 0 && left >= SI && S.use_graph) {
+    if (phase == 0 && left >= SI && S.use_graph && !S.profiling) {
       st = capture_cycle(S);
       if (st != PIC_OK) return st;
       HIPCHK(S, hipGraphLaunch(S.cycle_exec, S.stream));
@@ -601,6 +687,9 @@ pic_status sim_load(Sim& S, int inst, int32_t species, double rqm, int64_t n, co
     for (int k = 0; k < 3; k++) h.u[k][old + p] = (float)hu[p * 3 + k];
     h.w[old + p] = (float)hw[p];
   }
+  double wm = I.wmax[species];
+  for (double v : hw) wm = std::max(wm, std::fabs(v));
+  I.wmax[species] = wm;
   if (!sp.used || total > sp.cap) {
     int64_t cap = I.cfg.capacity > 0 ? I.cfg.capacity : total;
     int chunk = I.cfg.chunk > 0 ? I.cfg.chunk : 2048;
@@ -609,6 +698,7 @@ pic_status sim_load(Sim& S, int inst, int32_t species, double rqm, int64_t n, co
     sp.rqm = rqm;
     sp.desc.qm = (float)(1.0 / rqm);
   }
+  set_current_scale(I);
   return upload_binned(S, I, sp, h);
 }
 
@@ -786,6 +876,16 @@ pic_status sim_diag(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_byt
       HIPCHK(S, hipStreamSynchronize(S.stream));
       return PIC_OK;
     }
+    case PIC_DIAG_KERNEL_TIMES: {
+      if ((st = need(S, 6 * sizeof(double), out_bytes, written)) != PIC_OK) return st;
+      if ((st = prof_collect(S)) != PIC_OK) return st;
+      double* o = (double*)out;
+      for (int f = 0; f < 3; f++) {
+        o[2 * f] = S.prof_ms[f];
+        o[2 * f + 1] = S.prof_n[f];
+      }
+      return PIC_OK;
+    }
     case PIC_DIAG_COUNTS: {
       if ((st = need(S, 4 * sizeof(double), out_bytes, written)) != PIC_OK) return st;
       double* o = (double*)out;
@@ -836,6 +936,11 @@ pic_status sim_create(Sim& S, const pic_config* cfgs, int n, void* stream) {
     if (hipMalloc(&I.J, 3 * nc * sizeof(float)) != hipSuccess) return S.fail(PIC_E_NOMEM, "current allocation failed");
     HIPCHK(S, hipMemset(I.F, 0, 6 * nc * sizeof(float)));
     HIPCHK(S, hipMemset(I.J, 0, 3 * nc * sizeof(float)));
+    if (cfgs[i].accumulator == PIC_ACC_FIXED64) {
+      if (hipMalloc(&I.J64, 3 * nc * sizeof(unsigned long long)) != hipSuccess)
+        return S.fail(PIC_E_NOMEM, "current allocation failed");
+      HIPCHK(S, hipMemset(I.J64, 0, 3 * nc * sizeof(unsigned long long)));
+    }
   }
   HIPCHK(S, hipMalloc(&S.d_scratch, (size_t)2 * 4 * pic_reduce_blocks() * sizeof(double)));
   HIPCHK(S, hipMalloc(&S.d_out, 8 * sizeof(double)));
@@ -843,12 +948,30 @@ pic_status sim_create(Sim& S, const pic_config* cfgs, int n, void* stream) {
   return PIC_OK;
 }
 
+pic_status sim_profile(Sim& S, int enable) {
+  if (enable < 0 || enable > 2) return S.fail(PIC_E_INVALID, "profile mode must be 0, 1 or 2");
+  pic_status st = prof_collect(S);
+  if (st != PIC_OK) return st;
+  if (enable == 2)
+    for (int f = 0; f < 3; f++) S.prof_ms[f] = S.prof_n[f] = 0.0;
+  S.profiling = enable != 0;
+  return PIC_OK;
+}
+
 void sim_destroy(Sim& S) {
+  if (S.stream) (void)hipStreamSynchronize(S.stream);
+  for (int f = 0; f < 3; f++)
+    for (auto& pr : S.ev_pending[f]) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  for (hipEvent_t e : S.ev_free) (void)hipEventDestroy(e);
   if (S.cycle_exec) (void)hipGraphExecDestroy(S.cycle_exec);
   for (Instance& I : S.inst) {
     for (Species& sp : I.sp) free_species(sp);
     if (I.F) (void)hipFree(I.F);
     if (I.J) (void)hipFree(I.J);
+    if (I.J64) (void)hipFree(I.J64);
     if (I.rho_snap) (void)hipFree(I.rho_snap);
   }
   if (S.d_stores) (void)hipFree(S.d_stores);
@@ -944,6 +1067,11 @@ pic_status pic_get_info(const pic_ctx* ctx, pic_info* out) {
   return sim_info(ctx->s, 0, out);
 }
 
+pic_status pic_profile(pic_ctx* ctx, int32_t enable) {
+  if (!ctx) return PIC_E_INVALID;
+  return sim_profile(ctx->s, enable);
+}
+
 const char* pic_last_error(const pic_ctx* ctx) { return ctx ? ctx->s.err.c_str() : "null context"; }
 
 pic_status pic_batch_create(const pic_config* cfgs, int32_t n, void* hip_stream, pic_batch** out) {
@@ -995,6 +1123,11 @@ pic_status pic_batch_diag(pic_batch* b, int32_t inst, pic_diag_kind kind, void* 
 pic_status pic_batch_sync(pic_batch* b) {
   if (!b) return PIC_E_INVALID;
   return sim_sync(b->s);
+}
+
+pic_status pic_batch_profile(pic_batch* b, int32_t enable) {
+  if (!b) return PIC_E_INVALID;
+  return sim_profile(b->s, enable);
 }
 
 const char* pic_batch_last_error(const pic_batch* b) { return b ? b->s.err.c_str() : "null batch"; }

@@ -240,15 +240,16 @@ __global__ void __launch_bounds__(kBlock) rebin_scatter(const StoreDesc* __restr
         todo &= ~m;
       }
       __syncthreads();
+      int pos = -1;
       if (sl >= 0) {
-        int pos = run[sl] + rank;
+        pos = run[sl] + rank;
         for (int w = 0; w < wave; w++) pos += wcnt[w][sl];
         if (pos < 0 || pos >= S.np) {  // inconsistent counts: never write out of bounds
           atomicOr(&S.ctl->bad, 2);
-          sl = -1;
+          pos = -1;
         }
       }
-      if (sl >= 0) {
+      if (pos >= 0) {
         S.cell[nxt][pos] = S.cell[cur][p];
         for (int d = 0; d < g.dim; d++) S.eps[nxt][d][pos] = S.eps[cur][d][p];
         S.u[nxt][0][pos] = S.u[cur][0][p];

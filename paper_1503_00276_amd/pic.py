@@ -41,10 +41,11 @@ PIC_DIAG_EXPORT_STATE = 7
 PIC_DIAG_EXPORT_FIELDS = 8
 PIC_DIAG_EXPORT_CURRENT = 9
 PIC_DIAG_COUNTS = 10
+PIC_DIAG_KERNEL_TIMES = 11
 
 EXPORTED = [
     "pic_create", "pic_destroy", "pic_load_particles", "pic_load_fields", "pic_step", "pic_sync",
-    "pic_diag", "pic_get_info", "pic_last_error", "pic_batch_create", "pic_batch_destroy",
+    "pic_diag", "pic_get_info", "pic_last_error", "pic_profile", "pic_batch_profile", "pic_batch_create", "pic_batch_destroy",
     "pic_batch_load_particles", "pic_batch_load_fields", "pic_batch_step", "pic_batch_diag",
     "pic_batch_sync", "pic_batch_last_error",
 ]
@@ -103,6 +104,8 @@ def lib():
         L.pic_sync.argtypes = [V]
         L.pic_diag.argtypes = [V, C.c_int, V, SZ, C.POINTER(SZ)]
         L.pic_get_info.argtypes = [V, C.POINTER(pic_info)]
+        L.pic_profile.argtypes = [V, I32]
+        L.pic_batch_profile.argtypes = [V, I32]
         L.pic_last_error.argtypes = [V]
         L.pic_last_error.restype = C.c_char_p
         L.pic_batch_create.argtypes = [C.POINTER(pic_config), I32, V, C.POINTER(V)]
@@ -306,6 +309,14 @@ class Pic(_Base):
     def counts(self):
         return self.diag(PIC_DIAG_COUNTS, 4)
 
+    def profile(self, enable: int):
+        self._check(self._L.pic_profile(self._h, int(enable)))
+
+    def kernel_times(self):
+        """{family: (ms, launches)} for 'particle', 'field', 'rebin'."""
+        a = self.diag(PIC_DIAG_KERNEL_TIMES, 6)
+        return {"particle": (a[0], a[1]), "field": (a[2], a[3]), "rebin": (a[4], a[5])}
+
 
 class PicBatch(_Base):
     """Many independent instances advanced together (a pic_batch)."""
@@ -366,6 +377,16 @@ class PicBatch(_Base):
         d = self.cfgs[inst].ndim
         a = self.diag(inst, PIC_DIAG_EXPORT_STATE, n * (d + 4)).reshape(n, d + 4)
         return a[:, :d].copy(), a[:, d:d + 3].copy(), a[:, d + 3].copy()
+
+    def profile(self, enable: int):
+        self._check(self._L.pic_batch_profile(self._h, int(enable)))
+
+    def kernel_times(self):
+        a = self.diag(0, PIC_DIAG_KERNEL_TIMES, 6)
+        return {"particle": (a[0], a[1]), "field": (a[2], a[3]), "rebin": (a[4], a[5])}
+
+    def counts(self, inst: int):
+        return self.diag(inst, PIC_DIAG_COUNTS, 4)
 
     def fields(self, inst: int):
         nc = self.cfgs[inst].ncell

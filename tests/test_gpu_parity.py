@@ -32,8 +32,8 @@ CASES = [
     (2, (36, 20), (0.2, 0.2), 0.1, 2, 3, 0.3, (16, 8)),     # ragged tiles
     (2, (24, 24), (0.2, 0.2), 0.1, 3, 3, 0.5, (8, 8)),
     (3, (16, 12, 10), (0.2, 0.2, 0.25), 0.08, 1, 2, 0.2, (8, 6, 5)),
-    (3, (12, 12, 12), (0.2, 0.2, 0.2), 0.08, 2, 2, 0.3, (6, 6, 6)),
-    (3, (12, 10, 12), (0.2, 0.2, 0.2), 0.08, 3, 2, 0.3, (6, 5, 6)),
+    (3, (12, 12, 12), (0.2, 0.2, 0.2), 0.08, 2, 2, 0.3, (4, 4, 4)),
+    (3, (12, 10, 12), (0.2, 0.2, 0.2), 0.08, 3, 2, 0.3, (4, 5, 4)),
 ]
 
 
@@ -58,3 +58,31 @@ def test_step_parity(orc, case):
         assert err["J"] <= J_TOL
         assert err["E"] <= F_TOL and err["B"] <= F_TOL
     sim.sync()
+
+
+@pytest.mark.parametrize("ndim,order", [(2, 2), (3, 1)])
+def test_fixed64_parity_and_bitwise_determinism(orc, ndim, order):
+    """The int64 fold gives the same parity and bitwise identical results on
+    a re-run from the same state (order-independent current)."""
+    pic = _pic()
+    nx = (24, 16) if ndim == 2 else (12, 10, 8)
+    dx = (0.2,) * ndim
+    tile = (8, 8) if ndim == 2 else (6, 5, 4)
+    x, u, w = _thermal(ndim, nx, dx, 3, 0.2, 77 + ndim)
+    outs = []
+    for rep in range(2):
+        cfg = pic.Config(ndim=ndim, nx=nx, dx=dx, dt=0.08, shape_order=order, tile=tile, sort_interval=2,
+                         accumulator=pic.PIC_ACC_FIXED64, ion_density=1.0)
+        sim = pic.Pic(cfg)
+        sim.load_particles(x, u, w, rqm=-1.0)
+        if rep == 0:
+            err = step_parity(orc, sim, cfg)
+            assert err["pos"] <= POS_TOL and err["mom"] <= MOM_TOL and err["J"] <= J_TOL, err
+            sim.step(5)
+        else:
+            sim.step(6)
+        xs, us, _ = sim.state()
+        outs.append((xs, us, sim.current(), sim.fields()[0]))
+        sim.close()
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
