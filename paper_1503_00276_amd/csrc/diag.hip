@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(kBlock) charge64(const InstDesc* __restrict__ 
   const InstDesc& I = *ip;
   const int nc = I.g.ncell;
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x)
-    C[c] = (rho1[c] - rho0[c]) / I.g.dtd + div_at(I.g, I.J, nc, c, dim);
+    C[c] = (rho1[c] - rho0[c]) / I.g.dtd + div_at(I.g, I.Jout, nc, c, dim);
 }
 
 // ---------------------------------------------------------------------------

@@ -6,8 +6,8 @@
 // B -= (dt/2) curl E  with forward differences for curl E (E -> B mesh) and
 // backward differences for curl B (B -> E mesh).  The E3 update subtracts J3
 // (the printed j1 of the 2D E3 equation is a typo: the B terms are the curl's
-// third component).  Every kernel is one thread per cell, coalesced along x1,
-// periodic neighbours by wrap; blockIdx.y selects the instance of a batch.
+// third component).  All three parts run in one kernel on LDS tiles; periodic
+// neighbours by wrap; blockIdx.y selects the instance of a batch.
 #include "pic_dev.h"
 #include "pic_kernels.h"
 
@@ -15,137 +15,209 @@ namespace {
 
 constexpr int kBlock = 256;
 
-__device__ __forceinline__ void cell_coords(const GridDesc& g, int c, int& i, int& j, int& k) {
-  i = c % g.nx[0];
-  int r = c / g.nx[0];
-  j = r % g.nx[1];
-  k = r / g.nx[1];
-}
+typedef __attribute__((address_space(1))) float gfloat;
 
-__global__ void __launch_bounds__(kBlock) zero_current(const InstDesc* __restrict__ inst) {
-  const InstDesc& I = inst[blockIdx.y];
-  const int n = 3 * I.g.ncell;
-  if (I.g.acc_mode == 2) {
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) I.J64[c] = 0ull;
-  } else {
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) I.J[c] = 0.0f;
-  }
-}
+// Tile of cells one workgroup advances (256 cells, one per thread).
+template <int DIM> struct YeeTile;
+template <> struct YeeTile<2> { static constexpr int X = 32, Y = 8, Z = 1; };
+template <> struct YeeTile<3> { static constexpr int X = 16, Y = 4, Z = 4; };
 
-// Deterministic mode: the int64 fixed-point current becomes the FP32 current.
-__global__ void __launch_bounds__(kBlock) fold_current(const InstDesc* __restrict__ inst) {
-  const InstDesc& I = inst[blockIdx.y];
-  if (I.g.acc_mode != 2) return;
-  const int n = 3 * I.g.ncell;
-  const double inv = (double)I.g.jinv;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
-    I.J[c] = (float)((double)(long long)I.J64[c] * inv);
+// One full field step on a tile, B^n, E^n -> B^{n+1}, E^{n+1}, in LDS:
+//   Bh  = B^n - (dt/2) curl+ E^n     on the tile plus one node below and above
+//   E'  = E^n + dt (curl- Bh - J)    on the tile plus one node above
+//   B'  = Bh - (dt/2) curl+ E'       on the tile
+// The halos are recomputed by every tile that needs them, with the same
+// arithmetic on the same inputs, so neighbouring tiles agree bitwise.
+// The current of the step is read from the accumulator the particle kernel
+// filled (int64 fixed point in the deterministic mode), copied to Jout, and
+// the other accumulator is cleared for the next step.  The last workgroup to
+// finish flips which accumulator is in use.
+// Periodic wrap for an index at most one period out of range.
+__device__ __forceinline__ int wrap1(int v, int n) {
+  v = v < 0 ? v + n : v;
+  v = v >= n ? v - n : v;
+  return v >= n ? v - n : v;
 }
 
 template <int DIM>
-__global__ void __launch_bounds__(kBlock) yee_b(const InstDesc* __restrict__ inst, float hfrac) {
+__global__ void __launch_bounds__(kBlock) yee_step(const InstDesc* __restrict__ inst) {
+  using T = YeeTile<DIM>;
+  constexpr int EXM = T::X + 3, EYM = T::Y + 3, EZM = DIM == 3 ? T::Z + 3 : 1;
+  constexpr int BXM = T::X + 2, BYM = T::Y + 2, BZM = DIM == 3 ? T::Z + 2 : 1;
+  __shared__ float sE[3][EZM * EYM * EXM];
+  __shared__ float sB[3][BZM * BYM * BXM];
   const InstDesc& I = inst[blockIdx.y];
   const GridDesc& g = I.g;
-  const int nc = g.ncell;
-  const float h = hfrac * g.dt;
-  const float* E1 = I.F;
-  const float* E2 = I.F + nc;
-  const float* E3 = I.F + 2 * nc;
-  float* B1 = I.F + 3 * nc;
-  float* B2 = I.F + 4 * nc;
-  float* B3 = I.F + 5 * nc;
-  const int sx = 1, sy = g.nx[0], sz = g.nx[0] * g.nx[1];
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
-    int i, j, k;
-    cell_coords(g, c, i, j, k);
-    int cxp = c + (i + 1 < g.nx[0] ? sx : sx - g.nx[0] * sx);
-    int cyp = c + (j + 1 < g.nx[1] ? sy : sy - g.nx[1] * sy);
-    float e1 = E1[c], e2 = E2[c], e3 = E3[c];
-    float d2E3 = (E3[cyp] - e3) * g.rdx[1];
-    float d1E3 = (E3[cxp] - e3) * g.rdx[0];
-    float d1E2 = (E2[cxp] - e2) * g.rdx[0];
-    float d2E1 = (E1[cyp] - e1) * g.rdx[1];
-    float d3E2 = 0.0f, d3E1 = 0.0f;
-    if (DIM == 3) {
-      int czp = c + (k + 1 < g.nx[2] ? sz : sz - g.nx[2] * sz);
-      d3E2 = (E2[czp] - e2) * g.rdx[2];
-      d3E1 = (E1[czp] - e1) * g.rdx[2];
-    }
-    B1[c] -= h * (d2E3 - d3E2);
-    B2[c] -= h * (d3E1 - d1E3);
-    B3[c] -= h * (d1E2 - d2E1);
+  const int par = I.ictl->parity;
+  const int ntx = (g.nx[0] + T::X - 1) / T::X;
+  const int nty = (g.nx[1] + T::Y - 1) / T::Y;
+  const int ntz = DIM == 3 ? (g.nx[2] + T::Z - 1) / T::Z : 1;
+  const int tile = blockIdx.x;
+  // thread layout = tile shape (T::X * T::Y * T::Z == blockDim.x)
+  const int tx = threadIdx.x % T::X;
+  const int ty = (threadIdx.x / T::X) % T::Y;
+  const int tz = threadIdx.x / (T::X * T::Y);
+  if (tile < ntx * nty * ntz) {
+    const int nc = g.ncell;
+    const int n0 = g.nx[0], n1 = g.nx[1], n2 = g.nx[2];
+    const int o0 = (tile % ntx) * T::X;
+    const int o1 = ((tile / ntx) % nty) * T::Y;
+    const int o2 = DIM == 3 ? (tile / (ntx * nty)) * T::Z : 0;
+    const int e0 = min(T::X, n0 - o0);
+    const int e1 = min(T::Y, n1 - o1);
+    const int e2 = DIM == 3 ? min(T::Z, n2 - o2) : 1;
+    const int EX = e0 + 3, EY = e1 + 3, EZ = DIM == 3 ? e2 + 3 : 1;
+    const int BX = e0 + 2, BY = e1 + 2, BZ = DIM == 3 ? e2 + 2 : 1;
+    const int zoff = DIM == 3 ? 1 : 0;  // region origin is one node below the tile
+    auto gidx = [&](int x, int y, int z) {
+      int gx = wrap1(o0 - 1 + x, n0);
+      int gy = wrap1(o1 - 1 + y, n1);
+      int gz = DIM == 3 ? wrap1(o2 - zoff + z, n2) : 0;
+      return gx + n0 * (gy + n1 * gz);
+    };
+    const gfloat* F = (const gfloat*)I.F;
+    for (int z = (DIM == 3 ? tz : 0); z < EZ; z += T::Z)
+      for (int y = ty; y < EY; y += T::Y)
+        for (int x = tx; x < EX; x += T::X) {
+          int r = x + EX * (y + EY * z);
+          int gi = gidx(x, y, z);
+          sE[0][r] = F[gi];
+          sE[1][r] = F[nc + gi];
+          sE[2][r] = F[2 * nc + gi];
+          if (x < BX && y < BY && z < BZ) {
+            int rb = x + BX * (y + BY * z);
+            sB[0][rb] = F[3 * nc + gi];
+            sB[1][rb] = F[4 * nc + gi];
+            sB[2][rb] = F[5 * nc + gi];
+          }
+        }
+    __syncthreads();
+    const float h = 0.5f * g.dt;
+    const float r0 = g.rdx[0], r1 = g.rdx[1], r2 = g.rdx[2];
+    const int EXY = EX * EY;
+    // Bh on the whole B region
+    for (int z = (DIM == 3 ? tz : 0); z < BZ; z += T::Z)
+      for (int y = ty; y < BY; y += T::Y)
+        for (int x = tx; x < BX; x += T::X) {
+          int r = x + BX * (y + BY * z);
+          int c = x + EX * (y + EY * z);
+          float d2E3 = (sE[2][c + EX] - sE[2][c]) * r1;
+          float d1E3 = (sE[2][c + 1] - sE[2][c]) * r0;
+          float d1E2 = (sE[1][c + 1] - sE[1][c]) * r0;
+          float d2E1 = (sE[0][c + EX] - sE[0][c]) * r1;
+          float d3E2 = 0.0f, d3E1 = 0.0f;
+          if (DIM == 3) {
+            d3E2 = (sE[1][c + EXY] - sE[1][c]) * r2;
+            d3E1 = (sE[0][c + EXY] - sE[0][c]) * r2;
+          }
+          sB[0][r] -= h * (d2E3 - d3E2);
+          sB[1][r] -= h * (d3E1 - d1E3);
+          sB[2][r] -= h * (d1E2 - d2E1);
+        }
+    __syncthreads();
+    // E' on the tile plus one node above: region nodes 1 .. e+1 per axis
+    const int jp = par, jn = 1 - par;
+    const double jinv = (double)g.jinv;
+    const int BXY = BX * BY;
+    for (int z = zoff + (DIM == 3 ? tz : 0); z <= (DIM == 3 ? e2 + 1 : 0); z += T::Z)
+      for (int y = 1 + ty; y <= e1 + 1; y += T::Y)
+        for (int x = 1 + tx; x <= e0 + 1; x += T::X) {
+          int ce = x + EX * (y + EY * z);
+          int cb = x + BX * (y + BY * z);
+          int gi = gidx(x, y, z);
+          float J1, J2, J3;
+          if (g.acc_mode == 2) {
+            J1 = (float)((double)(long long)I.J64[jp][gi] * jinv);
+            J2 = (float)((double)(long long)I.J64[jp][nc + gi] * jinv);
+            J3 = (float)((double)(long long)I.J64[jp][2 * nc + gi] * jinv);
+          } else {
+            const gfloat* Ja = (const gfloat*)I.Jacc[jp];
+            J1 = Ja[gi];
+            J2 = Ja[nc + gi];
+            J3 = Ja[2 * nc + gi];
+          }
+          float d2B3 = (sB[2][cb] - sB[2][cb - BX]) * r1;
+          float d1B3 = (sB[2][cb] - sB[2][cb - 1]) * r0;
+          float d1B2 = (sB[1][cb] - sB[1][cb - 1]) * r0;
+          float d2B1 = (sB[0][cb] - sB[0][cb - BX]) * r1;
+          float d3B2 = 0.0f, d3B1 = 0.0f;
+          if (DIM == 3) {
+            d3B2 = (sB[1][cb] - sB[1][cb - BXY]) * r2;
+            d3B1 = (sB[0][cb] - sB[0][cb - BXY]) * r2;
+          }
+          sE[0][ce] += g.dt * ((d2B3 - d3B2) - J1);
+          sE[1][ce] += g.dt * ((d3B1 - d1B3) - J2);
+          sE[2][ce] += g.dt * ((d1B2 - d2B1) - J3);
+          // the tile's own cells: keep the step's current and clear the other accumulator
+          if (x <= e0 && y <= e1 && (DIM == 2 || z <= e2)) {
+            gfloat* Jo = (gfloat*)I.Jout;
+            Jo[gi] = J1;
+            Jo[nc + gi] = J2;
+            Jo[2 * nc + gi] = J3;
+            if (g.acc_mode == 2) {
+              I.J64[jn][gi] = 0ull;
+              I.J64[jn][nc + gi] = 0ull;
+              I.J64[jn][2 * nc + gi] = 0ull;
+            } else {
+              gfloat* Jz = (gfloat*)I.Jacc[jn];
+              Jz[gi] = 0.0f;
+              Jz[nc + gi] = 0.0f;
+              Jz[2 * nc + gi] = 0.0f;
+            }
+          }
+        }
+    __syncthreads();
+    // B' on the tile, and write E', B' back
+    gfloat* Fw = (gfloat*)I.F;
+    for (int z = zoff + (DIM == 3 ? tz : 0); z <= (DIM == 3 ? e2 : 0); z += T::Z)
+      for (int y = 1 + ty; y <= e1; y += T::Y)
+        for (int x = 1 + tx; x <= e0; x += T::X) {
+          int c = x + EX * (y + EY * z);
+          int cb = x + BX * (y + BY * z);
+          float d2E3 = (sE[2][c + EX] - sE[2][c]) * r1;
+          float d1E3 = (sE[2][c + 1] - sE[2][c]) * r0;
+          float d1E2 = (sE[1][c + 1] - sE[1][c]) * r0;
+          float d2E1 = (sE[0][c + EX] - sE[0][c]) * r1;
+          float d3E2 = 0.0f, d3E1 = 0.0f;
+          if (DIM == 3) {
+            d3E2 = (sE[1][c + EXY] - sE[1][c]) * r2;
+            d3E1 = (sE[0][c + EXY] - sE[0][c]) * r2;
+          }
+          int gi = gidx(x, y, z);
+          Fw[3 * nc + gi] = sB[0][cb] - h * (d2E3 - d3E2);
+          Fw[4 * nc + gi] = sB[1][cb] - h * (d3E1 - d1E3);
+          Fw[5 * nc + gi] = sB[2][cb] - h * (d1E2 - d2E1);
+          Fw[gi] = sE[0][c];
+          Fw[nc + gi] = sE[1][c];
+          Fw[2 * nc + gi] = sE[2][c];
+        }
   }
-}
-
-template <int DIM>
-__global__ void __launch_bounds__(kBlock) yee_e(const InstDesc* __restrict__ inst) {
-  const InstDesc& I = inst[blockIdx.y];
-  const GridDesc& g = I.g;
-  const int nc = g.ncell;
-  const float dt = g.dt;
-  float* E1 = I.F;
-  float* E2 = I.F + nc;
-  float* E3 = I.F + 2 * nc;
-  const float* B1 = I.F + 3 * nc;
-  const float* B2 = I.F + 4 * nc;
-  const float* B3 = I.F + 5 * nc;
-  const float* J1 = I.J;
-  const float* J2 = I.J + nc;
-  const float* J3 = I.J + 2 * nc;
-  const int sx = 1, sy = g.nx[0], sz = g.nx[0] * g.nx[1];
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
-    int i, j, k;
-    cell_coords(g, c, i, j, k);
-    int cxm = c - (i > 0 ? sx : sx - g.nx[0] * sx);
-    int cym = c - (j > 0 ? sy : sy - g.nx[1] * sy);
-    float b1 = B1[c], b2 = B2[c], b3 = B3[c];
-    float d2B3 = (b3 - B3[cym]) * g.rdx[1];
-    float d1B3 = (b3 - B3[cxm]) * g.rdx[0];
-    float d1B2 = (b2 - B2[cxm]) * g.rdx[0];
-    float d2B1 = (b1 - B1[cym]) * g.rdx[1];
-    float d3B2 = 0.0f, d3B1 = 0.0f;
-    if (DIM == 3) {
-      int czm = c - (k > 0 ? sz : sz - g.nx[2] * sz);
-      d3B2 = (b2 - B2[czm]) * g.rdx[2];
-      d3B1 = (b1 - B1[czm]) * g.rdx[2];
+  // completion: the last workgroup of this instance flips the accumulator.
+  // No fence: every workgroup has already used the parity it read, and the
+  // flipped value reaches the next kernel through the kernel boundary.
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned prev = atomicAdd(&I.ictl->done, 1u);
+    if (prev == gridDim.x - 1) {
+      I.ictl->done = 0u;
+      I.ictl->parity = 1 - par;
     }
-    E1[c] += dt * ((d2B3 - d3B2) - J1[c]);
-    E2[c] += dt * ((d3B1 - d1B3) - J2[c]);
-    E3[c] += dt * ((d1B2 - d2B1) - J3[c]);
   }
-}
-
-int grid_for(int max_n) {
-  int b = (max_n + kBlock - 1) / kBlock;
-  if (b > 4096) b = 4096;
-  return b < 1 ? 1 : b;
 }
 
 }  // namespace
 
-hipError_t pic_launch_zero_current(const InstDesc* d_inst, int ninst, int max_ncell, hipStream_t st) {
-  hipLaunchKernelGGL(zero_current, dim3(grid_for(3 * max_ncell), ninst), dim3(kBlock), 0, st, d_inst);
-  return hipGetLastError();
-}
-
-hipError_t pic_launch_fold_current(const InstDesc* d_inst, int ninst, int max_ncell, hipStream_t st) {
-  hipLaunchKernelGGL(fold_current, dim3(grid_for(3 * max_ncell), ninst), dim3(kBlock), 0, st, d_inst);
-  return hipGetLastError();
-}
-
-hipError_t pic_launch_yee_b(const InstDesc* d_inst, int ninst, int max_ncell, int dim, float hfrac,
-                            hipStream_t st) {
+int pic_yee_tiles(int dim, const int nx[3]) {
   if (dim == 2)
-    hipLaunchKernelGGL(yee_b<2>, dim3(grid_for(max_ncell), ninst), dim3(kBlock), 0, st, d_inst, hfrac);
-  else
-    hipLaunchKernelGGL(yee_b<3>, dim3(grid_for(max_ncell), ninst), dim3(kBlock), 0, st, d_inst, hfrac);
-  return hipGetLastError();
+    return ((nx[0] + YeeTile<2>::X - 1) / YeeTile<2>::X) * ((nx[1] + YeeTile<2>::Y - 1) / YeeTile<2>::Y);
+  return ((nx[0] + YeeTile<3>::X - 1) / YeeTile<3>::X) * ((nx[1] + YeeTile<3>::Y - 1) / YeeTile<3>::Y) *
+         ((nx[2] + YeeTile<3>::Z - 1) / YeeTile<3>::Z);
 }
 
-hipError_t pic_launch_yee_e(const InstDesc* d_inst, int ninst, int max_ncell, int dim, hipStream_t st) {
+hipError_t pic_launch_yee_step(const InstDesc* d_inst, int ninst, int max_tiles, int dim, hipStream_t st) {
   if (dim == 2)
-    hipLaunchKernelGGL(yee_e<2>, dim3(grid_for(max_ncell), ninst), dim3(kBlock), 0, st, d_inst);
+    hipLaunchKernelGGL(yee_step<2>, dim3(max_tiles, ninst), dim3(kBlock), 0, st, d_inst);
   else
-    hipLaunchKernelGGL(yee_e<3>, dim3(grid_for(max_ncell), ninst), dim3(kBlock), 0, st, d_inst);
+    hipLaunchKernelGGL(yee_step<3>, dim3(max_tiles, ninst), dim3(kBlock), 0, st, d_inst);
   return hipGetLastError();
 }

@@ -204,8 +204,10 @@ __device__ __forceinline__ void deposit_shape(float e0, float e1, int c, int& ba
 // in units of 1/scale (|v*scale| < 2^30) and summed exactly in int64.
 typedef unsigned long long acc_t;
 
-__device__ __forceinline__ void lds_add(acc_t* p, float v, float scale) {
-  int q = __float2int_rn(v * scale);
+// v is already in units of the fixed point (the scale is folded into the
+// per-particle prefactors); the conversion truncates (error < 1 unit).
+__device__ __forceinline__ void lds_add(acc_t* p, float v) {
+  int q = (int)v;
   if (q != 0)
     __hip_atomic_fetch_add(p, (acc_t)(long long)q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -215,7 +217,7 @@ __device__ __forceinline__ void lds_add(acc_t* p, float v, float scale) {
 // ---------------------------------------------------------------------------
 
 template <int DIM, int ORDER>
-__device__ void process_item(const StoreDesc& S, int cur, const Item it, float* smem) {
+__device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii, float* smem, int* scnt) {
   constexpr int NG = ORDER + 1;  // gather taps per axis
   constexpr int W = ORDER + 2;   // deposit window per axis
   const GridDesc& g = S.g;
@@ -257,8 +259,9 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, float* 
 #pragma unroll
     for (int c = 0; c < 6; c++) sF[c * fn + idx] = Fg[(size_t)c * ncell + gi];
   }
-  // 2. clear the current tile
+  // 2. clear the current tile and the rebin slot counters
   for (int idx = tid; idx < 3 * jn; idx += blockDim.x) sJ[idx] = 0ull;
+  if (tid < PIC_NSLOT) scnt[tid] = 0;
   __syncthreads();
 
   const int set = cur;
@@ -352,7 +355,7 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, float* 
     float mx = ux + h * Ex, my = uy + h * Ey, mz = uz + h * Ez;
     float gim = rsqrtf(1.0f + mx * mx + my * my + mz * mz);
     float tx = h * Bx * gim, ty = h * By * gim, tz = h * Bz * gim;
-    float sfac = 2.0f / (1.0f + tx * tx + ty * ty + tz * tz);
+    float sfac = 2.0f * __builtin_amdgcn_rcpf(1.0f + tx * tx + ty * ty + tz * tz);
     float px = mx + (my * tz - mz * ty);
     float py = my + (mz * tx - mx * tz);
     float pz = mz + (mx * ty - my * tx);
@@ -400,7 +403,7 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, float* 
     acc_t* J2 = sJ + jn;
     acc_t* J3 = sJ + 2 * jn;
     const float js = g.jscale;
-    float q1 = -wq * g.cdt[0], q2 = -wq * g.cdt[1];
+    float q1 = -wq * g.cdt[0] * js, q2 = -wq * g.cdt[1] * js;
     float P1[W - 1], P2[W - 1];
     {
       float a = 0.0f, b = 0.0f;
@@ -413,7 +416,7 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, float* 
       }
     }
     if constexpr (DIM == 2) {
-      float v3 = wq * uz * gi;
+      float v3 = wq * uz * gi * js;
 #pragma unroll
       for (int j = 0; j < W; j++) {
         float T1 = S0[1][j] + 0.5f * D[1][j];
@@ -421,19 +424,19 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, float* 
         acc_t* r1 = J1 + (jy + j) * JR[0] + jx;
         acc_t* r3 = J3 + (jy + j) * JR[0] + jx;
 #pragma unroll
-        for (int i = 0; i < W - 1; i++) lds_add(r1 + i, P1[i] * T1, js);
+        for (int i = 0; i < W - 1; i++) lds_add(r1 + i, P1[i] * T1);
 #pragma unroll
-        for (int i = 0; i < W; i++) lds_add(r3 + i, v3 * (S0[0][i] * T1 + D[0][i] * U2), js);
+        for (int i = 0; i < W; i++) lds_add(r3 + i, v3 * (S0[0][i] * T1 + D[0][i] * U2));
       }
 #pragma unroll
       for (int j = 0; j < W - 1; j++) {
         acc_t* r2 = J2 + (jy + j) * JR[0] + jx;
 #pragma unroll
-        for (int i = 0; i < W; i++) lds_add(r2 + i, P2[j] * (S0[0][i] + 0.5f * D[0][i]), js);
+        for (int i = 0; i < W; i++) lds_add(r2 + i, P2[j] * (S0[0][i] + 0.5f * D[0][i]));
       }
     } else {
       int jz = jlo[2] + l[2] + wb[2];
-      float q3 = -wq * g.cdt[2];
+      float q3 = -wq * g.cdt[2] * js;
       float P3[W - 1];
       {
         float a = 0.0f;
@@ -453,7 +456,7 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, float* 
                     th * D[1][j] * D[2][k];
           acc_t* r = J1 + ((jz + k) * JR[1] + (jy + j)) * JR[0] + jx;
 #pragma unroll
-          for (int i = 0; i < W - 1; i++) lds_add(r + i, P1[i] * T, js);
+          for (int i = 0; i < W - 1; i++) lds_add(r + i, P1[i] * T);
         }
       }
       // J2: P2[j] * T2[k][i]
@@ -468,7 +471,7 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, float* 
         for (int j = 0; j < W - 1; j++) {
           acc_t* r = J2 + ((jz + k) * JR[1] + (jy + j)) * JR[0] + jx;
 #pragma unroll
-          for (int i = 0; i < W; i++) lds_add(r + i, P2[j] * Tk[i], js);
+          for (int i = 0; i < W; i++) lds_add(r + i, P2[j] * Tk[i]);
         }
       }
       // J3: P3[k] * T3[j][i]
@@ -483,13 +486,14 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, float* 
         for (int k = 0; k < W - 1; k++) {
           acc_t* r = J3 + ((jz + k) * JR[1] + (jy + j)) * JR[0] + jx;
 #pragma unroll
-          for (int i = 0; i < W; i++) lds_add(r + i, P3[k] * Tj[i], js);
+          for (int i = 0; i < W; i++) lds_add(r + i, P3[k] * Tj[i]);
         }
       }
     }
 
-    // ---- store the new state
+    // ---- store the new state; count the particle's rebin slot
     int nc[3] = {0, 0, 0};
+    int dd[3] = {0, 0, 0};
 #pragma unroll
     for (int d = 0; d < DIM; d++) {
       nc[d] = cc[d] + mv[d];
@@ -497,6 +501,19 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, float* 
       if (nc[d] >= g.nx[d]) nc[d] -= g.nx[d];
       int ln = pic_local(nc[d], org[d], ext[d], g.nx[d]);
       strayed = strayed || ln < -g.flag_slack || ln >= ext[d] + g.flag_slack;
+      dd[d] = ln < 0 ? -1 : (ln >= ext[d] ? 1 : 0);
+    }
+    {
+      // wave-aggregated count per slot (almost every particle is in slot 13)
+      const int sl = pic_slot(dd[0], dd[1], dd[2]);
+      unsigned long long todo = __ballot(1);
+      while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int ls = __shfl(sl, leader);
+        const unsigned long long m = __ballot(sl == ls);
+        if ((int)(threadIdx.x & 63) == leader) atomicAdd(&scnt[ls], (int)__popcll(m));
+        todo &= ~m;
+      }
     }
     cellp[p] = pic_pack(g, nc[0], nc[1], DIM == 3 ? nc[2] : 0);
     ep0[p] = en[0];
@@ -509,6 +526,8 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, float* 
   if (strayed) atomicOr(&S.ctl->flag, 1);
   if (bad) atomicOr(&S.ctl->bad, 1);
   __syncthreads();
+  if (tid < PIC_NSLOT) S.cnt[ii * PIC_NSLOT + tid] = scnt[tid];
+  const int jp = S.ictl->parity;
 
   // 4. fold the LDS current into the global current (periodic wrap)
   for (int idx = tid; idx < jn; idx += blockDim.x) {
@@ -525,9 +544,9 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, float* 
       long long q = (long long)sJ[c * jn + idx];
       if (q != 0) {
         if (g.acc_mode == 2)
-          atomicAdd(S.J64 + (size_t)c * ncell + gi, (acc_t)q);
+          atomicAdd(S.J64[jp] + (size_t)c * ncell + gi, (acc_t)q);
         else
-          __builtin_amdgcn_global_atomic_fadd_f32((gfloat*)S.J + (size_t)c * ncell + gi,
+          __builtin_amdgcn_global_atomic_fadd_f32((gfloat*)S.Jacc[jp] + (size_t)c * ncell + gi,
                                                   (float)((double)q * (double)g.jinv));
       }
     }
@@ -537,9 +556,11 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, float* 
 
 template <int DIM, int ORDER>
 __global__ void __launch_bounds__(kBlock) gpd_kernel(const StoreDesc* __restrict__ stores, int nstores) {
-  extern __shared__ float smem[];
+  // 16-byte aligned: the int64 current tile inside it takes 8-byte LDS atomics
+  extern __shared__ __align__(16) float smem[];
   __shared__ int s_pref[kMaxGroup + 1];
   __shared__ int s_cur[kMaxGroup];
+  __shared__ int s_cnt[PIC_NSLOT];
   if (threadIdx.x == 0) {
     int acc = 0;
     for (int s = 0; s < nstores; s++) {
@@ -558,7 +579,7 @@ __global__ void __launch_bounds__(kBlock) gpd_kernel(const StoreDesc* __restrict
     const StoreDesc& S = stores[s];
     const int cur = s_cur[s];
     const Item it = S.items[cur][gi - s_pref[s]];
-    process_item<DIM, ORDER>(S, cur, it, smem);
+    process_item<DIM, ORDER>(S, cur, it, gi - s_pref[s], smem, s_cnt);
   }
 }
 

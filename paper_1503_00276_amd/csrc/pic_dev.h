@@ -45,7 +45,16 @@ struct StoreCtl {
   int bad;          // a particle was found outside its staged region (skipped)
   int nsorts;       // rebins performed
   int nchecks;      // rebin checks performed
-  int pad;
+  unsigned sdone;   // workgroups of the scatter that finished (group's first store)
+};
+
+// Control words of one instance: which of the two current accumulators the
+// step deposits into (the other is being cleared), and a completion counter
+// the field kernel uses to flip it once all its workgroups are done.
+struct InstCtl {
+  int parity;
+  unsigned done;
+  int pad[2];
 };
 
 // Work item: a contiguous run of particles that all belong to one tile.
@@ -61,8 +70,9 @@ struct StoreDesc {
   int chunk;                 // maximum particles per work item
   int max_items;
   float* F;                  // instance fields: E1 E2 E3 B1 B2 B3 planes of ncell floats
-  float* J;                  // instance current: J1 J2 J3 planes
-  unsigned long long* J64;   // int64 fixed-point current (deterministic mode only)
+  float* Jacc[2];            // FP32 current accumulators (J1 J2 J3 planes), double-buffered
+  unsigned long long* J64[2];// int64 fixed-point accumulators (deterministic mode only)
+  InstCtl* ictl;
   int* cell[2];              // packed cell index
   float* eps[2][3];          // in-cell offset in [0,1)
   float* u[2][3];            // u = gamma v
@@ -83,8 +93,10 @@ struct StoreDesc {
 struct InstDesc {
   GridDesc g;
   float* F;
-  float* J;
-  unsigned long long* J64;
+  float* Jacc[2];
+  unsigned long long* J64[2];
+  float* Jout;               // the current of the last step (FP32, used by the E update)
+  InstCtl* ictl;
 };
 
 // ---------------------------------------------------------------------------

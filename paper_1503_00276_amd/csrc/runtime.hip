@@ -16,6 +16,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/pic.h"
@@ -42,8 +43,10 @@ struct Instance {
   pic_config cfg{};
   GridDesc g{};
   float* F = nullptr;
-  float* J = nullptr;
-  unsigned long long* J64 = nullptr;
+  float* Jacc[2] = {nullptr, nullptr};
+  unsigned long long* J64[2] = {nullptr, nullptr};
+  float* Jout = nullptr;
+  InstCtl* ictl = nullptr;
   double wmax[PIC_MAX_SPECIES] = {0, 0, 0, 0, 0, 0, 0, 0};
   double* rho_snap = nullptr;
   bool have_snap = false;
@@ -296,8 +299,11 @@ pic_status alloc_species(Sim& S, Instance& I, Species& sp, int64_t cap, int chun
 #undef AL
   d.ctl = sp.ctl;
   d.F = I.F;
-  d.J = I.J;
-  d.J64 = I.J64;
+  for (int k = 0; k < 2; k++) {
+    d.Jacc[k] = I.Jacc[k];
+    d.J64[k] = I.J64[k];
+  }
+  d.ictl = I.ictl;
   StoreCtl z{};
   HIPCHK(S, hipMemcpy(sp.ctl, &z, sizeof z, hipMemcpyHostToDevice));
   sp.cap = cap;
@@ -344,10 +350,20 @@ pic_status refresh_descriptors(Sim& S) {
     for (size_t i = 0; i < S.inst.size(); i++) {
       Instance& I = S.inst[i];
       if (I.g.dim != dim) continue;
-      insts.push_back(InstDesc{I.g, I.F, I.J, I.J64});
+      InstDesc id{};
+      id.g = I.g;
+      id.F = I.F;
+      for (int k = 0; k < 2; k++) {
+        id.Jacc[k] = I.Jacc[k];
+        id.J64[k] = I.J64[k];
+      }
+      id.Jout = I.Jout;
+      id.ictl = I.ictl;
+      insts.push_back(id);
       if (I.g.acc_mode == PIC_ACC_FIXED64) gr.fixed64 = true;
       gr.count++;
       gr.max_ncell = std::max(gr.max_ncell, I.g.ncell);
+      gr.max_tiles = std::max(gr.max_tiles, pic_yee_tiles(dim, I.g.nx));
     }
     if (gr.count > 0) S.igroups.push_back(gr);
   }
@@ -436,24 +452,15 @@ pic_status prof_collect(Sim& S) {
 pic_status launch_steps(Sim& S, int nsteps, bool end_with_check) {
   for (int k = 0; k < nsteps; k++) {
     hipEvent_t e0 = prof_begin(S);
-    for (const Group& gr : S.igroups)
-      HIPCHK(S, pic_launch_zero_current(S.d_inst + gr.first, gr.count, gr.max_ncell, S.stream));
-    prof_end(S, 1, e0);
-    e0 = prof_begin(S);
     for (const Group& gr : S.sgroups) {
       int per_cu = std::max(1, std::min(8, (int)(kLdsMax / std::max<size_t>(gr.lds, 1))));
       int grid = std::max(1, std::min(gr.max_items, kNumCU * per_cu));
       HIPCHK(S, pic_launch_gpd(gr.dim, gr.order, S.d_stores + gr.first, gr.count, grid, gr.lds, S.stream));
     }
     prof_end(S, 0, e0);
-    for (const Group& gr : S.igroups)
-      if (gr.fixed64) HIPCHK(S, pic_launch_fold_current(S.d_inst + gr.first, gr.count, gr.max_ncell, S.stream));
     e0 = prof_begin(S);
-    for (const Group& gr : S.igroups) {
-      HIPCHK(S, pic_launch_yee_b(S.d_inst + gr.first, gr.count, gr.max_ncell, gr.dim, 0.5f, S.stream));
-      HIPCHK(S, pic_launch_yee_e(S.d_inst + gr.first, gr.count, gr.max_ncell, gr.dim, S.stream));
-      HIPCHK(S, pic_launch_yee_b(S.d_inst + gr.first, gr.count, gr.max_ncell, gr.dim, 0.5f, S.stream));
-    }
+    for (const Group& gr : S.igroups)
+      HIPCHK(S, pic_launch_yee_step(S.d_inst + gr.first, gr.count, gr.max_tiles, gr.dim, S.stream));
     prof_end(S, 1, e0);
     if (end_with_check && k == nsteps - 1) {
       e0 = prof_begin(S);
@@ -573,11 +580,37 @@ pic_status upload_binned(Sim& S, Instance& I, Species& sp, const HostParticles& 
   }
   std::vector<int> toff(g.ntiles + 1, 0);
   for (int t = 0; t < g.ntiles; t++) toff[t + 1] = toff[t] + count[t + 1];
-  std::vector<int> pos(toff.begin(), toff.end() - 1);
+  // order inside a tile: the k-th particle of every cell, cell by cell, for
+  // k = 0, 1, ...; neighbouring lanes of a wavefront then sit in different
+  // cells and their current deposits hit different LDS addresses
+  std::vector<int> order(n), slotpos(n);
+  {
+    std::vector<int> pos(toff.begin(), toff.end() - 1);
+    for (size_t p = 0; p < n; p++) order[pos[tile[p]]++] = (int)p;  // stable by tile
+    std::vector<long long> key;
+    std::vector<int> tmp;
+    std::unordered_map<int, int> seen;
+    for (int t = 0; t < g.ntiles; t++) {
+      int a = toff[t], b = toff[t + 1];
+      if (b - a < 2) continue;
+      key.resize(b - a);
+      seen.clear();
+      for (int k = a; k < b; k++) {
+        int cell = h.cell[order[k]];
+        int rank = seen[cell]++;
+        key[k - a] = ((long long)rank << 32) | (unsigned)cell;
+      }
+      tmp.resize(b - a);
+      for (int k = 0; k < b - a; k++) tmp[k] = k;
+      std::stable_sort(tmp.begin(), tmp.end(), [&](int x, int y) { return key[x] < key[y]; });
+      for (int k = 0; k < b - a; k++) slotpos[k] = order[a + tmp[k]];
+      for (int k = 0; k < b - a; k++) order[a + k] = slotpos[k];
+    }
+  }
   HostParticles o;
   o.resize(n);
-  for (size_t p = 0; p < n; p++) {
-    int q = pos[tile[p]]++;
+  for (size_t q = 0; q < n; q++) {
+    size_t p = (size_t)order[q];
     o.cell[q] = h.cell[p];
     o.id[q] = h.id[p];
     for (int k = 0; k < 3; k++) {
@@ -871,7 +904,7 @@ pic_status sim_diag(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_byt
       double* dbuf = nullptr;
       HIPCHK(S, hipMalloc(&dbuf, ncomp * nc * sizeof(double)));
       tmp.push_back(dbuf);
-      HIPCHK(S, pic_launch_f32_to_f64(kind == PIC_DIAG_EXPORT_FIELDS ? I.F : I.J, dbuf, ncomp * nc, S.stream));
+      HIPCHK(S, pic_launch_f32_to_f64(kind == PIC_DIAG_EXPORT_FIELDS ? I.F : I.Jout, dbuf, ncomp * nc, S.stream));
       HIPCHK(S, hipMemcpyAsync(out, dbuf, ncomp * nc * sizeof(double), hipMemcpyDeviceToHost, S.stream));
       HIPCHK(S, hipStreamSynchronize(S.stream));
       return PIC_OK;
@@ -933,14 +966,22 @@ pic_status sim_create(Sim& S, const pic_config* cfgs, int n, void* stream) {
     if (st != PIC_OK) return st;
     size_t nc = (size_t)I.g.ncell;
     if (hipMalloc(&I.F, 6 * nc * sizeof(float)) != hipSuccess) return S.fail(PIC_E_NOMEM, "field allocation failed");
-    if (hipMalloc(&I.J, 3 * nc * sizeof(float)) != hipSuccess) return S.fail(PIC_E_NOMEM, "current allocation failed");
     HIPCHK(S, hipMemset(I.F, 0, 6 * nc * sizeof(float)));
-    HIPCHK(S, hipMemset(I.J, 0, 3 * nc * sizeof(float)));
-    if (cfgs[i].accumulator == PIC_ACC_FIXED64) {
-      if (hipMalloc(&I.J64, 3 * nc * sizeof(unsigned long long)) != hipSuccess)
-        return S.fail(PIC_E_NOMEM, "current allocation failed");
-      HIPCHK(S, hipMemset(I.J64, 0, 3 * nc * sizeof(unsigned long long)));
+    if (hipMalloc(&I.Jout, 3 * nc * sizeof(float)) != hipSuccess) return S.fail(PIC_E_NOMEM, "current allocation failed");
+    HIPCHK(S, hipMemset(I.Jout, 0, 3 * nc * sizeof(float)));
+    for (int k = 0; k < 2; k++) {
+      if (cfgs[i].accumulator == PIC_ACC_FIXED64) {
+        if (hipMalloc(&I.J64[k], 3 * nc * sizeof(unsigned long long)) != hipSuccess)
+          return S.fail(PIC_E_NOMEM, "current allocation failed");
+        HIPCHK(S, hipMemset(I.J64[k], 0, 3 * nc * sizeof(unsigned long long)));
+      } else {
+        if (hipMalloc(&I.Jacc[k], 3 * nc * sizeof(float)) != hipSuccess)
+          return S.fail(PIC_E_NOMEM, "current allocation failed");
+        HIPCHK(S, hipMemset(I.Jacc[k], 0, 3 * nc * sizeof(float)));
+      }
     }
+    if (hipMalloc(&I.ictl, sizeof(InstCtl)) != hipSuccess) return S.fail(PIC_E_NOMEM, "allocation failed");
+    HIPCHK(S, hipMemset(I.ictl, 0, sizeof(InstCtl)));
   }
   HIPCHK(S, hipMalloc(&S.d_scratch, (size_t)2 * 4 * pic_reduce_blocks() * sizeof(double)));
   HIPCHK(S, hipMalloc(&S.d_out, 8 * sizeof(double)));
@@ -970,8 +1011,12 @@ void sim_destroy(Sim& S) {
   for (Instance& I : S.inst) {
     for (Species& sp : I.sp) free_species(sp);
     if (I.F) (void)hipFree(I.F);
-    if (I.J) (void)hipFree(I.J);
-    if (I.J64) (void)hipFree(I.J64);
+    for (int k = 0; k < 2; k++) {
+      if (I.Jacc[k]) (void)hipFree(I.Jacc[k]);
+      if (I.J64[k]) (void)hipFree(I.J64[k]);
+    }
+    if (I.Jout) (void)hipFree(I.Jout);
+    if (I.ictl) (void)hipFree(I.ictl);
     if (I.rho_snap) (void)hipFree(I.rho_snap);
   }
   if (S.d_stores) (void)hipFree(S.d_stores);

@@ -63,51 +63,18 @@ __device__ void group_prefix(const StoreDesc* stores, int nstores, int* pref, F 
   __syncthreads();
 }
 
-// --- 1. per old item: particles per slot --------------------------------------
-__global__ void __launch_bounds__(kBlock) rebin_count(const StoreDesc* __restrict__ stores, int nstores) {
-  __shared__ int pref[kMaxGroup + 1];
-  __shared__ int cnt[PIC_NSLOT];
-  group_prefix(stores, nstores, pref, [](const StoreDesc& S) { return S.ctl->n_items[S.ctl->cur]; });
-  const int total = pref[nstores];
-  const int lane = threadIdx.x & 63;
-  int s = 0;
-  for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
-    while (gi >= pref[s + 1]) s++;
-    const StoreDesc& S = stores[s];
-    const int cur = S.ctl->cur;
-    const int ii = gi - pref[s];
-    const Item it = S.items[cur][ii];
-    if (threadIdx.x < PIC_NSLOT) cnt[threadIdx.x] = 0;
-    __syncthreads();
-    for (int base = it.begin; base < it.end; base += blockDim.x) {
-      int p = base + threadIdx.x;
-      int sl = p < it.end ? particle_slot(S.g, it.tile, S.cell[cur][p]) : -1;
-      unsigned long long todo = __ballot(sl >= 0);
-      while (todo) {
-        int leader = __ffsll((long long)todo) - 1;
-        int ls = __shfl(sl, leader);
-        unsigned long long m = __ballot(sl == ls);
-        if (lane == leader) atomicAdd(&cnt[ls], (int)__popcll(m));
-        todo &= ~m;
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x < PIC_NSLOT) S.cnt[ii * PIC_NSLOT + threadIdx.x] = cnt[threadIdx.x];
-    __syncthreads();
-  }
-}
-
-// --- 2. per tile: running slot counts over its items ---------------------------
-__global__ void __launch_bounds__(kBlock) rebin_tile(const StoreDesc* __restrict__ stores, int nstores) {
-  __shared__ int pref[kMaxGroup + 1];
-  group_prefix(stores, nstores, pref, [](const StoreDesc& S) { return S.g.ntiles; });
-  const int total = pref[nstores];
-  int s = 0;
-  for (int gt = blockIdx.x * blockDim.x + threadIdx.x; gt < total; gt += gridDim.x * blockDim.x) {
-    while (gt >= pref[s + 1]) s++;
-    const StoreDesc& S = stores[s];
-    const int cur = S.ctl->cur;
-    const int t = gt - pref[s];
+// --- 1. per store, one workgroup: slot totals per tile, slot bases per
+// destination tile, tile offsets, item offsets and the new item list.  The
+// per-item slot counts come from the fused particle kernel of the last step.
+__global__ void __launch_bounds__(kScanBlock) rebin_plan(const StoreDesc* __restrict__ stores) {
+  const StoreDesc& S = stores[blockIdx.x];
+  if (!active(S)) return;
+  __shared__ int sa[kScanBlock], sb[kScanBlock];
+  const int nt = S.g.ntiles;
+  const int cur = S.ctl->cur;
+  const int nxt = 1 - cur;
+  // running slot counts over the items of each source tile
+  for (int t = threadIdx.x; t < nt; t += blockDim.x) {
     const int i0 = S.ioff[cur][t], i1 = S.ioff[cur][t + 1];
     for (int sl = 0; sl < PIC_NSLOT; sl++) {
       int run = 0;
@@ -118,18 +85,9 @@ __global__ void __launch_bounds__(kBlock) rebin_tile(const StoreDesc* __restrict
       S.tot[t * PIC_NSLOT + sl] = run;
     }
   }
-}
-
-// --- 3. per destination tile: incoming count and slot bases ---------------------
-__global__ void __launch_bounds__(kBlock) rebin_dest(const StoreDesc* __restrict__ stores, int nstores) {
-  __shared__ int pref[kMaxGroup + 1];
-  group_prefix(stores, nstores, pref, [](const StoreDesc& S) { return S.g.ntiles; });
-  const int total = pref[nstores];
-  int s = 0;
-  for (int gt = blockIdx.x * blockDim.x + threadIdx.x; gt < total; gt += gridDim.x * blockDim.x) {
-    while (gt >= pref[s + 1]) s++;
-    const StoreDesc& S = stores[s];
-    const int d = gt - pref[s];
+  __syncthreads();
+  // incoming particles of each destination tile, in slot order
+  for (int d = threadIdx.x; d < nt; d += blockDim.x) {
     int acc = 0;
     for (int sl = 0; sl < PIC_NSLOT; sl++) {
       int src = slot_tile(S.g, d, sl, -1);
@@ -138,15 +96,7 @@ __global__ void __launch_bounds__(kBlock) rebin_dest(const StoreDesc* __restrict
     }
     S.dcount[d] = acc;
   }
-}
-
-// --- 4. per store: tile offsets, item offsets and the new item list -------------
-__global__ void __launch_bounds__(kScanBlock) rebin_scan(const StoreDesc* __restrict__ stores) {
-  const StoreDesc& S = stores[blockIdx.x];
-  if (!active(S)) return;
-  __shared__ int sa[kScanBlock], sb[kScanBlock];
-  const int nt = S.g.ntiles;
-  const int nxt = 1 - S.ctl->cur;
+  __syncthreads();
   const int chunk = S.chunk;
   const int seg = (nt + kScanBlock - 1) / kScanBlock;
   const int t0 = threadIdx.x * seg;
@@ -200,7 +150,8 @@ __global__ void __launch_bounds__(kScanBlock) rebin_scan(const StoreDesc* __rest
   }
 }
 
-// --- 5. per old item: stable scatter into the other buffer set -----------------
+// --- 2. per old item: stable scatter into the other buffer set; the last
+// workgroup to finish flips the buffer set of every store that was rebinned -----------------
 __global__ void __launch_bounds__(kBlock) rebin_scatter(const StoreDesc* __restrict__ stores, int nstores) {
   __shared__ int pref[kMaxGroup + 1];
   __shared__ int run[PIC_NSLOT];
@@ -267,18 +218,24 @@ __global__ void __launch_bounds__(kBlock) rebin_scatter(const StoreDesc* __restr
     }
     __syncthreads();
   }
-}
-
-// --- 6. per store: flip the buffer set and clear the flag ----------------------
-__global__ void rebin_finish(const StoreDesc* __restrict__ stores, int nstores) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nstores) return;
-  StoreCtl* c = stores[s].ctl;
-  c->nchecks += 1;
-  if (c->flag) {
-    c->cur = 1 - c->cur;
-    c->flag = 0;
-    c->nsorts += 1;
+  // completion: the last workgroup (all others have finished their loads of
+  // the control words) flips the buffer sets and clears the flags
+  __syncthreads();
+  // No fence: the control words are only read here and by later kernels.
+  if (threadIdx.x == 0) {
+    unsigned prev = atomicAdd(&stores[0].ctl->sdone, 1u);
+    if (prev == gridDim.x - 1) {
+      for (int k = 0; k < nstores; k++) {
+        StoreCtl* c = stores[k].ctl;
+        c->nchecks += 1;
+        if (c->flag) {
+          c->cur = 1 - c->cur;
+          c->flag = 0;
+          c->nsorts += 1;
+        }
+      }
+      stores[0].ctl->sdone = 0u;
+    }
   }
 }
 
@@ -292,12 +249,9 @@ int cap_grid(long n, int per) {
 
 hipError_t pic_launch_rebin(const StoreDesc* d_stores, int nstores, int max_items, int max_tiles,
                             hipStream_t st) {
+  (void)max_tiles;
   if (nstores > kMaxGroup) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(rebin_count, dim3(cap_grid(max_items, 1)), dim3(kBlock), 0, st, d_stores, nstores);
-  hipLaunchKernelGGL(rebin_tile, dim3(cap_grid(max_tiles, kBlock)), dim3(kBlock), 0, st, d_stores, nstores);
-  hipLaunchKernelGGL(rebin_dest, dim3(cap_grid(max_tiles, kBlock)), dim3(kBlock), 0, st, d_stores, nstores);
-  hipLaunchKernelGGL(rebin_scan, dim3(nstores), dim3(kScanBlock), 0, st, d_stores);
+  hipLaunchKernelGGL(rebin_plan, dim3(nstores), dim3(kScanBlock), 0, st, d_stores);
   hipLaunchKernelGGL(rebin_scatter, dim3(cap_grid(max_items, 1)), dim3(kBlock), 0, st, d_stores, nstores);
-  hipLaunchKernelGGL(rebin_finish, dim3((nstores + 63) / 64), dim3(64), 0, st, d_stores, nstores);
   return hipGetLastError();
 }

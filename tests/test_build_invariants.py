@@ -1,0 +1,24 @@
+"""CPU checks of properties of the compiled gfx950 code that the kernels rely on."""
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1503_00276_amd", "csrc")
+
+
+@pytest.mark.skipif(shutil.which("hipcc") is None, reason="hipcc not available")
+def test_particle_kernel_dynamic_lds_is_16_byte_aligned(tmp_path):
+    """The int64 current tile lives in dynamic LDS right after the static LDS;
+    its 8-byte LDS atomics need the dynamic base (= the static segment size)
+    to be a multiple of 8, which the aligned extern declaration guarantees."""
+    out = tmp_path / "gpd.s"
+    subprocess.check_call(["hipcc", "-O3", "-std=c++17", "--offload-arch=gfx950", "--cuda-device-only", "-S",
+                           "-munsafe-fp-atomics", os.path.join(CSRC, "gpd.hip"), "-o", str(out)],
+                          stderr=subprocess.DEVNULL)
+    sizes = [int(v) for v in re.findall(r"amdhsa_group_segment_fixed_size (\d+)", out.read_text())]
+    assert len(sizes) == 6
+    assert all(v % 16 == 0 for v in sizes), sizes
