@@ -39,7 +39,7 @@ __device__ __forceinline__ int rho_weights(int order, double eps, double w[4]) {
 __global__ void __launch_bounds__(kBlock) rho64(const StoreDesc* __restrict__ sp, double* rho) {
   const StoreDesc& S = *sp;
   const GridDesc& g = S.g;
-  const int cur = S.ctl->cur;
+  const int cur = pic_cur(*S.ctl);
   const int np = S.np;
   const int no = g.order + 1;
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
@@ -202,7 +202,7 @@ __global__ void __launch_bounds__(kBlock) field_sums(const InstDesc* __restrict_
 __global__ void __launch_bounds__(kBlock) particle_sums(const StoreDesc* __restrict__ sp, double rqm,
                                                         double* partial) {
   const StoreDesc& S = *sp;
-  const int cur = S.ctl->cur;
+  const int cur = pic_cur(*S.ctl);
   Pair v[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < S.np; p += gridDim.x * blockDim.x) {
     double ux = S.u[cur][0][p], uy = S.u[cur][1][p], uz = S.u[cur][2][p];
@@ -227,7 +227,7 @@ __global__ void __launch_bounds__(kBlock) sq_sums(const double* x, int n, double
 __global__ void __launch_bounds__(kBlock) export_state(const StoreDesc* __restrict__ sp, double* out) {
   const StoreDesc& S = *sp;
   const GridDesc& g = S.g;
-  const int cur = S.ctl->cur;
+  const int cur = pic_cur(*S.ctl);
   const int stride = g.dim + 4;
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < S.np; p += gridDim.x * blockDim.x) {
     int c[3];

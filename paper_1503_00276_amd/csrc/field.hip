@@ -29,9 +29,9 @@ template <> struct YeeTile<3> { static constexpr int X = 16, Y = 4, Z = 4; };
 // The halos are recomputed by every tile that needs them, with the same
 // arithmetic on the same inputs, so neighbouring tiles agree bitwise.
 // The current of the step is read from the accumulator the particle kernel
-// filled (int64 fixed point in the deterministic mode), copied to Jout, and
-// the other accumulator is cleared for the next step.  The last workgroup to
-// finish flips which accumulator is in use.
+// filled (int64 fixed point in the deterministic mode; which of the two is
+// the step's parity), copied to Jout, and the other accumulator is cleared
+// for the next step.
 // Periodic wrap for an index at most one period out of range.
 __device__ __forceinline__ int wrap1(int v, int n) {
   v = v < 0 ? v + n : v;
@@ -40,7 +40,7 @@ __device__ __forceinline__ int wrap1(int v, int n) {
 }
 
 template <int DIM>
-__global__ void __launch_bounds__(kBlock) yee_step(const InstDesc* __restrict__ inst) {
+__global__ void __launch_bounds__(kBlock) yee_step(const InstDesc* __restrict__ inst, int par) {
   using T = YeeTile<DIM>;
   constexpr int EXM = T::X + 3, EYM = T::Y + 3, EZM = DIM == 3 ? T::Z + 3 : 1;
   constexpr int BXM = T::X + 2, BYM = T::Y + 2, BZM = DIM == 3 ? T::Z + 2 : 1;
@@ -48,7 +48,6 @@ __global__ void __launch_bounds__(kBlock) yee_step(const InstDesc* __restrict__ 
   __shared__ float sB[3][BZM * BYM * BXM];
   const InstDesc& I = inst[blockIdx.y];
   const GridDesc& g = I.g;
-  const int par = I.ictl->parity;
   const int ntx = (g.nx[0] + T::X - 1) / T::X;
   const int nty = (g.nx[1] + T::Y - 1) / T::Y;
   const int ntz = DIM == 3 ? (g.nx[2] + T::Z - 1) / T::Z : 1;
@@ -192,17 +191,6 @@ __global__ void __launch_bounds__(kBlock) yee_step(const InstDesc* __restrict__ 
           Fw[2 * nc + gi] = sE[2][c];
         }
   }
-  // completion: the last workgroup of this instance flips the accumulator.
-  // No fence: every workgroup has already used the parity it read, and the
-  // flipped value reaches the next kernel through the kernel boundary.
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned prev = atomicAdd(&I.ictl->done, 1u);
-    if (prev == gridDim.x - 1) {
-      I.ictl->done = 0u;
-      I.ictl->parity = 1 - par;
-    }
-  }
 }
 
 }  // namespace
@@ -214,10 +202,11 @@ int pic_yee_tiles(int dim, const int nx[3]) {
          ((nx[2] + YeeTile<3>::Z - 1) / YeeTile<3>::Z);
 }
 
-hipError_t pic_launch_yee_step(const InstDesc* d_inst, int ninst, int max_tiles, int dim, hipStream_t st) {
+hipError_t pic_launch_yee_step(const InstDesc* d_inst, int ninst, int max_tiles, int dim, int parity,
+                               hipStream_t st) {
   if (dim == 2)
-    hipLaunchKernelGGL(yee_step<2>, dim3(max_tiles, ninst), dim3(kBlock), 0, st, d_inst);
+    hipLaunchKernelGGL(yee_step<2>, dim3(max_tiles, ninst), dim3(kBlock), 0, st, d_inst, parity);
   else
-    hipLaunchKernelGGL(yee_step<3>, dim3(max_tiles, ninst), dim3(kBlock), 0, st, d_inst);
+    hipLaunchKernelGGL(yee_step<3>, dim3(max_tiles, ninst), dim3(kBlock), 0, st, d_inst, parity);
   return hipGetLastError();
 }

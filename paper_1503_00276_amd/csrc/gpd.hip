@@ -217,7 +217,8 @@ __device__ __forceinline__ void lds_add(acc_t* p, float v) {
 // ---------------------------------------------------------------------------
 
 template <int DIM, int ORDER>
-__device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii, float* smem, int* scnt) {
+__device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii, int jp, float* smem,
+                             int* scnt) {
   constexpr int NG = ORDER + 1;  // gather taps per axis
   constexpr int W = ORDER + 2;   // deposit window per axis
   const GridDesc& g = S.g;
@@ -523,11 +524,14 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
     up1[p] = uy;
     up2[p] = uz;
   }
-  if (strayed) atomicOr(&S.ctl->flag, 1);
-  if (bad) atomicOr(&S.ctl->bad, 1);
-  __syncthreads();
+  // one plain store per workgroup (all writers store the same value)
+  const int any_strayed = __syncthreads_or(strayed ? 1 : 0);
+  const int any_bad = __syncthreads_or(bad ? 1 : 0);
+  if (tid == 0) {
+    if (any_strayed) S.ctl->flag = 1;
+    if (any_bad) S.ctl->bad = 1;
+  }
   if (tid < PIC_NSLOT) S.cnt[ii * PIC_NSLOT + tid] = scnt[tid];
-  const int jp = S.ictl->parity;
 
   // 4. fold the LDS current into the global current (periodic wrap)
   for (int idx = tid; idx < jn; idx += blockDim.x) {
@@ -555,7 +559,7 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
 }
 
 template <int DIM, int ORDER>
-__global__ void __launch_bounds__(kBlock) gpd_kernel(const StoreDesc* __restrict__ stores, int nstores) {
+__global__ void __launch_bounds__(kBlock) gpd_kernel(const StoreDesc* __restrict__ stores, int nstores, int jp) {
   // 16-byte aligned: the int64 current tile inside it takes 8-byte LDS atomics
   extern __shared__ __align__(16) float smem[];
   __shared__ int s_pref[kMaxGroup + 1];
@@ -564,7 +568,7 @@ __global__ void __launch_bounds__(kBlock) gpd_kernel(const StoreDesc* __restrict
   if (threadIdx.x == 0) {
     int acc = 0;
     for (int s = 0; s < nstores; s++) {
-      int cur = stores[s].ctl->cur;
+      int cur = pic_cur(*stores[s].ctl);
       s_cur[s] = cur;
       s_pref[s] = acc;
       acc += stores[s].ctl->n_items[cur];
@@ -579,7 +583,7 @@ __global__ void __launch_bounds__(kBlock) gpd_kernel(const StoreDesc* __restrict
     const StoreDesc& S = stores[s];
     const int cur = s_cur[s];
     const Item it = S.items[cur][gi - s_pref[s]];
-    process_item<DIM, ORDER>(S, cur, it, gi - s_pref[s], smem, s_cnt);
+    process_item<DIM, ORDER>(S, cur, it, gi - s_pref[s], jp, smem, s_cnt);
   }
 }
 
@@ -590,8 +594,8 @@ hipError_t prepare_one(size_t lds) {
 }
 
 template <int DIM, int ORDER>
-hipError_t launch_one(const StoreDesc* stores, int nstores, int grid, size_t lds, hipStream_t st) {
-  gpd_kernel<DIM, ORDER><<<dim3(grid), dim3(kBlock), lds, st>>>(stores, nstores);
+hipError_t launch_one(const StoreDesc* stores, int nstores, int grid, size_t lds, int jp, hipStream_t st) {
+  gpd_kernel<DIM, ORDER><<<dim3(grid), dim3(kBlock), lds, st>>>(stores, nstores, jp);
   return hipGetLastError();
 }
 
@@ -624,15 +628,15 @@ hipError_t pic_gpd_prepare(int dim, int order, size_t lds) {
 }
 
 hipError_t pic_launch_gpd(int dim, int order, const StoreDesc* d_stores, int nstores, int grid,
-                          size_t lds, hipStream_t st) {
+                          size_t lds, int parity, hipStream_t st) {
   if (dim == 2) {
-    if (order == 1) return launch_one<2, 1>(d_stores, nstores, grid, lds, st);
-    if (order == 2) return launch_one<2, 2>(d_stores, nstores, grid, lds, st);
-    if (order == 3) return launch_one<2, 3>(d_stores, nstores, grid, lds, st);
+    if (order == 1) return launch_one<2, 1>(d_stores, nstores, grid, lds, parity, st);
+    if (order == 2) return launch_one<2, 2>(d_stores, nstores, grid, lds, parity, st);
+    if (order == 3) return launch_one<2, 3>(d_stores, nstores, grid, lds, parity, st);
   } else if (dim == 3) {
-    if (order == 1) return launch_one<3, 1>(d_stores, nstores, grid, lds, st);
-    if (order == 2) return launch_one<3, 2>(d_stores, nstores, grid, lds, st);
-    if (order == 3) return launch_one<3, 3>(d_stores, nstores, grid, lds, st);
+    if (order == 1) return launch_one<3, 1>(d_stores, nstores, grid, lds, parity, st);
+    if (order == 2) return launch_one<3, 2>(d_stores, nstores, grid, lds, parity, st);
+    if (order == 3) return launch_one<3, 3>(d_stores, nstores, grid, lds, parity, st);
   }
   return hipErrorInvalidValue;
 }

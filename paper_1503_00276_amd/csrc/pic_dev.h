@@ -37,25 +37,23 @@ struct GridDesc {
   int fa, fb, ja, jb;
 };
 
-// Control words of one particle store, written by the kernels.
+// Control words of one particle store.  The buffer set holding the particles
+// is cur ^ pending: the rebin planner (one workgroup, so no atomics are
+// needed) folds pending into cur when it next runs, and sets pending when it
+// plans a rebin whose scatter fills the other set.
 struct StoreCtl {
-  int cur;          // which ping-pong buffer set holds the particles
+  int cur;          // buffer set, before the pending flip
+  int pending;      // 1: the other set is current (a scatter filled it)
   int flag;         // a particle strayed beyond flag_slack: rebin at the next check
+  int active;       // the planned rebin of this check (read by the scatter)
   int n_items[2];   // work items of each buffer set
   int bad;          // a particle was found outside its staged region (skipped)
   int nsorts;       // rebins performed
   int nchecks;      // rebin checks performed
-  unsigned sdone;   // workgroups of the scatter that finished (group's first store)
+  int pad[3];
 };
 
-// Control words of one instance: which of the two current accumulators the
-// step deposits into (the other is being cleared), and a completion counter
-// the field kernel uses to flip it once all its workgroups are done.
-struct InstCtl {
-  int parity;
-  unsigned done;
-  int pad[2];
-};
+__host__ __device__ inline int pic_cur(const StoreCtl& c) { return c.cur ^ c.pending; }
 
 // Work item: a contiguous run of particles that all belong to one tile.
 struct Item {
@@ -72,7 +70,6 @@ struct StoreDesc {
   float* F;                  // instance fields: E1 E2 E3 B1 B2 B3 planes of ncell floats
   float* Jacc[2];            // FP32 current accumulators (J1 J2 J3 planes), double-buffered
   unsigned long long* J64[2];// int64 fixed-point accumulators (deterministic mode only)
-  InstCtl* ictl;
   int* cell[2];              // packed cell index
   float* eps[2][3];          // in-cell offset in [0,1)
   float* u[2][3];            // u = gamma v
@@ -96,7 +93,6 @@ struct InstDesc {
   float* Jacc[2];
   unsigned long long* J64[2];
   float* Jout;               // the current of the last step (FP32, used by the E update)
-  InstCtl* ictl;
 };
 
 // ---------------------------------------------------------------------------

@@ -12,11 +12,12 @@ int pic_gpd_max_group();
 // allow the LDS size a group needs (call before launching or capturing)
 hipError_t pic_gpd_prepare(int dim, int order, size_t lds);
 hipError_t pic_launch_gpd(int dim, int order, const StoreDesc* d_stores, int nstores, int grid,
-                          size_t lds, hipStream_t st);
+                          size_t lds, int parity, hipStream_t st);
 
 // Yee field solve (field.hip); instances in d_inst[0..ninst)
 int pic_yee_tiles(int dim, const int nx[3]);
-hipError_t pic_launch_yee_step(const InstDesc* d_inst, int ninst, int max_tiles, int dim, hipStream_t st);
+hipError_t pic_launch_yee_step(const InstDesc* d_inst, int ninst, int max_tiles, int dim, int parity,
+                               hipStream_t st);
 
 // tile rebin (sort.hip); stores in d_stores[0..nstores)
 hipError_t pic_launch_rebin(const StoreDesc* d_stores, int nstores, int max_items, int max_tiles,

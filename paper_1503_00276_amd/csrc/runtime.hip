@@ -46,7 +46,6 @@ struct Instance {
   float* Jacc[2] = {nullptr, nullptr};
   unsigned long long* J64[2] = {nullptr, nullptr};
   float* Jout = nullptr;
-  InstCtl* ictl = nullptr;
   double wmax[PIC_MAX_SPECIES] = {0, 0, 0, 0, 0, 0, 0, 0};
   double* rho_snap = nullptr;
   bool have_snap = false;
@@ -75,8 +74,9 @@ struct Sim {
   double* d_scratch = nullptr;  // reductions
   double* d_out = nullptr;      // reduction outputs
   std::string err;
-  // captured graphs: one rebin cycle (sort_interval steps ending with the check)
-  hipGraphExec_t cycle_exec = nullptr;
+  // captured graphs: one rebin cycle (sort_interval steps ending with the
+  // check), one per parity of the cycle's first step
+  hipGraphExec_t cycle_exec[2] = {nullptr, nullptr};
   bool use_graph = true;
   // profiling: event pairs around each kernel family, summed at read time
   bool profiling = false;
@@ -303,7 +303,6 @@ pic_status alloc_species(Sim& S, Instance& I, Species& sp, int64_t cap, int chun
     d.Jacc[k] = I.Jacc[k];
     d.J64[k] = I.J64[k];
   }
-  d.ictl = I.ictl;
   StoreCtl z{};
   HIPCHK(S, hipMemcpy(sp.ctl, &z, sizeof z, hipMemcpyHostToDevice));
   sp.cap = cap;
@@ -358,7 +357,6 @@ pic_status refresh_descriptors(Sim& S) {
         id.J64[k] = I.J64[k];
       }
       id.Jout = I.Jout;
-      id.ictl = I.ictl;
       insts.push_back(id);
       if (I.g.acc_mode == PIC_ACC_FIXED64) gr.fixed64 = true;
       gr.count++;
@@ -380,10 +378,11 @@ pic_status refresh_descriptors(Sim& S) {
   S.d_inst = nullptr;
   HIPCHK(S, hipMalloc(&S.d_inst, std::max<size_t>(insts.size(), 1) * sizeof(InstDesc)));
   HIPCHK(S, hipMemcpy(S.d_inst, insts.data(), insts.size() * sizeof(InstDesc), hipMemcpyHostToDevice));
-  if (S.cycle_exec) {
-    (void)hipGraphExecDestroy(S.cycle_exec);
-    S.cycle_exec = nullptr;
-  }
+  for (int k = 0; k < 2; k++)
+    if (S.cycle_exec[k]) {
+      (void)hipGraphExecDestroy(S.cycle_exec[k]);
+      S.cycle_exec[k] = nullptr;
+    }
   S.dirty = false;
   return PIC_OK;
 }
@@ -449,18 +448,21 @@ pic_status prof_collect(Sim& S) {
   return PIC_OK;
 }
 
-pic_status launch_steps(Sim& S, int nsteps, bool end_with_check) {
+// Launch nsteps steps starting at global step 'first' (whose parity picks
+// the current accumulator of each step).
+pic_status launch_steps(Sim& S, int64_t first, int nsteps, bool end_with_check) {
   for (int k = 0; k < nsteps; k++) {
+    const int par = (int)((first + k) & 1);
     hipEvent_t e0 = prof_begin(S);
     for (const Group& gr : S.sgroups) {
       int per_cu = std::max(1, std::min(8, (int)(kLdsMax / std::max<size_t>(gr.lds, 1))));
       int grid = std::max(1, std::min(gr.max_items, kNumCU * per_cu));
-      HIPCHK(S, pic_launch_gpd(gr.dim, gr.order, S.d_stores + gr.first, gr.count, grid, gr.lds, S.stream));
+      HIPCHK(S, pic_launch_gpd(gr.dim, gr.order, S.d_stores + gr.first, gr.count, grid, gr.lds, par, S.stream));
     }
     prof_end(S, 0, e0);
     e0 = prof_begin(S);
     for (const Group& gr : S.igroups)
-      HIPCHK(S, pic_launch_yee_step(S.d_inst + gr.first, gr.count, gr.max_tiles, gr.dim, S.stream));
+      HIPCHK(S, pic_launch_yee_step(S.d_inst + gr.first, gr.count, gr.max_tiles, gr.dim, par, S.stream));
     prof_end(S, 1, e0);
     if (end_with_check && k == nsteps - 1) {
       e0 = prof_begin(S);
@@ -472,21 +474,21 @@ pic_status launch_steps(Sim& S, int nsteps, bool end_with_check) {
   return PIC_OK;
 }
 
-pic_status capture_cycle(Sim& S) {
-  if (S.cycle_exec) return PIC_OK;
+pic_status capture_cycle(Sim& S, int par) {
+  if (S.cycle_exec[par]) return PIC_OK;
   hipGraph_t graph = nullptr;
   HIPCHK(S, hipStreamBeginCapture(S.stream, hipStreamCaptureModeThreadLocal));
-  pic_status st = launch_steps(S, S.sort_interval, true);
+  pic_status st = launch_steps(S, par, S.sort_interval, true);
   hipError_t e = hipStreamEndCapture(S.stream, &graph);
   if (st != PIC_OK) {
     if (graph) (void)hipGraphDestroy(graph);
     return st;
   }
   if (e != hipSuccess) return S.fail(PIC_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
-  e = hipGraphInstantiate(&S.cycle_exec, graph, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(&S.cycle_exec[par], graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) {
-    S.cycle_exec = nullptr;
+    S.cycle_exec[par] = nullptr;
     return S.fail(PIC_E_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
   }
   return PIC_OK;
@@ -504,16 +506,17 @@ pic_status sim_step(Sim& S, int64_t nsteps) {
     int64_t phase = S.steps % SI;  // steps already done in the current cycle
     int64_t left = nsteps - done;
     if (phase == 0 && left >= SI && S.use_graph && !S.profiling) {
-      st = capture_cycle(S);
+      const int par = (int)(S.steps & 1);
+      st = capture_cycle(S, par);
       if (st != PIC_OK) return st;
-      HIPCHK(S, hipGraphLaunch(S.cycle_exec, S.stream));
+      HIPCHK(S, hipGraphLaunch(S.cycle_exec[par], S.stream));
       S.steps += SI;
       done += SI;
       continue;
     }
     int64_t run = std::min<int64_t>(left, SI - phase);
     bool check = (phase + run == SI);
-    st = launch_steps(S, (int)run, check);
+    st = launch_steps(S, S.steps, (int)run, check);
     if (st != PIC_OK) return st;
     S.steps += run;
     done += run;
@@ -555,7 +558,7 @@ pic_status read_back(Sim& S, Species& sp, int dim, HostParticles& h) {
   if (sp.np == 0) return PIC_OK;
   StoreCtl c{};
   HIPCHK(S, hipMemcpy(&c, sp.ctl, sizeof c, hipMemcpyDeviceToHost));
-  const int s = c.cur;
+  const int s = pic_cur(c);
   const StoreDesc& d = sp.desc;
   size_t n = sp.np;
   HIPCHK(S, hipMemcpy(h.cell.data(), d.cell[s], n * 4, hipMemcpyDeviceToHost));
@@ -643,7 +646,9 @@ pic_status upload_binned(Sim& S, Instance& I, Species& sp, const HostParticles& 
   StoreCtl c{};
   HIPCHK(S, hipMemcpy(&c, sp.ctl, sizeof c, hipMemcpyDeviceToHost));
   c.cur = 0;
+  c.pending = 0;
   c.flag = 0;
+  c.active = 0;
   c.bad = 0;
   c.n_items[0] = (int)items.size();
   c.n_items[1] = 0;
@@ -980,8 +985,6 @@ pic_status sim_create(Sim& S, const pic_config* cfgs, int n, void* stream) {
         HIPCHK(S, hipMemset(I.Jacc[k], 0, 3 * nc * sizeof(float)));
       }
     }
-    if (hipMalloc(&I.ictl, sizeof(InstCtl)) != hipSuccess) return S.fail(PIC_E_NOMEM, "allocation failed");
-    HIPCHK(S, hipMemset(I.ictl, 0, sizeof(InstCtl)));
   }
   HIPCHK(S, hipMalloc(&S.d_scratch, (size_t)2 * 4 * pic_reduce_blocks() * sizeof(double)));
   HIPCHK(S, hipMalloc(&S.d_out, 8 * sizeof(double)));
@@ -1007,7 +1010,8 @@ void sim_destroy(Sim& S) {
       (void)hipEventDestroy(pr.second);
     }
   for (hipEvent_t e : S.ev_free) (void)hipEventDestroy(e);
-  if (S.cycle_exec) (void)hipGraphExecDestroy(S.cycle_exec);
+  for (int k = 0; k < 2; k++)
+    if (S.cycle_exec[k]) (void)hipGraphExecDestroy(S.cycle_exec[k]);
   for (Instance& I : S.inst) {
     for (Species& sp : I.sp) free_species(sp);
     if (I.F) (void)hipFree(I.F);
@@ -1016,7 +1020,6 @@ void sim_destroy(Sim& S) {
       if (I.J64[k]) (void)hipFree(I.J64[k]);
     }
     if (I.Jout) (void)hipFree(I.Jout);
-    if (I.ictl) (void)hipFree(I.ictl);
     if (I.rho_snap) (void)hipFree(I.rho_snap);
   }
   if (S.d_stores) (void)hipFree(S.d_stores);

@@ -22,7 +22,8 @@ constexpr int kBlock = 256;
 constexpr int kScanBlock = 1024;
 constexpr int kMaxGroup = 256;
 
-__device__ __forceinline__ bool active(const StoreDesc& S) { return S.ctl->flag != 0; }
+// The scatter of this check runs for stores whose planner found the flag set.
+__device__ __forceinline__ bool active(const StoreDesc& S) { return S.ctl->active != 0; }
 
 // Slot of a particle with packed cell 'cell' that is stored in tile t.
 __device__ __forceinline__ int particle_slot(const GridDesc& g, int t, int cell) {
@@ -68,10 +69,27 @@ __device__ void group_prefix(const StoreDesc* stores, int nstores, int* pref, F 
 // per-item slot counts come from the fused particle kernel of the last step.
 __global__ void __launch_bounds__(kScanBlock) rebin_plan(const StoreDesc* __restrict__ stores) {
   const StoreDesc& S = stores[blockIdx.x];
-  if (!active(S)) return;
   __shared__ int sa[kScanBlock], sb[kScanBlock];
+  __shared__ int s_cur, s_act;
+  if (threadIdx.x == 0) {
+    // fold the flip of the previous rebin and turn the flag into this
+    // check's decision; this workgroup is the only writer of these words
+    StoreCtl* c = S.ctl;
+    const int cur = c->cur ^ c->pending;
+    const int act = c->flag;
+    c->cur = cur;
+    c->pending = 0;
+    c->active = act;
+    c->flag = 0;
+    c->nchecks += 1;
+    c->nsorts += act;
+    s_cur = cur;
+    s_act = act;
+  }
+  __syncthreads();
+  if (!s_act) return;
   const int nt = S.g.ntiles;
-  const int cur = S.ctl->cur;
+  const int cur = s_cur;
   const int nxt = 1 - cur;
   // running slot counts over the items of each source tile
   for (int t = threadIdx.x; t < nt; t += blockDim.x) {
@@ -147,15 +165,16 @@ __global__ void __launch_bounds__(kScanBlock) rebin_plan(const StoreDesc* __rest
     toff[nt] = sa[kScanBlock - 1];
     ioff[nt] = sb[kScanBlock - 1];
     S.ctl->n_items[nxt] = min(sb[kScanBlock - 1], S.max_items);
+    S.ctl->pending = 1;  // the scatter of this check fills set nxt
   }
 }
 
-// --- 2. per old item: stable scatter into the other buffer set; the last
-// workgroup to finish flips the buffer set of every store that was rebinned -----------------
+// --- 2. per old item: stable scatter into the other buffer set -----------------
 __global__ void __launch_bounds__(kBlock) rebin_scatter(const StoreDesc* __restrict__ stores, int nstores) {
   __shared__ int pref[kMaxGroup + 1];
   __shared__ int run[PIC_NSLOT];
   __shared__ int wcnt[kBlock / 64][PIC_NSLOT];
+  // the source set is cur (the planner set pending for the destination)
   group_prefix(stores, nstores, pref, [](const StoreDesc& S) { return S.ctl->n_items[S.ctl->cur]; });
   const int total = pref[nstores];
   const int lane = threadIdx.x & 63;
@@ -217,25 +236,6 @@ __global__ void __launch_bounds__(kBlock) rebin_scatter(const StoreDesc* __restr
       }
     }
     __syncthreads();
-  }
-  // completion: the last workgroup (all others have finished their loads of
-  // the control words) flips the buffer sets and clears the flags
-  __syncthreads();
-  // No fence: the control words are only read here and by later kernels.
-  if (threadIdx.x == 0) {
-    unsigned prev = atomicAdd(&stores[0].ctl->sdone, 1u);
-    if (prev == gridDim.x - 1) {
-      for (int k = 0; k < nstores; k++) {
-        StoreCtl* c = stores[k].ctl;
-        c->nchecks += 1;
-        if (c->flag) {
-          c->cur = 1 - c->cur;
-          c->flag = 0;
-          c->nsorts += 1;
-        }
-      }
-      stores[0].ctl->sdone = 0u;
-    }
   }
 }
 
