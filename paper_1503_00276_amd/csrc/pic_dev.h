@@ -83,6 +83,8 @@ struct StoreDesc {
   int* tot;                  // [ntiles][27]
   int* dbase;                // [ntiles][27] slot base inside the destination tile
   int* dcount;               // [ntiles]
+  const int* nsrc;           // [ntiles][27] tile - delta_s (periodic), per instance
+  const int* ndst;           // [ntiles][27] tile + delta_s (periodic), per instance
   StoreCtl* ctl;
 };
 

@@ -16,7 +16,6 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
-#include <unordered_map>
 #include <vector>
 
 #include "../../include/pic.h"
@@ -46,6 +45,8 @@ struct Instance {
   float* Jacc[2] = {nullptr, nullptr};
   unsigned long long* J64[2] = {nullptr, nullptr};
   float* Jout = nullptr;
+  int* nsrc = nullptr;  // neighbour tile tables of the rebin
+  int* ndst = nullptr;
   double wmax[PIC_MAX_SPECIES] = {0, 0, 0, 0, 0, 0, 0, 0};
   double* rho_snap = nullptr;
   bool have_snap = false;
@@ -303,6 +304,8 @@ pic_status alloc_species(Sim& S, Instance& I, Species& sp, int64_t cap, int chun
     d.Jacc[k] = I.Jacc[k];
     d.J64[k] = I.J64[k];
   }
+  d.nsrc = I.nsrc;
+  d.ndst = I.ndst;
   StoreCtl z{};
   HIPCHK(S, hipMemcpy(sp.ctl, &z, sizeof z, hipMemcpyHostToDevice));
   sp.cap = cap;
@@ -590,24 +593,35 @@ pic_status upload_binned(Sim& S, Instance& I, Species& sp, const HostParticles& 
   {
     std::vector<int> pos(toff.begin(), toff.end() - 1);
     for (size_t p = 0; p < n; p++) order[pos[tile[p]]++] = (int)p;  // stable by tile
-    std::vector<long long> key;
-    std::vector<int> tmp;
-    std::unordered_map<int, int> seen;
+    // per tile: rank of each particle within its cell, then a counting sort
+    // by (rank, local cell); local cell indices are < tile volume
+    const int tvol = g.tile[0] * g.tile[1] * g.tile[2];
+    std::vector<int> seen(tvol, 0), lc(0), rk(0), bucket(0);
     for (int t = 0; t < g.ntiles; t++) {
       int a = toff[t], b = toff[t + 1];
       if (b - a < 2) continue;
-      key.resize(b - a);
-      seen.clear();
+      int tc[3];
+      pic_tile_coords(g, t, tc);
+      lc.resize(b - a);
+      rk.resize(b - a);
+      int maxr = 0;
       for (int k = a; k < b; k++) {
-        int cell = h.cell[order[k]];
-        int rank = seen[cell]++;
-        key[k - a] = ((long long)rank << 32) | (unsigned)cell;
+        int c[3];
+        pic_unpack(g, h.cell[order[k]], c);
+        int l0 = c[0] - tc[0] * g.tile[0], l1 = c[1] - tc[1] * g.tile[1];
+        int l2 = g.dim == 3 ? c[2] - tc[2] * g.tile[2] : 0;
+        int li = l0 + g.tile[0] * (l1 + g.tile[1] * l2);
+        lc[k - a] = li;
+        rk[k - a] = seen[li]++;
+        maxr = std::max(maxr, rk[k - a]);
       }
-      tmp.resize(b - a);
-      for (int k = 0; k < b - a; k++) tmp[k] = k;
-      std::stable_sort(tmp.begin(), tmp.end(), [&](int x, int y) { return key[x] < key[y]; });
-      for (int k = 0; k < b - a; k++) slotpos[k] = order[a + tmp[k]];
+      // counting sort by rank (stable keeps the cell order inside a rank)
+      bucket.assign(maxr + 2, 0);
+      for (int k = 0; k < b - a; k++) bucket[rk[k] + 1]++;
+      for (int r = 0; r <= maxr; r++) bucket[r + 1] += bucket[r];
+      for (int k = 0; k < b - a; k++) slotpos[bucket[rk[k]]++] = order[a + k];
       for (int k = 0; k < b - a; k++) order[a + k] = slotpos[k];
+      for (int k = 0; k < b - a; k++) seen[lc[k]] = 0;
     }
   }
   HostParticles o;
@@ -947,12 +961,7 @@ pic_status sim_diag(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_byt
 
 pic_status sim_create(Sim& S, const pic_config* cfgs, int n, void* stream) {
   if (!cfgs || n < 1) return S.fail(PIC_E_INVALID, "no configuration");
-  S.stream = (hipStream_t)stream;
-  if (!S.stream) {
-    // graph capture needs a stream of our own when the caller gives none
-    HIPCHK(S, hipStreamCreateWithFlags(&S.stream, hipStreamNonBlocking));
-    S.own_stream = true;
-  }
+  // everything that can be checked on the host is checked before any HIP call
   int SI = 0;
   for (int i = 0; i < n; i++) {
     pic_status st = validate(S, cfgs[i]);
@@ -960,7 +969,18 @@ pic_status sim_create(Sim& S, const pic_config* cfgs, int n, void* stream) {
     int si = cfgs[i].sort_interval > 0 ? cfgs[i].sort_interval : default_interval(cfgs[i]);
     SI = (i == 0) ? si : std::min(SI, si);
   }
+  for (int i = 0; i < n; i++) {
+    GridDesc g;
+    pic_status st = setup_grid(S, cfgs[i], SI, g);
+    if (st != PIC_OK) return st;
+  }
   S.sort_interval = SI;
+  S.stream = (hipStream_t)stream;
+  if (!S.stream) {
+    // graph capture needs a stream of our own when the caller gives none
+    HIPCHK(S, hipStreamCreateWithFlags(&S.stream, hipStreamNonBlocking));
+    S.own_stream = true;
+  }
   const char* env = getenv("PIC_NO_GRAPH");
   S.use_graph = !(env && env[0] == '1');
   S.inst.resize(n);
@@ -972,6 +992,30 @@ pic_status sim_create(Sim& S, const pic_config* cfgs, int n, void* stream) {
     size_t nc = (size_t)I.g.ncell;
     if (hipMalloc(&I.F, 6 * nc * sizeof(float)) != hipSuccess) return S.fail(PIC_E_NOMEM, "field allocation failed");
     HIPCHK(S, hipMemset(I.F, 0, 6 * nc * sizeof(float)));
+    {
+      // tile t -/+ delta_s for the 27 neighbour slots, periodic in tiles
+      const GridDesc& g = I.g;
+      std::vector<int> ns((size_t)g.ntiles * PIC_NSLOT), nd((size_t)g.ntiles * PIC_NSLOT);
+      for (int t = 0; t < g.ntiles; t++) {
+        int tc[3];
+        pic_tile_coords(g, t, tc);
+        for (int sl = 0; sl < PIC_NSLOT; sl++) {
+          int dd[3] = {sl % 3 - 1, (sl / 3) % 3 - 1, sl / 9 - 1};
+          int a[3], b[3];
+          for (int d = 0; d < 3; d++) {
+            a[d] = pic_wrap(tc[d] - dd[d], g.ntile[d]);
+            b[d] = pic_wrap(tc[d] + dd[d], g.ntile[d]);
+          }
+          ns[(size_t)t * PIC_NSLOT + sl] = pic_tile_index(g, a[0], a[1], a[2]);
+          nd[(size_t)t * PIC_NSLOT + sl] = pic_tile_index(g, b[0], b[1], b[2]);
+        }
+      }
+      if (hipMalloc(&I.nsrc, ns.size() * sizeof(int)) != hipSuccess ||
+          hipMalloc(&I.ndst, nd.size() * sizeof(int)) != hipSuccess)
+        return S.fail(PIC_E_NOMEM, "tile table allocation failed");
+      HIPCHK(S, hipMemcpy(I.nsrc, ns.data(), ns.size() * sizeof(int), hipMemcpyHostToDevice));
+      HIPCHK(S, hipMemcpy(I.ndst, nd.data(), nd.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
     if (hipMalloc(&I.Jout, 3 * nc * sizeof(float)) != hipSuccess) return S.fail(PIC_E_NOMEM, "current allocation failed");
     HIPCHK(S, hipMemset(I.Jout, 0, 3 * nc * sizeof(float)));
     for (int k = 0; k < 2; k++) {
@@ -1020,6 +1064,8 @@ void sim_destroy(Sim& S) {
       if (I.J64[k]) (void)hipFree(I.J64[k]);
     }
     if (I.Jout) (void)hipFree(I.Jout);
+    if (I.nsrc) (void)hipFree(I.nsrc);
+    if (I.ndst) (void)hipFree(I.ndst);
     if (I.rho_snap) (void)hipFree(I.rho_snap);
   }
   if (S.d_stores) (void)hipFree(S.d_stores);

@@ -40,16 +40,6 @@ __device__ __forceinline__ int particle_slot(const GridDesc& g, int t, int cell)
   return pic_slot(dd[0], dd[1], dd[2]);
 }
 
-// Tile reached from tile t by the displacement of slot s (periodic in tiles).
-__device__ __forceinline__ int slot_tile(const GridDesc& g, int t, int s, int sign) {
-  int tc[3];
-  pic_tile_coords(g, t, tc);
-  int dd[3] = {s % 3 - 1, (s / 3) % 3 - 1, s / 9 - 1};
-  int n[3];
-  for (int d = 0; d < 3; d++) n[d] = pic_wrap(tc[d] + sign * dd[d], g.ntile[d]);
-  return pic_tile_index(g, n[0], n[1], n[2]);
-}
-
 // Block-shared prefix over stores of a per-store count (0 for idle stores).
 template <typename F>
 __device__ void group_prefix(const StoreDesc* stores, int nstores, int* pref, F count) {
@@ -91,26 +81,39 @@ __global__ void __launch_bounds__(kScanBlock) rebin_plan(const StoreDesc* __rest
   const int nt = S.g.ntiles;
   const int cur = s_cur;
   const int nxt = 1 - cur;
-  // running slot counts over the items of each source tile
+  // running slot counts over the items of each source tile (27 independent
+  // loads per item, issued together)
   for (int t = threadIdx.x; t < nt; t += blockDim.x) {
     const int i0 = S.ioff[cur][t], i1 = S.ioff[cur][t + 1];
-    for (int sl = 0; sl < PIC_NSLOT; sl++) {
-      int run = 0;
-      for (int i = i0; i < i1; i++) {
-        S.pre[i * PIC_NSLOT + sl] = run;
-        run += S.cnt[i * PIC_NSLOT + sl];
+    int run[PIC_NSLOT];
+#pragma unroll
+    for (int sl = 0; sl < PIC_NSLOT; sl++) run[sl] = 0;
+    for (int i = i0; i < i1; i++) {
+      int c[PIC_NSLOT];
+#pragma unroll
+      for (int sl = 0; sl < PIC_NSLOT; sl++) c[sl] = S.cnt[i * PIC_NSLOT + sl];
+#pragma unroll
+      for (int sl = 0; sl < PIC_NSLOT; sl++) {
+        S.pre[i * PIC_NSLOT + sl] = run[sl];
+        run[sl] += c[sl];
       }
-      S.tot[t * PIC_NSLOT + sl] = run;
     }
+#pragma unroll
+    for (int sl = 0; sl < PIC_NSLOT; sl++) S.tot[t * PIC_NSLOT + sl] = run[sl];
   }
   __syncthreads();
   // incoming particles of each destination tile, in slot order
   for (int d = threadIdx.x; d < nt; d += blockDim.x) {
+    int src[PIC_NSLOT], v[PIC_NSLOT];
+#pragma unroll
+    for (int sl = 0; sl < PIC_NSLOT; sl++) src[sl] = S.nsrc[d * PIC_NSLOT + sl];
+#pragma unroll
+    for (int sl = 0; sl < PIC_NSLOT; sl++) v[sl] = S.tot[src[sl] * PIC_NSLOT + sl];
     int acc = 0;
+#pragma unroll
     for (int sl = 0; sl < PIC_NSLOT; sl++) {
-      int src = slot_tile(S.g, d, sl, -1);
       S.dbase[d * PIC_NSLOT + sl] = acc;
-      acc += S.tot[src * PIC_NSLOT + sl];
+      acc += v[sl];
     }
     S.dcount[d] = acc;
   }
@@ -190,7 +193,7 @@ __global__ void __launch_bounds__(kBlock) rebin_scatter(const StoreDesc* __restr
     const Item it = S.items[cur][ii];
     if (threadIdx.x < PIC_NSLOT) {
       int sl = threadIdx.x;
-      int d = slot_tile(g, it.tile, sl, +1);
+      int d = S.ndst[it.tile * PIC_NSLOT + sl];
       run[sl] = S.toff[nxt][d] + S.dbase[d * PIC_NSLOT + sl] + S.pre[ii * PIC_NSLOT + sl];
     }
     for (int base = it.begin; base < it.end; base += blockDim.x) {

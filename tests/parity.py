@@ -65,3 +65,51 @@ def step_parity(orc, sim, cfg, qm=-1.0):
         "B": rel_max(B1, ref.B),
         "Jmax": np.abs(ref.J).max(),
     }
+
+
+def sampled_step_parity(orc, sim, cfg, nsample, box_lo, box_hi, qm=-1.0, seed=0, margin=4):
+    """Per-step parity at sizes the oracle cannot step whole: positions and
+    momenta of a random sample of particles, and current and fields inside a
+    sub-box (cells box_lo..box_hi, FP64 oracle fed every particle within
+    'margin' cells of it, so the box interior sees all its contributions)."""
+    x0, u0, w0 = sim.state()
+    E0, B0 = sim.fields()
+    g = oracle_grid(orc, cfg)
+    d = cfg.ndim
+    dx = np.asarray(cfg.dx[:d])
+    nxa = np.asarray(cfg.nx[:d])
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(len(w0), size=min(nsample, len(w0)), replace=False)
+    ref_s = orc.step(g, x0[idx], u0[idx], w0[idx], qm, E0, B0)
+    cell = np.floor(x0 / dx).astype(np.int64)
+    lo = np.asarray(box_lo) - margin
+    hi = np.asarray(box_hi) + margin
+    rel = (cell - lo) % nxa
+    inside = np.all(rel < (hi - lo), axis=1)
+    sel = np.nonzero(inside)[0]
+    ref_b = orc.step(g, x0[sel], u0[sel], w0[sel], qm, E0, B0)
+    sim.step(1)
+    x1, u1, _ = sim.state()
+    E1, B1 = sim.fields()
+    J1 = sim.current()
+    ex, eu = compare_state(cfg, x1[idx], u1[idx], ref_s.x, ref_s.u)
+    # interior of the box (the Yee update reaches 2 cells, the deposit 3)
+    grids = np.meshgrid(*[np.arange(a + 2, b - 2) % n for a, b, n in zip(box_lo, box_hi, nxa)], indexing="ij")
+    flat = np.zeros_like(grids[0])
+    mul = 1
+    for k in range(d):
+        flat = flat + grids[k] * mul
+        mul *= int(nxa[k])
+    flat = flat.ravel()
+    Jr = ref_b.J[:, flat]
+    Jg = J1[:, flat]
+    Er, Br = ref_b.E[:, flat], ref_b.B[:, flat]
+    scaleJ = max(np.abs(Jr).max(), np.abs(J1).max())
+    return {
+        "pos": ex,
+        "mom": eu,
+        "J": np.abs(Jg - Jr).max() / scaleJ if scaleJ > 0 else np.abs(Jg).max(),
+        "E": rel_max(E1[:, flat], Er),
+        "B": rel_max(B1[:, flat], Br),
+        "nbox": len(sel),
+    }

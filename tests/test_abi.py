@@ -69,3 +69,51 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(pic, "_lib", None)
     with pytest.raises(ImportError):
         pic.lib()
+
+
+def _create_status(pic, **kw):
+    base = dict(ndim=2, nx=(16, 16), dx=(0.2, 0.2), dt=0.1, shape_order=1)
+    base.update(kw)
+    cfg = pic.Config(**base)
+    L = pic.lib()
+    h = ctypes.c_void_p()
+    c = cfg.c()
+    rc = L.pic_create(ctypes.byref(c), None, ctypes.byref(h))
+    if rc == 0:
+        L.pic_destroy(h)
+    return rc
+
+
+@pytest.mark.parametrize("kw,why", [
+    (dict(ndim=4), "dimension"),
+    (dict(shape_order=4), "shape order"),
+    (dict(shape_order=0), "shape order"),
+    (dict(nx=(0, 16)), "empty axis"),
+    (dict(dx=(-0.2, 0.2)), "negative cell"),
+    (dict(dt=0.15), "Courant: 0.15*sqrt(2)/0.2 > 1"),
+    (dict(dt=0.0), "zero step"),
+    (dict(dt=float("nan")), "nan step"),
+    (dict(capacity=-5), "negative capacity"),
+    (dict(tile=(3, 16)), "tile smaller than slack + 2"),
+    (dict(tile=(16, 13)), "ragged remainder 3 smaller than slack + 2 = 4"),
+    (dict(accumulator=7), "unknown accumulator"),
+    (dict(sort_interval=-1), "negative interval"),
+    (dict(ndim=3, nx=(64, 64, 64), dx=(0.2, 0.2, 0.2), dt=0.1, shape_order=3, tile=(64, 64, 64)),
+     "explicit tile that cannot fit the LDS"),
+])
+def test_invalid_configuration_rejected_on_host(kw, why):
+    """Invalid configurations fail with PIC_E_INVALID before any HIP call,
+    so this runs without a GPU."""
+    pic, _ = _lib()
+    assert _create_status(pic, **kw) == pic.PIC_E_INVALID, why
+
+
+def test_null_arguments_rejected():
+    pic, _ = _lib()
+    L = pic.lib()
+    assert L.pic_create(None, None, None) == pic.PIC_E_INVALID
+    assert L.pic_step(None, 1) == pic.PIC_E_INVALID
+    assert L.pic_diag(None, 0, None, 0, None) == pic.PIC_E_INVALID
+    assert L.pic_destroy(None) == 0
+    assert L.pic_batch_destroy(None) == 0
+    assert L.pic_last_error(None) == b"null context"
