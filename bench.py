@@ -5,9 +5,13 @@ Metric: particle pushes per second (one push = gather + Boris push + advance +
 charge-conserving deposit of one particle), whole step included (the Yee
 field solve and the rebin checks run inside the timed region), inputs already
 resident in HBM.  Workload (default): the 2D3V laser-wakefield case, 1024x256
-cells, 2,097,152 electrons, quadratic shape.  Prints one JSON line.
+cells, 2,097,152 electrons, quadratic shape, with the layout the autotuner
+picks.  A second leg times the batched scan (64 independent 2D thermal
+instances of uneven grids and particle counts advanced by the batched step)
+against the same instances run plain one after another.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload lwfa2d|thermal2d|beam3d|cubic3d]
+                  [--no-batched] [--no-cpu-baseline] [--tune-steps T]
 """
 from __future__ import annotations
 
@@ -58,9 +62,10 @@ def bytes_per_push(wl):
     return particle + 36.0 / ppc
 
 
-def cpu_baseline(wl, max_particles):
-    """Time the FP64 oracle (single thread, as it stands) on one full step of a
-    bounded sample of the workload's particles."""
+def cpu_baseline(wl, max_particles, min_seconds=10.0, max_steps=20):
+    """Time the FP64 oracle (single thread, as it stands) on consecutive full
+    steps of a bounded sample of the workload's particles, until about
+    min_seconds of CPU work."""
     import numpy as np
     import oracle
 
@@ -68,19 +73,123 @@ def cpu_baseline(wl, max_particles):
     g = oracle.Grid(dim=wl.ndim, nx=wl.nx, dx=wl.dx, dt=wl.dt, order=wl.order)
     n = min(wl.n, max_particles)
     idx = np.arange(wl.n) if n == wl.n else np.random.default_rng(0).choice(wl.n, n, replace=False)
+    x, u, w = wl.x[idx], wl.u[idx], wl.w[idx]
     E = wl.E if wl.E is not None else np.zeros((3, wl.ncell))
     B = wl.B if wl.B is not None else np.zeros((3, wl.ncell))
-    t0 = time.perf_counter()
-    oracle.step(g, wl.x[idx], wl.u[idx], wl.w[idx], 1.0 / wl.rqm, E, B)
-    t = time.perf_counter() - t0
+    t = 0.0
+    steps = 0
+    while steps < max_steps and (steps == 0 or t < min_seconds):
+        t0 = time.perf_counter()
+        r = oracle.step(g, x, u, w, 1.0 / wl.rqm, E, B)
+        t += time.perf_counter() - t0
+        x, u, E, B = r.x, r.u, r.E, r.B
+        steps += 1
     what = "all" if n == wl.n else "a random sample of"
     return {
-        "value": n / t,
+        "value": n * steps / t,
         "unit": "particle pushes/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"one FP64 oracle step (gather, push, deposit, field solve) of {what} {n} particles "
-                  f"of the workload, single thread, {t:.1f} s",
+        "sample": f"{steps} consecutive FP64 oracle steps (gather, push, deposit, field solve) of {what} {n} "
+                  f"particles of the workload, single thread, {t:.1f} s",
+    }
+
+
+def algorithmic_bytes(n, ndim, ncell):
+    """Algorithmic HBM bytes of one step's particle kernel for n particles on
+    ncell cells (see bytes_per_push)."""
+    particle = (4 + 4 * ndim + 12 + 4) + (4 + 4 * ndim + 12)
+    return n * particle + 36.0 * ncell
+
+
+def timed_steps(sim, stream, steps):
+    """Seconds for 'steps' steps: max of the wall clock and HIP events on the stream."""
+    import torch
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    sim.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sim.sync()
+    return max(wall, ev0.elapsed_time(ev1) / 1000.0)
+
+
+def run_batched(args, pic, stream):
+    """The batched scan against the same instances run plain one after another,
+    each plain run with the layout the batch's autotuner gave that instance."""
+    from paper_1503_00276_amd import workloads as W
+
+    log(f"batched leg: generating {args.batch_instances} instances")
+    wls = W.workload4(ninst=args.batch_instances, steps=args.batch_steps)
+    cfgs = [pic.Config(ndim=2, nx=wl.nx, dx=wl.dx, dt=wl.dt, shape_order=wl.order, ion_density=wl.ion_density)
+            for wl in wls]
+    ntot = sum(wl.n for wl in wls)
+    batch = pic.PicBatch(cfgs, stream=stream)
+    log(f"batched leg: loading {ntot} particles")
+    for k, wl in enumerate(wls):
+        batch.load_particles(k, wl.x, wl.u, wl.w, rqm=wl.rqm)
+    tune = None
+    if args.tune_steps > 0:
+        log("batched leg: autotune")
+        tune = batch.autotune(trial_steps=args.tune_steps)
+    batch.step(args.warmup)
+    batch.sync()
+    K = args.batch_steps
+    log(f"batched leg: timing {K} steps")
+    t_batch = timed_steps(batch, stream, K)
+    batch.profile(2)
+    batch.step(args.profile_steps)
+    kt = batch.kernel_times()
+    batch.profile(0)
+    batch.sync()
+    gpd_avg_s = kt["particle"][0] / max(kt["particle"][1], 1) / 1000.0
+    infos = [batch.info(k) for k in range(len(wls))]
+    batch.close()
+    abytes = sum(algorithmic_bytes(wl.n, 2, wl.ncell) for wl in wls)
+
+    log("batched leg: the same instances plain, one after another")
+    t_plain = 0.0
+    for k, wl in enumerate(wls):
+        inf = infos[k]
+        cfg = pic.Config(ndim=2, nx=wl.nx, dx=wl.dx, dt=wl.dt, shape_order=wl.order, ion_density=wl.ion_density,
+                         tile=tuple(inf.tile), sort_interval=inf.sort_interval, chunk=inf.chunk)
+        sim = pic.Pic(cfg, stream=stream)
+        sim.load_particles(wl.x, wl.u, wl.w, rqm=wl.rqm)
+        sim.step(args.warmup)
+        sim.sync()
+        t_plain += timed_steps(sim, stream, K)
+        sim.close()
+    v_batch = ntot * K / t_batch
+    v_plain = ntot * K / t_plain
+    return {
+        "workload": f"2d3v_thermal_scan_{len(wls)}_instances",
+        "instances": len(wls),
+        "particles": ntot,
+        "steps": K,
+        "value": v_batch,
+        "unit": "particle pushes/s",
+        "ms_per_step": t_batch * 1000.0 / K,
+        "plain_value": v_plain,
+        "plain_ms_per_step": t_plain * 1000.0 / K,
+        "batched_over_plain": v_batch / v_plain,
+        "autotune": tune,
+        "sort_interval": int(infos[0].sort_interval),
+        "roofline": {
+            "bound": "hbm",
+            "achieved": abytes / gpd_avg_s / 1e9,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": abytes / gpd_avg_s / 1e9 / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": "gpd_kernel, all instances in one launch per shape order",
+            "kernel_avg_us": gpd_avg_s * 1e6,
+            "kernel_pushes_per_s": ntot / gpd_avg_s,
+        },
     }
 
 
@@ -93,6 +202,14 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2_097_152)
+    ap.add_argument("--tune-steps", type=int, default=10,
+                    help="steps the autotuner times per candidate layout (0: no autotune)")
+    ap.add_argument("--tile", type=int, nargs="+", default=None, help="tile extents (default: automatic)")
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--sort-interval", type=int, default=0)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-instances", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -113,12 +230,17 @@ def main():
     log(f"generating workload {args.workload}")
     wl = make_workload(args.workload)
     cfg = pic.Config(ndim=wl.ndim, nx=wl.nx, dx=wl.dx, dt=wl.dt, shape_order=wl.order,
-                     ion_density=wl.ion_density)
+                     ion_density=wl.ion_density, tile=tuple((args.tile or []) + [0] * (3 - len(args.tile or []))),
+                     chunk=args.chunk, sort_interval=args.sort_interval)
     sim = pic.Pic(cfg, stream=stream)
     log(f"loading {wl.n} particles")
     sim.load_particles(wl.x, wl.u, wl.w, rqm=wl.rqm)
     if wl.E is not None:
         sim.load_fields(wl.E, wl.B)
+    tune = None
+    if args.tune_steps > 0:
+        log("autotune")
+        tune = sim.autotune(trial_steps=args.tune_steps)
     info = sim.info()
 
     log(f"warmup {args.warmup} steps")
@@ -126,18 +248,7 @@ def main():
     sim.sync()
 
     log(f"timing {args.steps} steps")
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    sim.step(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    sim.sync()
-    elapsed = max(wall, gpu_ms / 1000.0)
+    elapsed = timed_steps(sim, stream, args.steps)
     value = wl.n * args.steps / elapsed
 
     # per-kernel times: the same steps launched one by one with HIP events
@@ -162,13 +273,18 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    sim.close()
+    batched = None
+    if not args.no_batched:
+        batched = run_batched(args, pic, stream)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
         cpu = cpu_baseline(wl, args.cpu_sample)
 
     out = {
-        "metric": "particle pushes/sec (gather+push+deposit), whole step, 1 GPU",
+        "metric": "particle pushes/sec (gather+push+deposit) and % HBM roofline, plain vs batched, 1 GPU",
         "value": value,
         "unit": "particle pushes/s",
         "n_gpus": 1,
@@ -189,7 +305,9 @@ def main():
             "dx": list(wl.dx),
             "tile": list(info.tile)[:wl.ndim],
             "sort_interval": info.sort_interval,
+            "chunk": info.chunk,
             "slack": info.slack,
+            "autotune": tune,
             "rebins_done": int(counts[2]),
             "rebin_checks": int(counts[3]),
         },
@@ -206,10 +324,10 @@ def main():
             "kernel_pushes_per_s": wl.n / gpd_avg_s,
         },
         "kernel_times_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in kt.items()},
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    sim.close()
 
 
 if __name__ == "__main__":

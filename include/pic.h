@@ -93,9 +93,12 @@ typedef struct {
   double ion_density;    /* immobile neutralising background charge density,
                             used only by the rho and Gauss diagnostics */
   int64_t capacity;      /* maximum particles per species (num_par_max) */
-  int32_t tile[3];       /* tile extent in cells; 0 = choose automatically */
-  int32_t sort_interval; /* steps between rebin checks; 0 = choose automatically */
-  int32_t chunk;         /* maximum particles one workgroup takes from a tile; 0 = auto */
+  int32_t tile[3];       /* tile extent in cells; 0 = a default from the grid
+                            (pic_autotune searches it by measurement) */
+  int32_t sort_interval; /* steps between rebin checks; 0 = a default from the
+                            Courant number (searched by pic_autotune) */
+  int32_t chunk;         /* maximum particles one workgroup takes from a tile;
+                            0 = 2048 (searched by pic_autotune) */
   int32_t accumulator;   /* PIC_ACC_* */
 } pic_config;
 
@@ -188,6 +191,47 @@ typedef struct {
 
 pic_status pic_get_info(const pic_ctx* ctx, pic_info* out);
 
+/* Autotuner: a measured search of the launch layout on the loaded state.
+ * Three parameters are searched one after the other, each time keeping the
+ * best so far:
+ *   particles per tile -- every instance's tile shape is re-derived from a
+ *                         target number of particles per tile (its mean
+ *                         particles per cell), among the tile extents valid
+ *                         for its grid and sort interval and whose fused
+ *                         kernel fits the LDS;
+ *   sort_interval      -- steps between rebin checks (a longer interval
+ *                         widens the slack each tile stages);
+ *   chunk              -- maximum particles one workgroup takes from a tile
+ *                         (512, 1024 or 2048: larger chunks leave a tile
+ *                         whose density later grows several-fold as one
+ *                         long work item).
+ * Each candidate re-bins the particles, runs two warm-up rebin cycles and
+ * times trial_steps steps (rounded up to whole cycles) with HIP events on
+ * the context's stream, with a rebin at every check (the steady state of a
+ * plasma whose particles cross tiles, which the loaded state may not have
+ * reached yet).  The state is restored before every candidate and
+ * after the search: particles (in load order), fields, the last current and
+ * the step count are exactly those before the call; only the layout (tile,
+ * sort interval, chunk, order of particles inside a tile) changes, and the
+ * rebin counters of PIC_DIAG_COUNTS restart.  Synchronous.  Fails with
+ * PIC_E_STATE when no particles are loaded, PIC_E_INVALID on bad arguments. */
+typedef struct {
+  int32_t trial_steps;        /* in: steps timed per candidate, >= 1 */
+  int32_t what;               /* in: PIC_TUNE_* bits, 0 = all three */
+  int32_t candidates;         /* out: layouts timed, the starting one included */
+  int32_t particles_per_tile; /* out: target chosen (0: the starting tiles kept) */
+  int32_t sort_interval;      /* out */
+  int32_t chunk;              /* out */
+  double ms_before;           /* out: ms per step of the starting layout */
+  double ms_after;            /* out: ms per step of the chosen layout */
+} pic_tune;
+
+#define PIC_TUNE_TILE 1
+#define PIC_TUNE_SORT 2
+#define PIC_TUNE_CHUNK 4
+
+pic_status pic_autotune(pic_ctx* ctx, pic_tune* io);
+
 /* Message of the last failure on ctx (never NULL; "" when none). */
 const char* pic_last_error(const pic_ctx* ctx);
 
@@ -211,6 +255,11 @@ pic_status pic_batch_diag(pic_batch* b, int32_t inst, pic_diag_kind kind, void* 
                           size_t out_bytes, size_t* written);
 pic_status pic_batch_sync(pic_batch* b);
 pic_status pic_batch_profile(pic_batch* b, int32_t enable);
+pic_status pic_batch_get_info(const pic_batch* b, int32_t inst, pic_info* out);
+/* The autotuner over all instances of a batch at once: one particles-per-
+ * tile target (each instance derives its own tile shape from it), one sort
+ * interval and one chunk for the whole batch, timed on the batched step. */
+pic_status pic_batch_autotune(pic_batch* b, pic_tune* io);
 const char* pic_batch_last_error(const pic_batch* b);
 
 #ifdef __cplusplus

@@ -7,6 +7,7 @@
 
 #define PIC_MAX_SPECIES 8
 #define PIC_NSLOT 27  // neighbour slots (-1,0,+1)^3 for the rebin
+#define PIC_REBIN_TILES 256  // destination tiles per workgroup of the rebin planner
 
 // One periodic box: grid, time step, shape order and tiling.
 struct GridDesc {
@@ -38,9 +39,9 @@ struct GridDesc {
 };
 
 // Control words of one particle store.  The buffer set holding the particles
-// is cur ^ pending: the rebin planner (one workgroup, so no atomics are
-// needed) folds pending into cur when it next runs, and sets pending when it
-// plans a rebin whose scatter fills the other set.
+// is cur ^ pending: the rebin's fold kernel (one workgroup per store, so no
+// atomics are needed) folds pending into cur when it next runs, and sets
+// pending when it plans a rebin whose scatter fills the other set.
 struct StoreCtl {
   int cur;          // buffer set, before the pending flip
   int pending;      // 1: the other set is current (a scatter filled it)
@@ -50,7 +51,8 @@ struct StoreCtl {
   int bad;          // a particle was found outside its staged region (skipped)
   int nsorts;       // rebins performed
   int nchecks;      // rebin checks performed
-  int pad[3];
+  int force;        // set by the host: rebin at every check (autotuner trials)
+  int pad[2];
 };
 
 __host__ __device__ inline int pic_cur(const StoreCtl& c) { return c.cur ^ c.pending; }
@@ -83,6 +85,9 @@ struct StoreDesc {
   int* tot;                  // [ntiles][27]
   int* dbase;                // [ntiles][27] slot base inside the destination tile
   int* dcount;               // [ntiles]
+  int* bsum;                 // [nblk][2] particles and items of each block of kRebinTiles tiles
+  int* bpre;                 // [nblk][2] their exclusive prefix
+  int tile0, blk0;           // first tile and tile block of this store within its launch group
   const int* nsrc;           // [ntiles][27] tile - delta_s (periodic), per instance
   const int* ndst;           // [ntiles][27] tile + delta_s (periodic), per instance
   StoreCtl* ctl;

@@ -20,8 +20,8 @@ hipError_t pic_launch_yee_step(const InstDesc* d_inst, int ninst, int max_tiles,
                                hipStream_t st);
 
 // tile rebin (sort.hip); stores in d_stores[0..nstores)
-hipError_t pic_launch_rebin(const StoreDesc* d_stores, int nstores, int max_items, int max_tiles,
-                            hipStream_t st);
+hipError_t pic_launch_rebin(const StoreDesc* d_stores, int nstores, int max_items, int total_tiles,
+                            int total_blocks, hipStream_t st);
 
 // diagnostics (diag.hip)
 hipError_t pic_launch_rho64(const StoreDesc* d_store, int np_max, double* rho, hipStream_t st);

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -55,7 +57,7 @@ struct Instance {
 };
 
 struct Group {
-  int dim, order, first, count, max_ncell, max_items, max_tiles;
+  int dim, order, first, count, max_ncell, max_items, max_tiles, max_blocks;
   size_t lds;
   bool fixed64;
 };
@@ -296,6 +298,8 @@ pic_status alloc_species(Sim& S, Instance& I, Species& sp, int64_t cap, int chun
   AL(d.tot, (size_t)g.ntiles * PIC_NSLOT);
   AL(d.dbase, (size_t)g.ntiles * PIC_NSLOT);
   AL(d.dcount, g.ntiles);
+  AL(d.bsum, (size_t)2 * ((g.ntiles + PIC_REBIN_TILES - 1) / PIC_REBIN_TILES));
+  AL(d.bpre, (size_t)2 * ((g.ntiles + PIC_REBIN_TILES - 1) / PIC_REBIN_TILES));
   AL(sp.ctl, 1);
 #undef AL
   d.ctl = sp.ctl;
@@ -323,7 +327,7 @@ pic_status refresh_descriptors(Sim& S) {
   S.igroups.clear();
   for (int dim = 2; dim <= 3; dim++)
     for (int order = 1; order <= 3; order++) {
-      Group gr{dim, order, (int)stores.size(), 0, 0, 0, 0, 0, false};
+      Group gr{dim, order, (int)stores.size(), 0, 0, 0, 0, 0, 0, false};
       for (size_t i = 0; i < S.inst.size(); i++) {
         Instance& I = S.inst[i];
         if (I.g.dim != dim || I.g.order != order) continue;
@@ -331,12 +335,15 @@ pic_status refresh_descriptors(Sim& S) {
           Species& sp = I.sp[s];
           if (!sp.used || sp.np == 0) continue;
           sp.desc.np = (int)sp.np;
+          sp.desc.tile0 = gr.max_tiles;
+          sp.desc.blk0 = gr.max_blocks;
           stores.push_back(sp.desc);
           S.store_inst.push_back((int)i);
           S.store_species.push_back(s);
           gr.count++;
           gr.max_items += sp.max_items;
           gr.max_tiles += I.g.ntiles;
+          gr.max_blocks += (I.g.ntiles + PIC_REBIN_TILES - 1) / PIC_REBIN_TILES;
           gr.lds = std::max(gr.lds, pic_gpd_lds_bytes(I.g));
         }
       }
@@ -348,7 +355,7 @@ pic_status refresh_descriptors(Sim& S) {
     }
   std::vector<InstDesc> insts;
   for (int dim = 2; dim <= 3; dim++) {
-    Group gr{dim, 0, (int)insts.size(), 0, 0, 0, 0, 0, false};
+    Group gr{dim, 0, (int)insts.size(), 0, 0, 0, 0, 0, 0, false};
     for (size_t i = 0; i < S.inst.size(); i++) {
       Instance& I = S.inst[i];
       if (I.g.dim != dim) continue;
@@ -470,7 +477,8 @@ pic_status launch_steps(Sim& S, int64_t first, int nsteps, bool end_with_check) 
     if (end_with_check && k == nsteps - 1) {
       e0 = prof_begin(S);
       for (const Group& gr : S.sgroups)
-        HIPCHK(S, pic_launch_rebin(S.d_stores + gr.first, gr.count, gr.max_items, gr.max_tiles, S.stream));
+        HIPCHK(S, pic_launch_rebin(S.d_stores + gr.first, gr.count, gr.max_items, gr.max_tiles, gr.max_blocks,
+                                   S.stream));
       prof_end(S, 2, e0);
     }
   }
@@ -572,9 +580,18 @@ pic_status read_back(Sim& S, Species& sp, int dim, HostParticles& h) {
   return PIC_OK;
 }
 
-// Bin host particles by tile (stable) and upload them as buffer set 0.
-pic_status upload_binned(Sim& S, Instance& I, Species& sp, const HostParticles& h) {
-  const GridDesc& g = I.g;
+// Particles binned by tile on the host, ready for upload as buffer set 0.
+struct Binned {
+  HostParticles o;
+  std::vector<int> toff, ioff;
+  std::vector<Item> items;
+};
+
+// Stable bin by tile; inside a tile the k-th particle of every cell, cell by
+// cell, for k = 0, 1, ... (neighbouring lanes of a wavefront then sit in
+// different cells and their current deposits hit different LDS addresses).
+// Work items of at most 'chunk' particles per tile.  Pure host code.
+void bin_particles(const GridDesc& g, int chunk, const HostParticles& h, Binned& B) {
   const size_t n = h.cell.size();
   std::vector<int> tile(n), count(g.ntiles + 1, 0);
   for (size_t p = 0; p < n; p++) {
@@ -584,19 +601,17 @@ pic_status upload_binned(Sim& S, Instance& I, Species& sp, const HostParticles& 
     tile[p] = t;
     count[t + 1]++;
   }
-  std::vector<int> toff(g.ntiles + 1, 0);
+  std::vector<int>& toff = B.toff;
+  toff.assign(g.ntiles + 1, 0);
   for (int t = 0; t < g.ntiles; t++) toff[t + 1] = toff[t] + count[t + 1];
-  // order inside a tile: the k-th particle of every cell, cell by cell, for
-  // k = 0, 1, ...; neighbouring lanes of a wavefront then sit in different
-  // cells and their current deposits hit different LDS addresses
   std::vector<int> order(n), slotpos(n);
   {
     std::vector<int> pos(toff.begin(), toff.end() - 1);
     for (size_t p = 0; p < n; p++) order[pos[tile[p]]++] = (int)p;  // stable by tile
     // per tile: rank of each particle within its cell, then a counting sort
-    // by (rank, local cell); local cell indices are < tile volume
+    // by rank (stable, so cells keep their order inside a rank)
     const int tvol = g.tile[0] * g.tile[1] * g.tile[2];
-    std::vector<int> seen(tvol, 0), lc(0), rk(0), bucket(0);
+    std::vector<int> seen(tvol, 0), lc, rk, bucket;
     for (int t = 0; t < g.ntiles; t++) {
       int a = toff[t], b = toff[t + 1];
       if (b - a < 2) continue;
@@ -615,7 +630,6 @@ pic_status upload_binned(Sim& S, Instance& I, Species& sp, const HostParticles& 
         rk[k - a] = seen[li]++;
         maxr = std::max(maxr, rk[k - a]);
       }
-      // counting sort by rank (stable keeps the cell order inside a rank)
       bucket.assign(maxr + 2, 0);
       for (int k = 0; k < b - a; k++) bucket[rk[k] + 1]++;
       for (int r = 0; r <= maxr; r++) bucket[r + 1] += bucket[r];
@@ -624,7 +638,7 @@ pic_status upload_binned(Sim& S, Instance& I, Species& sp, const HostParticles& 
       for (int k = 0; k < b - a; k++) seen[lc[k]] = 0;
     }
   }
-  HostParticles o;
+  HostParticles& o = B.o;
   o.resize(n);
   for (size_t q = 0; q < n; q++) {
     size_t p = (size_t)order[q];
@@ -636,27 +650,34 @@ pic_status upload_binned(Sim& S, Instance& I, Species& sp, const HostParticles& 
     }
     o.w[q] = h.w[p];
   }
-  const int chunk = sp.desc.chunk;
-  std::vector<int> ioff(g.ntiles + 1, 0);
-  std::vector<Item> items;
+  B.ioff.assign(g.ntiles + 1, 0);
+  B.items.clear();
   for (int t = 0; t < g.ntiles; t++) {
     int c = toff[t + 1] - toff[t];
-    ioff[t] = (int)items.size();
-    for (int b = 0; b < c; b += chunk) items.push_back(Item{t, toff[t] + b, toff[t] + std::min(c, b + chunk), 0});
+    B.ioff[t] = (int)B.items.size();
+    for (int b = 0; b < c; b += chunk) B.items.push_back(Item{t, toff[t] + b, toff[t] + std::min(c, b + chunk), 0});
   }
-  ioff[g.ntiles] = (int)items.size();
-  if ((int)items.size() > sp.max_items) return S.fail(PIC_E_NOMEM, "work item list overflow");
+  B.ioff[g.ntiles] = (int)B.items.size();
+}
+
+// Upload binned particles as buffer set 0 and reset the store's control block.
+pic_status upload_bins(Sim& S, Species& sp, const Binned& B) {
+  const HostParticles& o = B.o;
+  const size_t n = o.cell.size();
+  const int dim = sp.desc.g.dim;
+  if ((int)B.items.size() > sp.max_items) return S.fail(PIC_E_NOMEM, "work item list overflow");
   const StoreDesc& d = sp.desc;
   if (n > 0) {
     HIPCHK(S, hipMemcpy(d.cell[0], o.cell.data(), n * 4, hipMemcpyHostToDevice));
     HIPCHK(S, hipMemcpy(d.id[0], o.id.data(), n * 4, hipMemcpyHostToDevice));
-    for (int k = 0; k < g.dim; k++) HIPCHK(S, hipMemcpy(d.eps[0][k], o.eps[k].data(), n * 4, hipMemcpyHostToDevice));
+    for (int k = 0; k < dim; k++) HIPCHK(S, hipMemcpy(d.eps[0][k], o.eps[k].data(), n * 4, hipMemcpyHostToDevice));
     for (int k = 0; k < 3; k++) HIPCHK(S, hipMemcpy(d.u[0][k], o.u[k].data(), n * 4, hipMemcpyHostToDevice));
     HIPCHK(S, hipMemcpy(d.w[0], o.w.data(), n * 4, hipMemcpyHostToDevice));
   }
-  HIPCHK(S, hipMemcpy(d.toff[0], toff.data(), toff.size() * 4, hipMemcpyHostToDevice));
-  HIPCHK(S, hipMemcpy(d.ioff[0], ioff.data(), ioff.size() * 4, hipMemcpyHostToDevice));
-  if (!items.empty()) HIPCHK(S, hipMemcpy(d.items[0], items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
+  HIPCHK(S, hipMemcpy(d.toff[0], B.toff.data(), B.toff.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(S, hipMemcpy(d.ioff[0], B.ioff.data(), B.ioff.size() * 4, hipMemcpyHostToDevice));
+  if (!B.items.empty())
+    HIPCHK(S, hipMemcpy(d.items[0], B.items.data(), B.items.size() * sizeof(Item), hipMemcpyHostToDevice));
   StoreCtl c{};
   HIPCHK(S, hipMemcpy(&c, sp.ctl, sizeof c, hipMemcpyDeviceToHost));
   c.cur = 0;
@@ -664,13 +685,33 @@ pic_status upload_binned(Sim& S, Instance& I, Species& sp, const HostParticles& 
   c.flag = 0;
   c.active = 0;
   c.bad = 0;
-  c.n_items[0] = (int)items.size();
+  c.n_items[0] = (int)B.items.size();
   c.n_items[1] = 0;
   HIPCHK(S, hipMemcpy(sp.ctl, &c, sizeof c, hipMemcpyHostToDevice));
   sp.np = (int64_t)n;
   sp.desc.np = (int)n;
   S.dirty = true;
   return PIC_OK;
+}
+
+pic_status upload_binned(Sim& S, Instance& I, Species& sp, const HostParticles& h) {
+  Binned B;
+  bin_particles(I.g, sp.desc.chunk, h, B);
+  return upload_bins(S, sp, B);
+}
+
+// Run f(0..n-1) on up to 16 host threads.
+template <class F>
+void parallel_for(int n, F f) {
+  unsigned hc = std::thread::hardware_concurrency();
+  int nt = std::max(1, std::min(n, (int)std::min(16u, hc ? hc : 1u)));
+  std::atomic<int> next{0};
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; t++)
+    th.emplace_back([&]() {
+      for (int i; (i = next.fetch_add(1)) < n;) f(i);
+    });
+  for (auto& x : th) x.join();
 }
 
 pic_status copy_in(Sim& S, std::vector<double>& dst, const double* src, size_t n, uint32_t flags) {
@@ -959,6 +1000,36 @@ pic_status sim_diag(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_byt
   return S.fail(PIC_E_INVALID, "unknown diagnostic kind %d", (int)kind);
 }
 
+// Neighbour tile tables of the rebin: tile t -/+ delta_s for the 27 slots,
+// periodic in tiles.
+pic_status build_tables(Sim& S, Instance& I) {
+  const GridDesc& g = I.g;
+  std::vector<int> ns((size_t)g.ntiles * PIC_NSLOT), nd((size_t)g.ntiles * PIC_NSLOT);
+  for (int t = 0; t < g.ntiles; t++) {
+    int tc[3];
+    pic_tile_coords(g, t, tc);
+    for (int sl = 0; sl < PIC_NSLOT; sl++) {
+      int dd[3] = {sl % 3 - 1, (sl / 3) % 3 - 1, sl / 9 - 1};
+      int a[3], b[3];
+      for (int d = 0; d < 3; d++) {
+        a[d] = pic_wrap(tc[d] - dd[d], g.ntile[d]);
+        b[d] = pic_wrap(tc[d] + dd[d], g.ntile[d]);
+      }
+      ns[(size_t)t * PIC_NSLOT + sl] = pic_tile_index(g, a[0], a[1], a[2]);
+      nd[(size_t)t * PIC_NSLOT + sl] = pic_tile_index(g, b[0], b[1], b[2]);
+    }
+  }
+  if (I.nsrc) (void)hipFree(I.nsrc);
+  if (I.ndst) (void)hipFree(I.ndst);
+  I.nsrc = I.ndst = nullptr;
+  if (hipMalloc(&I.nsrc, ns.size() * sizeof(int)) != hipSuccess ||
+      hipMalloc(&I.ndst, nd.size() * sizeof(int)) != hipSuccess)
+    return S.fail(PIC_E_NOMEM, "tile table allocation failed");
+  HIPCHK(S, hipMemcpy(I.nsrc, ns.data(), ns.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(S, hipMemcpy(I.ndst, nd.data(), nd.size() * sizeof(int), hipMemcpyHostToDevice));
+  return PIC_OK;
+}
+
 pic_status sim_create(Sim& S, const pic_config* cfgs, int n, void* stream) {
   if (!cfgs || n < 1) return S.fail(PIC_E_INVALID, "no configuration");
   // everything that can be checked on the host is checked before any HIP call
@@ -992,30 +1063,7 @@ pic_status sim_create(Sim& S, const pic_config* cfgs, int n, void* stream) {
     size_t nc = (size_t)I.g.ncell;
     if (hipMalloc(&I.F, 6 * nc * sizeof(float)) != hipSuccess) return S.fail(PIC_E_NOMEM, "field allocation failed");
     HIPCHK(S, hipMemset(I.F, 0, 6 * nc * sizeof(float)));
-    {
-      // tile t -/+ delta_s for the 27 neighbour slots, periodic in tiles
-      const GridDesc& g = I.g;
-      std::vector<int> ns((size_t)g.ntiles * PIC_NSLOT), nd((size_t)g.ntiles * PIC_NSLOT);
-      for (int t = 0; t < g.ntiles; t++) {
-        int tc[3];
-        pic_tile_coords(g, t, tc);
-        for (int sl = 0; sl < PIC_NSLOT; sl++) {
-          int dd[3] = {sl % 3 - 1, (sl / 3) % 3 - 1, sl / 9 - 1};
-          int a[3], b[3];
-          for (int d = 0; d < 3; d++) {
-            a[d] = pic_wrap(tc[d] - dd[d], g.ntile[d]);
-            b[d] = pic_wrap(tc[d] + dd[d], g.ntile[d]);
-          }
-          ns[(size_t)t * PIC_NSLOT + sl] = pic_tile_index(g, a[0], a[1], a[2]);
-          nd[(size_t)t * PIC_NSLOT + sl] = pic_tile_index(g, b[0], b[1], b[2]);
-        }
-      }
-      if (hipMalloc(&I.nsrc, ns.size() * sizeof(int)) != hipSuccess ||
-          hipMalloc(&I.ndst, nd.size() * sizeof(int)) != hipSuccess)
-        return S.fail(PIC_E_NOMEM, "tile table allocation failed");
-      HIPCHK(S, hipMemcpy(I.nsrc, ns.data(), ns.size() * sizeof(int), hipMemcpyHostToDevice));
-      HIPCHK(S, hipMemcpy(I.ndst, nd.data(), nd.size() * sizeof(int), hipMemcpyHostToDevice));
-    }
+    if ((st = build_tables(S, I)) != PIC_OK) return st;
     if (hipMalloc(&I.Jout, 3 * nc * sizeof(float)) != hipSuccess) return S.fail(PIC_E_NOMEM, "current allocation failed");
     HIPCHK(S, hipMemset(I.Jout, 0, 3 * nc * sizeof(float)));
     for (int k = 0; k < 2; k++) {
@@ -1095,6 +1143,330 @@ pic_status sim_info(const Sim& S, int i, pic_info* out) {
   return PIC_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+
+// Launch layout of a whole Sim: a particles-per-tile target (0 = keep the
+// tiles in use), the sort interval and the chunk.
+struct Layout {
+  int ppt = 0, si = 1, chunk = 2048;
+};
+
+// The state an autotune restores before every candidate and at the end.
+struct Snapshot {
+  std::vector<std::vector<HostParticles>> parts;  // [instance][species]
+  std::vector<float*> F, Jout;                     // device copies
+  int64_t steps = 0;
+  ~Snapshot() {
+    for (float* p : F) (void)hipFree(p);
+    for (float* p : Jout) (void)hipFree(p);
+  }
+};
+
+int64_t instance_particles(const Instance& I) {
+  int64_t n = 0;
+  for (const Species& sp : I.sp)
+    if (sp.used) n += sp.np;
+  return n;
+}
+
+// Tile extents worth trying along an axis of n cells.
+std::vector<int> tile_ladder(int n, int need) {
+  static const int L[] = {2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32, 40, 48, 64, 96, 128, 192, 256, 384, 512};
+  std::vector<int> v;
+  for (int t : L)
+    if (t < n && tile_ok(n, t, need)) v.push_back(t);
+  v.push_back(n);
+  return v;
+}
+
+// Tile shape whose volume is closest (in log) to 'cells', preferring x-long
+// tiles (contiguous field rows) and an LDS footprint that leaves room for two
+// workgroups per CU; g carries the slack of the sort interval in question.
+void tile_for_cells(const GridDesc& g0, double cells, int out[3]) {
+  GridDesc g = g0;
+  const int need = g.slack + 2;
+  std::vector<int> lad[3];
+  for (int d = 0; d < 3; d++) lad[d] = d < g.dim ? tile_ladder(g.nx[d], need) : std::vector<int>{1};
+  double best = 1e300;
+  out[0] = g0.tile[0];
+  out[1] = g0.tile[1];
+  out[2] = g0.tile[2];
+  for (int pass = 0; pass < 2 && best == 1e300; pass++) {
+    const size_t lim = pass == 0 ? (size_t)kLdsMax / 2 : (size_t)kLdsMax;
+    for (int a : lad[0])
+      for (int b : lad[1])
+        for (int c : lad[2]) {
+          g.tile[0] = a;
+          g.tile[1] = b;
+          g.tile[2] = c;
+          if (pic_gpd_lds_bytes(g) > lim) continue;
+          double vol = (double)a * b * c;
+          double sc = std::fabs(std::log2(vol / cells)) + 0.25 * std::fabs(std::log2((double)a / (2.0 * b)));
+          if (g.dim == 3) sc += 0.25 * std::fabs(std::log2((double)b / c));
+          if (sc < best) {
+            best = sc;
+            out[0] = a;
+            out[1] = b;
+            out[2] = c;
+          }
+        }
+  }
+}
+
+// Per-instance configurations of a layout (tile extents resolved).
+pic_status layout_configs(Sim& S, const Layout& L, std::vector<pic_config>& out) {
+  out.resize(S.inst.size());
+  for (size_t i = 0; i < S.inst.size(); i++) {
+    const Instance& I = S.inst[i];
+    pic_config c = I.cfg;
+    c.sort_interval = L.si;
+    c.chunk = L.chunk;
+    for (int d = 0; d < 3; d++) c.tile[d] = d < c.ndim ? I.g.tile[d] : 0;
+    if (L.ppt > 0) {
+      pic_config probe = c;
+      for (int d = 0; d < 3; d++) probe.tile[d] = 0;
+      GridDesc g;
+      pic_status st = setup_grid(S, probe, L.si, g);
+      if (st != PIC_OK) return st;
+      int64_t n = instance_particles(I);
+      double ppc = n > 0 ? (double)n / (double)g.ncell : 1.0;
+      int t[3];
+      tile_for_cells(g, std::max(1.0, L.ppt / ppc), t);
+      for (int d = 0; d < 3; d++) c.tile[d] = d < c.ndim ? t[d] : 0;
+    }
+    GridDesc g;
+    pic_status st = setup_grid(S, c, L.si, g);
+    if (st != PIC_OK) return st;
+    out[i] = c;
+  }
+  return PIC_OK;
+}
+
+// Install a layout and reload the snapshot into it (host binning of all
+// instances and species in parallel, then the uploads).
+pic_status apply_layout(Sim& S, const std::vector<pic_config>& cfgs, int si, const Snapshot& snap) {
+  HIPCHK(S, hipStreamSynchronize(S.stream));
+  pic_status st;
+  const int ni = (int)S.inst.size();
+  std::vector<GridDesc> gs(ni);
+  for (int i = 0; i < ni; i++)
+    if ((st = setup_grid(S, cfgs[i], si, gs[i])) != PIC_OK) return st;
+  std::vector<Binned> bins((size_t)ni * PIC_MAX_SPECIES);
+  parallel_for(ni * PIC_MAX_SPECIES, [&](int k) {
+    const int i = k / PIC_MAX_SPECIES, s = k % PIC_MAX_SPECIES;
+    if (S.inst[i].sp[s].used) bin_particles(gs[i], cfgs[i].chunk, snap.parts[i][s], bins[k]);
+  });
+  for (int i = 0; i < ni; i++) {
+    Instance& I = S.inst[i];
+    I.cfg.sort_interval = cfgs[i].sort_interval;
+    I.cfg.chunk = cfgs[i].chunk;
+    for (int d = 0; d < 3; d++) I.cfg.tile[d] = cfgs[i].tile[d];
+    I.g = gs[i];
+    if ((st = build_tables(S, I)) != PIC_OK) return st;
+    for (int s = 0; s < PIC_MAX_SPECIES; s++) {
+      Species& sp = I.sp[s];
+      if (!sp.used) continue;
+      int64_t cap = std::max<int64_t>(sp.cap, 1);
+      if ((st = alloc_species(S, I, sp, cap, cfgs[i].chunk)) != PIC_OK) return st;
+      sp.desc.qm = (float)(1.0 / sp.rqm);
+    }
+    set_current_scale(I);
+    for (int s = 0; s < PIC_MAX_SPECIES; s++) {
+      Species& sp = I.sp[s];
+      if (!sp.used) continue;
+      Binned& B = bins[(size_t)i * PIC_MAX_SPECIES + s];
+      if ((st = upload_bins(S, sp, B)) != PIC_OK) return st;
+      B = Binned();
+    }
+    const size_t nc = (size_t)I.g.ncell;
+    HIPCHK(S, hipMemcpy(I.F, snap.F[i], 6 * nc * sizeof(float), hipMemcpyDeviceToDevice));
+    HIPCHK(S, hipMemcpy(I.Jout, snap.Jout[i], 3 * nc * sizeof(float), hipMemcpyDeviceToDevice));
+    for (int k = 0; k < 2; k++) {
+      if (I.J64[k]) HIPCHK(S, hipMemset(I.J64[k], 0, 3 * nc * sizeof(unsigned long long)));
+      if (I.Jacc[k]) HIPCHK(S, hipMemset(I.Jacc[k], 0, 3 * nc * sizeof(float)));
+    }
+  }
+  S.sort_interval = si;
+  S.steps = snap.steps;
+  for (Instance& I : S.inst) I.steps = snap.steps;
+  S.dirty = true;
+  return refresh_descriptors(S);
+}
+
+// Set or clear the host's rebin-at-every-check request on every store.
+pic_status set_force(Sim& S, int v) {
+  HIPCHK(S, hipStreamSynchronize(S.stream));
+  for (Instance& I : S.inst)
+    for (Species& sp : I.sp)
+      if (sp.used && sp.ctl) HIPCHK(S, hipMemcpy(&sp.ctl->force, &v, sizeof v, hipMemcpyHostToDevice));
+  return PIC_OK;
+}
+
+// Milliseconds per step of the installed layout, with a rebin at every check
+// (the steady state of a plasma whose particles cross tiles; the loaded state
+// may not have reached it): two warm-up cycles (graph capture of both
+// parities), then 'trial' steps rounded up to whole cycles.
+pic_status time_layout(Sim& S, int trial, double* ms) {
+  const int SI = S.sort_interval;
+  pic_status fs = set_force(S, 1);
+  if (fs != PIC_OK) return fs;
+  int64_t phase = S.steps % SI;
+  pic_status st = sim_step(S, (SI - phase) % SI + 2 * SI);
+  if (st != PIC_OK) return st;
+  const int64_t n = ((int64_t)trial + SI - 1) / SI * SI;
+  hipEvent_t a = nullptr, b = nullptr;
+  HIPCHK(S, hipEventCreate(&a));
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return S.fail(PIC_E_HIP, "hipEventCreate failed");
+  }
+  float t = 0.0f;
+  hipError_t e = hipEventRecord(a, S.stream);
+  if (e == hipSuccess) {
+    st = sim_step(S, n);
+    if (st == PIC_OK) {
+      e = hipEventRecord(b, S.stream);
+      if (e == hipSuccess) e = hipEventSynchronize(b);
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (st != PIC_OK) return st;
+  if (e != hipSuccess) return S.fail(PIC_E_HIP, "timing a layout: %s", hipGetErrorString(e));
+  if ((st = sim_sync(S)) != PIC_OK) return st;
+  if ((st = set_force(S, 0)) != PIC_OK) return st;
+  *ms = (double)t / (double)n;
+  return PIC_OK;
+}
+
+pic_status sim_autotune(Sim& S, pic_tune* io) {
+  if (!io) return S.fail(PIC_E_INVALID, "null pic_tune");
+  if (io->trial_steps < 1) return S.fail(PIC_E_INVALID, "trial_steps must be >= 1");
+  if (io->what < 0 || io->what > 7) return S.fail(PIC_E_INVALID, "unknown PIC_TUNE bits");
+  const int what = io->what ? io->what : 7;
+  pic_status st = refresh_descriptors(S);
+  if (st != PIC_OK) return st;
+  if (S.sgroups.empty()) return S.fail(PIC_E_STATE, "autotune needs loaded particles");
+  if ((st = sim_sync(S)) != PIC_OK) return st;
+  const bool was_profiling = S.profiling;
+  if ((st = prof_collect(S)) != PIC_OK) return st;
+  S.profiling = false;
+  Snapshot snap;
+  snap.steps = S.steps;
+  snap.parts.resize(S.inst.size());
+  for (size_t i = 0; i < S.inst.size(); i++) {
+    Instance& I = S.inst[i];
+    snap.parts[i].resize(PIC_MAX_SPECIES);
+    for (int s = 0; s < PIC_MAX_SPECIES; s++)
+      if (I.sp[s].used && (st = read_back(S, I.sp[s], I.g.dim, snap.parts[i][s])) != PIC_OK) return st;
+    const size_t nc = (size_t)I.g.ncell;
+    float *f = nullptr, *j = nullptr;
+    HIPCHK(S, hipMalloc(&f, 6 * nc * sizeof(float)));
+    snap.F.push_back(f);
+    HIPCHK(S, hipMalloc(&j, 3 * nc * sizeof(float)));
+    snap.Jout.push_back(j);
+    HIPCHK(S, hipMemcpy(f, I.F, 6 * nc * sizeof(float), hipMemcpyDeviceToDevice));
+    HIPCHK(S, hipMemcpy(j, I.Jout, 3 * nc * sizeof(float), hipMemcpyDeviceToDevice));
+  }
+  Layout start;
+  start.si = S.sort_interval;
+  start.chunk = 2048;
+  for (const Species& sp : S.inst[0].sp)
+    if (sp.used) {
+      start.chunk = sp.desc.chunk;
+      break;
+    }
+  std::vector<pic_config> start_cfgs;
+  if ((st = layout_configs(S, start, start_cfgs)) != PIC_OK) return st;
+  // every layout tried, by its resolved per-instance tiles, interval and chunk
+  std::vector<std::vector<int>> seen;
+  auto key = [&](const std::vector<pic_config>& c, int si, int chunk) {
+    std::vector<int> k{si, chunk};
+    for (const pic_config& x : c) k.insert(k.end(), x.tile, x.tile + 3);
+    return k;
+  };
+  Layout best = start;
+  std::vector<pic_config> best_cfgs = start_cfgs;
+  double best_ms = 0.0;
+  int tried = 0;
+  auto trial = [&](const Layout& L, const std::vector<pic_config>& c, double* ms) -> pic_status {
+    pic_status r = apply_layout(S, c, L.si, snap);
+    if (r == PIC_OK) r = time_layout(S, io->trial_steps, ms);
+    tried++;
+    return r;
+  };
+  if ((st = trial(start, start_cfgs, &best_ms)) != PIC_OK) {
+    (void)apply_layout(S, start_cfgs, start.si, snap);
+    return st;
+  }
+  seen.push_back(key(start_cfgs, start.si, start.chunk));
+  const double ms_before = best_ms;
+  auto consider = [&](const Layout& L) -> pic_status {
+    std::vector<pic_config> c;
+    if (layout_configs(S, L, c) != PIC_OK) return PIC_OK;  // not valid for some instance: skip
+    std::vector<int> k = key(c, L.si, L.chunk);
+    for (auto& q : seen)
+      if (q == k) return PIC_OK;
+    seen.push_back(k);
+    double ms = 0.0;
+    pic_status r = trial(L, c, &ms);
+    if (r != PIC_OK) return r;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = L;
+      best_cfgs = c;
+    }
+    return PIC_OK;
+  };
+  static const int kPpt[] = {256, 512, 1024, 2048, 4096, 8192};
+  static const int kSi[] = {1, 2, 3, 4, 6, 8};
+  // chunks above 2048 are left out: a tile whose density grows several-fold
+  // later in a run (wakes, beams) would become one long item, a tail no trial
+  // on the loaded state can see
+  static const int kChunk[] = {512, 1024, 2048};
+  for (int round = 0; round < 2 && st == PIC_OK; round++) {
+    if (what & PIC_TUNE_TILE)
+      for (int p : kPpt) {
+        Layout L = best;
+        L.ppt = p;
+        if ((st = consider(L)) != PIC_OK) break;
+      }
+    if (st == PIC_OK && (what & PIC_TUNE_SORT) && round == 0)
+      for (int si : kSi) {
+        Layout L = best;
+        L.si = si;
+        if ((st = consider(L)) != PIC_OK) break;
+      }
+    if (st == PIC_OK && (what & PIC_TUNE_CHUNK) && round == 0)
+      for (int ch : kChunk) {
+        Layout L = best;
+        L.chunk = ch;
+        if ((st = consider(L)) != PIC_OK) break;
+      }
+    if (!(what & PIC_TUNE_TILE)) break;
+  }
+  if (st != PIC_OK) {
+    std::string why = S.err;
+    (void)apply_layout(S, start_cfgs, start.si, snap);
+    S.profiling = was_profiling;
+    S.err = why;
+    return st;
+  }
+  if ((st = apply_layout(S, best_cfgs, best.si, snap)) != PIC_OK) return st;
+  S.profiling = was_profiling;
+  io->candidates = tried;
+  io->particles_per_tile = best.ppt;
+  io->sort_interval = best.si;
+  io->chunk = best.chunk;
+  io->ms_before = ms_before;
+  io->ms_after = best_ms;
+  return PIC_OK;
+}
+
 }  // namespace
 
 struct pic_ctx {
@@ -1166,6 +1538,11 @@ pic_status pic_profile(pic_ctx* ctx, int32_t enable) {
   return sim_profile(ctx->s, enable);
 }
 
+pic_status pic_autotune(pic_ctx* ctx, pic_tune* io) {
+  if (!ctx) return PIC_E_INVALID;
+  return sim_autotune(ctx->s, io);
+}
+
 const char* pic_last_error(const pic_ctx* ctx) { return ctx ? ctx->s.err.c_str() : "null context"; }
 
 pic_status pic_batch_create(const pic_config* cfgs, int32_t n, void* hip_stream, pic_batch** out) {
@@ -1222,6 +1599,16 @@ pic_status pic_batch_sync(pic_batch* b) {
 pic_status pic_batch_profile(pic_batch* b, int32_t enable) {
   if (!b) return PIC_E_INVALID;
   return sim_profile(b->s, enable);
+}
+
+pic_status pic_batch_get_info(const pic_batch* b, int32_t inst, pic_info* out) {
+  if (!b) return PIC_E_INVALID;
+  return sim_info(b->s, inst, out);
+}
+
+pic_status pic_batch_autotune(pic_batch* b, pic_tune* io) {
+  if (!b) return PIC_E_INVALID;
+  return sim_autotune(b->s, io);
 }
 
 const char* pic_batch_last_error(const pic_batch* b) { return b ? b->s.err.c_str() : "null batch"; }

@@ -7,12 +7,17 @@
 // so at a rebin every particle moves to its own tile or to one of the 3^d - 1
 // neighbours.  The rebin is a stable counting sort over those 27 neighbour
 // slots: the particles of destination tile d are, in order, those of source
-// tile d - delta_s with slot s, for s = 0..26, each in its old order.
+// tile d - delta_s with slot s, for s = 0..26, each in its old order.  The
+// per-item slot counts come from the fused particle kernel of the last step.
 //
-// The rebin runs only when the fused kernel raised the store's flag (some
-// particle strayed beyond flag_slack); every kernel returns at once otherwise,
-// so the check costs a few empty launches.  The sorted particles go to the
-// other buffer set and the final kernel flips the current set.
+// A check is five launches over every store of a launch group:
+//   count   (per source tile)       slot prefix over the tile's items, slot totals
+//   dest    (per destination tile)  slot bases, particles, items; block sums
+//   fold    (per store)             scan of the block sums; control words
+//   offsets (per destination tile)  tile offsets, item offsets, item list
+//   scatter (per source item)       stable scatter into the other buffer set
+// Only stores whose fused kernel raised the flag (or whose host set 'force')
+// do any work; for the others every launch returns at once.
 #include "pic_dev.h"
 #include "pic_kernels.h"
 
@@ -21,9 +26,21 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kScanBlock = 1024;
 constexpr int kMaxGroup = 256;
+constexpr int kTB = PIC_REBIN_TILES;
 
-// The scatter of this check runs for stores whose planner found the flag set.
-__device__ __forceinline__ bool active(const StoreDesc& S) { return S.ctl->active != 0; }
+static_assert(kTB == kBlock, "one destination tile per thread of the planner");
+
+// Store of a flat index over the stores of a group, given per-store starts
+// (pref[0..n-1], increasing) in LDS.
+__device__ __forceinline__ int store_of(const int* pref, int n, int x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (pref[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
 
 // Slot of a particle with packed cell 'cell' that is stored in tile t.
 __device__ __forceinline__ int particle_slot(const GridDesc& g, int t, int cell) {
@@ -40,50 +57,53 @@ __device__ __forceinline__ int particle_slot(const GridDesc& g, int t, int cell)
   return pic_slot(dd[0], dd[1], dd[2]);
 }
 
-// Block-shared prefix over stores of a per-store count (0 for idle stores).
-template <typename F>
-__device__ void group_prefix(const StoreDesc* stores, int nstores, int* pref, F count) {
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int s = 0; s < nstores; s++) {
-      pref[s] = acc;
-      acc += active(stores[s]) ? count(stores[s]) : 0;
+// Exclusive scan of two ints over a 256-thread block; returns the totals.
+__device__ __forceinline__ void block_scan2(int a, int b, int& ea, int& eb, int& ta, int& tb) {
+  __shared__ int wa[kBlock / 64], wb[kBlock / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int ia = a, ib = b;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    int va = __shfl_up(ia, off);
+    int vb = __shfl_up(ib, off);
+    if (lane >= off) {
+      ia += va;
+      ib += vb;
     }
-    pref[nstores] = acc;
   }
+  if (lane == 63) {
+    wa[wave] = ia;
+    wb[wave] = ib;
+  }
+  __syncthreads();
+  int ca = 0, cb = 0;
+  ta = 0;
+  tb = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; w++) {
+    if (w < wave) {
+      ca += wa[w];
+      cb += wb[w];
+    }
+    ta += wa[w];
+    tb += wb[w];
+  }
+  ea = ca + ia - a;
+  eb = cb + ib - b;
   __syncthreads();
 }
 
-// --- 1. per store, one workgroup: slot totals per tile, slot bases per
-// destination tile, tile offsets, item offsets and the new item list.  The
-// per-item slot counts come from the fused particle kernel of the last step.
-__global__ void __launch_bounds__(kScanBlock) rebin_plan(const StoreDesc* __restrict__ stores) {
-  const StoreDesc& S = stores[blockIdx.x];
-  __shared__ int sa[kScanBlock], sb[kScanBlock];
-  __shared__ int s_cur, s_act;
-  if (threadIdx.x == 0) {
-    // fold the flip of the previous rebin and turn the flag into this
-    // check's decision; this workgroup is the only writer of these words
-    StoreCtl* c = S.ctl;
-    const int cur = c->cur ^ c->pending;
-    const int act = c->flag;
-    c->cur = cur;
-    c->pending = 0;
-    c->active = act;
-    c->flag = 0;
-    c->nchecks += 1;
-    c->nsorts += act;
-    s_cur = cur;
-    s_act = act;
-  }
+// --- 1. per source tile: running slot counts over the tile's items ----------
+__global__ void __launch_bounds__(kBlock) rebin_count(const StoreDesc* __restrict__ stores, int nstores,
+                                                      int total_tiles) {
+  __shared__ int t0[kMaxGroup];
+  for (int i = threadIdx.x; i < nstores; i += blockDim.x) t0[i] = stores[i].tile0;
   __syncthreads();
-  if (!s_act) return;
-  const int nt = S.g.ntiles;
-  const int cur = s_cur;
-  const int nxt = 1 - cur;
-  // running slot counts over the items of each source tile (27 independent
-  // loads per item, issued together)
-  for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+  for (int gt = blockIdx.x * blockDim.x + threadIdx.x; gt < total_tiles; gt += gridDim.x * blockDim.x) {
+    const StoreDesc& S = stores[store_of(t0, nstores, gt)];
+    if (!(S.ctl->flag | S.ctl->force)) continue;
+    const int cur = pic_cur(*S.ctl);
+    const int t = gt - S.tile0;
     const int i0 = S.ioff[cur][t], i1 = S.ioff[cur][t + 1];
     int run[PIC_NSLOT];
 #pragma unroll
@@ -101,59 +121,121 @@ __global__ void __launch_bounds__(kScanBlock) rebin_plan(const StoreDesc* __rest
 #pragma unroll
     for (int sl = 0; sl < PIC_NSLOT; sl++) S.tot[t * PIC_NSLOT + sl] = run[sl];
   }
+}
+
+// --- 2. per destination tile: incoming particles in slot order; block sums ---
+__global__ void __launch_bounds__(kBlock) rebin_dest(const StoreDesc* __restrict__ stores, int nstores) {
+  __shared__ int b0[kMaxGroup];
+  for (int i = threadIdx.x; i < nstores; i += blockDim.x) b0[i] = stores[i].blk0;
   __syncthreads();
-  // incoming particles of each destination tile, in slot order
-  for (int d = threadIdx.x; d < nt; d += blockDim.x) {
+  const StoreDesc& S = stores[store_of(b0, nstores, blockIdx.x)];
+  if (!(S.ctl->flag | S.ctl->force)) return;
+  const int blk = blockIdx.x - S.blk0;
+  const int d = blk * kTB + threadIdx.x;
+  int acc = 0, ni = 0;
+  if (d < S.g.ntiles) {
     int src[PIC_NSLOT], v[PIC_NSLOT];
 #pragma unroll
     for (int sl = 0; sl < PIC_NSLOT; sl++) src[sl] = S.nsrc[d * PIC_NSLOT + sl];
 #pragma unroll
     for (int sl = 0; sl < PIC_NSLOT; sl++) v[sl] = S.tot[src[sl] * PIC_NSLOT + sl];
-    int acc = 0;
 #pragma unroll
     for (int sl = 0; sl < PIC_NSLOT; sl++) {
       S.dbase[d * PIC_NSLOT + sl] = acc;
       acc += v[sl];
     }
     S.dcount[d] = acc;
+    ni = (acc + S.chunk - 1) / S.chunk;
+  }
+  int ea, eb, ta, tb;
+  block_scan2(acc, ni, ea, eb, ta, tb);
+  if (threadIdx.x == 0) {
+    S.bsum[2 * blk] = ta;
+    S.bsum[2 * blk + 1] = tb;
+  }
+}
+
+// --- 3. per store: scan of the block sums, totals, control words ---------------
+__global__ void __launch_bounds__(kScanBlock) rebin_fold(const StoreDesc* __restrict__ stores) {
+  const StoreDesc& S = stores[blockIdx.x];
+  __shared__ int sa[kScanBlock], sb[kScanBlock];
+  __shared__ int s_cur, s_act;
+  if (threadIdx.x == 0) {
+    const StoreCtl c = *S.ctl;
+    s_cur = c.cur ^ c.pending;
+    s_act = (c.flag | c.force) ? 1 : 0;
   }
   __syncthreads();
-  const int chunk = S.chunk;
-  const int seg = (nt + kScanBlock - 1) / kScanBlock;
-  const int t0 = threadIdx.x * seg;
-  const int t1 = min(nt, t0 + seg);
-  int a = 0, b = 0;
-  for (int t = t0; t < t1; t++) {
-    int c = S.dcount[t];
-    a += c;
-    b += (c + chunk - 1) / chunk;
-  }
-  sa[threadIdx.x] = a;
-  sb[threadIdx.x] = b;
-  __syncthreads();
-  // inclusive scan (Hillis-Steele) over the block
-  for (int off = 1; off < kScanBlock; off <<= 1) {
-    int va = threadIdx.x >= off ? sa[threadIdx.x - off] : 0;
-    int vb = threadIdx.x >= off ? sb[threadIdx.x - off] : 0;
-    __syncthreads();
-    sa[threadIdx.x] += va;
-    sb[threadIdx.x] += vb;
-    __syncthreads();
-  }
-  int ra = sa[threadIdx.x] - a, rb = sb[threadIdx.x] - b;  // exclusive
-  int* toff = S.toff[nxt];
-  int* ioff = S.ioff[nxt];
-  Item* items = S.items[nxt];
-  for (int t = t0; t < t1; t++) {
-    int c = S.dcount[t];
-    int ni = (c + chunk - 1) / chunk;
-    toff[t] = ra;
-    ioff[t] = rb;
-    for (int k = 0; k < ni; k++) {
-      if (rb + k >= S.max_items) {
-        atomicOr(&S.ctl->bad, 4);
-        break;
+  const int cur = s_cur;
+  const int act = s_act;
+  if (act) {
+    const int nblk = (S.g.ntiles + kTB - 1) / kTB;
+    int carry_a = 0, carry_b = 0;
+    for (int base = 0; base < nblk; base += kScanBlock) {
+      const int k = base + threadIdx.x;
+      const int a = k < nblk ? S.bsum[2 * k] : 0;
+      const int b = k < nblk ? S.bsum[2 * k + 1] : 0;
+      sa[threadIdx.x] = a;
+      sb[threadIdx.x] = b;
+      __syncthreads();
+      for (int off = 1; off < kScanBlock; off <<= 1) {
+        int va = threadIdx.x >= off ? sa[threadIdx.x - off] : 0;
+        int vb = threadIdx.x >= off ? sb[threadIdx.x - off] : 0;
+        __syncthreads();
+        sa[threadIdx.x] += va;
+        sb[threadIdx.x] += vb;
+        __syncthreads();
       }
+      if (k < nblk) {
+        S.bpre[2 * k] = carry_a + sa[threadIdx.x] - a;
+        S.bpre[2 * k + 1] = carry_b + sb[threadIdx.x] - b;
+      }
+      carry_a += sa[kScanBlock - 1];
+      carry_b += sb[kScanBlock - 1];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const int nxt = 1 - cur;
+      S.toff[nxt][S.g.ntiles] = carry_a;
+      S.ioff[nxt][S.g.ntiles] = carry_b;
+      S.ctl->n_items[nxt] = min(carry_b, S.max_items);
+      if (carry_b > S.max_items || carry_a != S.np) S.ctl->bad |= 4;
+    }
+  }
+  if (threadIdx.x == 0) {
+    // this workgroup is the only writer of the control words during a check
+    StoreCtl* c = S.ctl;
+    c->cur = cur;
+    c->pending = act ? 1 : 0;  // the scatter of this check fills set 1 - cur
+    c->active = act;
+    c->flag = 0;
+    c->nchecks += 1;
+    c->nsorts += act;
+  }
+}
+
+// --- 4. per destination tile: tile offsets, item offsets, item list -----------
+__global__ void __launch_bounds__(kBlock) rebin_offsets(const StoreDesc* __restrict__ stores, int nstores) {
+  __shared__ int b0[kMaxGroup];
+  for (int i = threadIdx.x; i < nstores; i += blockDim.x) b0[i] = stores[i].blk0;
+  __syncthreads();
+  const StoreDesc& S = stores[store_of(b0, nstores, blockIdx.x)];
+  if (!S.ctl->active) return;
+  const int nxt = 1 - S.ctl->cur;
+  const int blk = blockIdx.x - S.blk0;
+  const int t = blk * kTB + threadIdx.x;
+  const int chunk = S.chunk;
+  const int c = t < S.g.ntiles ? S.dcount[t] : 0;
+  const int ni = (c + chunk - 1) / chunk;
+  int ea, eb, ta, tb;
+  block_scan2(c, ni, ea, eb, ta, tb);
+  if (t < S.g.ntiles) {
+    const int ra = S.bpre[2 * blk] + ea;
+    const int rb = S.bpre[2 * blk + 1] + eb;
+    S.toff[nxt][t] = ra;
+    S.ioff[nxt][t] = rb;
+    Item* items = S.items[nxt];
+    for (int k = 0; k < ni && rb + k < S.max_items; k++) {
       Item it;
       it.tile = t;
       it.begin = ra + k * chunk;
@@ -161,23 +243,29 @@ __global__ void __launch_bounds__(kScanBlock) rebin_plan(const StoreDesc* __rest
       it.pad = 0;
       items[rb + k] = it;
     }
-    ra += c;
-    rb += ni;
-  }
-  if (threadIdx.x == kScanBlock - 1) {
-    toff[nt] = sa[kScanBlock - 1];
-    ioff[nt] = sb[kScanBlock - 1];
-    S.ctl->n_items[nxt] = min(sb[kScanBlock - 1], S.max_items);
-    S.ctl->pending = 1;  // the scatter of this check fills set nxt
   }
 }
 
-// --- 2. per old item: stable scatter into the other buffer set -----------------
+// Block-shared prefix over stores of a per-store count (0 for idle stores).
+template <typename F>
+__device__ void group_prefix(const StoreDesc* stores, int nstores, int* pref, F count) {
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int s = 0; s < nstores; s++) {
+      pref[s] = acc;
+      acc += stores[s].ctl->active ? count(stores[s]) : 0;
+    }
+    pref[nstores] = acc;
+  }
+  __syncthreads();
+}
+
+// --- 5. per old item: stable scatter into the other buffer set ---------------
 __global__ void __launch_bounds__(kBlock) rebin_scatter(const StoreDesc* __restrict__ stores, int nstores) {
   __shared__ int pref[kMaxGroup + 1];
   __shared__ int run[PIC_NSLOT];
   __shared__ int wcnt[kBlock / 64][PIC_NSLOT];
-  // the source set is cur (the planner set pending for the destination)
+  // the source set is cur (the fold set pending for the destination)
   group_prefix(stores, nstores, pref, [](const StoreDesc& S) { return S.ctl->n_items[S.ctl->cur]; });
   const int total = pref[nstores];
   const int lane = threadIdx.x & 63;
@@ -250,11 +338,14 @@ int cap_grid(long n, int per) {
 
 }  // namespace
 
-hipError_t pic_launch_rebin(const StoreDesc* d_stores, int nstores, int max_items, int max_tiles,
-                            hipStream_t st) {
-  (void)max_tiles;
-  if (nstores > kMaxGroup) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(rebin_plan, dim3(nstores), dim3(kScanBlock), 0, st, d_stores);
+hipError_t pic_launch_rebin(const StoreDesc* d_stores, int nstores, int max_items, int total_tiles,
+                            int total_blocks, hipStream_t st) {
+  if (nstores > kMaxGroup || nstores < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(rebin_count, dim3(cap_grid(total_tiles, kBlock)), dim3(kBlock), 0, st, d_stores, nstores,
+                     total_tiles);
+  hipLaunchKernelGGL(rebin_dest, dim3(total_blocks), dim3(kBlock), 0, st, d_stores, nstores);
+  hipLaunchKernelGGL(rebin_fold, dim3(nstores), dim3(kScanBlock), 0, st, d_stores);
+  hipLaunchKernelGGL(rebin_offsets, dim3(total_blocks), dim3(kBlock), 0, st, d_stores, nstores);
   hipLaunchKernelGGL(rebin_scatter, dim3(cap_grid(max_items, 1)), dim3(kBlock), 0, st, d_stores, nstores);
   return hipGetLastError();
 }

@@ -47,8 +47,12 @@ EXPORTED = [
     "pic_create", "pic_destroy", "pic_load_particles", "pic_load_fields", "pic_step", "pic_sync",
     "pic_diag", "pic_get_info", "pic_last_error", "pic_profile", "pic_batch_profile", "pic_batch_create", "pic_batch_destroy",
     "pic_batch_load_particles", "pic_batch_load_fields", "pic_batch_step", "pic_batch_diag",
-    "pic_batch_sync", "pic_batch_last_error",
+    "pic_batch_sync", "pic_batch_last_error", "pic_autotune", "pic_batch_autotune", "pic_batch_get_info",
 ]
+
+PIC_TUNE_TILE = 1
+PIC_TUNE_SORT = 2
+PIC_TUNE_CHUNK = 4
 
 
 class pic_config(C.Structure):
@@ -84,6 +88,23 @@ class pic_info(C.Structure):
     ]
 
 
+class pic_tune(C.Structure):
+    _fields_ = [
+        ("trial_steps", C.c_int32),
+        ("what", C.c_int32),
+        ("candidates", C.c_int32),
+        ("particles_per_tile", C.c_int32),
+        ("sort_interval", C.c_int32),
+        ("chunk", C.c_int32),
+        ("ms_before", C.c_double),
+        ("ms_after", C.c_double),
+    ]
+
+
+def _tune_dict(t: pic_tune) -> dict:
+    return {k: getattr(t, k) for k, _ in pic_tune._fields_}
+
+
 _lib = None
 
 
@@ -117,6 +138,9 @@ def lib():
         L.pic_batch_sync.argtypes = [V]
         L.pic_batch_last_error.argtypes = [V]
         L.pic_batch_last_error.restype = C.c_char_p
+        L.pic_autotune.argtypes = [V, C.POINTER(pic_tune)]
+        L.pic_batch_autotune.argtypes = [V, C.POINTER(pic_tune)]
+        L.pic_batch_get_info.argtypes = [V, I32, C.POINTER(pic_info)]
         for name in EXPORTED:
             fn = getattr(L, name)
             if fn.restype is None or fn.restype is C.c_int:
@@ -312,6 +336,12 @@ class Pic(_Base):
     def profile(self, enable: int):
         self._check(self._L.pic_profile(self._h, int(enable)))
 
+    def autotune(self, trial_steps: int = 20, what: int = 0) -> dict:
+        """Measured search of tile, sort interval and chunk (pic_autotune)."""
+        t = pic_tune(trial_steps=int(trial_steps), what=int(what))
+        self._check(self._L.pic_autotune(self._h, C.byref(t)))
+        return _tune_dict(t)
+
     def kernel_times(self):
         """{family: (ms, launches)} for 'particle', 'field', 'rebin'."""
         a = self.diag(PIC_DIAG_KERNEL_TIMES, 6)
@@ -380,6 +410,16 @@ class PicBatch(_Base):
 
     def profile(self, enable: int):
         self._check(self._L.pic_batch_profile(self._h, int(enable)))
+
+    def autotune(self, trial_steps: int = 20, what: int = 0) -> dict:
+        t = pic_tune(trial_steps=int(trial_steps), what=int(what))
+        self._check(self._L.pic_batch_autotune(self._h, C.byref(t)))
+        return _tune_dict(t)
+
+    def info(self, inst: int) -> pic_info:
+        i = pic_info()
+        self._check(self._L.pic_batch_get_info(self._h, inst, C.byref(i)))
+        return i
 
     def kernel_times(self):
         a = self.diag(0, PIC_DIAG_KERNEL_TIMES, 6)

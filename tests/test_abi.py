@@ -51,7 +51,7 @@ def _c_layout(tmp_path, struct, fields):
     return {k: int(v) for k, v in (line.split() for line in out.strip().splitlines())}
 
 
-@pytest.mark.parametrize("struct", ["pic_config", "pic_info"])
+@pytest.mark.parametrize("struct", ["pic_config", "pic_info", "pic_tune"])
 def test_struct_layout_matches_header(tmp_path, struct):
     pic, _ = _lib()
     cls = getattr(pic, struct)
@@ -117,3 +117,6 @@ def test_null_arguments_rejected():
     assert L.pic_destroy(None) == 0
     assert L.pic_batch_destroy(None) == 0
     assert L.pic_last_error(None) == b"null context"
+    assert L.pic_autotune(None, None) == pic.PIC_E_INVALID
+    assert L.pic_batch_autotune(None, None) == pic.PIC_E_INVALID
+    assert L.pic_batch_get_info(None, 0, None) == pic.PIC_E_INVALID
