@@ -559,3 +559,89 @@ def test_cold_plasma_frequency(orc):
     omega = math.pi / (np.mean(half_periods) * dt)
     assert len(zc) >= 8
     assert abs(omega / CF["plasma_omega"] - 1) < 1e-4, omega
+
+
+# --------------------------------------------------------------------------
+# energy and momentum diagnostics (App. A diagnostics; the kinetic and field
+# energies of Sec. 3.1's normalised units)
+# --------------------------------------------------------------------------
+
+
+def test_energy_exchange_in_plasma_oscillation(orc):
+    """In a cold plasma oscillation the field energy rises and falls by its
+    whole amount while the kinetic energy takes it up: their sum (kinetic at
+    the time level of the fields, as the mean of the two half steps) stays
+    constant to O((w_p dt)^2) of the exchanged energy.  A wrong factor in
+    either energy (the 1/2 of (E^2+B^2)/2, the sign of w*rqm, gamma-1) breaks
+    the balance by order one."""
+    nx, ppc_x = (64, 2), 2
+    dx, dt = (0.2, 0.2), 0.1
+    g = orc.Grid(dim=2, nx=nx, dx=dx, dt=dt, order=1)
+    L = nx[0] * dx[0]
+    ii, jj = np.meshgrid(np.arange(nx[0] * ppc_x), np.arange(nx[1] * ppc_x), indexing="ij")
+    x = np.stack([(ii.ravel() + 0.5) * dx[0] / ppc_x, (jj.ravel() + 0.5) * dx[1] / ppc_x], axis=1)
+    k = 2 * math.pi / L
+    x[:, 0] += 0.01 * np.sin(k * x[:, 0])
+    u = np.zeros((len(x), 3))
+    w = -1.0 / (ppc_x * ppc_x)
+    E = np.zeros((3, g.ncell))
+    B = np.zeros((3, g.ncell))
+    rho = orc.rho(g, x, w).reshape(nx[1], nx[0]) + 1.0
+    e1 = np.cumsum(rho.mean(axis=0)) * dx[0]
+    e1 -= e1.mean()
+    E[0] = np.tile(e1, nx[1])
+    wf, tot = [], []
+    for _ in range(100):
+        fe = orc.field_energy(g, E, B)
+        k_old = orc.particle_moments(g, u, w, -1.0)[0]
+        r = orc.step(g, x, u, w, -1.0, E, B)
+        k_new = orc.particle_moments(g, r.u, w, -1.0)[0]
+        wf.append(fe[0] + fe[1])
+        tot.append(fe[0] + fe[1] + 0.5 * (k_old + k_new))
+        x, u, E, B = r.x, r.u, r.E, r.B
+    wf, tot = np.array(wf), np.array(tot)
+    assert wf.max() > 0 and wf.min() < 0.05 * wf.max()  # the field energy is exchanged fully
+    assert (tot.max() - tot.min()) < 0.01 * wf.max(), (tot.max() - tot.min()) / wf.max()
+
+
+def test_kinetic_energy_of_a_drifting_plasma(orc):
+    """A uniform plasma of density n drifting with momentum u carries kinetic
+    energy n * volume * (gamma - 1) and momentum n * volume * u (in m c^2 n_n
+    and m c n_n units): the macro-particle weights and the cell volume must
+    add up to the physical electron count of the box."""
+    nx, dx = (6, 5, 4), (0.2, 0.3, 0.25)
+    g = orc.Grid(dim=3, nx=nx, dx=dx, dt=0.05, order=2)
+    rng = np.random.default_rng(5)
+    ppc, n = 3, 1.7
+    cells = np.repeat(np.arange(g.ncell), ppc)
+    idx = np.stack(np.unravel_index(cells, nx[::-1])[::-1], axis=1)
+    x = (idx + rng.random((len(cells), 3))) * np.array(dx)
+    u0 = np.array([0.3, -1.2, 0.5])
+    u = np.tile(u0, (len(x), 1))
+    w = np.full(len(x), -n / ppc)
+    vol = np.prod(np.array(nx) * np.array(dx))
+    ke, px, py, pz = orc.particle_moments(g, u, w, -1.0)
+    gamma = math.sqrt(1 + u0 @ u0)
+    assert abs(ke - n * vol * (gamma - 1)) < 1e-12 * ke
+    assert np.allclose([px, py, pz], n * vol * u0, rtol=1e-12)
+
+
+def test_momentum_impulse_equals_charge_times_field(orc):
+    """Over one step in a uniform external field E0 (no grid fields) the
+    particles' total momentum changes by Q E0 dt, Q the total charge of the
+    box (sum of w times the cell volume): Newton's law for the whole plasma
+    pins the w * rqm * u normalisation of the momentum diagnostic."""
+    nx, dx, dt = (8, 6), (0.2, 0.25), 0.1
+    e0 = (0.03, -0.02, 0.05)
+    g = orc.Grid(dim=2, nx=nx, dx=dx, dt=dt, order=3, e0=e0)
+    rng = np.random.default_rng(2)
+    x = rng.random((40, 2)) * np.array([nx[0] * dx[0], nx[1] * dx[1]])
+    u = rng.normal(0, 0.2, (40, 3))
+    w = rng.uniform(-0.5, -0.1, 40)
+    E = np.zeros((3, g.ncell))
+    B = np.zeros((3, g.ncell))
+    p0 = np.array(orc.particle_moments(g, u, w, -1.0)[1:])
+    r = orc.step(g, x, u, w, -1.0, E, B)
+    p1 = np.array(orc.particle_moments(g, r.u, w, -1.0)[1:])
+    Q = w.sum() * dx[0] * dx[1]
+    assert np.allclose(p1 - p0, Q * np.array(e0) * dt, rtol=1e-12, atol=1e-15)
