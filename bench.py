@@ -95,6 +95,30 @@ def cpu_baseline(wl, max_particles, min_seconds=10.0, max_steps=20):
     }
 
 
+def measured_traffic(wl, info, kernel_avg_s):
+    """HBM traffic of the particle kernel in GB/s from the committed counter
+    record (rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by
+    what the same counter reads for a plain device copy of known size), or
+    None when no record matches this workload and layout or the kernel's
+    source changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "gpd_lwfa2d_1024x256_counters.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in ["gpd.hip", "pic_dev.h"]:
+        with open(os.path.join(ROOT, "paper_1503_00276_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if (rec.get("source_sha256") != h.hexdigest() or rec.get("workload_name") != wl.name
+            or list(rec.get("tile", [])) != list(info.tile)[:wl.ndim]
+            or rec.get("sort_interval") != info.sort_interval or rec.get("chunk") != info.chunk):
+        return None
+    kib = rec["fetch_kib_per_dispatch"] * rec["fetch_scale"] + rec["write_kib_per_dispatch"] * rec["write_scale"]
+    return kib * 1024.0 / kernel_avg_s / 1e9
+
+
 def algorithmic_bytes(n, ndim, ncell):
     """Algorithmic HBM bytes of one step's particle kernel for n particles on
     ncell cells (see bytes_per_push)."""
@@ -208,6 +232,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--sort-interval", type=int, default=0)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run only the batched leg and print its record (for profiling)")
     ap.add_argument("--batch-instances", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -226,6 +252,9 @@ def main():
     assert torch.cuda.is_available(), "no GPU visible"
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()  # a non-default stream so the library can capture graphs on it
+    if args.only_batched:
+        print(json.dumps(run_batched(args, pic, stream)), flush=True)
+        return
 
     log(f"generating workload {args.workload}")
     wl = make_workload(args.workload)
@@ -317,7 +346,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(wl, info, gpd_avg_s),
             "kernel": "gpd_kernel (fused gather+push+deposit)",
             "bytes_per_push": bpp,
             "kernel_avg_us": gpd_avg_s * 1e6,
