@@ -255,6 +255,12 @@ def test_deposit_continuity(orc, dim, order):
         r1 = orc.rho(g, b[p:p + 1] * dx, w[p:p + 1])
         Cres = orc.charge_residual(g, r0, r1, J)
         assert np.abs(Cres).max() < 1e-13 * np.abs(r0).max() / g.dt
+        # the residual is not trivially zero: a current off by 1% in one
+        # component (a planted mistake) violates continuity visibly
+        Jbad = np.array(J, copy=True)
+        Jbad[0] *= 1.01
+        if np.abs(J[0]).max() > 0:
+            assert np.abs(orc.charge_residual(g, r0, r1, Jbad)).max() > 1e-4 * np.abs(J[0]).max() / dx[0]
 
 
 @pytest.mark.parametrize("dim,order", [(2, 1), (2, 3), (3, 2)])
