@@ -92,11 +92,11 @@ __device__ __forceinline__ double div_at(const GridDesc& g, const T* V, int nc, 
 }
 
 __global__ void __launch_bounds__(kBlock) gauss64(const InstDesc* __restrict__ ip, const double* rho, double* G,
-                                                  int dim) {
+                                                  int dim, int fpar) {
   const InstDesc& I = *ip;
   const int nc = I.g.ncell;
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x)
-    G[c] = div_at(I.g, I.F, nc, c, dim) - rho[c];
+    G[c] = div_at(I.g, I.F[fpar], nc, c, dim) - rho[c];
 }
 
 __global__ void __launch_bounds__(kBlock) charge64(const InstDesc* __restrict__ ip, const double* rho0,
@@ -184,13 +184,14 @@ __global__ void __launch_bounds__(kBlock) reduce_final(const double* partial, in
 }
 
 // sum E^2 and B^2 over all cells (times V/2 applied on the host)
-__global__ void __launch_bounds__(kBlock) field_sums(const InstDesc* __restrict__ ip, double* partial) {
+__global__ void __launch_bounds__(kBlock) field_sums(const InstDesc* __restrict__ ip, double* partial, int fpar) {
   const InstDesc& I = *ip;
   const int nc = I.g.ncell;
   Pair v[2] = {{0.0, 0.0}, {0.0, 0.0}};
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
     for (int k = 0; k < 3; k++) {
-      double e = I.F[(size_t)k * nc + c], b = I.F[(size_t)(3 + k) * nc + c];
+      const float* F = I.F[fpar];
+      double e = F[(size_t)k * nc + c], b = F[(size_t)(3 + k) * nc + c];
       neumaier(v[0], e * e);
       neumaier(v[1], b * b);
     }
@@ -271,9 +272,9 @@ hipError_t pic_launch_fill64(double* p, double v, size_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t pic_launch_gauss64(const InstDesc* d_inst, const double* rho, double* G, int ncell, int dim,
+hipError_t pic_launch_gauss64(const InstDesc* d_inst, const double* rho, double* G, int ncell, int dim, int fpar,
                               hipStream_t st) {
-  hipLaunchKernelGGL(gauss64, dim3(grid_for(ncell)), dim3(kBlock), 0, st, d_inst, rho, G, dim);
+  hipLaunchKernelGGL(gauss64, dim3(grid_for(ncell)), dim3(kBlock), 0, st, d_inst, rho, G, dim, fpar);
   return hipGetLastError();
 }
 
@@ -283,10 +284,10 @@ hipError_t pic_launch_charge64(const InstDesc* d_inst, const double* rho0, const
   return hipGetLastError();
 }
 
-hipError_t pic_launch_field_sums(const InstDesc* d_inst, int ncell, double* scratch, double* out,
+hipError_t pic_launch_field_sums(const InstDesc* d_inst, int ncell, int fpar, double* scratch, double* out,
                                  hipStream_t st) {
   (void)ncell;
-  hipLaunchKernelGGL(field_sums, dim3(kRedBlocks), dim3(kBlock), 0, st, d_inst, scratch);
+  hipLaunchKernelGGL(field_sums, dim3(kRedBlocks), dim3(kBlock), 0, st, d_inst, scratch, fpar);
   hipLaunchKernelGGL(reduce_final, dim3(1), dim3(kBlock), 0, st, scratch, kRedBlocks, 2, out);
   return hipGetLastError();
 }

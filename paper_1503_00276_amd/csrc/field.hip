@@ -32,6 +32,9 @@ template <> struct YeeTile<3> { static constexpr int X = 16, Y = 4, Z = 4; };
 // filled (int64 fixed point in the deterministic mode; which of the two is
 // the step's parity), copied to Jout, and the other accumulator is cleared
 // for the next step.
+// The fields are double-buffered: the step reads E^n, B^n from set par and
+// writes E^{n+1}, B^{n+1} to the other set, so a tile never reads a halo
+// node that a neighbouring workgroup has already advanced.
 // Periodic wrap for an index at most one period out of range.
 __device__ __forceinline__ int wrap1(int v, int n) {
   v = v < 0 ? v + n : v;
@@ -74,7 +77,7 @@ __global__ void __launch_bounds__(kBlock) yee_step(const InstDesc* __restrict__ 
       int gz = DIM == 3 ? wrap1(o2 - zoff + z, n2) : 0;
       return gx + n0 * (gy + n1 * gz);
     };
-    const gfloat* F = (const gfloat*)I.F;
+    const gfloat* F = (const gfloat*)I.F[par];
     for (int z = (DIM == 3 ? tz : 0); z < EZ; z += T::Z)
       for (int y = ty; y < EY; y += T::Y)
         for (int x = tx; x < EX; x += T::X) {
@@ -167,7 +170,7 @@ __global__ void __launch_bounds__(kBlock) yee_step(const InstDesc* __restrict__ 
         }
     __syncthreads();
     // B' on the tile, and write E', B' back
-    gfloat* Fw = (gfloat*)I.F;
+    gfloat* Fw = (gfloat*)I.F[1 - par];
     for (int z = zoff + (DIM == 3 ? tz : 0); z <= (DIM == 3 ? e2 : 0); z += T::Z)
       for (int y = 1 + ty; y <= e1; y += T::Y)
         for (int x = 1 + tx; x <= e0; x += T::X) {

@@ -256,7 +256,7 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
     int gy = pic_wrap(org[1] - flo[1] + ry, g.nx[1]);
     int gz = DIM == 3 ? pic_wrap(org[2] - flo[2] + rz, g.nx[2]) : 0;
     int gi = gx + g.nx[0] * (gy + g.nx[1] * gz);
-    const gfloat* Fg = (const gfloat*)S.F;
+    const gfloat* Fg = (const gfloat*)S.F[jp];
 #pragma unroll
     for (int c = 0; c < 6; c++) sF[c * fn + idx] = Fg[(size_t)c * ncell + gi];
   }

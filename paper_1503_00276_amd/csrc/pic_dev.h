@@ -69,7 +69,8 @@ struct StoreDesc {
   int np;                    // particles stored
   int chunk;                 // maximum particles per work item
   int max_items;
-  float* F;                  // instance fields: E1 E2 E3 B1 B2 B3 planes of ncell floats
+  float* F[2];               // instance fields E1 E2 E3 B1 B2 B3 (planes of ncell floats), double-
+                             // buffered: step n reads set n&1, the Yee step writes the other
   float* Jacc[2];            // FP32 current accumulators (J1 J2 J3 planes), double-buffered
   unsigned long long* J64[2];// int64 fixed-point accumulators (deterministic mode only)
   int* cell[2];              // packed cell index
@@ -96,7 +97,7 @@ struct StoreDesc {
 // One instance (for the field kernels).
 struct InstDesc {
   GridDesc g;
-  float* F;
+  float* F[2];
   float* Jacc[2];
   unsigned long long* J64[2];
   float* Jout;               // the current of the last step (FP32, used by the E update)

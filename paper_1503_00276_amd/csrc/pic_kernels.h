@@ -26,13 +26,13 @@ hipError_t pic_launch_rebin(const StoreDesc* d_stores, int nstores, int max_item
 // diagnostics (diag.hip)
 hipError_t pic_launch_rho64(const StoreDesc* d_store, int np_max, double* rho, hipStream_t st);
 hipError_t pic_launch_fill64(double* p, double v, size_t n, hipStream_t st);
-hipError_t pic_launch_gauss64(const InstDesc* d_inst, const double* rho, double* G, int ncell,
-                              int dim, hipStream_t st);
+hipError_t pic_launch_gauss64(const InstDesc* d_inst, const double* rho, double* G, int ncell, int dim,
+                              int fpar, hipStream_t st);
 hipError_t pic_launch_charge64(const InstDesc* d_inst, const double* rho0, const double* rho1,
                                double* C, int ncell, int dim, hipStream_t st);
 // compensated FP64 sums: out[0..nout) with partial scratch (>= 2*nout*pic_reduce_blocks() doubles)
 int pic_reduce_blocks();
-hipError_t pic_launch_field_sums(const InstDesc* d_inst, int ncell, double* scratch, double* out,
+hipError_t pic_launch_field_sums(const InstDesc* d_inst, int ncell, int fpar, double* scratch, double* out,
                                  hipStream_t st);
 hipError_t pic_launch_particle_sums(const StoreDesc* d_store, int np, double rqm, double* scratch,
                                     double* out, hipStream_t st);

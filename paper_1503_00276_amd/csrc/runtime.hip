@@ -43,7 +43,7 @@ struct Species {
 struct Instance {
   pic_config cfg{};
   GridDesc g{};
-  float* F = nullptr;
+  float* F[2] = {nullptr, nullptr};  // fields, double-buffered by step parity
   float* Jacc[2] = {nullptr, nullptr};
   unsigned long long* J64[2] = {nullptr, nullptr};
   float* Jout = nullptr;
@@ -303,7 +303,8 @@ pic_status alloc_species(Sim& S, Instance& I, Species& sp, int64_t cap, int chun
   AL(sp.ctl, 1);
 #undef AL
   d.ctl = sp.ctl;
-  d.F = I.F;
+  d.F[0] = I.F[0];
+  d.F[1] = I.F[1];
   for (int k = 0; k < 2; k++) {
     d.Jacc[k] = I.Jacc[k];
     d.J64[k] = I.J64[k];
@@ -361,7 +362,8 @@ pic_status refresh_descriptors(Sim& S) {
       if (I.g.dim != dim) continue;
       InstDesc id{};
       id.g = I.g;
-      id.F = I.F;
+      id.F[0] = I.F[0];
+      id.F[1] = I.F[1];
       for (int k = 0; k < 2; k++) {
         id.Jacc[k] = I.Jacc[k];
         id.J64[k] = I.J64[k];
@@ -811,7 +813,7 @@ pic_status sim_load_fields(Sim& S, int inst, const double* e, const double* b, u
     f[n + i] = (float)hb[i];
   }
   HIPCHK(S, hipStreamSynchronize(S.stream));
-  HIPCHK(S, hipMemcpy(I.F, f.data(), 2 * n * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHK(S, hipMemcpy(I.F[S.steps & 1], f.data(), 2 * n * sizeof(float), hipMemcpyHostToDevice));
   return PIC_OK;
 }
 
@@ -862,7 +864,7 @@ pic_status sim_diag(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_byt
       size_t want = (kind == PIC_DIAG_ENERGY ? 4 : 3) * sizeof(double);
       if ((st = need(S, want, out_bytes, written)) != PIC_OK) return st;
       double fe[2] = {0, 0}, pm[4] = {0, 0, 0, 0};
-      HIPCHK(S, pic_launch_field_sums(S.d_inst + ii, g.ncell, S.d_scratch, S.d_out, S.stream));
+      HIPCHK(S, pic_launch_field_sums(S.d_inst + ii, g.ncell, (int)(S.steps & 1), S.d_scratch, S.d_out, S.stream));
       HIPCHK(S, hipMemcpyAsync(fe, S.d_out, 2 * sizeof(double), hipMemcpyDeviceToHost, S.stream));
       HIPCHK(S, hipStreamSynchronize(S.stream));
       for (int s = 0; s < PIC_MAX_SPECIES; s++) {
@@ -907,7 +909,7 @@ pic_status sim_diag(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_byt
         if (kind == PIC_DIAG_CHARGE_RESIDUAL)
           HIPCHK(S, pic_launch_charge64(S.d_inst + ii, I.rho_snap, rho, res, g.ncell, g.dim, S.stream));
         else
-          HIPCHK(S, pic_launch_gauss64(S.d_inst + ii, rho, res, g.ncell, g.dim, S.stream));
+          HIPCHK(S, pic_launch_gauss64(S.d_inst + ii, rho, res, g.ncell, g.dim, (int)(S.steps & 1), S.stream));
         src = res;
       }
       if (kind == PIC_DIAG_GAUSS_NORM) {
@@ -964,7 +966,7 @@ pic_status sim_diag(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_byt
       double* dbuf = nullptr;
       HIPCHK(S, hipMalloc(&dbuf, ncomp * nc * sizeof(double)));
       tmp.push_back(dbuf);
-      HIPCHK(S, pic_launch_f32_to_f64(kind == PIC_DIAG_EXPORT_FIELDS ? I.F : I.Jout, dbuf, ncomp * nc, S.stream));
+      HIPCHK(S, pic_launch_f32_to_f64(kind == PIC_DIAG_EXPORT_FIELDS ? I.F[S.steps & 1] : I.Jout, dbuf, ncomp * nc, S.stream));
       HIPCHK(S, hipMemcpyAsync(out, dbuf, ncomp * nc * sizeof(double), hipMemcpyDeviceToHost, S.stream));
       HIPCHK(S, hipStreamSynchronize(S.stream));
       return PIC_OK;
@@ -1061,8 +1063,11 @@ pic_status sim_create(Sim& S, const pic_config* cfgs, int n, void* stream) {
     pic_status st = setup_grid(S, cfgs[i], SI, I.g);
     if (st != PIC_OK) return st;
     size_t nc = (size_t)I.g.ncell;
-    if (hipMalloc(&I.F, 6 * nc * sizeof(float)) != hipSuccess) return S.fail(PIC_E_NOMEM, "field allocation failed");
-    HIPCHK(S, hipMemset(I.F, 0, 6 * nc * sizeof(float)));
+    for (int k = 0; k < 2; k++) {
+      if (hipMalloc(&I.F[k], 6 * nc * sizeof(float)) != hipSuccess)
+        return S.fail(PIC_E_NOMEM, "field allocation failed");
+      HIPCHK(S, hipMemset(I.F[k], 0, 6 * nc * sizeof(float)));
+    }
     if ((st = build_tables(S, I)) != PIC_OK) return st;
     if (hipMalloc(&I.Jout, 3 * nc * sizeof(float)) != hipSuccess) return S.fail(PIC_E_NOMEM, "current allocation failed");
     HIPCHK(S, hipMemset(I.Jout, 0, 3 * nc * sizeof(float)));
@@ -1106,7 +1111,8 @@ void sim_destroy(Sim& S) {
     if (S.cycle_exec[k]) (void)hipGraphExecDestroy(S.cycle_exec[k]);
   for (Instance& I : S.inst) {
     for (Species& sp : I.sp) free_species(sp);
-    if (I.F) (void)hipFree(I.F);
+    for (int k = 0; k < 2; k++)
+      if (I.F[k]) (void)hipFree(I.F[k]);
     for (int k = 0; k < 2; k++) {
       if (I.Jacc[k]) (void)hipFree(I.Jacc[k]);
       if (I.J64[k]) (void)hipFree(I.J64[k]);
@@ -1282,7 +1288,7 @@ pic_status apply_layout(Sim& S, const std::vector<pic_config>& cfgs, int si, con
       B = Binned();
     }
     const size_t nc = (size_t)I.g.ncell;
-    HIPCHK(S, hipMemcpy(I.F, snap.F[i], 6 * nc * sizeof(float), hipMemcpyDeviceToDevice));
+    HIPCHK(S, hipMemcpy(I.F[snap.steps & 1], snap.F[i], 6 * nc * sizeof(float), hipMemcpyDeviceToDevice));
     HIPCHK(S, hipMemcpy(I.Jout, snap.Jout[i], 3 * nc * sizeof(float), hipMemcpyDeviceToDevice));
     for (int k = 0; k < 2; k++) {
       if (I.J64[k]) HIPCHK(S, hipMemset(I.J64[k], 0, 3 * nc * sizeof(unsigned long long)));
@@ -1369,7 +1375,7 @@ pic_status sim_autotune(Sim& S, pic_tune* io) {
     snap.F.push_back(f);
     HIPCHK(S, hipMalloc(&j, 3 * nc * sizeof(float)));
     snap.Jout.push_back(j);
-    HIPCHK(S, hipMemcpy(f, I.F, 6 * nc * sizeof(float), hipMemcpyDeviceToDevice));
+    HIPCHK(S, hipMemcpy(f, I.F[S.steps & 1], 6 * nc * sizeof(float), hipMemcpyDeviceToDevice));
     HIPCHK(S, hipMemcpy(j, I.Jout, 3 * nc * sizeof(float), hipMemcpyDeviceToDevice));
   }
   Layout start;
