@@ -157,12 +157,14 @@ def run_batched(args, pic, stream):
     log(f"batched leg: loading {ntot} particles")
     for k, wl in enumerate(wls):
         batch.load_particles(k, wl.x, wl.u, wl.w, rqm=wl.rqm)
+    batch.step(args.warmup)
+    batch.sync()
     tune = None
     if args.tune_steps > 0:
         log("batched leg: autotune")
         tune = batch.autotune(trial_steps=args.tune_steps)
-    batch.step(args.warmup)
-    batch.sync()
+        batch.step(args.warmup)
+        batch.sync()
     K = args.batch_steps
     log(f"batched leg: timing {K} steps")
     t_batch = timed_steps(batch, stream, K)
@@ -266,15 +268,18 @@ def main():
     sim.load_particles(wl.x, wl.u, wl.w, rqm=wl.rqm)
     if wl.E is not None:
         sim.load_fields(wl.E, wl.B)
-    tune = None
-    if args.tune_steps > 0:
-        log("autotune")
-        tune = sim.autotune(trial_steps=args.tune_steps)
-    info = sim.info()
-
     log(f"warmup {args.warmup} steps")
     sim.step(args.warmup)
     sim.sync()
+    tune = None
+    if args.tune_steps > 0:
+        # tuned on the state the warm-up reached (the loaded state of a driven
+        # plasma is quieter than the run it starts)
+        log("autotune")
+        tune = sim.autotune(trial_steps=args.tune_steps)
+        sim.step(args.warmup)
+        sim.sync()
+    info = sim.info()
 
     log(f"timing {args.steps} steps")
     elapsed = timed_steps(sim, stream, args.steps)

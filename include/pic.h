@@ -196,9 +196,10 @@ pic_status pic_get_info(const pic_ctx* ctx, pic_info* out);
  * best so far:
  *   particles per tile -- every instance's tile shape is re-derived from a
  *                         target number of particles per tile (its mean
- *                         particles per cell), among the tile extents valid
- *                         for its grid and sort interval and whose fused
- *                         kernel fits the LDS;
+ *                         particles per cell) and a preferred x:y aspect
+ *                         (1, 2, 4, 8), among the tile extents valid for its
+ *                         grid and sort interval and whose fused kernel fits
+ *                         the LDS;
  *   sort_interval      -- steps between rebin checks (a longer interval
  *                         widens the slack each tile stages);
  *   chunk              -- maximum particles one workgroup takes from a tile

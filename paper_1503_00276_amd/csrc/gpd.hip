@@ -88,8 +88,12 @@ __device__ __forceinline__ void gather_weights(float eps, bool half, int& base, 
 // cells away.  When no knot of the shape is crossed D is formed from factored
 // differences (proportional to the displacement), keeping full FP32 relative
 // accuracy for small moves; otherwise D = S1 - S0 directly.
+// p0 (0 or 1) is the window position of the old shape's first node and wide
+// is true when the new shape's support is shifted by one node (the union
+// then fills all ORDER+2 window positions; otherwise D vanishes outside the
+// ORDER+1 positions p0 .. p0+ORDER).
 template <int ORDER>
-__device__ __forceinline__ void deposit_shape(float e0, float e1, int c, int& base,
+__device__ __forceinline__ void deposit_shape(float e0, float e1, int c, int& base, int& p0, bool& wide,
                                               float S0[ORDER + 2], float D[ORDER + 2]) {
   constexpr int W = ORDER + 2;
 #pragma unroll
@@ -100,7 +104,8 @@ __device__ __forceinline__ void deposit_shape(float e0, float e1, int c, int& ba
   if constexpr (ORDER == 1) {
     // old nodes 0,1; new nodes c, c+1
     base = c < 0 ? -1 : 0;
-    int p0 = -base;  // window position of old node 0
+    p0 = -base;  // window position of old node 0
+    wide = c != 0;
     float a0 = 1.0f - e0;
     if (p0 == 0) {
       S0[0] = a0;
@@ -130,7 +135,8 @@ __device__ __forceinline__ void deposit_shape(float e0, float e1, int c, int& ba
     float t0 = e0 - (float)h0, t1 = e1 - (float)h1;
     int nlo = n0 < n1 ? n0 : n1;
     base = nlo - 1;
-    int p0 = n0 - 1 - base;  // 0 or 1
+    p0 = n0 - 1 - base;  // 0 or 1
+    wide = n1 != n0;
     float a = 0.5f - t0, b = 0.5f + t0;
     float w0 = 0.5f * a * a, w1 = 0.75f - t0 * t0, w2 = 0.5f * b * b;
     if (p0 == 0) {
@@ -162,7 +168,8 @@ __device__ __forceinline__ void deposit_shape(float e0, float e1, int c, int& ba
   } else {
     // old nodes -1..2 (floor = 0), new nodes c-1..c+2
     base = (c < 0 ? c : 0) - 1;
-    int p0 = -1 - base;  // 0 or 1
+    p0 = -1 - base;  // 0 or 1
+    wide = c != 0;
     const float s6 = 1.0f / 6.0f;
     float g0 = 1.0f - e0, f2 = e0 * e0, f3 = f2 * e0;
     float w0 = g0 * g0 * g0 * s6, w1 = (4.0f - 6.0f * f2 + 3.0f * f3) * s6;
@@ -210,6 +217,11 @@ __device__ __forceinline__ void lds_add(acc_t* p, float v) {
   int q = (int)v;
   if (q != 0)
     __hip_atomic_fetch_add(p, (acc_t)(long long)q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Unconditional add (for nodes whose contribution is rarely zero).
+__device__ __forceinline__ void lds_add_any(acc_t* p, float v) {
+  __hip_atomic_fetch_add(p, (acc_t)(long long)(int)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // ---------------------------------------------------------------------------
@@ -394,10 +406,11 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
     }
 
     // ---- deposit (ISIS ordering average in Esirkepov's closed form)
-    int wb[3];
+    int wb[3], p0[3];
+    bool wide[3];
     float S0[3][W], D[3][W];
 #pragma unroll
-    for (int d = 0; d < DIM; d++) deposit_shape<ORDER>(e[d], en[d], mv[d], wb[d], S0[d], D[d]);
+    for (int d = 0; d < DIM; d++) deposit_shape<ORDER>(e[d], en[d], mv[d], wb[d], p0[d], wide[d], S0[d], D[d]);
     int jx = jlo[0] + l[0] + wb[0];
     int jy = jlo[1] + l[1] + wb[1];
     acc_t* J1 = sJ;
@@ -417,23 +430,95 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
       }
     }
     if constexpr (DIM == 2) {
-      float v3 = wq * uz * gi * js;
+      // The window of ORDER+2 nodes per axis splits into a core of K = ORDER+1
+      // nodes starting at p0 (the old shape's support, never all zero) and one
+      // extra node (p0 = 1: the node below the core; p0 = 0: the node above),
+      // which is nonzero only when the support is wide along that axis.  Core
+      // adds are unconditional; the extra row, column and corner are added
+      // only by the lanes that need them, one branch per group instead of one
+      // per add.  J3 is skipped by lanes without out-of-plane motion (an
+      // in-plane laser drives none).
+      constexpr int K = ORDER + 1;
+      const float v3 = wq * uz * gi * js;
+      const bool px = p0[0] != 0, py = p0[1] != 0;
+      // core and extra of the S0, D windows (S-type: K core values) and of the
+      // prefix currents P (K-1 core values)
+      float Sx[K], Dx[K], Sy[K], Dy[K], Px[K - 1], Py[K - 1];
 #pragma unroll
-      for (int j = 0; j < W; j++) {
-        float T1 = S0[1][j] + 0.5f * D[1][j];
-        float U2 = 0.5f * S0[1][j] + (1.0f / 3.0f) * D[1][j];
-        acc_t* r1 = J1 + (jy + j) * JR[0] + jx;
-        acc_t* r3 = J3 + (jy + j) * JR[0] + jx;
-#pragma unroll
-        for (int i = 0; i < W - 1; i++) lds_add(r1 + i, P1[i] * T1);
-#pragma unroll
-        for (int i = 0; i < W; i++) lds_add(r3 + i, v3 * (S0[0][i] * T1 + D[0][i] * U2));
+      for (int k = 0; k < K; k++) {
+        Sx[k] = px ? S0[0][k + 1] : S0[0][k];
+        Dx[k] = px ? D[0][k + 1] : D[0][k];
+        Sy[k] = py ? S0[1][k + 1] : S0[1][k];
+        Dy[k] = py ? D[1][k + 1] : D[1][k];
       }
 #pragma unroll
-      for (int j = 0; j < W - 1; j++) {
-        acc_t* r2 = J2 + (jy + j) * JR[0] + jx;
+      for (int k = 0; k < K - 1; k++) {
+        Px[k] = px ? P1[k + 1] : P1[k];
+        Py[k] = py ? P2[k + 1] : P2[k];
+      }
+      const float Sxe = px ? S0[0][0] : S0[0][K], Dxe = px ? D[0][0] : D[0][K];
+      const float Sye = py ? S0[1][0] : S0[1][K], Dye = py ? D[1][0] : D[1][K];
+      const float Pxe = wide[0] ? (px ? P1[0] : P1[K - 1]) : 0.0f;
+      const float Pye = wide[1] ? (py ? P2[0] : P2[K - 1]) : 0.0f;
+      // node offsets of the extras relative to the core base, per array type
+      const int exS = px ? -1 : K, exP = px ? -1 : K - 1;
+      const int eyS = py ? -1 : K, eyP = py ? -1 : K - 1;
+      const int cx = jx + p0[0], cy = jy + p0[1];
+      const int R = JR[0];
+      // y-direction factors of J1 and J3 (T1 = S0 + D/2, U2 = S0/2 + D/3) and
+      // x-direction factor of J2 (S0 + D/2)
+      float T1[K], U2[K], X2[K];
 #pragma unroll
-        for (int i = 0; i < W; i++) lds_add(r2 + i, P2[j] * (S0[0][i] + 0.5f * D[0][i]));
+      for (int k = 0; k < K; k++) {
+        T1[k] = Sy[k] + 0.5f * Dy[k];
+        U2[k] = 0.5f * Sy[k] + (1.0f / 3.0f) * Dy[k];
+        X2[k] = Sx[k] + 0.5f * Dx[k];
+      }
+      const float T1e = Sye + 0.5f * Dye, U2e = 0.5f * Sye + (1.0f / 3.0f) * Dye;
+      const float X2e = Sxe + 0.5f * Dxe;
+      // core
+#pragma unroll
+      for (int j = 0; j < K; j++) {
+        acc_t* r1 = J1 + (cy + j) * R + cx;
+        acc_t* r3 = J3 + (cy + j) * R + cx;
+#pragma unroll
+        for (int i = 0; i < K - 1; i++) lds_add_any(r1 + i, Px[i] * T1[j]);
+        if (v3 != 0.0f) {
+#pragma unroll
+          for (int i = 0; i < K; i++) lds_add_any(r3 + i, v3 * (Sx[i] * T1[j] + Dx[i] * U2[j]));
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < K - 1; j++) {
+        acc_t* r2 = J2 + (cy + j) * R + cx;
+#pragma unroll
+        for (int i = 0; i < K; i++) lds_add_any(r2 + i, Py[j] * X2[i]);
+      }
+      // extra column (x)
+      if (wide[0]) {
+#pragma unroll
+        for (int j = 0; j < K; j++) {
+          lds_add_any(J1 + (cy + j) * R + cx + exP, Pxe * T1[j]);
+          if (v3 != 0.0f) lds_add_any(J3 + (cy + j) * R + cx + exS, v3 * (Sxe * T1[j] + Dxe * U2[j]));
+        }
+#pragma unroll
+        for (int j = 0; j < K - 1; j++) lds_add_any(J2 + (cy + j) * R + cx + exS, Py[j] * X2e);
+      }
+      // extra row (y)
+      if (wide[1]) {
+#pragma unroll
+        for (int i = 0; i < K - 1; i++) lds_add_any(J1 + (cy + eyS) * R + cx + i, Px[i] * T1e);
+#pragma unroll
+        for (int i = 0; i < K; i++) {
+          if (v3 != 0.0f) lds_add_any(J3 + (cy + eyS) * R + cx + i, v3 * (Sx[i] * T1e + Dx[i] * U2e));
+          lds_add_any(J2 + (cy + eyP) * R + cx + i, Pye * X2[i]);
+        }
+      }
+      // extra corner
+      if (wide[0] && wide[1]) {
+        lds_add_any(J1 + (cy + eyS) * R + cx + exP, Pxe * T1e);
+        if (v3 != 0.0f) lds_add_any(J3 + (cy + eyS) * R + cx + exS, v3 * (Sxe * T1e + Dxe * U2e));
+        lds_add_any(J2 + (cy + eyP) * R + cx + exS, Pye * X2e);
       }
     } else {
       int jz = jlo[2] + l[2] + wb[2];

@@ -1157,7 +1157,7 @@ pic_status sim_info(const Sim& S, int i, pic_info* out) {
 // Launch layout of a whole Sim: a particles-per-tile target (0 = keep the
 // tiles in use), the sort interval and the chunk.
 struct Layout {
-  int ppt = 0, si = 1, chunk = 2048;
+  int ppt = 0, aspect = 2, si = 1, chunk = 2048;
 };
 
 // The state an autotune restores before every candidate and at the end.
@@ -1188,10 +1188,11 @@ std::vector<int> tile_ladder(int n, int need) {
   return v;
 }
 
-// Tile shape whose volume is closest (in log) to 'cells', preferring x-long
-// tiles (contiguous field rows) and an LDS footprint that leaves room for two
-// workgroups per CU; g carries the slack of the sort interval in question.
-void tile_for_cells(const GridDesc& g0, double cells, int out[3]) {
+// Tile shape whose volume is closest (in log) to 'cells' and whose x extent
+// is closest to 'aspect' times the y extent (x-long tiles give contiguous
+// field rows), with an LDS footprint that leaves room for two workgroups per
+// CU; g carries the slack of the sort interval in question.
+void tile_for_cells(const GridDesc& g0, double cells, int aspect, int out[3]) {
   GridDesc g = g0;
   const int need = g.slack + 2;
   std::vector<int> lad[3];
@@ -1210,7 +1211,7 @@ void tile_for_cells(const GridDesc& g0, double cells, int out[3]) {
           g.tile[2] = c;
           if (pic_gpd_lds_bytes(g) > lim) continue;
           double vol = (double)a * b * c;
-          double sc = std::fabs(std::log2(vol / cells)) + 0.25 * std::fabs(std::log2((double)a / (2.0 * b)));
+          double sc = std::fabs(std::log2(vol / cells)) + 0.25 * std::fabs(std::log2((double)a / ((double)aspect * b)));
           if (g.dim == 3) sc += 0.25 * std::fabs(std::log2((double)b / c));
           if (sc < best) {
             best = sc;
@@ -1240,7 +1241,7 @@ pic_status layout_configs(Sim& S, const Layout& L, std::vector<pic_config>& out)
       int64_t n = instance_particles(I);
       double ppc = n > 0 ? (double)n / (double)g.ncell : 1.0;
       int t[3];
-      tile_for_cells(g, std::max(1.0, L.ppt / ppc), t);
+      tile_for_cells(g, std::max(1.0, L.ppt / ppc), L.aspect, t);
       for (int d = 0; d < 3; d++) c.tile[d] = d < c.ndim ? t[d] : 0;
     }
     GridDesc g;
@@ -1431,6 +1432,7 @@ pic_status sim_autotune(Sim& S, pic_tune* io) {
     return PIC_OK;
   };
   static const int kPpt[] = {256, 512, 1024, 2048, 4096, 8192};
+  static const int kAspect[] = {1, 2, 4, 8};
   static const int kSi[] = {1, 2, 3, 4, 6, 8};
   // chunks above 2048 are left out: a tile whose density grows several-fold
   // later in a run (wakes, beams) would become one long item, a tail no trial
@@ -1439,9 +1441,13 @@ pic_status sim_autotune(Sim& S, pic_tune* io) {
   for (int round = 0; round < 2 && st == PIC_OK; round++) {
     if (what & PIC_TUNE_TILE)
       for (int p : kPpt) {
-        Layout L = best;
-        L.ppt = p;
-        if ((st = consider(L)) != PIC_OK) break;
+        for (int a : kAspect) {
+          Layout L = best;
+          L.ppt = p;
+          L.aspect = a;
+          if ((st = consider(L)) != PIC_OK) break;
+        }
+        if (st != PIC_OK) break;
       }
     if (st == PIC_OK && (what & PIC_TUNE_SORT) && round == 0)
       for (int si : kSi) {

@@ -289,7 +289,21 @@ __global__ void __launch_bounds__(kBlock) rebin_scatter(const StoreDesc* __restr
       if (threadIdx.x < (kBlock / 64) * PIC_NSLOT) (&wcnt[0][0])[threadIdx.x] = 0;
       __syncthreads();
       int p = base + threadIdx.x;
-      int sl = p < it.end ? particle_slot(g, it.tile, S.cell[cur][p]) : -1;
+      // every load of the particle is issued here, before the rank
+      // computation, so the round waits for one memory latency, not two
+      const bool have = p < it.end;
+      int cell = 0, pid = 0;
+      float ev[3] = {0.0f, 0.0f, 0.0f}, uv[3] = {0.0f, 0.0f, 0.0f}, wv = 0.0f;
+      if (have) {
+        cell = S.cell[cur][p];
+        for (int d = 0; d < g.dim; d++) ev[d] = S.eps[cur][d][p];
+        uv[0] = S.u[cur][0][p];
+        uv[1] = S.u[cur][1][p];
+        uv[2] = S.u[cur][2][p];
+        wv = S.w[cur][p];
+        pid = S.id[cur][p];
+      }
+      int sl = have ? particle_slot(g, it.tile, cell) : -1;
       int rank = 0;
       unsigned long long todo = __ballot(sl >= 0);
       while (todo) {
@@ -311,13 +325,13 @@ __global__ void __launch_bounds__(kBlock) rebin_scatter(const StoreDesc* __restr
         }
       }
       if (pos >= 0) {
-        S.cell[nxt][pos] = S.cell[cur][p];
-        for (int d = 0; d < g.dim; d++) S.eps[nxt][d][pos] = S.eps[cur][d][p];
-        S.u[nxt][0][pos] = S.u[cur][0][p];
-        S.u[nxt][1][pos] = S.u[cur][1][p];
-        S.u[nxt][2][pos] = S.u[cur][2][p];
-        S.w[nxt][pos] = S.w[cur][p];
-        S.id[nxt][pos] = S.id[cur][p];
+        S.cell[nxt][pos] = cell;
+        for (int d = 0; d < g.dim; d++) S.eps[nxt][d][pos] = ev[d];
+        S.u[nxt][0][pos] = uv[0];
+        S.u[nxt][1][pos] = uv[1];
+        S.u[nxt][2][pos] = uv[2];
+        S.w[nxt][pos] = wv;
+        S.id[nxt][pos] = pid;
       }
       __syncthreads();
       if (threadIdx.x < PIC_NSLOT) {
