@@ -5,6 +5,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 """
 from .oracle import (  # noqa: F401
     Grid,
+    ISIS,
+    TRISTAN,
     build,
     shape,
     gather,

@@ -40,7 +40,11 @@ class _Grid(C.Structure):
         ("order", C.c_int32),
         ("e0", C.c_double * 3),
         ("b0", C.c_double * 3),
+        ("deposit", C.c_int32),
     ]
+
+ISIS = 0
+TRISTAN = 1
 
 
 @dataclass
@@ -55,6 +59,7 @@ class Grid:
     xmin: tuple = (0.0, 0.0, 0.0)
     e0: tuple = (0.0, 0.0, 0.0)
     b0: tuple = (0.0, 0.0, 0.0)
+    deposit: int = ISIS  # ISIS, or TRISTAN (linear shape only)
 
     def c(self) -> _Grid:
         g = _Grid()
@@ -70,6 +75,9 @@ class Grid:
             g.b0[i] = float(self.b0[i])
         g.dt = float(self.dt)
         g.order = int(self.order)
+        if self.deposit not in (ISIS, TRISTAN) or (self.deposit == TRISTAN and self.order != 1):
+            raise ValueError("TRISTAN deposit is defined for the linear shape only")
+        g.deposit = int(self.deposit)
         return g
 
     @property

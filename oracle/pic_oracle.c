@@ -58,6 +58,7 @@ typedef struct {
   int32_t order;     /* B-spline shape order: 1, 2 or 3 */
   double e0[3];      /* uniform external E added at the particle */
   double b0[3];      /* uniform external B added at the particle */
+  int32_t deposit;   /* 0: ISIS ordering average; 1: TRISTAN path split (order 1) */
 } orc_grid;
 
 /* ------------------------------------------------------------------ */
@@ -265,29 +266,80 @@ static void deposit_j3_2d(const orc_grid* g, double* J, double w, double v3,
   }
 }
 
+/* The ISIS current of one straight move pa -> pb: the average over every
+ * ordering of the orthogonal sub-moves; in 2D also the out-of-plane current
+ * with velocity v3. */
+static void deposit_isis(const orc_grid* g, double* J, double w, double v3, const double* pa,
+                         const double* pb) {
+  int dim = g->dim;
+  int nperm = dim == 3 ? 6 : 2;
+  for (int o = 0; o < nperm; o++) {
+    double cur[3] = {0, 0, 0};
+    for (int d = 0; d < dim; d++) cur[d] = pa[d];
+    for (int s = 0; s < dim; s++) {
+      int k = dim == 3 ? perm3[o][s] : perm2[o][s];
+      submove(g, J, w, cur, k, pb[k], 1.0 / nperm);
+      cur[k] = pb[k];
+    }
+  }
+  if (dim == 2) {
+    double aa[3] = {pa[0], pa[1], 0}, bb[3] = {pb[0], pb[1], 0};
+    deposit_j3_2d(g, J, w, v3, aa, bb);
+  }
+}
+
+/* The TRISTAN (Villasenor-Buneman) current of one straight move (Sec. 3.2):
+ * the same as ISIS while the particle stays in its cell; otherwise the
+ * straight path is cut where it crosses cell faces (integer coordinates
+ * for the linear shape) and each piece, which lies in one cell, deposits
+ * the ISIS current of its own move.  The out-of-plane current of a piece
+ * carries the piece's share of the time step. */
+static void deposit_tristan(const orc_grid* g, double* J, double w, double v3, const double* pa,
+                            const double* pb) {
+  int dim = g->dim;
+  double t[5];
+  int nt = 0;
+  t[nt++] = 0.0;
+  for (int d = 0; d < dim; d++) {
+    double fa = floor(pa[d]), fb = floor(pb[d]);
+    if (fa != fb) {
+      double face = fa > fb ? fa : fb; /* the one integer crossed (|move| < 1) */
+      double tc = (face - pa[d]) / (pb[d] - pa[d]);
+      if (tc > 0.0 && tc < 1.0) t[nt++] = tc;
+    }
+  }
+  t[nt++] = 1.0;
+  /* sort the cut parameters (at most five values) */
+  for (int i = 1; i < nt; i++)
+    for (int j = i; j > 0 && t[j] < t[j - 1]; j--) {
+      double x = t[j]; t[j] = t[j - 1]; t[j - 1] = x;
+    }
+  for (int k = 0; k + 1 < nt; k++) {
+    double frac = t[k + 1] - t[k];
+    if (frac <= 0.0) continue;
+    double q0[3] = {0, 0, 0}, q1[3] = {0, 0, 0};
+    for (int d = 0; d < dim; d++) {
+      q0[d] = pa[d] + t[k] * (pb[d] - pa[d]);
+      q1[d] = pa[d] + t[k + 1] * (pb[d] - pa[d]);
+    }
+    deposit_isis(g, J, w, v3 * frac, q0, q1);
+  }
+}
+
 /* Current of n particles moving from a (cell units) to b = a + delta (cell
  * units, unwrapped); v3[n] is the out-of-plane velocity (2D only).  J[3*nc]
- * is accumulated into (not cleared). */
+ * is accumulated into (not cleared).  g->deposit selects ISIS or TRISTAN. */
 void orc_deposit_cells(const orc_grid* g, int64_t n, const double* a, const double* b,
                        const double* w, const double* v3, double* J) {
   int dim = g->dim;
-  int nperm = dim == 3 ? 6 : 2;
   for (int64_t p = 0; p < n; p++) {
     const double* pa = a + p * dim;
     const double* pb = b + p * dim;
-    for (int o = 0; o < nperm; o++) {
-      double cur[3] = {0, 0, 0};
-      for (int d = 0; d < dim; d++) cur[d] = pa[d];
-      for (int s = 0; s < dim; s++) {
-        int k = dim == 3 ? perm3[o][s] : perm2[o][s];
-        submove(g, J, w[p], cur, k, pb[k], 1.0 / nperm);
-        cur[k] = pb[k];
-      }
-    }
-    if (dim == 2) {
-      double aa[3] = {pa[0], pa[1], 0}, bb[3] = {pb[0], pb[1], 0};
-      deposit_j3_2d(g, J, w[p], v3 ? v3[p] : 0.0, aa, bb);
-    }
+    double vz = v3 ? v3[p] : 0.0;
+    if (g->deposit == 1)
+      deposit_tristan(g, J, w[p], vz, pa, pb);
+    else
+      deposit_isis(g, J, w[p], vz, pa, pb);
   }
 }
 

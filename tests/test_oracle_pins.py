@@ -651,3 +651,115 @@ def test_momentum_impulse_equals_charge_times_field(orc):
     p1 = np.array(orc.particle_moments(g, r.u, w, -1.0)[1:])
     Q = w.sum() * dx[0] * dx[1]
     assert np.allclose(p1 - p0, Q * np.array(e0) * dt, rtol=1e-12, atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# TRISTAN (Villasenor-Buneman) deposit, Sec. 3.2 (linear shape)
+# --------------------------------------------------------------------------
+
+
+def _tristan_golden():
+    rows = {"2d": {}, "3d": {}}
+    with open(os.path.join(GOLD, "tristan_deposit.txt")) as f:
+        for line in f:
+            t = line.split()
+            if not t or t[0].startswith("#"):
+                continue
+            key = tuple(int(v) for v in t[2:-1])
+            rows[t[0]][(t[1], key)] = float(t[-1])
+    return rows
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_tristan_worked_example(orc, dim):
+    """Hand-derived currents of a move that crosses one x face."""
+    gold = _tristan_golden()["%dd" % dim]
+    nx = (8,) * dim
+    dx = (0.2, 0.25, 0.3)[:dim]
+    g = orc.Grid(dim=dim, nx=nx, dx=dx, dt=0.1, order=1, deposit=orc.TRISTAN)
+    a = np.array([[2.5, 3.5, 4.5][:dim]])
+    b = np.array([[3.5, 3.7, 4.4][:dim]])
+    J = orc.deposit_cells(g, a, b, np.array([1.0]))
+    comp = {"J1": 0, "J2": 1, "J3": 2}
+    for (c, ijk), v in gold.items():
+        idx = ijk[0] + nx[0] * (ijk[1] + (nx[1] * ijk[2] if dim == 3 else 0))
+        assert abs(J[comp[c], idx] - v) < 1e-13, (c, ijk, J[comp[c], idx], v)
+    if dim == 2:
+        # every other J1/J2 node is zero
+        nz = {(comp[c], ijk[0] + nx[0] * ijk[1]) for (c, ijk) in gold}
+        for c in range(2):
+            for idx in np.nonzero(J[c])[0]:
+                assert (c, idx) in nz, (c, idx)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_tristan_equals_isis_inside_a_cell(orc, dim):
+    """If the particle stays within a cell both methods give the same current
+    (Sec. 3.2)."""
+    rng = np.random.default_rng(21 + dim)
+    nx = (8,) * dim
+    dx = (0.2, 0.25, 0.3)[:dim]
+    gi = orc.Grid(dim=dim, nx=nx, dx=dx, dt=0.1, order=1)
+    gt = orc.Grid(dim=dim, nx=nx, dx=dx, dt=0.1, order=1, deposit=orc.TRISTAN)
+    for _ in range(20):
+        c = rng.integers(2, 5, size=dim)
+        a = c + rng.uniform(0.05, 0.95, dim)
+        b = c + rng.uniform(0.05, 0.95, dim)
+        w = np.array([rng.uniform(-2, 2)])
+        v3 = np.array([0.3])
+        Ji = orc.deposit_cells(gi, a[None], b[None], w, v3=v3)
+        Jt = orc.deposit_cells(gt, a[None], b[None], w, v3=v3)
+        assert np.abs(Ji - Jt).max() < 1e-14 * max(np.abs(Ji).max(), 1e-300)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_tristan_continuity_and_curl(orc, dim):
+    """Across cell faces TRISTAN still satisfies Eq. continuity to roundoff
+    and carries the same total current as ISIS, but a different curl."""
+    rng = np.random.default_rng(31 + dim)
+    nx = (9,) * dim
+    dx = (0.2, 0.25, 0.3)[:dim]
+    gi = orc.Grid(dim=dim, nx=nx, dx=dx, dt=0.1, order=1)
+    gt = orc.Grid(dim=dim, nx=nx, dx=dx, dt=0.1, order=1, deposit=orc.TRISTAN)
+    a, b = _moves(rng, dim, 16)
+    # force crossings of one, two (and three) faces
+    a[2] = [3.9, 4.95, 3.97][:dim]
+    b[2] = [4.3, 5.2, 4.1][:dim]
+    w = rng.uniform(-2, 2, len(a))
+    differs = False
+    for p in range(len(a)):
+        Jt = orc.deposit_cells(gt, a[p:p + 1], b[p:p + 1], w[p:p + 1], v3=0.3)
+        Ji = orc.deposit_cells(gi, a[p:p + 1], b[p:p + 1], w[p:p + 1], v3=0.3)
+        r0 = orc.rho(gt, a[p:p + 1] * dx, w[p:p + 1])
+        r1 = orc.rho(gt, b[p:p + 1] * dx, w[p:p + 1])
+        C = orc.charge_residual(gt, r0, r1, Jt)
+        assert np.abs(C).max() < 1e-13 * np.abs(r0).max() / gt.dt
+        for d in range(dim):  # sum rule: total current = charge x velocity
+            assert abs(Jt[d].sum() - Ji[d].sum()) < 1e-13 * max(abs(Ji[d].sum()), 1e-12)
+        if np.abs(Jt[:dim] - Ji[:dim]).max() > 1e-6 * np.abs(Ji[:dim]).max():
+            differs = True
+    assert differs
+
+
+def test_tristan_out_of_plane_current_is_the_path_average(orc):
+    """2D J3 = w v3 times the time average of S(x(t)) S(y(t)) along the
+    straight path, evaluated here by adaptive quadrature with breakpoints at
+    the face crossings."""
+    from scipy.integrate import quad
+
+    nx, dx = (8, 8), (0.2, 0.25)
+    g = orc.Grid(dim=2, nx=nx, dx=dx, dt=0.1, order=1, deposit=orc.TRISTAN)
+    rng = np.random.default_rng(41)
+    for _ in range(6):
+        a = rng.uniform(2.2, 4.8, 2)
+        b = a + rng.uniform(-0.95, 0.95, 2)
+        w, v3 = 0.7, -0.4
+        J = orc.deposit_cells(g, a[None], b[None], np.array([w]), v3=np.array([v3]))
+        cuts = sorted({(f - a[d]) / (b[d] - a[d]) for d in range(2) for f in range(1, 8)
+                       if min(a[d], b[d]) < f < max(a[d], b[d])})
+        for j in range(1, 7):
+            for i in range(1, 7):
+                f = lambda t: max(0.0, 1 - abs(a[0] + t * (b[0] - a[0]) - i)) * \
+                    max(0.0, 1 - abs(a[1] + t * (b[1] - a[1]) - j))
+                val, _ = quad(f, 0, 1, points=cuts or None, epsabs=1e-14, epsrel=1e-13)
+                assert abs(J[2, i + nx[0] * j] - w * v3 * val) < 1e-12, (i, j)
