@@ -100,7 +100,18 @@ typedef struct {
   int32_t chunk;         /* maximum particles one workgroup takes from a tile;
                             0 = 2048 (searched by pic_autotune) */
   int32_t accumulator;   /* PIC_ACC_* */
+  int32_t deposit;       /* PIC_DEPOSIT_*: which charge-conserving current */
 } pic_config;
+
+/* Current deposit (Sec. 3.2).  Both satisfy the continuity equation; they
+ * differ in the curl of the current when a particle crosses a cell face. */
+enum {
+  PIC_DEPOSIT_ISIS = 0,   /* average over the orderings of the orthogonal
+                             moves of the whole straight path; every shape order */
+  PIC_DEPOSIT_TRISTAN = 1 /* Villasenor-Buneman: the straight path cut at the
+                             cell faces it crosses, each piece depositing its
+                             in-cell current; linear shape (shape_order 1) only */
+};
 
 /* Flags for the load calls. */
 #define PIC_DEVICE_PTRS 1u /* input pointers are device memory */

@@ -224,6 +224,95 @@ __device__ __forceinline__ void lds_add_any(acc_t* p, float v) {
   __hip_atomic_fetch_add(p, (acc_t)(long long)(int)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// TRISTAN (Villasenor-Buneman) current of one particle for the linear shape
+// (Sec. 3.2): the straight move from offset e in the old cell by dl cells
+// (|dl| < 1 per axis) is cut where it crosses cell faces; each piece lies in
+// one cell and adds that cell's in-cell current, the average over the
+// orderings of its orthogonal moves:
+//   2D  J1 on the two x edges: a1 dx (1 - ym | ym), J2 likewise, and J3 at
+//       the four nodes the piece's share of w v3 times the time average of
+//       the product of the two linear shapes;
+//   3D  J1 on the four x edges: a1 dx (Wy Wz + s dy dz / 12), s = +1 on the
+//       (0,0), (1,1) edges and -1 on the others; J2, J3 likewise.
+// b0..b2 are the LDS current-region coordinates of the old cell; a_d are
+// w (dx_d/dt) in fixed-point units, v3s = w v3 in fixed-point units (2D).
+template <int DIM>
+__device__ __forceinline__ void deposit_tristan(acc_t* sJ, int jn, const int JR[3], int b0, int b1, int b2,
+                                                const float e[3], const float dl[3], const int mv[3], float a1,
+                                                float a2, float a3, float v3s) {
+  // crossing parameter of each axis (2 when the axis stays in its cell)
+  float tc[3] = {2.0f, 2.0f, 2.0f};
+#pragma unroll
+  for (int d = 0; d < DIM; d++)
+    if (mv[d] != 0) {
+      float t = (mv[d] > 0 ? 1.0f - e[d] : -e[d]) / dl[d];
+      tc[d] = fminf(fmaxf(t, 0.0f), 1.0f);
+    }
+  // the cut parameters in increasing order
+  float c0 = tc[0], c1 = tc[1], c2 = tc[2];
+  if (c1 < c0) { float x = c0; c0 = c1; c1 = x; }
+  if (DIM == 3) {
+    if (c2 < c1) { float x = c1; c1 = c2; c2 = x; }
+    if (c1 < c0) { float x = c0; c0 = c1; c1 = x; }
+  }
+  const float cut[4] = {c0, c1, c2, 2.0f};
+  acc_t* J1 = sJ;
+  acc_t* J2 = sJ + jn;
+  acc_t* J3 = sJ + 2 * jn;
+  const int R0 = JR[0], R01 = JR[0] * JR[1];
+  float ta = 0.0f;
+#pragma unroll
+  for (int s = 0; s <= DIM; s++) {
+    const float tb = fminf(cut[s], 1.0f);
+    if (tb > ta) {
+      float pa[3], pb[3];
+      int o[3] = {0, 0, 0};
+#pragma unroll
+      for (int d = 0; d < DIM; d++) {
+        o[d] = (mv[d] != 0 && tc[d] <= ta) ? mv[d] : 0;  // faces crossed before this piece
+        pa[d] = fminf(fmaxf(e[d] + ta * dl[d] - (float)o[d], 0.0f), 1.0f);
+        pb[d] = fminf(fmaxf(e[d] + tb * dl[d] - (float)o[d], 0.0f), 1.0f);
+      }
+      const float dx = pb[0] - pa[0], dy = pb[1] - pa[1];
+      const float xm = 0.5f * (pa[0] + pb[0]), ym = 0.5f * (pa[1] + pb[1]);
+      if constexpr (DIM == 2) {
+        const int c = (b1 + o[1]) * R0 + b0 + o[0];
+        const float f1 = a1 * dx, f2 = a2 * dy;
+        lds_add(J1 + c, f1 * (1.0f - ym));
+        lds_add(J1 + c + R0, f1 * ym);
+        lds_add(J2 + c, f2 * (1.0f - xm));
+        lds_add(J2 + c + 1, f2 * xm);
+        const float f3 = v3s * (tb - ta);
+        const float sxa[2] = {1.0f - pa[0], pa[0]}, sxb[2] = {1.0f - pb[0], pb[0]};
+        const float sya[2] = {1.0f - pa[1], pa[1]}, syb[2] = {1.0f - pb[1], pb[1]};
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+          for (int i = 0; i < 2; i++)
+            lds_add(J3 + c + j * R0 + i,
+                    f3 * ((sxa[i] * sya[j] + sxb[i] * syb[j]) * (1.0f / 3.0f) +
+                          (sxa[i] * syb[j] + sxb[i] * sya[j]) * (1.0f / 6.0f)));
+      } else {
+        const float dz = pb[2] - pa[2], zm = 0.5f * (pa[2] + pb[2]);
+        const int c = ((b2 + o[2]) * JR[1] + b1 + o[1]) * R0 + b0 + o[0];
+        const float Wx[2] = {1.0f - xm, xm}, Wy[2] = {1.0f - ym, ym}, Wz[2] = {1.0f - zm, zm};
+        const float s[2] = {-1.0f, 1.0f};
+        const float yz = dy * dz * (1.0f / 12.0f), xz = dx * dz * (1.0f / 12.0f), xy = dx * dy * (1.0f / 12.0f);
+        const float f1 = a1 * dx, f2 = a2 * dy, f3 = a3 * dz;
+#pragma unroll
+        for (int k = 0; k < 2; k++)
+#pragma unroll
+          for (int j = 0; j < 2; j++) {
+            lds_add(J1 + c + k * R01 + j * R0, f1 * (Wy[j] * Wz[k] + s[j] * s[k] * yz));
+            lds_add(J2 + c + k * R01 + j, f2 * (Wx[j] * Wz[k] + s[j] * s[k] * xz));
+            lds_add(J3 + c + k * R0 + j, f3 * (Wx[j] * Wy[k] + s[j] * s[k] * xy));
+          }
+      }
+    }
+    ta = fmaxf(ta, tb);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // one work item
 // ---------------------------------------------------------------------------
@@ -405,176 +494,189 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
       mv[d] = c;
     }
 
-    // ---- deposit (ISIS ordering average in Esirkepov's closed form)
-    int wb[3], p0[3];
-    bool wide[3];
-    float S0[3][W], D[3][W];
+    // ---- deposit
+    if (ORDER == 1 && g.deposit == 1) {
+      // TRISTAN: the straight move cut at the faces it crosses
+      const float js = g.jscale;
+      float dl[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int d = 0; d < DIM; d++) deposit_shape<ORDER>(e[d], en[d], mv[d], wb[d], p0[d], wide[d], S0[d], D[d]);
-    int jx = jlo[0] + l[0] + wb[0];
-    int jy = jlo[1] + l[1] + wb[1];
-    acc_t* J1 = sJ;
-    acc_t* J2 = sJ + jn;
-    acc_t* J3 = sJ + 2 * jn;
-    const float js = g.jscale;
-    float q1 = -wq * g.cdt[0] * js, q2 = -wq * g.cdt[1] * js;
-    float P1[W - 1], P2[W - 1];
-    {
-      float a = 0.0f, b = 0.0f;
-#pragma unroll
-      for (int k = 0; k < W - 1; k++) {
-        a += D[0][k];
-        b += D[1][k];
-        P1[k] = q1 * a;
-        P2[k] = q2 * b;
-      }
-    }
-    if constexpr (DIM == 2) {
-      // The window of ORDER+2 nodes per axis splits into a core of K = ORDER+1
-      // nodes starting at p0 (the old shape's support, never all zero) and one
-      // extra node (p0 = 1: the node below the core; p0 = 0: the node above),
-      // which is nonzero only when the support is wide along that axis.  Core
-      // adds are unconditional; the extra row, column and corner are added
-      // only by the lanes that need them, one branch per group instead of one
-      // per add.  J3 is skipped by lanes without out-of-plane motion (an
-      // in-plane laser drives none).
-      constexpr int K = ORDER + 1;
-      const float v3 = wq * uz * gi * js;
-      const bool px = p0[0] != 0, py = p0[1] != 0;
-      // core and extra of the S0, D windows (S-type: K core values) and of the
-      // prefix currents P (K-1 core values)
-      float Sx[K], Dx[K], Sy[K], Dy[K], Px[K - 1], Py[K - 1];
-#pragma unroll
-      for (int k = 0; k < K; k++) {
-        Sx[k] = px ? S0[0][k + 1] : S0[0][k];
-        Dx[k] = px ? D[0][k + 1] : D[0][k];
-        Sy[k] = py ? S0[1][k + 1] : S0[1][k];
-        Dy[k] = py ? D[1][k + 1] : D[1][k];
-      }
-#pragma unroll
-      for (int k = 0; k < K - 1; k++) {
-        Px[k] = px ? P1[k + 1] : P1[k];
-        Py[k] = py ? P2[k + 1] : P2[k];
-      }
-      const float Sxe = px ? S0[0][0] : S0[0][K], Dxe = px ? D[0][0] : D[0][K];
-      const float Sye = py ? S0[1][0] : S0[1][K], Dye = py ? D[1][0] : D[1][K];
-      const float Pxe = wide[0] ? (px ? P1[0] : P1[K - 1]) : 0.0f;
-      const float Pye = wide[1] ? (py ? P2[0] : P2[K - 1]) : 0.0f;
-      // node offsets of the extras relative to the core base, per array type
-      const int exS = px ? -1 : K, exP = px ? -1 : K - 1;
-      const int eyS = py ? -1 : K, eyP = py ? -1 : K - 1;
-      const int cx = jx + p0[0], cy = jy + p0[1];
-      const int R = JR[0];
-      // y-direction factors of J1 and J3 (T1 = S0 + D/2, U2 = S0/2 + D/3) and
-      // x-direction factor of J2 (S0 + D/2)
-      float T1[K], U2[K], X2[K];
-#pragma unroll
-      for (int k = 0; k < K; k++) {
-        T1[k] = Sy[k] + 0.5f * Dy[k];
-        U2[k] = 0.5f * Sy[k] + (1.0f / 3.0f) * Dy[k];
-        X2[k] = Sx[k] + 0.5f * Dx[k];
-      }
-      const float T1e = Sye + 0.5f * Dye, U2e = 0.5f * Sye + (1.0f / 3.0f) * Dye;
-      const float X2e = Sxe + 0.5f * Dxe;
-      // core
-#pragma unroll
-      for (int j = 0; j < K; j++) {
-        acc_t* r1 = J1 + (cy + j) * R + cx;
-        acc_t* r3 = J3 + (cy + j) * R + cx;
-#pragma unroll
-        for (int i = 0; i < K - 1; i++) lds_add_any(r1 + i, Px[i] * T1[j]);
-        if (v3 != 0.0f) {
-#pragma unroll
-          for (int i = 0; i < K; i++) lds_add_any(r3 + i, v3 * (Sx[i] * T1[j] + Dx[i] * U2[j]));
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < K - 1; j++) {
-        acc_t* r2 = J2 + (cy + j) * R + cx;
-#pragma unroll
-        for (int i = 0; i < K; i++) lds_add_any(r2 + i, Py[j] * X2[i]);
-      }
-      // extra column (x)
-      if (wide[0]) {
-#pragma unroll
-        for (int j = 0; j < K; j++) {
-          lds_add_any(J1 + (cy + j) * R + cx + exP, Pxe * T1[j]);
-          if (v3 != 0.0f) lds_add_any(J3 + (cy + j) * R + cx + exS, v3 * (Sxe * T1[j] + Dxe * U2[j]));
-        }
-#pragma unroll
-        for (int j = 0; j < K - 1; j++) lds_add_any(J2 + (cy + j) * R + cx + exS, Py[j] * X2e);
-      }
-      // extra row (y)
-      if (wide[1]) {
-#pragma unroll
-        for (int i = 0; i < K - 1; i++) lds_add_any(J1 + (cy + eyS) * R + cx + i, Px[i] * T1e);
-#pragma unroll
-        for (int i = 0; i < K; i++) {
-          if (v3 != 0.0f) lds_add_any(J3 + (cy + eyS) * R + cx + i, v3 * (Sx[i] * T1e + Dx[i] * U2e));
-          lds_add_any(J2 + (cy + eyP) * R + cx + i, Pye * X2[i]);
-        }
-      }
-      // extra corner
-      if (wide[0] && wide[1]) {
-        lds_add_any(J1 + (cy + eyS) * R + cx + exP, Pxe * T1e);
-        if (v3 != 0.0f) lds_add_any(J3 + (cy + eyS) * R + cx + exS, v3 * (Sxe * T1e + Dxe * U2e));
-        lds_add_any(J2 + (cy + eyP) * R + cx + exS, Pye * X2e);
-      }
+      for (int d = 0; d < DIM; d++) dl[d] = (float)mv[d] + en[d] - e[d];
+      const int b0 = jlo[0] + l[0], b1 = jlo[1] + l[1], b2 = DIM == 3 ? jlo[2] + l[2] : 0;
+      deposit_tristan<DIM>(sJ, jn, JR, b0, b1, b2, e, dl, mv, wq * g.cdt[0] * js, wq * g.cdt[1] * js,
+                           wq * g.cdt[2] * js, wq * uz * gi * js);
     } else {
-      int jz = jlo[2] + l[2] + wb[2];
-      float q3 = -wq * g.cdt[2] * js;
-      float P3[W - 1];
+      // ISIS ordering average in Esirkepov's closed form
+      int wb[3], p0[3];
+      bool wide[3];
+      float S0[3][W], D[3][W];
+  #pragma unroll
+      for (int d = 0; d < DIM; d++) deposit_shape<ORDER>(e[d], en[d], mv[d], wb[d], p0[d], wide[d], S0[d], D[d]);
+      int jx = jlo[0] + l[0] + wb[0];
+      int jy = jlo[1] + l[1] + wb[1];
+      acc_t* J1 = sJ;
+      acc_t* J2 = sJ + jn;
+      acc_t* J3 = sJ + 2 * jn;
+      const float js = g.jscale;
+      float q1 = -wq * g.cdt[0] * js, q2 = -wq * g.cdt[1] * js;
+      float P1[W - 1], P2[W - 1];
       {
-        float a = 0.0f;
-#pragma unroll
+        float a = 0.0f, b = 0.0f;
+  #pragma unroll
         for (int k = 0; k < W - 1; k++) {
-          a += D[2][k];
-          P3[k] = q3 * a;
+          a += D[0][k];
+          b += D[1][k];
+          P1[k] = q1 * a;
+          P2[k] = q2 * b;
         }
       }
-      const float th = 1.0f / 3.0f;
-      // J1: P1[i] * T1[k][j]
-#pragma unroll
-      for (int k = 0; k < W; k++) {
-#pragma unroll
+      if constexpr (DIM == 2) {
+        // The window of ORDER+2 nodes per axis splits into a core of K = ORDER+1
+        // nodes starting at p0 (the old shape's support, never all zero) and one
+        // extra node (p0 = 1: the node below the core; p0 = 0: the node above),
+        // which is nonzero only when the support is wide along that axis.  Core
+        // adds are unconditional; the extra row, column and corner are added
+        // only by the lanes that need them, one branch per group instead of one
+        // per add.  J3 is skipped by lanes without out-of-plane motion (an
+        // in-plane laser drives none).
+        constexpr int K = ORDER + 1;
+        const float v3 = wq * uz * gi * js;
+        const bool px = p0[0] != 0, py = p0[1] != 0;
+        // core and extra of the S0, D windows (S-type: K core values) and of the
+        // prefix currents P (K-1 core values)
+        float Sx[K], Dx[K], Sy[K], Dy[K], Px[K - 1], Py[K - 1];
+  #pragma unroll
+        for (int k = 0; k < K; k++) {
+          Sx[k] = px ? S0[0][k + 1] : S0[0][k];
+          Dx[k] = px ? D[0][k + 1] : D[0][k];
+          Sy[k] = py ? S0[1][k + 1] : S0[1][k];
+          Dy[k] = py ? D[1][k + 1] : D[1][k];
+        }
+  #pragma unroll
+        for (int k = 0; k < K - 1; k++) {
+          Px[k] = px ? P1[k + 1] : P1[k];
+          Py[k] = py ? P2[k + 1] : P2[k];
+        }
+        const float Sxe = px ? S0[0][0] : S0[0][K], Dxe = px ? D[0][0] : D[0][K];
+        const float Sye = py ? S0[1][0] : S0[1][K], Dye = py ? D[1][0] : D[1][K];
+        const float Pxe = wide[0] ? (px ? P1[0] : P1[K - 1]) : 0.0f;
+        const float Pye = wide[1] ? (py ? P2[0] : P2[K - 1]) : 0.0f;
+        // node offsets of the extras relative to the core base, per array type
+        const int exS = px ? -1 : K, exP = px ? -1 : K - 1;
+        const int eyS = py ? -1 : K, eyP = py ? -1 : K - 1;
+        const int cx = jx + p0[0], cy = jy + p0[1];
+        const int R = JR[0];
+        // y-direction factors of J1 and J3 (T1 = S0 + D/2, U2 = S0/2 + D/3) and
+        // x-direction factor of J2 (S0 + D/2)
+        float T1[K], U2[K], X2[K];
+  #pragma unroll
+        for (int k = 0; k < K; k++) {
+          T1[k] = Sy[k] + 0.5f * Dy[k];
+          U2[k] = 0.5f * Sy[k] + (1.0f / 3.0f) * Dy[k];
+          X2[k] = Sx[k] + 0.5f * Dx[k];
+        }
+        const float T1e = Sye + 0.5f * Dye, U2e = 0.5f * Sye + (1.0f / 3.0f) * Dye;
+        const float X2e = Sxe + 0.5f * Dxe;
+        // core
+  #pragma unroll
+        for (int j = 0; j < K; j++) {
+          acc_t* r1 = J1 + (cy + j) * R + cx;
+          acc_t* r3 = J3 + (cy + j) * R + cx;
+  #pragma unroll
+          for (int i = 0; i < K - 1; i++) lds_add_any(r1 + i, Px[i] * T1[j]);
+          if (v3 != 0.0f) {
+  #pragma unroll
+            for (int i = 0; i < K; i++) lds_add_any(r3 + i, v3 * (Sx[i] * T1[j] + Dx[i] * U2[j]));
+          }
+        }
+  #pragma unroll
+        for (int j = 0; j < K - 1; j++) {
+          acc_t* r2 = J2 + (cy + j) * R + cx;
+  #pragma unroll
+          for (int i = 0; i < K; i++) lds_add_any(r2 + i, Py[j] * X2[i]);
+        }
+        // extra column (x)
+        if (wide[0]) {
+  #pragma unroll
+          for (int j = 0; j < K; j++) {
+            lds_add_any(J1 + (cy + j) * R + cx + exP, Pxe * T1[j]);
+            if (v3 != 0.0f) lds_add_any(J3 + (cy + j) * R + cx + exS, v3 * (Sxe * T1[j] + Dxe * U2[j]));
+          }
+  #pragma unroll
+          for (int j = 0; j < K - 1; j++) lds_add_any(J2 + (cy + j) * R + cx + exS, Py[j] * X2e);
+        }
+        // extra row (y)
+        if (wide[1]) {
+  #pragma unroll
+          for (int i = 0; i < K - 1; i++) lds_add_any(J1 + (cy + eyS) * R + cx + i, Px[i] * T1e);
+  #pragma unroll
+          for (int i = 0; i < K; i++) {
+            if (v3 != 0.0f) lds_add_any(J3 + (cy + eyS) * R + cx + i, v3 * (Sx[i] * T1e + Dx[i] * U2e));
+            lds_add_any(J2 + (cy + eyP) * R + cx + i, Pye * X2[i]);
+          }
+        }
+        // extra corner
+        if (wide[0] && wide[1]) {
+          lds_add_any(J1 + (cy + eyS) * R + cx + exP, Pxe * T1e);
+          if (v3 != 0.0f) lds_add_any(J3 + (cy + eyS) * R + cx + exS, v3 * (Sxe * T1e + Dxe * U2e));
+          lds_add_any(J2 + (cy + eyP) * R + cx + exS, Pye * X2e);
+        }
+      } else {
+        int jz = jlo[2] + l[2] + wb[2];
+        float q3 = -wq * g.cdt[2] * js;
+        float P3[W - 1];
+        {
+          float a = 0.0f;
+  #pragma unroll
+          for (int k = 0; k < W - 1; k++) {
+            a += D[2][k];
+            P3[k] = q3 * a;
+          }
+        }
+        const float th = 1.0f / 3.0f;
+        // J1: P1[i] * T1[k][j]
+  #pragma unroll
+        for (int k = 0; k < W; k++) {
+  #pragma unroll
+          for (int j = 0; j < W; j++) {
+            float T = S0[1][j] * S0[2][k] + 0.5f * (D[1][j] * S0[2][k] + S0[1][j] * D[2][k]) +
+                      th * D[1][j] * D[2][k];
+            acc_t* r = J1 + ((jz + k) * JR[1] + (jy + j)) * JR[0] + jx;
+  #pragma unroll
+            for (int i = 0; i < W - 1; i++) lds_add(r + i, P1[i] * T);
+          }
+        }
+        // J2: P2[j] * T2[k][i]
+  #pragma unroll
+        for (int k = 0; k < W; k++) {
+          float Tk[W];
+  #pragma unroll
+          for (int i = 0; i < W; i++)
+            Tk[i] = S0[0][i] * S0[2][k] + 0.5f * (D[0][i] * S0[2][k] + S0[0][i] * D[2][k]) +
+                    th * D[0][i] * D[2][k];
+  #pragma unroll
+          for (int j = 0; j < W - 1; j++) {
+            acc_t* r = J2 + ((jz + k) * JR[1] + (jy + j)) * JR[0] + jx;
+  #pragma unroll
+            for (int i = 0; i < W; i++) lds_add(r + i, P2[j] * Tk[i]);
+          }
+        }
+        // J3: P3[k] * T3[j][i]
+  #pragma unroll
         for (int j = 0; j < W; j++) {
-          float T = S0[1][j] * S0[2][k] + 0.5f * (D[1][j] * S0[2][k] + S0[1][j] * D[2][k]) +
-                    th * D[1][j] * D[2][k];
-          acc_t* r = J1 + ((jz + k) * JR[1] + (jy + j)) * JR[0] + jx;
-#pragma unroll
-          for (int i = 0; i < W - 1; i++) lds_add(r + i, P1[i] * T);
+          float Tj[W];
+  #pragma unroll
+          for (int i = 0; i < W; i++)
+            Tj[i] = S0[0][i] * S0[1][j] + 0.5f * (D[0][i] * S0[1][j] + S0[0][i] * D[1][j]) +
+                    th * D[0][i] * D[1][j];
+  #pragma unroll
+          for (int k = 0; k < W - 1; k++) {
+            acc_t* r = J3 + ((jz + k) * JR[1] + (jy + j)) * JR[0] + jx;
+  #pragma unroll
+            for (int i = 0; i < W; i++) lds_add(r + i, P3[k] * Tj[i]);
+          }
         }
       }
-      // J2: P2[j] * T2[k][i]
-#pragma unroll
-      for (int k = 0; k < W; k++) {
-        float Tk[W];
-#pragma unroll
-        for (int i = 0; i < W; i++)
-          Tk[i] = S0[0][i] * S0[2][k] + 0.5f * (D[0][i] * S0[2][k] + S0[0][i] * D[2][k]) +
-                  th * D[0][i] * D[2][k];
-#pragma unroll
-        for (int j = 0; j < W - 1; j++) {
-          acc_t* r = J2 + ((jz + k) * JR[1] + (jy + j)) * JR[0] + jx;
-#pragma unroll
-          for (int i = 0; i < W; i++) lds_add(r + i, P2[j] * Tk[i]);
-        }
-      }
-      // J3: P3[k] * T3[j][i]
-#pragma unroll
-      for (int j = 0; j < W; j++) {
-        float Tj[W];
-#pragma unroll
-        for (int i = 0; i < W; i++)
-          Tj[i] = S0[0][i] * S0[1][j] + 0.5f * (D[0][i] * S0[1][j] + S0[0][i] * D[1][j]) +
-                  th * D[0][i] * D[1][j];
-#pragma unroll
-        for (int k = 0; k < W - 1; k++) {
-          acc_t* r = J3 + ((jz + k) * JR[1] + (jy + j)) * JR[0] + jx;
-#pragma unroll
-          for (int i = 0; i < W; i++) lds_add(r + i, P3[k] * Tj[i]);
-        }
-      }
+
     }
 
     // ---- store the new state; count the particle's rebin slot

@@ -33,6 +33,7 @@ struct GridDesc {
   // jinv = 1/jscale (a power of two) and summed exactly in int64
   float jscale, jinv;
   int acc_mode;       // 0/1: FP32 fold of the tile sums, 2: int64 fold (deterministic)
+  int deposit;        // 0: ISIS ordering average, 1: TRISTAN path cut at faces (linear shape)
   // LDS region geometry (nodes relative to the tile origin):
   // field region [-(slack+fa), e+slack+fb), current region [-(slack+ja), e+slack+jb)
   int fa, fb, ja, jb;

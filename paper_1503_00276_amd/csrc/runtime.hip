@@ -155,6 +155,7 @@ pic_status setup_grid(Sim& S, const pic_config& c, int sort_interval, GridDesc& 
   g.dt = (float)c.dt;
   g.dtd = c.dt;
   g.acc_mode = c.accumulator;
+  g.deposit = c.deposit;
   g.jscale = 1.0f;
   g.jinv = 1.0f;
   g.flag_slack = 1;
@@ -219,6 +220,10 @@ pic_status validate(Sim& S, const pic_config& c) {
   if (c.accumulator < PIC_ACC_FP32 || c.accumulator > PIC_ACC_FIXED64)
     return S.fail(PIC_E_INVALID, "unknown accumulator %d", c.accumulator);
   if (c.sort_interval < 0 || c.chunk < 0) return S.fail(PIC_E_INVALID, "negative sort_interval or chunk");
+  if (c.deposit != PIC_DEPOSIT_ISIS && c.deposit != PIC_DEPOSIT_TRISTAN)
+    return S.fail(PIC_E_INVALID, "unknown deposit %d", c.deposit);
+  if (c.deposit == PIC_DEPOSIT_TRISTAN && c.shape_order != 1)
+    return S.fail(PIC_E_INVALID, "the TRISTAN deposit needs the linear shape (shape_order 1)");
   for (int d = 0; d < 3; d++)
     if (!std::isfinite(c.e0[d]) || !std::isfinite(c.b0[d])) return S.fail(PIC_E_INVALID, "external field not finite");
   return PIC_OK;

@@ -28,6 +28,9 @@ PIC_ACC_FP32 = 0
 PIC_ACC_COMPENSATED = 1
 PIC_ACC_FIXED64 = 2
 
+PIC_DEPOSIT_ISIS = 0
+PIC_DEPOSIT_TRISTAN = 1
+
 PIC_DEVICE_PTRS = 1
 
 PIC_DIAG_ENERGY = 0
@@ -71,6 +74,7 @@ class pic_config(C.Structure):
         ("sort_interval", C.c_int32),
         ("chunk", C.c_int32),
         ("accumulator", C.c_int32),
+        ("deposit", C.c_int32),
     ]
 
 
@@ -173,6 +177,7 @@ class Config:
     sort_interval: int = 0
     chunk: int = 0
     accumulator: int = PIC_ACC_FP32
+    deposit: int = PIC_DEPOSIT_ISIS
 
     def c(self) -> pic_config:
         c = pic_config()
@@ -191,6 +196,7 @@ class Config:
         c.sort_interval = int(self.sort_interval)
         c.chunk = int(self.chunk)
         c.accumulator = int(self.accumulator)
+        c.deposit = int(self.deposit)
         return c
 
     @property

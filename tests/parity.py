@@ -20,7 +20,8 @@ F_TOL = 1e-5
 
 def oracle_grid(orc, cfg):
     return orc.Grid(dim=cfg.ndim, nx=tuple(cfg.nx[:cfg.ndim]), dx=tuple(cfg.dx[:cfg.ndim]), dt=cfg.dt,
-                    order=cfg.shape_order, xmin=tuple(cfg.xmin), e0=tuple(cfg.e0), b0=tuple(cfg.b0))
+                    order=cfg.shape_order, xmin=tuple(cfg.xmin), e0=tuple(cfg.e0), b0=tuple(cfg.b0),
+                    deposit=getattr(cfg, "deposit", 0))
 
 
 def periodic_dx(a, b, L):

@@ -120,3 +120,9 @@ def test_null_arguments_rejected():
     assert L.pic_autotune(None, None) == pic.PIC_E_INVALID
     assert L.pic_batch_autotune(None, None) == pic.PIC_E_INVALID
     assert L.pic_batch_get_info(None, 0, None) == pic.PIC_E_INVALID
+
+
+def test_tristan_needs_linear_shape():
+    pic, _ = _lib()
+    assert _create_status(pic, shape_order=2, deposit=pic.PIC_DEPOSIT_TRISTAN) == pic.PIC_E_INVALID
+    assert _create_status(pic, shape_order=1, deposit=7) == pic.PIC_E_INVALID
