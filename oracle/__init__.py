@@ -20,4 +20,5 @@ from .oracle import (  # noqa: F401
     charge_residual,
     field_energy,
     particle_moments,
+    smooth_current,
 )

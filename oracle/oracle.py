@@ -41,6 +41,8 @@ class _Grid(C.Structure):
         ("e0", C.c_double * 3),
         ("b0", C.c_double * 3),
         ("deposit", C.c_int32),
+        ("smooth_level", C.c_int32 * 3),
+        ("smooth_w", C.c_double * 72),
     ]
 
 ISIS = 0
@@ -60,6 +62,7 @@ class Grid:
     e0: tuple = (0.0, 0.0, 0.0)
     b0: tuple = (0.0, 0.0, 0.0)
     deposit: int = ISIS  # ISIS, or TRISTAN (linear shape only)
+    smooth: tuple = ()    # per axis: a list of (a, b, c) weights, one per smoothing pass
 
     def c(self) -> _Grid:
         g = _Grid()
@@ -78,6 +81,13 @@ class Grid:
         if self.deposit not in (ISIS, TRISTAN) or (self.deposit == TRISTAN and self.order != 1):
             raise ValueError("TRISTAN deposit is defined for the linear shape only")
         g.deposit = int(self.deposit)
+        for ax, passes in enumerate(self.smooth):
+            if len(passes) > 8:
+                raise ValueError("at most 8 smoothing passes per axis")
+            g.smooth_level[ax] = len(passes)
+            for p, wts in enumerate(passes):
+                for k in range(3):
+                    g.smooth_w[(ax * 8 + p) * 3 + k] = float(wts[k])
         return g
 
     @property
@@ -118,6 +128,7 @@ def _L():
         lib.orc_charge_residual.argtypes = [G, P, P, P, P]
         lib.orc_field_energy.argtypes = [G, P, P, P]
         lib.orc_particle_moments.argtypes = [G, C.c_int64, P, P, P, P]
+        lib.orc_smooth_current.argtypes = [G, P]
         _lib = lib
     return _lib
 
@@ -199,6 +210,14 @@ def yee_e(g: Grid, E, B, J, dt):
     gc = g.c()
     _L().orc_yee_e(C.byref(gc), _p(E), _p(B), _p(J), float(dt))
     return E
+
+
+def smooth_current(g: Grid, J):
+    """The current after the smoothing passes of g (returns a new array)."""
+    J = _f64(J).reshape(3, g.ncell).copy()
+    gc = g.c()
+    _L().orc_smooth_current(C.byref(gc), _p(J))
+    return J
 
 
 @dataclass

@@ -59,6 +59,8 @@ typedef struct {
   double e0[3];      /* uniform external E added at the particle */
   double b0[3];      /* uniform external B added at the particle */
   int32_t deposit;   /* 0: ISIS ordering average; 1: TRISTAN path split (order 1) */
+  int32_t smooth_level[3];        /* current smoothing passes along each axis (0: none) */
+  double smooth_w[3][8][3];       /* 3-point weights of each pass, normalised by their sum */
 } orc_grid;
 
 /* ------------------------------------------------------------------ */
@@ -343,6 +345,36 @@ void orc_deposit_cells(const orc_grid* g, int64_t n, const double* a, const doub
   }
 }
 
+/* Smoothing of the current (App. A, current smoothing section): along each
+ * axis separately, smooth_level passes over nearest neighbours, pass p with
+ * the weights (a, b, c) / (a + b + c):
+ *   J[i] <- (a J[i-1] + b J[i] + c J[i+1]) / (a + b + c),
+ * applied to every component, periodic.  Axes are taken in order 1, 2, 3. */
+void orc_smooth_current(const orc_grid* g, double* J) {
+  int64_t nc = ncells(g);
+  double* tmp = (double*)malloc(sizeof(double) * (size_t)nc);
+  if (!tmp) return;
+  for (int ax = 0; ax < g->dim; ax++) {
+    int64_t stride = ax == 0 ? 1 : (ax == 1 ? g->nx[0] : (int64_t)g->nx[0] * g->nx[1]);
+    int n = g->nx[ax];
+    for (int pass = 0; pass < g->smooth_level[ax]; pass++) {
+      double a = g->smooth_w[ax][pass][0], b = g->smooth_w[ax][pass][1], c = g->smooth_w[ax][pass][2];
+      double s = a + b + c;
+      for (int comp = 0; comp < 3; comp++) {
+        double* V = J + comp * nc;
+        for (int64_t q = 0; q < nc; q++) {
+          int64_t i = (q / stride) % n;
+          int64_t qm = q + ((i == 0) ? (int64_t)(n - 1) * stride : -stride);
+          int64_t qp = q + ((i == n - 1) ? -(int64_t)(n - 1) * stride : stride);
+          tmp[q] = (a * V[qm] + b * V[q] + c * V[qp]) / s;
+        }
+        memcpy(V, tmp, sizeof(double) * (size_t)nc);
+      }
+    }
+  }
+  free(tmp);
+}
+
 /* Charge density of n particles at the rho nodes (accumulated). */
 void orc_rho(const orc_grid* g, int64_t n, const double* x, const double* w, double* rho) {
   int dim = g->dim;
@@ -466,6 +498,7 @@ int orc_step(const orc_grid* g, int64_t n, double* x, double* u, const double* w
   /* 4. deposit J^{n+1/2} from the old and new positions */
   memset(J, 0, sizeof(double) * 3 * (size_t)nc);
   orc_deposit_cells(g, n, a, b, w, v3, J);
+  orc_smooth_current(g, J);
   /* new absolute positions, wrapped into the periodic box */
   for (int64_t p = 0; p < n; p++)
     for (int d = 0; d < dim; d++) {

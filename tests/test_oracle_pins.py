@@ -763,3 +763,52 @@ def test_tristan_out_of_plane_current_is_the_path_average(orc):
                     max(0.0, 1 - abs(a[1] + t * (b[1] - a[1]) - j))
                 val, _ = quad(f, 0, 1, points=cuts or None, epsabs=1e-14, epsrel=1e-13)
                 assert abs(J[2, i + nx[0] * j] - w * v3 * val) < 1e-12, (i, j)
+
+
+# --------------------------------------------------------------------------
+# current smoothing (App. A, smoothing of the current density)
+# --------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("dim,axis", [(2, 0), (2, 1), (3, 2)])
+def test_smoothing_transfer_function(orc, dim, axis):
+    """A 3-point filter (a, b, c)/(a+b+c) applied along one axis multiplies a
+    Fourier mode exp(i k x) by (a e^{-ik dx} + b + c e^{ik dx})/(a+b+c) (Birdsall
+    and Langdon's digital filtering); L passes multiply the factors.  For the
+    binomial (1,2,1) the factor is cos^2(k dx/2): the mean passes unchanged
+    and the shortest wavelength (k dx = pi) is removed."""
+    nx = (16, 12, 10)[:dim]
+    passes = [(1, 2, 1), (1, 2, 1), (-1, 6, -1)]  # two binomial passes and a compensator
+    smooth = [[] for _ in range(dim)]
+    smooth[axis] = passes
+    g = orc.Grid(dim=dim, nx=nx, dx=(0.2,) * dim, dt=0.05, order=1, smooth=tuple(smooth))
+    idx = np.indices(nx[::-1]).reshape(dim, -1)[::-1]  # idx[d] = cell index along axis d
+    for m in range(nx[axis] // 2 + 1):
+        kdx = 2 * math.pi * m / nx[axis]
+        J = np.zeros((3, g.ncell))
+        for c in range(3):
+            J[c] = np.cos(kdx * idx[axis] + 0.3 * c) * (1 + 0.1 * c)
+        out = orc.smooth_current(g, J)
+        factor = 1.0
+        for a, b, c in passes:
+            factor *= (a * math.cos(kdx) + b + c * math.cos(kdx)) / (a + b + c)
+        assert np.abs(out - factor * J).max() < 1e-13, (m, factor)
+    # nothing moves along the other axes: a mode varying only across them is untouched
+    other = (axis + 1) % dim
+    J = np.zeros((3, g.ncell))
+    J[0] = np.sin(2 * math.pi * idx[other] / nx[other])
+    assert np.abs(orc.smooth_current(g, J) - J).max() < 1e-13
+
+
+def test_smoothing_of_nyquist_and_mean(orc):
+    """Binomial passes keep the total current and remove the grid-scale
+    checkerboard (k dx = pi along each smoothed axis)."""
+    nx = (8, 6)
+    g = orc.Grid(dim=2, nx=nx, dx=(0.2, 0.2), dt=0.05, order=1, smooth=(((1, 2, 1),), ((1, 2, 1),)))
+    rng = np.random.default_rng(3)
+    J = rng.normal(size=(3, g.ncell))
+    out = orc.smooth_current(g, J)
+    assert np.allclose(out.sum(axis=1), J.sum(axis=1), rtol=0, atol=1e-12)
+    i, j = np.indices(nx[::-1])[::-1]
+    chk = np.tile(((-1.0) ** (i + j)).ravel(), (3, 1))
+    assert np.abs(orc.smooth_current(g, chk)).max() < 1e-15
