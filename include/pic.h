@@ -101,7 +101,19 @@ typedef struct {
                             0 = 2048 (searched by pic_autotune) */
   int32_t accumulator;   /* PIC_ACC_* */
   int32_t deposit;       /* PIC_DEPOSIT_*: which charge-conserving current */
+  /* Smoothing of the current before the field solve (App. A, current
+   * smoothing section): along each axis separately, smooth_level[axis]
+   * passes (0 = off, at most PIC_MAX_SMOOTH), pass p mapping every component
+   * to (a J[i-1] + b J[i] + c J[i+1]) / (a + b + c) with
+   * (a, b, c) = smooth_weights[axis][p], periodic; axes in order 1, 2, 3.
+   * The exported current is the smoothed one.  With smoothing on, the
+   * current no longer satisfies the continuity equation with the
+   * unsmoothed charge density (the charge residual is then not zero). */
+  int32_t smooth_level[3];
+  double smooth_weights[3][8][3];
 } pic_config;
+
+#define PIC_MAX_SMOOTH 8
 
 /* Current deposit (Sec. 3.2).  Both satisfy the continuity equation; they
  * differ in the curl of the current when a particle crosses a cell face. */

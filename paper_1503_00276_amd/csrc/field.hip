@@ -128,7 +128,12 @@ __global__ void __launch_bounds__(kBlock) yee_step(const InstDesc* __restrict__ 
           int cb = x + BX * (y + BY * z);
           int gi = gidx(x, y, z);
           float J1, J2, J3;
-          if (g.acc_mode == 2) {
+          if (I.sm_npass > 0) {
+            const gfloat* Js = (const gfloat*)I.Jsm[(I.sm_npass - 1) & 1];
+            J1 = Js[gi];
+            J2 = Js[nc + gi];
+            J3 = Js[2 * nc + gi];
+          } else if (g.acc_mode == 2) {
             J1 = (float)((double)(long long)I.J64[jp][gi] * jinv);
             J2 = (float)((double)(long long)I.J64[jp][nc + gi] * jinv);
             J3 = (float)((double)(long long)I.J64[jp][2 * nc + gi] * jinv);
@@ -196,7 +201,61 @@ __global__ void __launch_bounds__(kBlock) yee_step(const InstDesc* __restrict__ 
   }
 }
 
+// One smoothing pass of the current along 'axis' (pass 'lev' of that axis)
+// for every instance that has it: J <- a J[i-1] + b J[i] + c J[i+1] with the
+// normalised weights, periodic.  The instance's first pass reads the
+// accumulator of the step's parity; later passes read the other buffer.
+__global__ void __launch_bounds__(kBlock) smooth_pass(const InstDesc* __restrict__ inst, int axis, int lev,
+                                                      int par) {
+  const InstDesc& I = inst[blockIdx.y];
+  if (lev >= I.sm_level[axis]) return;
+  const GridDesc& g = I.g;
+  const int k = I.sm_first[axis] + lev;
+  const int nc = g.ncell;
+  const int n = g.nx[axis];
+  const int stride = axis == 0 ? 1 : (axis == 1 ? g.nx[0] : g.nx[0] * g.nx[1]);
+  const float a = I.sm_w[axis][lev][0], b = I.sm_w[axis][lev][1], c = I.sm_w[axis][lev][2];
+  gfloat* dst = (gfloat*)I.Jsm[k & 1];
+  const gfloat* src = (const gfloat*)I.Jsm[(k - 1) & 1];
+  const bool first = k == 0;
+  const bool fixed = g.acc_mode == 2;
+  const double jinv = (double)g.jinv;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < 3 * nc; e += gridDim.x * blockDim.x) {
+    const int comp = e / nc;
+    const int q = e - comp * nc;
+    const int i = (q / stride) % n;
+    const int qm = i == 0 ? q + (n - 1) * stride : q - stride;
+    const int qp = i == n - 1 ? q - (n - 1) * stride : q + stride;
+    const int o = comp * nc;
+    float vm, v0, vp;
+    if (!first) {
+      vm = src[o + qm];
+      v0 = src[o + q];
+      vp = src[o + qp];
+    } else if (fixed) {
+      vm = (float)((double)(long long)I.J64[par][o + qm] * jinv);
+      v0 = (float)((double)(long long)I.J64[par][o + q] * jinv);
+      vp = (float)((double)(long long)I.J64[par][o + qp] * jinv);
+    } else {
+      const gfloat* Ja = (const gfloat*)I.Jacc[par];
+      vm = Ja[o + qm];
+      v0 = Ja[o + q];
+      vp = Ja[o + qp];
+    }
+    dst[e] = a * vm + b * v0 + c * vp;
+  }
+}
+
 }  // namespace
+
+hipError_t pic_launch_smooth_pass(const InstDesc* d_inst, int ninst, int max_ncell, int axis, int lev,
+                                  int parity, hipStream_t st) {
+  long b = ((long)3 * max_ncell + kBlock - 1) / kBlock;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(smooth_pass, dim3((int)b, ninst), dim3(kBlock), 0, st, d_inst, axis, lev, parity);
+  return hipGetLastError();
+}
 
 int pic_yee_tiles(int dim, const int nx[3]) {
   if (dim == 2)

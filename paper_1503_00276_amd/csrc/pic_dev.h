@@ -102,6 +102,14 @@ struct InstDesc {
   float* Jacc[2];
   unsigned long long* J64[2];
   float* Jout;               // the current of the last step (FP32, used by the E update)
+  // current smoothing: passes per axis, normalised 3-point weights, the
+  // instance's pass number of each axis' first pass, and two FP32 buffers
+  // the passes alternate between (the last one feeds the E update)
+  int sm_level[3];
+  int sm_first[3];
+  int sm_npass;
+  float sm_w[3][8][3];
+  float* Jsm[2];
 };
 
 // ---------------------------------------------------------------------------

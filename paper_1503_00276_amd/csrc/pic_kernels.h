@@ -16,6 +16,8 @@ hipError_t pic_launch_gpd(int dim, int order, const StoreDesc* d_stores, int nst
 
 // Yee field solve (field.hip); instances in d_inst[0..ninst)
 int pic_yee_tiles(int dim, const int nx[3]);
+hipError_t pic_launch_smooth_pass(const InstDesc* d_inst, int ninst, int max_ncell, int axis, int lev,
+                                  int parity, hipStream_t st);
 hipError_t pic_launch_yee_step(const InstDesc* d_inst, int ninst, int max_tiles, int dim, int parity,
                                hipStream_t st);
 

@@ -47,6 +47,7 @@ struct Instance {
   float* Jacc[2] = {nullptr, nullptr};
   unsigned long long* J64[2] = {nullptr, nullptr};
   float* Jout = nullptr;
+  float* Jsm[2] = {nullptr, nullptr};  // smoothing buffers (only when smoothing is on)
   int* nsrc = nullptr;  // neighbour tile tables of the rebin
   int* ndst = nullptr;
   double wmax[PIC_MAX_SPECIES] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -60,6 +61,7 @@ struct Group {
   int dim, order, first, count, max_ncell, max_items, max_tiles, max_blocks;
   size_t lds;
   bool fixed64;
+  int sm_max[3];  // most smoothing passes of any instance, per axis
 };
 
 struct Sim {
@@ -224,6 +226,16 @@ pic_status validate(Sim& S, const pic_config& c) {
     return S.fail(PIC_E_INVALID, "unknown deposit %d", c.deposit);
   if (c.deposit == PIC_DEPOSIT_TRISTAN && c.shape_order != 1)
     return S.fail(PIC_E_INVALID, "the TRISTAN deposit needs the linear shape (shape_order 1)");
+  for (int a = 0; a < c.ndim; a++) {
+    if (c.smooth_level[a] < 0 || c.smooth_level[a] > PIC_MAX_SMOOTH)
+      return S.fail(PIC_E_INVALID, "smooth_level[%d] must be 0..%d", a, PIC_MAX_SMOOTH);
+    for (int p = 0; p < c.smooth_level[a]; p++) {
+      const double* wt = c.smooth_weights[a][p];
+      double s = wt[0] + wt[1] + wt[2];
+      if (!std::isfinite(wt[0]) || !std::isfinite(wt[1]) || !std::isfinite(wt[2]) || !(std::fabs(s) > 0.0))
+        return S.fail(PIC_E_INVALID, "smoothing weights of axis %d pass %d must be finite with a nonzero sum", a, p);
+    }
+  }
   for (int d = 0; d < 3; d++)
     if (!std::isfinite(c.e0[d]) || !std::isfinite(c.b0[d])) return S.fail(PIC_E_INVALID, "external field not finite");
   return PIC_OK;
@@ -333,7 +345,7 @@ pic_status refresh_descriptors(Sim& S) {
   S.igroups.clear();
   for (int dim = 2; dim <= 3; dim++)
     for (int order = 1; order <= 3; order++) {
-      Group gr{dim, order, (int)stores.size(), 0, 0, 0, 0, 0, 0, false};
+      Group gr{dim, order, (int)stores.size(), 0, 0, 0, 0, 0, 0, false, {0, 0, 0}};
       for (size_t i = 0; i < S.inst.size(); i++) {
         Instance& I = S.inst[i];
         if (I.g.dim != dim || I.g.order != order) continue;
@@ -361,7 +373,7 @@ pic_status refresh_descriptors(Sim& S) {
     }
   std::vector<InstDesc> insts;
   for (int dim = 2; dim <= 3; dim++) {
-    Group gr{dim, 0, (int)insts.size(), 0, 0, 0, 0, 0, 0, false};
+    Group gr{dim, 0, (int)insts.size(), 0, 0, 0, 0, 0, 0, false, {0, 0, 0}};
     for (size_t i = 0; i < S.inst.size(); i++) {
       Instance& I = S.inst[i];
       if (I.g.dim != dim) continue;
@@ -374,6 +386,22 @@ pic_status refresh_descriptors(Sim& S) {
         id.J64[k] = I.J64[k];
       }
       id.Jout = I.Jout;
+      int npass = 0;
+      for (int a = 0; a < 3; a++) {
+        const int lv = a < I.g.dim ? I.cfg.smooth_level[a] : 0;
+        id.sm_level[a] = lv;
+        id.sm_first[a] = npass;
+        npass += lv;
+        gr.sm_max[a] = std::max(gr.sm_max[a], lv);
+        for (int p = 0; p < lv; p++) {
+          const double* wt = I.cfg.smooth_weights[a][p];
+          const double s = wt[0] + wt[1] + wt[2];
+          for (int k = 0; k < 3; k++) id.sm_w[a][p][k] = (float)(wt[k] / s);
+        }
+      }
+      id.sm_npass = npass;
+      id.Jsm[0] = I.Jsm[0];
+      id.Jsm[1] = I.Jsm[1];
       insts.push_back(id);
       if (I.g.acc_mode == PIC_ACC_FIXED64) gr.fixed64 = true;
       gr.count++;
@@ -478,6 +506,10 @@ pic_status launch_steps(Sim& S, int64_t first, int nsteps, bool end_with_check) 
     }
     prof_end(S, 0, e0);
     e0 = prof_begin(S);
+    for (const Group& gr : S.igroups)
+      for (int a = 0; a < gr.dim; a++)
+        for (int lev = 0; lev < gr.sm_max[a]; lev++)
+          HIPCHK(S, pic_launch_smooth_pass(S.d_inst + gr.first, gr.count, gr.max_ncell, a, lev, par, S.stream));
     for (const Group& gr : S.igroups)
       HIPCHK(S, pic_launch_yee_step(S.d_inst + gr.first, gr.count, gr.max_tiles, gr.dim, par, S.stream));
     prof_end(S, 1, e0);
@@ -1075,6 +1107,14 @@ pic_status sim_create(Sim& S, const pic_config* cfgs, int n, void* stream) {
     }
     if ((st = build_tables(S, I)) != PIC_OK) return st;
     if (hipMalloc(&I.Jout, 3 * nc * sizeof(float)) != hipSuccess) return S.fail(PIC_E_NOMEM, "current allocation failed");
+    int npass = 0;
+    for (int a = 0; a < I.cfg.ndim; a++) npass += I.cfg.smooth_level[a];
+    if (npass > 0)
+      for (int k = 0; k < 2; k++) {
+        if (hipMalloc(&I.Jsm[k], 3 * nc * sizeof(float)) != hipSuccess)
+          return S.fail(PIC_E_NOMEM, "smoothing buffer allocation failed");
+        HIPCHK(S, hipMemset(I.Jsm[k], 0, 3 * nc * sizeof(float)));
+      }
     HIPCHK(S, hipMemset(I.Jout, 0, 3 * nc * sizeof(float)));
     for (int k = 0; k < 2; k++) {
       if (cfgs[i].accumulator == PIC_ACC_FIXED64) {
@@ -1123,6 +1163,8 @@ void sim_destroy(Sim& S) {
       if (I.J64[k]) (void)hipFree(I.J64[k]);
     }
     if (I.Jout) (void)hipFree(I.Jout);
+    for (int k = 0; k < 2; k++)
+      if (I.Jsm[k]) (void)hipFree(I.Jsm[k]);
     if (I.nsrc) (void)hipFree(I.nsrc);
     if (I.ndst) (void)hipFree(I.ndst);
     if (I.rho_snap) (void)hipFree(I.rho_snap);

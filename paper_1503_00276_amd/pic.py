@@ -75,6 +75,8 @@ class pic_config(C.Structure):
         ("chunk", C.c_int32),
         ("accumulator", C.c_int32),
         ("deposit", C.c_int32),
+        ("smooth_level", C.c_int32 * 3),
+        ("smooth_weights", C.c_double * 72),
     ]
 
 
@@ -178,6 +180,7 @@ class Config:
     chunk: int = 0
     accumulator: int = PIC_ACC_FP32
     deposit: int = PIC_DEPOSIT_ISIS
+    smooth: Sequence = ()  # per axis: a list of (a, b, c) weights, one per smoothing pass
 
     def c(self) -> pic_config:
         c = pic_config()
@@ -197,6 +200,11 @@ class Config:
         c.chunk = int(self.chunk)
         c.accumulator = int(self.accumulator)
         c.deposit = int(self.deposit)
+        for ax, passes in enumerate(self.smooth):
+            c.smooth_level[ax] = len(passes)
+            for p, wts in enumerate(passes[:8]):
+                for k in range(3):
+                    c.smooth_weights[(ax * 8 + p) * 3 + k] = float(wts[k])
         return c
 
     @property

@@ -115,3 +115,27 @@ def test_tristan_step_parity(orc, ndim, nx, tile):
     C = sim.charge_residual()
     assert np.abs(C).max() * cfg.dt <= 1e-6 * np.abs(rho_e).max()
     sim.close()
+
+
+@pytest.mark.parametrize("ndim,order,acc", [(2, 2, 0), (2, 1, 2), (3, 1, 0)])
+def test_smoothed_current_step_parity(orc, ndim, order, acc):
+    """Current smoothing between the deposit and the field solve: binomial
+    and compensator passes per axis, on the FP32 and the int64 accumulator;
+    the smoothed current, E and B against the oracle."""
+    pic = _pic()
+    nx = (36, 20) if ndim == 2 else (16, 12, 10)
+    tile = (12, 10) if ndim == 2 else (8, 6, 5)
+    dx = (0.2, 0.25, 0.2)[:ndim]
+    smooth = [[(1, 2, 1), (1, 2, 1), (-1, 6, -1)], [(1, 2, 1)], [(1, 2, 1), (1, 2, 1)]][:ndim]
+    x, u, w = _thermal(ndim, nx, dx, 3, 0.3, 17 + ndim)
+    cfg = pic.Config(ndim=ndim, nx=nx, dx=dx, dt=0.08, shape_order=order, tile=tile, sort_interval=2,
+                     ion_density=1.0, accumulator=acc, smooth=smooth)
+    sim = pic.Pic(cfg)
+    sim.load_particles(x, u, w, rqm=-1.0)
+    for k in range(3):
+        err = step_parity(orc, sim, cfg)
+        print(k, err, flush=True)
+        assert err["pos"] <= POS_TOL and err["mom"] <= MOM_TOL
+        assert err["J"] <= J_TOL
+        assert err["E"] <= F_TOL and err["B"] <= F_TOL
+    sim.close()
