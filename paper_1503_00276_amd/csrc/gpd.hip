@@ -313,6 +313,35 @@ __device__ __forceinline__ void deposit_tristan(acc_t* sJ, int jn, const int JR[
   }
 }
 
+// Coordinates of a flat index over a box of extents R[3] that advances by a
+// fixed step: kept up to date by additions, so the staging and flush loops
+// divide only once per workgroup.
+struct BoxWalk {
+  int x, y, z, sx, sy, sz;
+  __device__ BoxWalk(int start, int step, const int R[3]) {
+    x = start % R[0];
+    int r = start / R[0];
+    y = r % R[1];
+    z = r / R[1];
+    sx = step % R[0];
+    r = step / R[0];
+    sy = r % R[1];
+    sz = r / R[1];
+  }
+  __device__ void advance(const int R[3]) {
+    x += sx;
+    const int cy = x >= R[0] ? 1 : 0;
+    x -= cy ? R[0] : 0;
+    y += sy + cy;
+    const int cz = y >= R[1] ? 1 : 0;
+    y -= cz ? R[1] : 0;
+    z += sz + cz;
+  }
+};
+
+// Periodic wrap, cheap when the index is already inside.
+__device__ __forceinline__ int wrap_fast(int v, int n) { return (unsigned)v < (unsigned)n ? v : pic_wrap(v, n); }
+
 // ---------------------------------------------------------------------------
 // one work item
 // ---------------------------------------------------------------------------
@@ -348,18 +377,17 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
 
   // 1. stage E, B with periodic wrap
   const int ncell = g.ncell;
-  for (int idx = tid; idx < fn; idx += blockDim.x) {
-    int rx = idx % FR[0];
-    int rr = idx / FR[0];
-    int ry = rr % FR[1];
-    int rz = rr / FR[1];
-    int gx = pic_wrap(org[0] - flo[0] + rx, g.nx[0]);
-    int gy = pic_wrap(org[1] - flo[1] + ry, g.nx[1]);
-    int gz = DIM == 3 ? pic_wrap(org[2] - flo[2] + rz, g.nx[2]) : 0;
-    int gi = gx + g.nx[0] * (gy + g.nx[1] * gz);
+  {
+    BoxWalk bw(tid, blockDim.x, FR);
     const gfloat* Fg = (const gfloat*)S.F[jp];
+    for (int idx = tid; idx < fn; idx += blockDim.x, bw.advance(FR)) {
+      int gx = wrap_fast(org[0] - flo[0] + bw.x, g.nx[0]);
+      int gy = wrap_fast(org[1] - flo[1] + bw.y, g.nx[1]);
+      int gz = DIM == 3 ? wrap_fast(org[2] - flo[2] + bw.z, g.nx[2]) : 0;
+      int gi = gx + g.nx[0] * (gy + g.nx[1] * gz);
 #pragma unroll
-    for (int c = 0; c < 6; c++) sF[c * fn + idx] = Fg[(size_t)c * ncell + gi];
+      for (int c = 0; c < 6; c++) sF[c * fn + idx] = Fg[(size_t)c * ncell + gi];
+    }
   }
   // 2. clear the current tile and the rebin slot counters
   for (int idx = tid; idx < 3 * jn; idx += blockDim.x) sJ[idx] = 0ull;
@@ -410,6 +438,12 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
       gather_weights<ORDER>(e[d], true, bh[d], wh[d]);
     }
     float Fp[6];
+    // LDS offsets of the first tap: one multiply per particle; the offsets of
+    // the half-staggered nodes differ from the node ones by 0 or -1 per axis
+    const int FR0 = FR[0];
+    const int gb0 = (flo[1] + l[1] + b0[1]) * FR0 + flo[0] + l[0] + b0[0];
+    const int dgx = bh[0] - b0[0];
+    const int dgy = bh[1] == b0[1] ? 0 : (bh[1] < b0[1] ? -FR0 : FR0);
 #pragma unroll
     for (int c = 0; c < 6; c++) {
       // component c: E_c staggered half along axis c, B_c half along the others
@@ -423,13 +457,14 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
       const float* Fc = sF + c * fn;
       float acc = 0.0f;
       if constexpr (DIM == 2) {
+        const float* row = Fc + gb0 + (hx ? dgx : 0) + (hy ? dgy : 0);
 #pragma unroll
         for (int j = 0; j < NG; j++) {
-          const float* row = Fc + (sy + j) * FR[0] + sx;
           float r = 0.0f;
 #pragma unroll
           for (int i = 0; i < NG; i++) r += wx[i] * row[i];
           acc += wy[j] * r;
+          row += FR0;
         }
       } else {
         const float* wz = hz ? wh[2] : w0[2];
@@ -562,9 +597,11 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
         const float Pye = wide[1] ? (py ? P2[0] : P2[K - 1]) : 0.0f;
         // node offsets of the extras relative to the core base, per array type
         const int exS = px ? -1 : K, exP = px ? -1 : K - 1;
-        const int eyS = py ? -1 : K, eyP = py ? -1 : K - 1;
         const int cx = jx + p0[0], cy = jy + p0[1];
         const int R = JR[0];
+        const int cb = cy * R + cx;  // core base: the only multiply of the deposit
+        const int ey = py ? -R : K * R;  // row offset of the extra row (S-type)
+        const int eyp = py ? -R : (K - 1) * R;  // (P-type)
         // y-direction factors of J1 and J3 (T1 = S0 + D/2, U2 = S0/2 + D/3) and
         // x-direction factor of J2 (S0 + D/2)
         float T1[K], U2[K], X2[K];
@@ -579,8 +616,8 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
         // core
   #pragma unroll
         for (int j = 0; j < K; j++) {
-          acc_t* r1 = J1 + (cy + j) * R + cx;
-          acc_t* r3 = J3 + (cy + j) * R + cx;
+          acc_t* r1 = J1 + cb + j * R;
+          acc_t* r3 = J3 + cb + j * R;
   #pragma unroll
           for (int i = 0; i < K - 1; i++) lds_add_any(r1 + i, Px[i] * T1[j]);
           if (v3 != 0.0f) {
@@ -590,7 +627,7 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
         }
   #pragma unroll
         for (int j = 0; j < K - 1; j++) {
-          acc_t* r2 = J2 + (cy + j) * R + cx;
+          acc_t* r2 = J2 + cb + j * R;
   #pragma unroll
           for (int i = 0; i < K; i++) lds_add_any(r2 + i, Py[j] * X2[i]);
         }
@@ -598,27 +635,27 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
         if (wide[0]) {
   #pragma unroll
           for (int j = 0; j < K; j++) {
-            lds_add_any(J1 + (cy + j) * R + cx + exP, Pxe * T1[j]);
-            if (v3 != 0.0f) lds_add_any(J3 + (cy + j) * R + cx + exS, v3 * (Sxe * T1[j] + Dxe * U2[j]));
+            lds_add_any(J1 + cb + j * R + exP, Pxe * T1[j]);
+            if (v3 != 0.0f) lds_add_any(J3 + cb + j * R + exS, v3 * (Sxe * T1[j] + Dxe * U2[j]));
           }
   #pragma unroll
-          for (int j = 0; j < K - 1; j++) lds_add_any(J2 + (cy + j) * R + cx + exS, Py[j] * X2e);
+          for (int j = 0; j < K - 1; j++) lds_add_any(J2 + cb + j * R + exS, Py[j] * X2e);
         }
         // extra row (y)
         if (wide[1]) {
   #pragma unroll
-          for (int i = 0; i < K - 1; i++) lds_add_any(J1 + (cy + eyS) * R + cx + i, Px[i] * T1e);
+          for (int i = 0; i < K - 1; i++) lds_add_any(J1 + cb + ey + i, Px[i] * T1e);
   #pragma unroll
           for (int i = 0; i < K; i++) {
-            if (v3 != 0.0f) lds_add_any(J3 + (cy + eyS) * R + cx + i, v3 * (Sx[i] * T1e + Dx[i] * U2e));
-            lds_add_any(J2 + (cy + eyP) * R + cx + i, Pye * X2[i]);
+            if (v3 != 0.0f) lds_add_any(J3 + cb + ey + i, v3 * (Sx[i] * T1e + Dx[i] * U2e));
+            lds_add_any(J2 + cb + eyp + i, Pye * X2[i]);
           }
         }
         // extra corner
         if (wide[0] && wide[1]) {
-          lds_add_any(J1 + (cy + eyS) * R + cx + exP, Pxe * T1e);
-          if (v3 != 0.0f) lds_add_any(J3 + (cy + eyS) * R + cx + exS, v3 * (Sxe * T1e + Dxe * U2e));
-          lds_add_any(J2 + (cy + eyP) * R + cx + exS, Pye * X2e);
+          lds_add_any(J1 + cb + ey + exP, Pxe * T1e);
+          if (v3 != 0.0f) lds_add_any(J3 + cb + ey + exS, v3 * (Sxe * T1e + Dxe * U2e));
+          lds_add_any(J2 + cb + eyp + exS, Pye * X2e);
         }
       } else {
         int jz = jlo[2] + l[2] + wb[2];
@@ -721,14 +758,11 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
   if (tid < PIC_NSLOT) S.cnt[ii * PIC_NSLOT + tid] = scnt[tid];
 
   // 4. fold the LDS current into the global current (periodic wrap)
-  for (int idx = tid; idx < jn; idx += blockDim.x) {
-    int rx = idx % JR[0];
-    int rr = idx / JR[0];
-    int ry = rr % JR[1];
-    int rz = rr / JR[1];
-    int gx = pic_wrap(org[0] - jlo[0] + rx, g.nx[0]);
-    int gy = pic_wrap(org[1] - jlo[1] + ry, g.nx[1]);
-    int gz = DIM == 3 ? pic_wrap(org[2] - jlo[2] + rz, g.nx[2]) : 0;
+  BoxWalk bj(tid, blockDim.x, JR);
+  for (int idx = tid; idx < jn; idx += blockDim.x, bj.advance(JR)) {
+    int gx = wrap_fast(org[0] - jlo[0] + bj.x, g.nx[0]);
+    int gy = wrap_fast(org[1] - jlo[1] + bj.y, g.nx[1]);
+    int gz = DIM == 3 ? wrap_fast(org[2] - jlo[2] + bj.z, g.nx[2]) : 0;
     int gi = gx + g.nx[0] * (gy + g.nx[1] * gz);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
