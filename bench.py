@@ -230,6 +230,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=2_097_152)
     ap.add_argument("--tune-steps", type=int, default=10,
                     help="steps the autotuner times per candidate layout (0: no autotune)")
+    ap.add_argument("--tune-after", type=int, default=100,
+                    help="untimed steps run before the autotuner, so it tunes the developed state")
     ap.add_argument("--tile", type=int, nargs="+", default=None, help="tile extents (default: automatic)")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--sort-interval", type=int, default=0)
@@ -273,8 +275,10 @@ def main():
     sim.sync()
     tune = None
     if args.tune_steps > 0:
-        # tuned on the state the warm-up reached (the loaded state of a driven
-        # plasma is quieter than the run it starts)
+        # tuned on a developed state (the loaded state of a driven plasma is
+        # quieter than the run it starts: the wake, its density spikes and the
+        # face crossings come later)
+        sim.step(args.tune_after)
         log("autotune")
         tune = sim.autotune(trial_steps=args.tune_steps)
         sim.step(args.warmup)
