@@ -21,4 +21,6 @@ from .oracle import (  # noqa: F401
     field_energy,
     particle_moments,
     smooth_current,
+    step_window,
+    window_shifts,
 )

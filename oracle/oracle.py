@@ -8,6 +8,7 @@ lives in ``pic_oracle.c`` (which cites the dissertation's Ch. 3 passages).
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 from dataclasses import dataclass, field
@@ -43,6 +44,7 @@ class _Grid(C.Structure):
         ("deposit", C.c_int32),
         ("smooth_level", C.c_int32 * 3),
         ("smooth_w", C.c_double * 72),
+        ("window", C.c_int32),
     ]
 
 ISIS = 0
@@ -63,6 +65,9 @@ class Grid:
     b0: tuple = (0.0, 0.0, 0.0)
     deposit: int = ISIS  # ISIS, or TRISTAN (linear shape only)
     smooth: tuple = ()    # per axis: a list of (a, b, c) weights, one per smoothing pass
+    window: int = 0       # 1: moving window along x1 (see step_window)
+    inject_ppc: tuple = (1, 1, 1)  # moving window: injected particles per cell, per axis
+    inject_w: float = 0.0          # moving window: weight of an injected particle
 
     def c(self) -> _Grid:
         g = _Grid()
@@ -81,6 +86,7 @@ class Grid:
         if self.deposit not in (ISIS, TRISTAN) or (self.deposit == TRISTAN and self.order != 1):
             raise ValueError("TRISTAN deposit is defined for the linear shape only")
         g.deposit = int(self.deposit)
+        g.window = int(self.window)
         for ax, passes in enumerate(self.smooth):
             if len(passes) > 8:
                 raise ValueError("at most 8 smoothing passes per axis")
@@ -244,6 +250,76 @@ def step(g: Grid, x, u, w, qm, E, B) -> StepResult:
     if rc != 0:
         raise MemoryError("oracle step failed to allocate")
     return StepResult(x=x, u=u, E=E, B=B, J=J)
+
+
+def window_shifts(g: Grid, n: int) -> int:
+    """Cell shifts of a window moving along x1 at the speed of light after n
+    steps: the window is moved by dx1 whenever the distance c t it should have
+    travelled exceeds the distance it has been moved by a whole cell (Sec. 4.5,
+    dynamic spaces; c = 1 in the normalised units)."""
+    return int(math.floor(n * (g.dt / g.dx[0])))
+
+
+def step_window(g: Grid, n: int, x, u, w, qm, E, B) -> StepResult:
+    """One PIC step of a box whose window moves along x1 at c (Sec. 4.5).
+
+    x are positions relative to the window's current lower corner.  The step
+    is the ordinary one with x1 not periodic (grid values beyond the x1 ends
+    are zero, currents deposited there are dropped); then
+      1. particles that left the window through an x1 face are removed;
+      2. if the window moves after this step (n -> n+1), every grid array
+         moves down by one x1 cell, the new front cell column gets zero E, B
+         (and J), particles move by -dx1 and those that fall behind the window
+         are removed, and a cold plasma is initialised in the front column:
+         inject_ppc per axis on a regular sub-lattice of each cell, u = 0,
+         weight inject_w, cells in increasing linear index, lattice points
+         with axis 1 fastest.
+    Returns x, u, w of the survivors (in input order) followed by the
+    injected particles, E, B, J, and 'keep', the survivors' input indices."""
+    assert g.window == 1
+    r = step(g, x, u, w, qm, E, B)
+    w = _f64(np.broadcast_to(w, (len(r.x),))).copy()
+    L1 = g.nx[0] * g.dx[0]
+    keep = np.nonzero((r.x[:, 0] >= 0.0) & (r.x[:, 0] < L1))[0]
+    x1, u1, w1 = r.x[keep], r.u[keep], w[keep]
+    E1, B1, J1 = r.E, r.B, r.J
+    if window_shifts(g, n + 1) > window_shifts(g, n):
+        shape = g.shape
+        def shift(F):
+            F = F.reshape((3,) + shape).copy()
+            F[..., :-1] = F[..., 1:]
+            F[..., -1] = 0.0
+            return F.reshape(3, -1)
+        E1, B1, J1 = shift(E1), shift(B1), shift(J1)
+        x1 = x1.copy()
+        x1[:, 0] -= g.dx[0]
+        back = np.nonzero(x1[:, 0] >= 0.0)[0]
+        keep = keep[back]
+        x1, u1, w1 = x1[back], u1[back], w1[back]
+        # cold plasma in the new front column
+        d = g.dim
+        ppc = list(g.inject_ppc)[:d]
+        if d == 2:
+            offs = np.stack(np.meshgrid((np.arange(ppc[0]) + 0.5) / ppc[0], (np.arange(ppc[1]) + 0.5) / ppc[1],
+                                        indexing="xy"), -1).reshape(-1, 2)
+        else:
+            o = np.meshgrid((np.arange(ppc[0]) + 0.5) / ppc[0], (np.arange(ppc[1]) + 0.5) / ppc[1],
+                            (np.arange(ppc[2]) + 0.5) / ppc[2], indexing="ij")
+            offs = np.stack([o[0].transpose(2, 1, 0), o[1].transpose(2, 1, 0), o[2].transpose(2, 1, 0)],
+                            -1).reshape(-1, 3)
+        cells = []
+        if d == 2:
+            for j in range(g.nx[1]):
+                cells.append((g.nx[0] - 1, j))
+        else:
+            for k in range(g.nx[2]):
+                for j in range(g.nx[1]):
+                    cells.append((g.nx[0] - 1, j, k))
+        newx = np.concatenate([(np.asarray(c, dtype=float) + offs) * np.asarray(g.dx[:d]) for c in cells])
+        x1 = np.concatenate([x1, newx])
+        u1 = np.concatenate([u1, np.zeros((len(newx), 3))])
+        w1 = np.concatenate([w1, np.full(len(newx), float(g.inject_w))])
+    return StepResult(x=x1, u=u1, E=E1, B=B1, J=J1), w1, keep
 
 
 def gauss_residual(g: Grid, E, rho_):

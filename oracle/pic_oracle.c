@@ -61,6 +61,9 @@ typedef struct {
   int32_t deposit;   /* 0: ISIS ordering average; 1: TRISTAN path split (order 1) */
   int32_t smooth_level[3];        /* current smoothing passes along each axis (0: none) */
   double smooth_w[3][8][3];       /* 3-point weights of each pass, normalised by their sum */
+  int32_t window;    /* 1: moving window along x1 -- x1 is not periodic: grid values
+                        beyond the first and last x1 cell are zero and currents
+                        deposited there are dropped (Sec. 4.5 dynamic spaces) */
 } orc_grid;
 
 /* ------------------------------------------------------------------ */
@@ -77,12 +80,18 @@ static int wrapi(int64_t i, int n) {
   return (int)r;
 }
 
+/* Linear index of node (i0, i1, i2), periodic; -1 for a node beyond the x1
+ * ends of a moving window. */
 static int64_t cidx(const orc_grid* g, int64_t i0, int64_t i1, int64_t i2) {
+  if (g->window && (i0 < 0 || i0 >= g->nx[0])) return -1;
   int a = wrapi(i0, g->nx[0]);
   int b = wrapi(i1, g->nx[1]);
   int c = g->dim == 3 ? wrapi(i2, g->nx[2]) : 0;
   return (int64_t)a + (int64_t)g->nx[0] * ((int64_t)b + (int64_t)g->nx[1] * c);
 }
+
+/* Grid value at an index from cidx (zero beyond a moving window). */
+static double at(const double* F, int64_t c) { return c < 0 ? 0.0 : F[c]; }
 
 /* Staggered offset of field component comp (0..2) of E (kind 0), B (kind 1),
  * along axis d; J shares E's offsets and rho sits at the node. */
@@ -138,7 +147,7 @@ static double gather_one(const orc_grid* g, const double* F, const double xi[3],
       for (int64_t i0 = lo[0]; i0 <= hi[0]; i0++) {
         double s0 = orc_shape(g->order, t[0] - (double)i0);
         if (s0 == 0.0) continue;
-        sum += s0 * s1 * s2 * F[cidx(g, i0, i1, i2)];
+        sum += s0 * s1 * s2 * at(F, cidx(g, i0, i1, i2));
       }
     }
   }
@@ -230,7 +239,8 @@ static void submove(const orc_grid* g, double* J, double w, const double p[3], i
         ii[k] = ik;
         ii[o1] = j1;
         if (dim == 3) ii[o2] = j2;
-        Jk[cidx(g, ii[0], ii[1], ii[2])] += flux * scale;
+        int64_t ci = cidx(g, ii[0], ii[1], ii[2]);
+        if (ci >= 0) Jk[ci] += flux * scale;
       }
     }
   }
@@ -263,7 +273,8 @@ static void deposit_j3_2d(const orc_grid* g, double* J, double w, double v3,
       double fh = (0.5 * (s0a + s0b)) * (0.5 * (s1a + s1b));
       double f1 = s0b * s1b;
       double avg = (f0 + 4.0 * fh + f1) / 6.0;
-      if (avg != 0.0) J3[cidx(g, i0, i1, 0)] += w * v3 * avg;
+      int64_t ci = cidx(g, i0, i1, 0);
+      if (avg != 0.0 && ci >= 0) J3[ci] += w * v3 * avg;
     }
   }
 }
@@ -366,7 +377,10 @@ void orc_smooth_current(const orc_grid* g, double* J) {
           int64_t i = (q / stride) % n;
           int64_t qm = q + ((i == 0) ? (int64_t)(n - 1) * stride : -stride);
           int64_t qp = q + ((i == n - 1) ? -(int64_t)(n - 1) * stride : stride);
-          tmp[q] = (a * V[qm] + b * V[q] + c * V[qp]) / s;
+          /* beyond the x1 ends of a moving window the current is zero */
+          double vm = (g->window && ax == 0 && i == 0) ? 0.0 : V[qm];
+          double vp = (g->window && ax == 0 && i == n - 1) ? 0.0 : V[qp];
+          tmp[q] = (a * vm + b * V[q] + c * vp) / s;
         }
         memcpy(V, tmp, sizeof(double) * (size_t)nc);
       }
@@ -395,7 +409,8 @@ void orc_rho(const orc_grid* g, int64_t n, const double* x, const double* w, dou
         for (int64_t i0 = lo[0]; i0 <= hi[0]; i0++) {
           double s0 = orc_shape(g->order, xi[0] - (double)i0);
           if (s0 == 0.0) continue;
-          rho[cidx(g, i0, i1, i2)] += w[p] * s0 * s1 * s2;
+          int64_t ci = cidx(g, i0, i1, i2);
+          if (ci >= 0) rho[ci] += w[p] * s0 * s1 * s2;
         }
       }
     }
@@ -417,14 +432,14 @@ void orc_yee_b(const orc_grid* g, const double* E, double* B, double h) {
     for (int j = 0; j < g->nx[1]; j++)
       for (int i = 0; i < g->nx[0]; i++) {
         int64_t c = cidx(g, i, j, k);
-        double d2E3 = (E3[cidx(g, i, j + 1, k)] - E3[c]) / g->dx[1];
-        double d1E3 = (E3[cidx(g, i + 1, j, k)] - E3[c]) / g->dx[0];
-        double d1E2 = (E2[cidx(g, i + 1, j, k)] - E2[c]) / g->dx[0];
-        double d2E1 = (E1[cidx(g, i, j + 1, k)] - E1[c]) / g->dx[1];
+        double d2E3 = (at(E3, cidx(g, i, j + 1, k)) - E3[c]) / g->dx[1];
+        double d1E3 = (at(E3, cidx(g, i + 1, j, k)) - E3[c]) / g->dx[0];
+        double d1E2 = (at(E2, cidx(g, i + 1, j, k)) - E2[c]) / g->dx[0];
+        double d2E1 = (at(E1, cidx(g, i, j + 1, k)) - E1[c]) / g->dx[1];
         double d3E2 = 0.0, d3E1 = 0.0;
         if (dim == 3) {
-          d3E2 = (E2[cidx(g, i, j, k + 1)] - E2[c]) / g->dx[2];
-          d3E1 = (E1[cidx(g, i, j, k + 1)] - E1[c]) / g->dx[2];
+          d3E2 = (at(E2, cidx(g, i, j, k + 1)) - E2[c]) / g->dx[2];
+          d3E1 = (at(E1, cidx(g, i, j, k + 1)) - E1[c]) / g->dx[2];
         }
         B1[c] -= h * (d2E3 - d3E2);
         B2[c] -= h * (d3E1 - d1E3);
@@ -443,14 +458,14 @@ void orc_yee_e(const orc_grid* g, double* E, const double* B, const double* J, d
     for (int j = 0; j < g->nx[1]; j++)
       for (int i = 0; i < g->nx[0]; i++) {
         int64_t c = cidx(g, i, j, k);
-        double d2B3 = (B3[c] - B3[cidx(g, i, j - 1, k)]) / g->dx[1];
-        double d1B3 = (B3[c] - B3[cidx(g, i - 1, j, k)]) / g->dx[0];
-        double d1B2 = (B2[c] - B2[cidx(g, i - 1, j, k)]) / g->dx[0];
-        double d2B1 = (B1[c] - B1[cidx(g, i, j - 1, k)]) / g->dx[1];
+        double d2B3 = (B3[c] - at(B3, cidx(g, i, j - 1, k))) / g->dx[1];
+        double d1B3 = (B3[c] - at(B3, cidx(g, i - 1, j, k))) / g->dx[0];
+        double d1B2 = (B2[c] - at(B2, cidx(g, i - 1, j, k))) / g->dx[0];
+        double d2B1 = (B1[c] - at(B1, cidx(g, i, j - 1, k))) / g->dx[1];
         double d3B2 = 0.0, d3B1 = 0.0;
         if (dim == 3) {
-          d3B2 = (B2[c] - B2[cidx(g, i, j, k - 1)]) / g->dx[2];
-          d3B1 = (B1[c] - B1[cidx(g, i, j, k - 1)]) / g->dx[2];
+          d3B2 = (B2[c] - at(B2, cidx(g, i, j, k - 1))) / g->dx[2];
+          d3B1 = (B1[c] - at(B1, cidx(g, i, j, k - 1))) / g->dx[2];
         }
         E1[c] += dt * ((d2B3 - d3B2) - J[c]);
         E2[c] += dt * ((d3B1 - d1B3) - J[nc + c]);
@@ -499,14 +514,17 @@ int orc_step(const orc_grid* g, int64_t n, double* x, double* u, const double* w
   memset(J, 0, sizeof(double) * 3 * (size_t)nc);
   orc_deposit_cells(g, n, a, b, w, v3, J);
   orc_smooth_current(g, J);
-  /* new absolute positions, wrapped into the periodic box */
+  /* new absolute positions, wrapped into the periodic box (x1 of a moving
+   * window is not wrapped: a particle that left it is removed by the caller) */
   for (int64_t p = 0; p < n; p++)
     for (int d = 0; d < dim; d++) {
       double xi = b[p * dim + d];
       double L = (double)g->nx[d];
-      xi = fmod(xi, L);
-      if (xi < 0.0) xi += L;
-      if (xi >= L) xi -= L;
+      if (!(g->window && d == 0)) {
+        xi = fmod(xi, L);
+        if (xi < 0.0) xi += L;
+        if (xi >= L) xi -= L;
+      }
       x[p * dim + d] = g->xmin[d] + xi * g->dx[d];
     }
   /* 5. field solve: B half step, E full step, B half step */
@@ -530,9 +548,9 @@ void orc_gauss_residual(const orc_grid* g, const double* E, const double* rho, d
     for (int j = 0; j < g->nx[1]; j++)
       for (int i = 0; i < g->nx[0]; i++) {
         int64_t c = cidx(g, i, j, k);
-        double div = (E[c] - E[cidx(g, i - 1, j, k)]) / g->dx[0] +
-                     (E[nc + c] - E[nc + cidx(g, i, j - 1, k)]) / g->dx[1];
-        if (dim == 3) div += (E[2 * nc + c] - E[2 * nc + cidx(g, i, j, k - 1)]) / g->dx[2];
+        double div = (E[c] - at(E, cidx(g, i - 1, j, k))) / g->dx[0] +
+                     (E[nc + c] - at(E + nc, cidx(g, i, j - 1, k))) / g->dx[1];
+        if (dim == 3) div += (E[2 * nc + c] - at(E + 2 * nc, cidx(g, i, j, k - 1))) / g->dx[2];
         G[c] = div - rho[c];
       }
 }
@@ -547,9 +565,9 @@ void orc_charge_residual(const orc_grid* g, const double* rho0, const double* rh
     for (int j = 0; j < g->nx[1]; j++)
       for (int i = 0; i < g->nx[0]; i++) {
         int64_t c = cidx(g, i, j, k);
-        double div = (J[c] - J[cidx(g, i - 1, j, k)]) / g->dx[0] +
-                     (J[nc + c] - J[nc + cidx(g, i, j - 1, k)]) / g->dx[1];
-        if (dim == 3) div += (J[2 * nc + c] - J[2 * nc + cidx(g, i, j, k - 1)]) / g->dx[2];
+        double div = (J[c] - at(J, cidx(g, i - 1, j, k))) / g->dx[0] +
+                     (J[nc + c] - at(J + nc, cidx(g, i, j - 1, k))) / g->dx[1];
+        if (dim == 3) div += (J[2 * nc + c] - at(J + 2 * nc, cidx(g, i, j, k - 1))) / g->dx[2];
         C[c] = (rho1[c] - rho0[c]) / g->dt + div;
       }
 }
