@@ -111,6 +111,23 @@ typedef struct {
    * unsmoothed charge density (the charge residual is then not zero). */
   int32_t smooth_level[3];
   double smooth_weights[3][8][3];
+  /* Moving window (Sec. 4.5, dynamic simulation spaces): with move_window = 1
+   * the window moves along +x1 at the speed of light.  x1 is then open: grid
+   * values beyond the first and last x1 cell are zero, currents deposited
+   * there are dropped and particles that leave through an x1 face are
+   * removed.  After every step that brings c t past the next whole cell
+   * (floor(n dt / dx1) shifts after n steps) the window moves by one cell:
+   * the back cell column is discarded with its particles, and the new front
+   * column starts with E = B = 0 and a cold plasma of species 0:
+   * inject_ppc[d] particles per cell per axis on a regular sub-lattice
+   * ((k + 1/2) / inject_ppc[d] of the cell), u = 0, weight inject_w.  The
+   * sort interval is 1.  Positions exported and loaded are lab positions
+   * (xmin1 + shifts dx1 + window position); grid arrays exported and loaded
+   * are in window order (index 0 at the back).  Species 0 must be loaded
+   * before the first step.  Not available with pic_autotune. */
+  int32_t move_window;
+  int32_t inject_ppc[3];
+  double inject_w;
 } pic_config;
 
 #define PIC_MAX_SMOOTH 8
@@ -177,7 +194,10 @@ typedef enum {
                                    with J of the last step (Eq. continuity); meaningful
                                    when exactly one step ran since the snapshot */
   PIC_DIAG_EXPORT_STATE = 7,    /* double[n*(ndim+4)]: per particle x[ndim], u[3], w,
-                                   species by species, each in load order */
+                                   species by species, each in load order (moving
+                                   window: surviving loaded particles in load order,
+                                   then the injected ones in injection order; n is
+                                   the count after the last pic_sync) */
   PIC_DIAG_EXPORT_FIELDS = 8,   /* double[6*ncell]: E1 E2 E3 B1 B2 B3 at time n */
   PIC_DIAG_EXPORT_CURRENT = 9,  /* double[3*ncell]: J^{n+1/2} of the last step */
   PIC_DIAG_COUNTS = 10,         /* double[4]: steps done, particles, rebins done,

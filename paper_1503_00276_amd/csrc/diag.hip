@@ -42,9 +42,14 @@ __global__ void __launch_bounds__(kBlock) rho64(const StoreDesc* __restrict__ sp
   const int cur = pic_cur(*S.ctl);
   const int np = S.np;
   const int no = g.order + 1;
+  const int wo = g.window ? S.win->origin : 0;
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
+    const int cell = S.cell[cur][p];
+    if (cell < 0) continue;  // removed by a moving window
     int c[3];
-    pic_unpack(g, S.cell[cur][p], c);
+    pic_unpack(g, cell, c);
+    int wc = c[0] - wo;  // window column (moving window)
+    if (wc < 0) wc += g.nx[0];
     double wx[4], wy[4], wz[4] = {1.0, 0.0, 0.0, 0.0};
     int bx = rho_weights(g.order, (double)S.eps[cur][0][p], wx);
     int by = rho_weights(g.order, (double)S.eps[cur][1][p], wy);
@@ -60,6 +65,7 @@ __global__ void __launch_bounds__(kBlock) rho64(const StoreDesc* __restrict__ sp
       for (int j = 0; j < no; j++) {
         int gy = pic_wrap(c[1] + by + j, g.nx[1]);
         for (int i = 0; i < no; i++) {
+          if (g.window && (unsigned)(wc + bx + i) >= (unsigned)g.nx[0]) continue;  // beyond the window
           int gx = pic_wrap(c[0] + bx + i, g.nx[0]);
           unsafeAtomicAdd(rho + gx + (size_t)g.nx[0] * (gy + (size_t)g.nx[1] * gz), q * wx[i] * wy[j] * wz[k]);
         }
@@ -74,14 +80,17 @@ __global__ void fill64(double* p, double v, size_t n) {
 
 // Backward-difference divergence of a 3-component staggered field at node c.
 template <typename T>
-__device__ __forceinline__ double div_at(const GridDesc& g, const T* V, int nc, int c, int dim) {
+// wo: ring origin of a moving window (-1 without one); the x1 neighbour
+// behind the window's back column is zero.
+__device__ __forceinline__ double div_at(const GridDesc& g, const T* V, int nc, int c, int dim, int wo = -1) {
   int i = c % g.nx[0];
   int r = c / g.nx[0];
   int j = r % g.nx[1];
   int k = r / g.nx[1];
   int cxm = (i > 0) ? c - 1 : c + g.nx[0] - 1;
   int cym = (j > 0) ? c - g.nx[0] : c + (g.nx[1] - 1) * g.nx[0];
-  double d = ((double)V[c] - (double)V[cxm]) / g.dxd[0] +
+  const double vxm = (wo >= 0 && i == wo) ? 0.0 : (double)V[cxm];
+  double d = ((double)V[c] - vxm) / g.dxd[0] +
              ((double)V[nc + c] - (double)V[nc + cym]) / g.dxd[1];
   if (dim == 3) {
     int sz = g.nx[0] * g.nx[1];
@@ -96,7 +105,7 @@ __global__ void __launch_bounds__(kBlock) gauss64(const InstDesc* __restrict__ i
   const InstDesc& I = *ip;
   const int nc = I.g.ncell;
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x)
-    G[c] = div_at(I.g, I.F[fpar], nc, c, dim) - rho[c];
+    G[c] = div_at(I.g, I.F[fpar], nc, c, dim, I.g.window ? I.win->origin : -1) - rho[c];
 }
 
 __global__ void __launch_bounds__(kBlock) charge64(const InstDesc* __restrict__ ip, const double* rho0,
@@ -104,7 +113,7 @@ __global__ void __launch_bounds__(kBlock) charge64(const InstDesc* __restrict__ 
   const InstDesc& I = *ip;
   const int nc = I.g.ncell;
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x)
-    C[c] = (rho1[c] - rho0[c]) / I.g.dtd + div_at(I.g, I.Jout, nc, c, dim);
+    C[c] = (rho1[c] - rho0[c]) / I.g.dtd + div_at(I.g, I.Jout, nc, c, dim, I.g.window ? I.win->origin : -1);
 }
 
 // ---------------------------------------------------------------------------
@@ -206,6 +215,7 @@ __global__ void __launch_bounds__(kBlock) particle_sums(const StoreDesc* __restr
   const int cur = pic_cur(*S.ctl);
   Pair v[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < S.np; p += gridDim.x * blockDim.x) {
+    if (S.cell[cur][p] < 0) continue;  // removed by a moving window
     double ux = S.u[cur][0][p], uy = S.u[cur][1][p], uz = S.u[cur][2][p];
     double usq = ux * ux + uy * uy + uz * uz;
     double m = (double)S.w[cur][p] * rqm;
@@ -225,15 +235,21 @@ __global__ void __launch_bounds__(kBlock) sq_sums(const double* x, int n, double
 
 // Export position in cell units (cell + offset), u and w of every particle
 // into row id (load order); the host scales positions by the FP64 cell size.
-__global__ void __launch_bounds__(kBlock) export_state(const StoreDesc* __restrict__ sp, double* out) {
+// Rows go to their id (ids = 0..np-1), or, with ids != null (moving window:
+// ids have gaps), to their storage index with the id in ids[] (-1 for a
+// removed particle) for the host to sort.
+__global__ void __launch_bounds__(kBlock) export_state(const StoreDesc* __restrict__ sp, double* out, int* ids) {
   const StoreDesc& S = *sp;
   const GridDesc& g = S.g;
   const int cur = pic_cur(*S.ctl);
   const int stride = g.dim + 4;
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < S.np; p += gridDim.x * blockDim.x) {
+    const int cell = S.cell[cur][p];
+    if (ids) ids[p] = cell < 0 ? -1 : S.id[cur][p];
+    if (cell < 0) continue;
     int c[3];
-    pic_unpack(g, S.cell[cur][p], c);
-    double* row = out + (size_t)S.id[cur][p] * stride;
+    pic_unpack(g, cell, c);
+    double* row = out + (size_t)(ids ? p : S.id[cur][p]) * stride;
     for (int d = 0; d < g.dim; d++) row[d] = (double)c[d] + (double)S.eps[cur][d][p];
     row[g.dim + 0] = S.u[cur][0][p];
     row[g.dim + 1] = S.u[cur][1][p];
@@ -306,8 +322,8 @@ hipError_t pic_launch_sq_sums(const double* v, int n, double* scratch, double* o
   return hipGetLastError();
 }
 
-hipError_t pic_launch_export_state(const StoreDesc* d_store, int np, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(export_state, dim3(grid_for(np)), dim3(kBlock), 0, st, d_store, out);
+hipError_t pic_launch_export_state(const StoreDesc* d_store, int np, double* out, int* ids, hipStream_t st) {
+  hipLaunchKernelGGL(export_state, dim3(grid_for(np)), dim3(kBlock), 0, st, d_store, out, ids);
   return hipGetLastError();
 }
 

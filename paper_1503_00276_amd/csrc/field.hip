@@ -71,6 +71,21 @@ __global__ void __launch_bounds__(kBlock) yee_step(const InstDesc* __restrict__ 
     const int EX = e0 + 3, EY = e1 + 3, EZ = DIM == 3 ? e2 + 3 : 1;
     const int BX = e0 + 2, BY = e1 + 2, BZ = DIM == 3 ? e2 + 2 : 1;
     const int zoff = DIM == 3 ? 1 : 0;  // region origin is one node below the tile
+    // moving window: the window column of region x index x (the x1 neighbour
+    // beyond the window's front or back is zero), and whether the window
+    // moves after this step (its back column then becomes the new, empty front)
+    const bool win = g.window != 0;
+    int wo = 0;
+    bool wshift = false;
+    if (win) {
+      const WinCtl wc = *I.win;
+      wo = wc.origin;
+      wshift = pic_win_shifts(g.wa, wc.step + 1) > pic_win_shifts(g.wa, wc.step);
+    }
+    auto wcol = [&](int x) {
+      int r = wrap1(o0 - 1 + x, n0) - wo;
+      return r < 0 ? r + n0 : r;
+    };
     auto gidx = [&](int x, int y, int z) {
       int gx = wrap1(o0 - 1 + x, n0);
       int gy = wrap1(o1 - 1 + y, n1);
@@ -103,9 +118,10 @@ __global__ void __launch_bounds__(kBlock) yee_step(const InstDesc* __restrict__ 
         for (int x = tx; x < BX; x += T::X) {
           int r = x + BX * (y + BY * z);
           int c = x + EX * (y + EY * z);
+          const bool front = win && wcol(x) == n0 - 1;
           float d2E3 = (sE[2][c + EX] - sE[2][c]) * r1;
-          float d1E3 = (sE[2][c + 1] - sE[2][c]) * r0;
-          float d1E2 = (sE[1][c + 1] - sE[1][c]) * r0;
+          float d1E3 = ((front ? 0.0f : sE[2][c + 1]) - sE[2][c]) * r0;
+          float d1E2 = ((front ? 0.0f : sE[1][c + 1]) - sE[1][c]) * r0;
           float d2E1 = (sE[0][c + EX] - sE[0][c]) * r1;
           float d3E2 = 0.0f, d3E1 = 0.0f;
           if (DIM == 3) {
@@ -143,9 +159,10 @@ __global__ void __launch_bounds__(kBlock) yee_step(const InstDesc* __restrict__ 
             J2 = Ja[nc + gi];
             J3 = Ja[2 * nc + gi];
           }
+          const bool back = win && wcol(x) == 0;
           float d2B3 = (sB[2][cb] - sB[2][cb - BX]) * r1;
-          float d1B3 = (sB[2][cb] - sB[2][cb - 1]) * r0;
-          float d1B2 = (sB[1][cb] - sB[1][cb - 1]) * r0;
+          float d1B3 = (sB[2][cb] - (back ? 0.0f : sB[2][cb - 1])) * r0;
+          float d1B2 = (sB[1][cb] - (back ? 0.0f : sB[1][cb - 1])) * r0;
           float d2B1 = (sB[0][cb] - sB[0][cb - BX]) * r1;
           float d3B2 = 0.0f, d3B1 = 0.0f;
           if (DIM == 3) {
@@ -158,9 +175,10 @@ __global__ void __launch_bounds__(kBlock) yee_step(const InstDesc* __restrict__ 
           // the tile's own cells: keep the step's current and clear the other accumulator
           if (x <= e0 && y <= e1 && (DIM == 2 || z <= e2)) {
             gfloat* Jo = (gfloat*)I.Jout;
-            Jo[gi] = J1;
-            Jo[nc + gi] = J2;
-            Jo[2 * nc + gi] = J3;
+            const float keep = (back && wshift) ? 0.0f : 1.0f;  // discarded column
+            Jo[gi] = J1 * keep;
+            Jo[nc + gi] = J2 * keep;
+            Jo[2 * nc + gi] = J3 * keep;
             if (g.acc_mode == 2) {
               I.J64[jn][gi] = 0ull;
               I.J64[jn][nc + gi] = 0ull;
@@ -181,9 +199,11 @@ __global__ void __launch_bounds__(kBlock) yee_step(const InstDesc* __restrict__ 
         for (int x = 1 + tx; x <= e0; x += T::X) {
           int c = x + EX * (y + EY * z);
           int cb = x + BX * (y + BY * z);
+          const int wx = win ? wcol(x) : 1;
+          const bool front = win && wx == n0 - 1;
           float d2E3 = (sE[2][c + EX] - sE[2][c]) * r1;
-          float d1E3 = (sE[2][c + 1] - sE[2][c]) * r0;
-          float d1E2 = (sE[1][c + 1] - sE[1][c]) * r0;
+          float d1E3 = ((front ? 0.0f : sE[2][c + 1]) - sE[2][c]) * r0;
+          float d1E2 = ((front ? 0.0f : sE[1][c + 1]) - sE[1][c]) * r0;
           float d2E1 = (sE[0][c + EX] - sE[0][c]) * r1;
           float d3E2 = 0.0f, d3E1 = 0.0f;
           if (DIM == 3) {
@@ -191,12 +211,14 @@ __global__ void __launch_bounds__(kBlock) yee_step(const InstDesc* __restrict__ 
             d3E1 = (sE[0][c + EXY] - sE[0][c]) * r2;
           }
           int gi = gidx(x, y, z);
-          Fw[3 * nc + gi] = sB[0][cb] - h * (d2E3 - d3E2);
-          Fw[4 * nc + gi] = sB[1][cb] - h * (d3E1 - d1E3);
-          Fw[5 * nc + gi] = sB[2][cb] - h * (d1E2 - d2E1);
-          Fw[gi] = sE[0][c];
-          Fw[nc + gi] = sE[1][c];
-          Fw[2 * nc + gi] = sE[2][c];
+          // the window's back column becomes its empty front after a shift
+          const float keep = (win && wshift && wx == 0) ? 0.0f : 1.0f;
+          Fw[3 * nc + gi] = (sB[0][cb] - h * (d2E3 - d3E2)) * keep;
+          Fw[4 * nc + gi] = (sB[1][cb] - h * (d3E1 - d1E3)) * keep;
+          Fw[5 * nc + gi] = (sB[2][cb] - h * (d1E2 - d2E1)) * keep;
+          Fw[gi] = sE[0][c] * keep;
+          Fw[nc + gi] = sE[1][c] * keep;
+          Fw[2 * nc + gi] = sE[2][c] * keep;
         }
   }
 }
@@ -226,6 +248,14 @@ __global__ void __launch_bounds__(kBlock) smooth_pass(const InstDesc* __restrict
     const int i = (q / stride) % n;
     const int qm = i == 0 ? q + (n - 1) * stride : q - stride;
     const int qp = i == n - 1 ? q - (n - 1) * stride : q + stride;
+    // moving window: beyond the x1 ends the current is zero
+    float am = a, cp = c;
+    if (g.window && axis == 0) {
+      int wr = i - I.win->origin;
+      if (wr < 0) wr += n;
+      if (wr == 0) am = 0.0f;
+      if (wr == n - 1) cp = 0.0f;
+    }
     const int o = comp * nc;
     float vm, v0, vp;
     if (!first) {
@@ -242,11 +272,35 @@ __global__ void __launch_bounds__(kBlock) smooth_pass(const InstDesc* __restrict
       v0 = Ja[o + q];
       vp = Ja[o + qp];
     }
-    dst[e] = a * vm + b * v0 + c * vp;
+    dst[e] = am * vm + b * v0 + cp * vp;
   }
 }
 
+// End of a step of a moving window: count the step and, when c t has passed
+// the next whole cell, move the window (advance the ring origin, count the
+// injected particles' ids).  One thread per instance.
+__global__ void window_advance(const InstDesc* __restrict__ inst, int ninst) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ninst) return;
+  const InstDesc& I = inst[k];
+  if (!I.g.window) return;
+  WinCtl w = *I.win;
+  const bool sh = pic_win_shifts(I.g.wa, w.step + 1) > pic_win_shifts(I.g.wa, w.step);
+  w.step += 1;
+  if (sh) {
+    w.shifts += 1;
+    w.origin = w.origin + 1 == I.g.nx[0] ? 0 : w.origin + 1;
+    w.next_id += I.win_inject;
+  }
+  *I.win = w;
+}
+
 }  // namespace
+
+hipError_t pic_launch_window_advance(const InstDesc* d_inst, int ninst, hipStream_t st) {
+  hipLaunchKernelGGL(window_advance, dim3((ninst + 63) / 64), dim3(64), 0, st, d_inst, ninst);
+  return hipGetLastError();
+}
 
 hipError_t pic_launch_smooth_pass(const InstDesc* d_inst, int ninst, int max_ncell, int axis, int lev,
                                   int parity, hipStream_t st) {

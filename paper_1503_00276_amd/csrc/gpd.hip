@@ -237,9 +237,11 @@ __device__ __forceinline__ void lds_add_any(acc_t* p, float v) {
 // b0..b2 are the LDS current-region coordinates of the old cell; a_d are
 // w (dx_d/dt) in fixed-point units, v3s = w v3 in fixed-point units (2D).
 template <int DIM>
+// With a moving window (wcol >= 0, the particle's window column) the adds to
+// x1 nodes beyond the window's ends are dropped.
 __device__ __forceinline__ void deposit_tristan(acc_t* sJ, int jn, const int JR[3], int b0, int b1, int b2,
                                                 const float e[3], const float dl[3], const int mv[3], float a1,
-                                                float a2, float a3, float v3s) {
+                                                float a2, float a3, float v3s, int wcol, int nx0) {
   // crossing parameter of each axis (2 when the axis stays in its cell)
   float tc[3] = {2.0f, 2.0f, 2.0f};
 #pragma unroll
@@ -275,15 +277,18 @@ __device__ __forceinline__ void deposit_tristan(acc_t* sJ, int jn, const int JR[
       }
       const float dx = pb[0] - pa[0], dy = pb[1] - pa[1];
       const float xm = 0.5f * (pa[0] + pb[0]), ym = 0.5f * (pa[1] + pb[1]);
+      // x1 nodes of the piece's cell: inside the window or not
+      const float in0 = (wcol < 0 || (unsigned)(wcol + o[0]) < (unsigned)nx0) ? 1.0f : 0.0f;
+      const float in1 = (wcol < 0 || (unsigned)(wcol + o[0] + 1) < (unsigned)nx0) ? 1.0f : 0.0f;
       if constexpr (DIM == 2) {
         const int c = (b1 + o[1]) * R0 + b0 + o[0];
-        const float f1 = a1 * dx, f2 = a2 * dy;
+        const float f1 = a1 * dx * in0, f2 = a2 * dy;
         lds_add(J1 + c, f1 * (1.0f - ym));
         lds_add(J1 + c + R0, f1 * ym);
-        lds_add(J2 + c, f2 * (1.0f - xm));
-        lds_add(J2 + c + 1, f2 * xm);
+        lds_add(J2 + c, f2 * (1.0f - xm) * in0);
+        lds_add(J2 + c + 1, f2 * xm * in1);
         const float f3 = v3s * (tb - ta);
-        const float sxa[2] = {1.0f - pa[0], pa[0]}, sxb[2] = {1.0f - pb[0], pb[0]};
+        const float sxa[2] = {(1.0f - pa[0]) * in0, pa[0] * in1}, sxb[2] = {(1.0f - pb[0]) * in0, pb[0] * in1};
         const float sya[2] = {1.0f - pa[1], pa[1]}, syb[2] = {1.0f - pb[1], pb[1]};
 #pragma unroll
         for (int j = 0; j < 2; j++)
@@ -297,15 +302,16 @@ __device__ __forceinline__ void deposit_tristan(acc_t* sJ, int jn, const int JR[
         const int c = ((b2 + o[2]) * JR[1] + b1 + o[1]) * R0 + b0 + o[0];
         const float Wx[2] = {1.0f - xm, xm}, Wy[2] = {1.0f - ym, ym}, Wz[2] = {1.0f - zm, zm};
         const float s[2] = {-1.0f, 1.0f};
+        const float inx[2] = {in0, in1};
         const float yz = dy * dz * (1.0f / 12.0f), xz = dx * dz * (1.0f / 12.0f), xy = dx * dy * (1.0f / 12.0f);
-        const float f1 = a1 * dx, f2 = a2 * dy, f3 = a3 * dz;
+        const float f1 = a1 * dx * in0, f2 = a2 * dy, f3 = a3 * dz;
 #pragma unroll
         for (int k = 0; k < 2; k++)
 #pragma unroll
           for (int j = 0; j < 2; j++) {
             lds_add(J1 + c + k * R01 + j * R0, f1 * (Wy[j] * Wz[k] + s[j] * s[k] * yz));
-            lds_add(J2 + c + k * R01 + j, f2 * (Wx[j] * Wz[k] + s[j] * s[k] * xz));
-            lds_add(J3 + c + k * R0 + j, f3 * (Wx[j] * Wy[k] + s[j] * s[k] * xy));
+            lds_add(J2 + c + k * R01 + j, f2 * inx[j] * (Wx[j] * Wz[k] + s[j] * s[k] * xz));
+            lds_add(J3 + c + k * R0 + j, f3 * inx[j] * (Wx[j] * Wy[k] + s[j] * s[k] * xy));
           }
       }
     }
@@ -404,11 +410,22 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
   gfloat* __restrict__ up2 = (gfloat*)S.u[set][2];
   const gfloat* __restrict__ wp = (const gfloat*)S.w[set];
   const float h = 0.5f * S.qm * g.dt;
-  bool strayed = false, bad = false;
+  bool strayed = false, bad = false, died = false;
+  // moving window: ring origin of the x1 columns and whether the window
+  // moves after this step (its back column is then discarded)
+  const bool win = g.window != 0;
+  int wo = 0;
+  bool wshift = false;
+  if (win) {
+    const WinCtl wc = *S.win;
+    wo = wc.origin;
+    wshift = pic_win_shifts(g.wa, wc.step + 1) > pic_win_shifts(g.wa, wc.step);
+  }
 
   // 3. particles
   for (int p = it.begin + tid; p < it.end; p += blockDim.x) {
     int cell = cellp[p];
+    if (win && cell < 0) continue;  // removed, awaiting the rebin
     float e[3];
     e[0] = ep0[p];
     e[1] = ep1[p];
@@ -436,6 +453,17 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
     for (int d = 0; d < DIM; d++) {
       gather_weights<ORDER>(e[d], false, b0[d], w0[d]);
       gather_weights<ORDER>(e[d], true, bh[d], wh[d]);
+    }
+    // moving window: x1 nodes beyond the window's ends hold zero fields
+    int wcol = 0;
+    if (win) {
+      wcol = cc[0] - wo;
+      if (wcol < 0) wcol += g.nx[0];
+#pragma unroll
+      for (int i = 0; i < NG; i++) {
+        if ((unsigned)(wcol + b0[0] + i) >= (unsigned)g.nx[0]) w0[0][i] = 0.0f;
+        if ((unsigned)(wcol + bh[0] + i) >= (unsigned)g.nx[0]) wh[0][i] = 0.0f;
+      }
     }
     float Fp[6];
     // LDS offsets of the first tap: one multiply per particle; the offsets of
@@ -538,7 +566,7 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
       for (int d = 0; d < DIM; d++) dl[d] = (float)mv[d] + en[d] - e[d];
       const int b0 = jlo[0] + l[0], b1 = jlo[1] + l[1], b2 = DIM == 3 ? jlo[2] + l[2] : 0;
       deposit_tristan<DIM>(sJ, jn, JR, b0, b1, b2, e, dl, mv, wq * g.cdt[0] * js, wq * g.cdt[1] * js,
-                           wq * g.cdt[2] * js, wq * uz * gi * js);
+                           wq * g.cdt[2] * js, wq * uz * gi * js, win ? wcol : -1, g.nx[0]);
     } else {
       // ISIS ordering average in Esirkepov's closed form
       int wb[3], p0[3];
@@ -563,6 +591,17 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
           P1[k] = q1 * a;
           P2[k] = q2 * b;
         }
+      }
+      if (win) {
+        // moving window: currents at x1 nodes beyond the window are dropped
+        // (the prefix above still counts the charge change there)
+#pragma unroll
+        for (int k = 0; k < W; k++)
+          if ((unsigned)(wcol + wb[0] + k) >= (unsigned)g.nx[0]) {
+            S0[0][k] = 0.0f;
+            D[0][k] = 0.0f;
+            if (k < W - 1) P1[k] = 0.0f;
+          }
       }
       if constexpr (DIM == 2) {
         // The window of ORDER+2 nodes per axis splits into a core of K = ORDER+1
@@ -728,10 +767,19 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
       strayed = strayed || ln < -g.flag_slack || ln >= ext[d] + g.flag_slack;
       dd[d] = ln < 0 ? -1 : (ln >= ext[d] ? 1 : 0);
     }
+    // moving window: a particle that left through an x1 face, or sits in the
+    // back column when the window moves after this step, is removed (its
+    // current of this step is already deposited)
+    bool dead = false;
+    if (win) {
+      const int wn = wcol + mv[0];
+      dead = wn < 0 || wn >= g.nx[0] || (wshift && wn == 0);
+      died = died || dead;
+    }
     {
       // wave-aggregated count per slot (almost every particle is in slot 13)
-      const int sl = pic_slot(dd[0], dd[1], dd[2]);
-      unsigned long long todo = __ballot(1);
+      const int sl = dead ? -1 : pic_slot(dd[0], dd[1], dd[2]);
+      unsigned long long todo = __ballot(sl >= 0);
       while (todo) {
         const int leader = __ffsll((long long)todo) - 1;
         const int ls = __shfl(sl, leader);
@@ -740,7 +788,7 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
         todo &= ~m;
       }
     }
-    cellp[p] = pic_pack(g, nc[0], nc[1], DIM == 3 ? nc[2] : 0);
+    cellp[p] = dead ? -1 : pic_pack(g, nc[0], nc[1], DIM == 3 ? nc[2] : 0);
     ep0[p] = en[0];
     ep1[p] = en[1];
     if (DIM == 3) ep2[p] = en[2];
@@ -749,7 +797,7 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
     up2[p] = uz;
   }
   // one plain store per workgroup (all writers store the same value)
-  const int any_strayed = __syncthreads_or(strayed ? 1 : 0);
+  const int any_strayed = __syncthreads_or((strayed || died) ? 1 : 0);
   const int any_bad = __syncthreads_or(bad ? 1 : 0);
   if (tid == 0) {
     if (any_strayed) S.ctl->flag = 1;

@@ -34,6 +34,8 @@ struct GridDesc {
   float jscale, jinv;
   int acc_mode;       // 0/1: FP32 fold of the tile sums, 2: int64 fold (deterministic)
   int deposit;        // 0: ISIS ordering average, 1: TRISTAN path cut at faces (linear shape)
+  int window;         // 1: moving window along x1 (x1 open; grid stored as a ring, see WinCtl)
+  double wa;          // moving window: c dt / dx1 (shifts after n steps: floor(n wa))
   // LDS region geometry (nodes relative to the tile origin):
   // field region [-(slack+fa), e+slack+fb), current region [-(slack+ja), e+slack+jb)
   int fa, fb, ja, jb;
@@ -53,10 +55,27 @@ struct StoreCtl {
   int nsorts;       // rebins performed
   int nchecks;      // rebin checks performed
   int force;        // set by the host: rebin at every check (autotuner trials)
-  int pad[2];
+  int np;           // particles in the current set after the last rebin (moving window)
+  int pad;
 };
 
 __host__ __device__ inline int pic_cur(const StoreCtl& c) { return c.cur ^ c.pending; }
+
+// Moving-window state of one instance.  The grid and the particles' cell
+// indices are kept in ring coordinates along x1: ring column r holds window
+// column (r - origin) mod nx1, so a shift only advances the origin, zeroes
+// the old back column (the new front) and refills it.  Kernels read the
+// state at launch; the step's last kernel advances it.
+struct WinCtl {
+  long long step;     // steps done
+  int shifts;         // cell shifts done
+  int origin;         // ring column of window column 0
+  long long next_id;  // id of the next injected particle
+  int pad[2];
+};
+
+// Shifts after n steps of a window moving at c.
+__host__ __device__ inline int pic_win_shifts(double wa, long long n) { return (int)floor((double)n * wa); }
 
 // Work item: a contiguous run of particles that all belong to one tile.
 struct Item {
@@ -90,6 +109,10 @@ struct StoreDesc {
   int* bsum;                 // [nblk][2] particles and items of each block of kRebinTiles tiles
   int* bpre;                 // [nblk][2] their exclusive prefix
   int tile0, blk0;           // first tile and tile block of this store within its launch group
+  int cap;                   // particles the buffer sets hold
+  WinCtl* win;               // moving window state of the instance (null without a window)
+  int inj_ppc[3];            // moving window: injected particles per cell per axis
+  float inj_w;               // moving window: weight of an injected particle
   const int* nsrc;           // [ntiles][27] tile - delta_s (periodic), per instance
   const int* ndst;           // [ntiles][27] tile + delta_s (periodic), per instance
   StoreCtl* ctl;
@@ -110,6 +133,8 @@ struct InstDesc {
   int sm_npass;
   float sm_w[3][8][3];
   float* Jsm[2];
+  WinCtl* win;               // moving window state (null without a window)
+  int win_inject;            // moving window: particles injected per shift
 };
 
 // ---------------------------------------------------------------------------

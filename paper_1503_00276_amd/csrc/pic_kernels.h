@@ -16,6 +16,7 @@ hipError_t pic_launch_gpd(int dim, int order, const StoreDesc* d_stores, int nst
 
 // Yee field solve (field.hip); instances in d_inst[0..ninst)
 int pic_yee_tiles(int dim, const int nx[3]);
+hipError_t pic_launch_window_advance(const InstDesc* d_inst, int ninst, hipStream_t st);
 hipError_t pic_launch_smooth_pass(const InstDesc* d_inst, int ninst, int max_ncell, int axis, int lev,
                                   int parity, hipStream_t st);
 hipError_t pic_launch_yee_step(const InstDesc* d_inst, int ninst, int max_tiles, int dim, int parity,
@@ -23,7 +24,7 @@ hipError_t pic_launch_yee_step(const InstDesc* d_inst, int ninst, int max_tiles,
 
 // tile rebin (sort.hip); stores in d_stores[0..nstores)
 hipError_t pic_launch_rebin(const StoreDesc* d_stores, int nstores, int max_items, int total_tiles,
-                            int total_blocks, hipStream_t st);
+                            int total_blocks, int inject_max, hipStream_t st);
 
 // diagnostics (diag.hip)
 hipError_t pic_launch_rho64(const StoreDesc* d_store, int np_max, double* rho, hipStream_t st);
@@ -39,6 +40,6 @@ hipError_t pic_launch_field_sums(const InstDesc* d_inst, int ncell, int fpar, do
 hipError_t pic_launch_particle_sums(const StoreDesc* d_store, int np, double rqm, double* scratch,
                                     double* out, hipStream_t st);
 hipError_t pic_launch_sq_sums(const double* v, int n, double* scratch, double* out, hipStream_t st);
-hipError_t pic_launch_export_state(const StoreDesc* d_store, int np, double* out, hipStream_t st);
+hipError_t pic_launch_export_state(const StoreDesc* d_store, int np, double* out, int* ids, hipStream_t st);
 hipError_t pic_launch_f32_to_f64(const float* in, double* out, size_t n, hipStream_t st);
 hipError_t pic_launch_f64_to_f32(const double* in, float* out, size_t n, hipStream_t st);

@@ -48,6 +48,7 @@ struct Instance {
   unsigned long long* J64[2] = {nullptr, nullptr};
   float* Jout = nullptr;
   float* Jsm[2] = {nullptr, nullptr};  // smoothing buffers (only when smoothing is on)
+  WinCtl* win = nullptr;               // moving window state (device)
   int* nsrc = nullptr;  // neighbour tile tables of the rebin
   int* ndst = nullptr;
   double wmax[PIC_MAX_SPECIES] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -62,6 +63,8 @@ struct Group {
   size_t lds;
   bool fixed64;
   int sm_max[3];  // most smoothing passes of any instance, per axis
+  int inject_max; // moving window: most particles a store injects per shift
+  bool window;    // some instance has a moving window
 };
 
 struct Sim {
@@ -158,6 +161,8 @@ pic_status setup_grid(Sim& S, const pic_config& c, int sort_interval, GridDesc& 
   g.dtd = c.dt;
   g.acc_mode = c.accumulator;
   g.deposit = c.deposit;
+  g.window = c.move_window;
+  g.wa = c.dt / c.dx[0];
   g.jscale = 1.0f;
   g.jinv = 1.0f;
   g.flag_slack = 1;
@@ -226,6 +231,14 @@ pic_status validate(Sim& S, const pic_config& c) {
     return S.fail(PIC_E_INVALID, "unknown deposit %d", c.deposit);
   if (c.deposit == PIC_DEPOSIT_TRISTAN && c.shape_order != 1)
     return S.fail(PIC_E_INVALID, "the TRISTAN deposit needs the linear shape (shape_order 1)");
+  if (c.move_window != 0 && c.move_window != 1) return S.fail(PIC_E_INVALID, "move_window must be 0 or 1");
+  if (c.move_window) {
+    for (int a = 0; a < c.ndim; a++)
+      if (c.inject_ppc[a] < 1 || c.inject_ppc[a] > 64)
+        return S.fail(PIC_E_INVALID, "inject_ppc[%d] must be 1..64 with a moving window", a);
+    if (!std::isfinite(c.inject_w)) return S.fail(PIC_E_INVALID, "inject_w not finite");
+    if (c.sort_interval > 1) return S.fail(PIC_E_INVALID, "a moving window needs sort_interval 1 (or 0)");
+  }
   for (int a = 0; a < c.ndim; a++) {
     if (c.smooth_level[a] < 0 || c.smooth_level[a] > PIC_MAX_SMOOTH)
       return S.fail(PIC_E_INVALID, "smooth_level[%d] must be 0..%d", a, PIC_MAX_SMOOTH);
@@ -242,8 +255,9 @@ pic_status validate(Sim& S, const pic_config& c) {
 }
 
 int default_interval(const pic_config& c) {
-  // 3D tiles are LDS-bound: keep the slack at one cell and check every step
-  if (c.ndim == 3) return 1;
+  // 3D tiles are LDS-bound: keep the slack at one cell and check every step;
+  // a moving window removes and injects particles at every step's check
+  if (c.ndim == 3 || c.move_window) return 1;
   double vmax = 0.0;
   for (int d = 0; d < c.ndim; d++) vmax = std::max(vmax, c.dt / c.dx[d]);
   // largest interval whose slack stays at 2 cells
@@ -328,6 +342,8 @@ pic_status alloc_species(Sim& S, Instance& I, Species& sp, int64_t cap, int chun
   }
   d.nsrc = I.nsrc;
   d.ndst = I.ndst;
+  d.cap = (int)cap;
+  d.win = I.win;
   StoreCtl z{};
   HIPCHK(S, hipMemcpy(sp.ctl, &z, sizeof z, hipMemcpyHostToDevice));
   sp.cap = cap;
@@ -345,7 +361,7 @@ pic_status refresh_descriptors(Sim& S) {
   S.igroups.clear();
   for (int dim = 2; dim <= 3; dim++)
     for (int order = 1; order <= 3; order++) {
-      Group gr{dim, order, (int)stores.size(), 0, 0, 0, 0, 0, 0, false, {0, 0, 0}};
+      Group gr{dim, order, (int)stores.size(), 0, 0, 0, 0, 0, 0, false, {0, 0, 0}, 0, false};
       for (size_t i = 0; i < S.inst.size(); i++) {
         Instance& I = S.inst[i];
         if (I.g.dim != dim || I.g.order != order) continue;
@@ -363,6 +379,8 @@ pic_status refresh_descriptors(Sim& S) {
           gr.max_tiles += I.g.ntiles;
           gr.max_blocks += (I.g.ntiles + PIC_REBIN_TILES - 1) / PIC_REBIN_TILES;
           gr.lds = std::max(gr.lds, pic_gpd_lds_bytes(I.g));
+          gr.inject_max = std::max(gr.inject_max, sp.desc.inj_ppc[0] * sp.desc.inj_ppc[1] * sp.desc.inj_ppc[2] *
+                                                      (I.g.ncell / I.g.nx[0]));
         }
       }
           if (gr.count > 0) {
@@ -373,7 +391,7 @@ pic_status refresh_descriptors(Sim& S) {
     }
   std::vector<InstDesc> insts;
   for (int dim = 2; dim <= 3; dim++) {
-    Group gr{dim, 0, (int)insts.size(), 0, 0, 0, 0, 0, 0, false, {0, 0, 0}};
+    Group gr{dim, 0, (int)insts.size(), 0, 0, 0, 0, 0, 0, false, {0, 0, 0}, 0, false};
     for (size_t i = 0; i < S.inst.size(); i++) {
       Instance& I = S.inst[i];
       if (I.g.dim != dim) continue;
@@ -402,6 +420,13 @@ pic_status refresh_descriptors(Sim& S) {
       id.sm_npass = npass;
       id.Jsm[0] = I.Jsm[0];
       id.Jsm[1] = I.Jsm[1];
+      id.win = I.win;
+      if (I.cfg.move_window) {
+        int ppc = 1;
+        for (int a = 0; a < I.g.dim; a++) ppc *= I.cfg.inject_ppc[a];
+        id.win_inject = ppc * (I.g.ncell / I.g.nx[0]);
+        gr.window = true;
+      }
       insts.push_back(id);
       if (I.g.acc_mode == PIC_ACC_FIXED64) gr.fixed64 = true;
       gr.count++;
@@ -517,9 +542,12 @@ pic_status launch_steps(Sim& S, int64_t first, int nsteps, bool end_with_check) 
       e0 = prof_begin(S);
       for (const Group& gr : S.sgroups)
         HIPCHK(S, pic_launch_rebin(S.d_stores + gr.first, gr.count, gr.max_items, gr.max_tiles, gr.max_blocks,
-                                   S.stream));
+                                   gr.inject_max, S.stream));
       prof_end(S, 2, e0);
     }
+    // moving windows: count the step, move the window when it is due
+    for (const Group& gr : S.igroups)
+      if (gr.window) HIPCHK(S, pic_launch_window_advance(S.d_inst + gr.first, gr.count, S.stream));
   }
   return PIC_OK;
 }
@@ -575,6 +603,14 @@ pic_status sim_step(Sim& S, int64_t nsteps) {
   return PIC_OK;
 }
 
+// Host copy of an instance's moving-window state (zero without a window).
+pic_status read_win(Sim& S, const Instance& I, WinCtl& w) {
+  memset(&w, 0, sizeof w);
+  if (!I.win) return PIC_OK;
+  HIPCHK(S, hipMemcpy(&w, I.win, sizeof w, hipMemcpyDeviceToHost));
+  return PIC_OK;
+}
+
 pic_status sim_sync(Sim& S) {
   HIPCHK(S, hipStreamSynchronize(S.stream));
   for (Instance& I : S.inst)
@@ -583,6 +619,12 @@ pic_status sim_sync(Sim& S) {
       StoreCtl c{};
       HIPCHK(S, hipMemcpy(&c, sp.ctl, sizeof c, hipMemcpyDeviceToHost));
       if (c.bad) return S.fail(PIC_E_STATE, "a particle left the region staged for its tile");
+      if (I.cfg.move_window && c.nchecks > 0 && c.np != sp.np) {
+        // a moving window removed and injected particles
+        sp.np = c.np;
+        sp.desc.np = c.np;
+        S.dirty = true;
+      }
     }
   return PIC_OK;
 }
@@ -791,6 +833,12 @@ pic_status sim_load(Sim& S, int inst, int32_t species, double rqm, int64_t n, co
     return S.fail(PIC_E_NOMEM, "species %d would hold %lld particles, capacity %lld", species, (long long)total,
                   (long long)I.cfg.capacity);
   if (total > 0x7fffff00LL) return S.fail(PIC_E_NOMEM, "too many particles");
+  if ((st = sim_sync(S)) != PIC_OK) return st;  // fresh particle counts (moving window)
+  WinCtl wc;
+  if ((st = read_win(S, I, wc)) != PIC_OK) return st;
+  const bool win = I.cfg.move_window != 0;
+  if (win && species != 0 && !I.sp[0].used)
+    return S.fail(PIC_E_STATE, "with a moving window species 0 (the injected one) is loaded first");
   HostParticles h;
   if ((st = read_back(S, sp, dim, h)) != PIC_OK) return st;
   const size_t old = h.cell.size();
@@ -800,6 +848,12 @@ pic_status sim_load(Sim& S, int inst, int32_t species, double rqm, int64_t n, co
     for (int d = 0; d < dim; d++) {
       double L = (double)I.g.nx[d];
       double xi = (hx[p * dim + d] - I.cfg.xmin[d]) / I.cfg.dx[d];
+      if (win && d == 0) {
+        // window position, then ring column
+        xi -= (double)wc.shifts;
+        if (!(xi >= 0.0 && xi < L)) return S.fail(PIC_E_RANGE, "particle outside the moving window");
+        xi += (double)wc.origin;
+      }
       xi = std::fmod(xi, L);
       if (xi < 0.0) xi += L;
       if (xi >= L) xi -= L;
@@ -815,23 +869,70 @@ pic_status sim_load(Sim& S, int inst, int32_t species, double rqm, int64_t n, co
       h.eps[d][old + p] = e;
     }
     h.cell[old + p] = pic_pack(I.g, c[0], c[1], c[2]);
-    h.id[old + p] = (int)(old + p);
+    h.id[old + p] = win ? (int)(wc.next_id + p) : (int)(old + p);
     for (int k = 0; k < 3; k++) h.u[k][old + p] = (float)hu[p * 3 + k];
     h.w[old + p] = (float)hw[p];
   }
   double wm = I.wmax[species];
   for (double v : hw) wm = std::max(wm, std::fabs(v));
   I.wmax[species] = wm;
-  if (!sp.used || total > sp.cap) {
-    int64_t cap = I.cfg.capacity > 0 ? I.cfg.capacity : total;
+  int64_t want = total;
+  if (win && species == 0) {
+    // room for the window's plasma: a full window of injected lattice plus
+    // two columns in flight
+    int64_t ppc = 1;
+    for (int a = 0; a < dim; a++) ppc *= I.cfg.inject_ppc[a];
+    int64_t col = ppc * (I.g.ncell / I.g.nx[0]);
+    want = std::max<int64_t>(total, ppc * I.g.ncell) + 2 * col + 1024;
+  }
+  if (!sp.used || want > sp.cap) {
+    int64_t cap = I.cfg.capacity > 0 ? std::max<int64_t>(I.cfg.capacity, want) : want;
     int chunk = I.cfg.chunk > 0 ? I.cfg.chunk : 2048;
     if ((st = alloc_species(S, I, sp, std::max<int64_t>(cap, 1), chunk)) != PIC_OK) return st;
     sp.used = true;
     sp.rqm = rqm;
     sp.desc.qm = (float)(1.0 / rqm);
   }
+  if (win && species == 0) {
+    for (int a = 0; a < 3; a++) sp.desc.inj_ppc[a] = a < dim ? I.cfg.inject_ppc[a] : 1;
+    sp.desc.inj_w = (float)I.cfg.inject_w;
+    I.wmax[0] = std::max(I.wmax[0], std::fabs(I.cfg.inject_w));
+  }
   set_current_scale(I);
-  return upload_binned(S, I, sp, h);
+  if (win) {
+    wc.next_id += n;
+    HIPCHK(S, hipMemcpy(I.win, &wc, sizeof wc, hipMemcpyHostToDevice));
+  }
+  st = upload_binned(S, I, sp, h);
+  if (st == PIC_OK && win) {
+    StoreCtl c{};
+    HIPCHK(S, hipMemcpy(&c, sp.ctl, sizeof c, hipMemcpyDeviceToHost));
+    c.np = (int)sp.np;
+    HIPCHK(S, hipMemcpy(sp.ctl, &c, sizeof c, hipMemcpyHostToDevice));
+  }
+  return st;
+}
+
+// Moving window: grid arrays are kept in ring order along x1 (ring column r
+// holds window column (r - origin) mod nx1).  to_window copies ncomp
+// components from ring to window order in place; to_ring the other way.
+void ring_rotate(double* a, size_t ncomp, const GridDesc& g, int origin, bool to_window) {
+  if (origin == 0) return;
+  const size_t nc = (size_t)g.ncell;
+  const int n0 = g.nx[0];
+  std::vector<double> row(n0);
+  for (size_t c = 0; c < ncomp; c++)
+    for (size_t r0 = 0; r0 < nc; r0 += n0) {
+      double* v = a + c * nc + r0;
+      for (int w = 0; w < n0; w++) {
+        const int r = (w + origin) % n0;
+        if (to_window)
+          row[w] = v[r];
+        else
+          row[r] = v[w];
+      }
+      memcpy(v, row.data(), n0 * sizeof(double));
+    }
 }
 
 pic_status sim_load_fields(Sim& S, int inst, const double* e, const double* b, uint32_t flags) {
@@ -843,6 +944,13 @@ pic_status sim_load_fields(Sim& S, int inst, const double* e, const double* b, u
   pic_status st;
   if ((st = copy_in(S, he, e, n, flags)) != PIC_OK) return st;
   if ((st = copy_in(S, hb, b, n, flags)) != PIC_OK) return st;
+  if (I.cfg.move_window) {
+    if ((st = sim_sync(S)) != PIC_OK) return st;
+    WinCtl wc;
+    if ((st = read_win(S, I, wc)) != PIC_OK) return st;
+    ring_rotate(he.data(), 3, I.g, wc.origin, false);
+    ring_rotate(hb.data(), 3, I.g, wc.origin, false);
+  }
   std::vector<float> f(2 * n);
   for (size_t i = 0; i < n; i++) {
     if (!std::isfinite(he[i]) || !std::isfinite(hb[i])) return S.fail(PIC_E_RANGE, "non-finite field value");
@@ -879,9 +987,9 @@ pic_status compute_rho(Sim& S, int i, double* d_rho) {
 pic_status sim_diag(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_bytes, size_t* written) {
   if (i < 0 || i >= (int)S.inst.size()) return S.fail(PIC_E_INVALID, "instance out of range");
   if (written) *written = 0;
-  pic_status st = refresh_descriptors(S);
+  pic_status st = sim_sync(S);  // first: a moving window changes the particle counts
   if (st != PIC_OK) return st;
-  if ((st = sim_sync(S)) != PIC_OK) return st;
+  if ((st = refresh_descriptors(S)) != PIC_OK) return st;
   Instance& I = S.inst[i];
   const GridDesc& g = I.g;
   const size_t nc = (size_t)g.ncell;
@@ -964,6 +1072,11 @@ pic_status sim_diag(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_byt
       }
       HIPCHK(S, hipMemcpyAsync(out, src, nc * sizeof(double), hipMemcpyDeviceToHost, S.stream));
       HIPCHK(S, hipStreamSynchronize(S.stream));
+      if (I.cfg.move_window) {
+        WinCtl wc;
+        if ((st = read_win(S, I, wc)) != PIC_OK) return st;
+        ring_rotate((double*)out, 1, g, wc.origin, true);
+      }
       return PIC_OK;
     }
     case PIC_DIAG_RHO_SNAPSHOT: {
@@ -987,11 +1100,44 @@ pic_status sim_diag(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_byt
         double* dbuf = nullptr;
         HIPCHK(S, hipMalloc(&dbuf, (size_t)sp.np * stride * sizeof(double)));
         tmp.push_back(dbuf);
-        HIPCHK(S, pic_launch_export_state(S.d_stores + k, (int)sp.np, dbuf, S.stream));
-        HIPCHK(S, hipMemcpyAsync(o, dbuf, (size_t)sp.np * stride * sizeof(double), hipMemcpyDeviceToHost, S.stream));
-        HIPCHK(S, hipStreamSynchronize(S.stream));
-        for (int64_t p = 0; p < sp.np; p++)
-          for (int d = 0; d < g.dim; d++) o[p * stride + d] = I.cfg.xmin[d] + o[p * stride + d] * I.cfg.dx[d];
+        if (I.cfg.move_window) {
+          // rows in storage order with their ids; sorted by id here, x1 from
+          // the ring column to the lab position
+          int* dids = nullptr;
+          HIPCHK(S, hipMalloc(&dids, (size_t)sp.np * sizeof(int)));
+          tmp.push_back(dids);
+          HIPCHK(S, pic_launch_export_state(S.d_stores + k, (int)sp.np, dbuf, dids, S.stream));
+          std::vector<double> rows((size_t)sp.np * stride);
+          std::vector<int> ids(sp.np);
+          HIPCHK(S, hipMemcpyAsync(rows.data(), dbuf, rows.size() * sizeof(double), hipMemcpyDeviceToHost, S.stream));
+          HIPCHK(S, hipMemcpyAsync(ids.data(), dids, ids.size() * sizeof(int), hipMemcpyDeviceToHost, S.stream));
+          HIPCHK(S, hipStreamSynchronize(S.stream));
+          WinCtl wc;
+          if ((st = read_win(S, I, wc)) != PIC_OK) return st;
+          std::vector<int64_t> order;
+          order.reserve(sp.np);
+          for (int64_t p = 0; p < sp.np; p++)
+            if (ids[p] >= 0) order.push_back(p);
+          std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return ids[a] < ids[b]; });
+          if ((int64_t)order.size() != sp.np) return S.fail(PIC_E_STATE, "removed particles left in the store");
+          for (size_t q = 0; q < order.size(); q++) {
+            const double* r = rows.data() + (size_t)order[q] * stride;
+            double* dst = o + q * stride;
+            for (int c = 0; c < stride; c++) dst[c] = r[c];
+            const double v = r[0];
+            const double cr = std::floor(v);
+            int wcol = (int)cr - wc.origin;
+            if (wcol < 0) wcol += g.nx[0];
+            dst[0] = I.cfg.xmin[0] + ((double)wc.shifts + (double)wcol + (v - cr)) * I.cfg.dx[0];
+            for (int d = 1; d < g.dim; d++) dst[d] = I.cfg.xmin[d] + r[d] * I.cfg.dx[d];
+          }
+        } else {
+          HIPCHK(S, pic_launch_export_state(S.d_stores + k, (int)sp.np, dbuf, nullptr, S.stream));
+          HIPCHK(S, hipMemcpyAsync(o, dbuf, (size_t)sp.np * stride * sizeof(double), hipMemcpyDeviceToHost, S.stream));
+          HIPCHK(S, hipStreamSynchronize(S.stream));
+          for (int64_t p = 0; p < sp.np; p++)
+            for (int d = 0; d < g.dim; d++) o[p * stride + d] = I.cfg.xmin[d] + o[p * stride + d] * I.cfg.dx[d];
+        }
         o += (size_t)sp.np * stride;
       }
       return PIC_OK;
@@ -1006,6 +1152,11 @@ pic_status sim_diag(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_byt
       HIPCHK(S, pic_launch_f32_to_f64(kind == PIC_DIAG_EXPORT_FIELDS ? I.F[S.steps & 1] : I.Jout, dbuf, ncomp * nc, S.stream));
       HIPCHK(S, hipMemcpyAsync(out, dbuf, ncomp * nc * sizeof(double), hipMemcpyDeviceToHost, S.stream));
       HIPCHK(S, hipStreamSynchronize(S.stream));
+      if (I.cfg.move_window) {
+        WinCtl wc;
+        if ((st = read_win(S, I, wc)) != PIC_OK) return st;
+        ring_rotate((double*)out, ncomp, g, wc.origin, true);
+      }
       return PIC_OK;
     }
     case PIC_DIAG_KERNEL_TIMES: {
@@ -1107,6 +1258,10 @@ pic_status sim_create(Sim& S, const pic_config* cfgs, int n, void* stream) {
     }
     if ((st = build_tables(S, I)) != PIC_OK) return st;
     if (hipMalloc(&I.Jout, 3 * nc * sizeof(float)) != hipSuccess) return S.fail(PIC_E_NOMEM, "current allocation failed");
+    if (I.cfg.move_window) {
+      if (hipMalloc(&I.win, sizeof(WinCtl)) != hipSuccess) return S.fail(PIC_E_NOMEM, "window state allocation failed");
+      HIPCHK(S, hipMemset(I.win, 0, sizeof(WinCtl)));
+    }
     int npass = 0;
     for (int a = 0; a < I.cfg.ndim; a++) npass += I.cfg.smooth_level[a];
     if (npass > 0)
@@ -1165,6 +1320,7 @@ void sim_destroy(Sim& S) {
     if (I.Jout) (void)hipFree(I.Jout);
     for (int k = 0; k < 2; k++)
       if (I.Jsm[k]) (void)hipFree(I.Jsm[k]);
+    if (I.win) (void)hipFree(I.win);
     if (I.nsrc) (void)hipFree(I.nsrc);
     if (I.ndst) (void)hipFree(I.ndst);
     if (I.rho_snap) (void)hipFree(I.rho_snap);
@@ -1402,6 +1558,8 @@ pic_status sim_autotune(Sim& S, pic_tune* io) {
   if (io->trial_steps < 1) return S.fail(PIC_E_INVALID, "trial_steps must be >= 1");
   if (io->what < 0 || io->what > 7) return S.fail(PIC_E_INVALID, "unknown PIC_TUNE bits");
   const int what = io->what ? io->what : 7;
+  for (const Instance& I : S.inst)
+    if (I.cfg.move_window) return S.fail(PIC_E_UNSUPPORTED, "the autotuner does not handle a moving window");
   pic_status st = refresh_descriptors(S);
   if (st != PIC_OK) return st;
   if (S.sgroups.empty()) return S.fail(PIC_E_STATE, "autotune needs loaded particles");

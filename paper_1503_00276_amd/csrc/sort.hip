@@ -42,8 +42,33 @@ __device__ __forceinline__ int store_of(const int* pref, int n, int x) {
   return lo;
 }
 
-// Slot of a particle with packed cell 'cell' that is stored in tile t.
+// Moving window: whether the window moves after the current step.
+__device__ __forceinline__ bool win_shift_now(const StoreDesc& S) {
+  if (!S.g.window) return false;
+  const long long n = S.win->step;
+  return pic_win_shifts(S.g.wa, n + 1) > pic_win_shifts(S.g.wa, n);
+}
+
+// Particles a moving window injects into destination tile d at this check
+// (the tile's cells in the new front column, which is the ring column of the
+// old origin, times the particles per cell).
+__device__ __forceinline__ int win_inject_count(const StoreDesc& S, int d) {
+  if (!S.g.window || !win_shift_now(S)) return 0;
+  const GridDesc& g = S.g;
+  int tc[3];
+  pic_tile_coords(g, d, tc);
+  const int o = S.win->origin;
+  const int org0 = tc[0] * g.tile[0];
+  if (o < org0 || o >= org0 + min(g.tile[0], g.nx[0] - org0)) return 0;
+  int cells = 1;
+  for (int k = 1; k < g.dim; k++) cells *= min(g.tile[k], g.nx[k] - tc[k] * g.tile[k]);
+  return cells * S.inj_ppc[0] * S.inj_ppc[1] * S.inj_ppc[2];
+}
+
+// Slot of a particle with packed cell 'cell' that is stored in tile t
+// (-1 for a particle a moving window removed).
 __device__ __forceinline__ int particle_slot(const GridDesc& g, int t, int cell) {
+  if (cell < 0) return -1;
   int tc[3], c[3];
   pic_tile_coords(g, t, tc);
   pic_unpack(g, cell, c);
@@ -101,7 +126,7 @@ __global__ void __launch_bounds__(kBlock) rebin_count(const StoreDesc* __restric
   __syncthreads();
   for (int gt = blockIdx.x * blockDim.x + threadIdx.x; gt < total_tiles; gt += gridDim.x * blockDim.x) {
     const StoreDesc& S = stores[store_of(t0, nstores, gt)];
-    if (!(S.ctl->flag | S.ctl->force)) continue;
+    if (!(S.ctl->flag | S.ctl->force) && !win_shift_now(S)) continue;
     const int cur = pic_cur(*S.ctl);
     const int t = gt - S.tile0;
     const int i0 = S.ioff[cur][t], i1 = S.ioff[cur][t + 1];
@@ -129,7 +154,7 @@ __global__ void __launch_bounds__(kBlock) rebin_dest(const StoreDesc* __restrict
   for (int i = threadIdx.x; i < nstores; i += blockDim.x) b0[i] = stores[i].blk0;
   __syncthreads();
   const StoreDesc& S = stores[store_of(b0, nstores, blockIdx.x)];
-  if (!(S.ctl->flag | S.ctl->force)) return;
+  if (!(S.ctl->flag | S.ctl->force) && !win_shift_now(S)) return;
   const int blk = blockIdx.x - S.blk0;
   const int d = blk * kTB + threadIdx.x;
   int acc = 0, ni = 0;
@@ -144,6 +169,7 @@ __global__ void __launch_bounds__(kBlock) rebin_dest(const StoreDesc* __restrict
       S.dbase[d * PIC_NSLOT + sl] = acc;
       acc += v[sl];
     }
+    acc += win_inject_count(S, d);  // injected particles follow the incoming ones
     S.dcount[d] = acc;
     ni = (acc + S.chunk - 1) / S.chunk;
   }
@@ -163,7 +189,7 @@ __global__ void __launch_bounds__(kScanBlock) rebin_fold(const StoreDesc* __rest
   if (threadIdx.x == 0) {
     const StoreCtl c = *S.ctl;
     s_cur = c.cur ^ c.pending;
-    s_act = (c.flag | c.force) ? 1 : 0;
+    s_act = (c.flag | c.force || win_shift_now(S)) ? 1 : 0;
   }
   __syncthreads();
   const int cur = s_cur;
@@ -199,7 +225,10 @@ __global__ void __launch_bounds__(kScanBlock) rebin_fold(const StoreDesc* __rest
       S.toff[nxt][S.g.ntiles] = carry_a;
       S.ioff[nxt][S.g.ntiles] = carry_b;
       S.ctl->n_items[nxt] = min(carry_b, S.max_items);
-      if (carry_b > S.max_items || carry_a != S.np) S.ctl->bad |= 4;
+      S.ctl->np = carry_a;
+      // without a window the count is fixed; with one it changes (removal,
+      // injection) but never exceeds the capacity
+      if (carry_b > S.max_items || (S.g.window ? carry_a > S.cap : carry_a != S.np)) S.ctl->bad |= 4;
     }
   }
   if (threadIdx.x == 0) {
@@ -319,7 +348,7 @@ __global__ void __launch_bounds__(kBlock) rebin_scatter(const StoreDesc* __restr
       if (sl >= 0) {
         pos = run[sl] + rank;
         for (int w = 0; w < wave; w++) pos += wcnt[w][sl];
-        if (pos < 0 || pos >= S.np) {  // inconsistent counts: never write out of bounds
+        if (pos < 0 || pos >= S.cap) {  // inconsistent counts: never write out of bounds
           atomicOr(&S.ctl->bad, 2);
           pos = -1;
         }
@@ -344,6 +373,48 @@ __global__ void __launch_bounds__(kBlock) rebin_scatter(const StoreDesc* __restr
   }
 }
 
+// --- 6. moving window: a cold plasma in the new front column ------------------
+// Particle k of the column (cells in increasing linear index, lattice points
+// of a cell with axis 1 fastest) goes to its tile's range after the incoming
+// particles, at its rank among the tile's injected particles; ids continue
+// from the window's counter.
+__global__ void __launch_bounds__(kBlock) rebin_inject(const StoreDesc* __restrict__ stores, int nstores) {
+  const StoreDesc& S = stores[blockIdx.y];
+  if (!S.g.window || !S.ctl->active || !win_shift_now(S)) return;
+  const GridDesc& g = S.g;
+  const int nxt = 1 - S.ctl->cur;
+  const int p0 = S.inj_ppc[0], p1 = S.inj_ppc[1], p2 = g.dim == 3 ? S.inj_ppc[2] : 1;
+  const int ppc = p0 * p1 * p2;
+  const int ny = g.nx[1], nz = g.dim == 3 ? g.nx[2] : 1;
+  const int total = ppc * ny * nz;
+  const int o = S.win->origin;
+  const long long id0 = S.win->next_id;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < total; k += gridDim.x * blockDim.x) {
+    const int cidx = k / ppc, li = k - cidx * ppc;
+    const int cy = cidx % ny, cz = cidx / ny;
+    const int l0 = li % p0, l1 = (li / p0) % p1, l2 = li / (p0 * p1);
+    const int ty = cy / g.tile[1], tz = g.dim == 3 ? cz / g.tile[2] : 0;
+    const int t = pic_tile_index(g, o / g.tile[0], ty, tz);
+    const int oy = ty * g.tile[1], oz = tz * g.tile[2];
+    const int ey = min(g.tile[1], ny - oy);
+    const int rank = ((cy - oy) + ey * (cz - oz)) * ppc + li;
+    const int pos = S.toff[nxt][t] + S.dcount[t] - win_inject_count(S, t) + rank;
+    if (pos < 0 || pos >= S.cap) {
+      atomicOr(&S.ctl->bad, 2);
+      continue;
+    }
+    S.cell[nxt][pos] = pic_pack(g, o, cy, cz);
+    S.eps[nxt][0][pos] = ((float)l0 + 0.5f) / (float)p0;
+    S.eps[nxt][1][pos] = ((float)l1 + 0.5f) / (float)p1;
+    if (g.dim == 3) S.eps[nxt][2][pos] = ((float)l2 + 0.5f) / (float)p2;
+    S.u[nxt][0][pos] = 0.0f;
+    S.u[nxt][1][pos] = 0.0f;
+    S.u[nxt][2][pos] = 0.0f;
+    S.w[nxt][pos] = S.inj_w;
+    S.id[nxt][pos] = (int)(id0 + k);
+  }
+}
+
 int cap_grid(long n, int per) {
   long b = (n + per - 1) / per;
   if (b > 8192) b = 8192;
@@ -353,7 +424,7 @@ int cap_grid(long n, int per) {
 }  // namespace
 
 hipError_t pic_launch_rebin(const StoreDesc* d_stores, int nstores, int max_items, int total_tiles,
-                            int total_blocks, hipStream_t st) {
+                            int total_blocks, int inject_max, hipStream_t st) {
   if (nstores > kMaxGroup || nstores < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(rebin_count, dim3(cap_grid(total_tiles, kBlock)), dim3(kBlock), 0, st, d_stores, nstores,
                      total_tiles);
@@ -361,5 +432,8 @@ hipError_t pic_launch_rebin(const StoreDesc* d_stores, int nstores, int max_item
   hipLaunchKernelGGL(rebin_fold, dim3(nstores), dim3(kScanBlock), 0, st, d_stores);
   hipLaunchKernelGGL(rebin_offsets, dim3(total_blocks), dim3(kBlock), 0, st, d_stores, nstores);
   hipLaunchKernelGGL(rebin_scatter, dim3(cap_grid(max_items, 1)), dim3(kBlock), 0, st, d_stores, nstores);
+  if (inject_max > 0)
+    hipLaunchKernelGGL(rebin_inject, dim3(cap_grid(inject_max, kBlock), nstores), dim3(kBlock), 0, st, d_stores,
+                       nstores);
   return hipGetLastError();
 }

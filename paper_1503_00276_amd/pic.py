@@ -77,6 +77,9 @@ class pic_config(C.Structure):
         ("deposit", C.c_int32),
         ("smooth_level", C.c_int32 * 3),
         ("smooth_weights", C.c_double * 72),
+        ("move_window", C.c_int32),
+        ("inject_ppc", C.c_int32 * 3),
+        ("inject_w", C.c_double),
     ]
 
 
@@ -181,6 +184,9 @@ class Config:
     accumulator: int = PIC_ACC_FP32
     deposit: int = PIC_DEPOSIT_ISIS
     smooth: Sequence = ()  # per axis: a list of (a, b, c) weights, one per smoothing pass
+    move_window: int = 0   # 1: the window moves along +x1 at c
+    inject_ppc: Sequence[int] = (1, 1, 1)  # moving window: injected particles per cell per axis
+    inject_w: float = 0.0  # moving window: weight of an injected particle
 
     def c(self) -> pic_config:
         c = pic_config()
@@ -200,6 +206,10 @@ class Config:
         c.chunk = int(self.chunk)
         c.accumulator = int(self.accumulator)
         c.deposit = int(self.deposit)
+        c.move_window = int(self.move_window)
+        for i in range(3):
+            c.inject_ppc[i] = int(self.inject_ppc[i]) if i < len(self.inject_ppc) else 1
+        c.inject_w = float(self.inject_w)
         for ax, passes in enumerate(self.smooth):
             c.smooth_level[ax] = len(passes)
             for p, wts in enumerate(passes[:8]):
@@ -313,6 +323,8 @@ class Pic(_Base):
 
     def state(self):
         """(x [n, ndim], u [n, 3], w [n]) of all species in load order."""
+        if self.cfg.move_window:
+            self.sync()  # the window removes and injects particles
         n = self.nparticles()
         d = self.cfg.ndim
         a = self.diag(PIC_DIAG_EXPORT_STATE, n * (d + 4)).reshape(n, d + 4)

@@ -21,7 +21,9 @@ F_TOL = 1e-5
 def oracle_grid(orc, cfg):
     return orc.Grid(dim=cfg.ndim, nx=tuple(cfg.nx[:cfg.ndim]), dx=tuple(cfg.dx[:cfg.ndim]), dt=cfg.dt,
                     order=cfg.shape_order, xmin=tuple(cfg.xmin), e0=tuple(cfg.e0), b0=tuple(cfg.b0),
-                    deposit=getattr(cfg, "deposit", 0), smooth=tuple(tuple(p) for p in getattr(cfg, "smooth", ())))
+                    deposit=getattr(cfg, "deposit", 0), smooth=tuple(tuple(p) for p in getattr(cfg, "smooth", ())),
+                    window=getattr(cfg, "move_window", 0), inject_ppc=tuple(getattr(cfg, "inject_ppc", (1, 1, 1))),
+                    inject_w=getattr(cfg, "inject_w", 0.0))
 
 
 def periodic_dx(a, b, L):
