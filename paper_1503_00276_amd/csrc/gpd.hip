@@ -352,7 +352,9 @@ __device__ __forceinline__ int wrap_fast(int v, int n) { return (unsigned)v < (u
 // one work item
 // ---------------------------------------------------------------------------
 
-template <int DIM, int ORDER>
+// WIN: compiled with the moving-window logic (a launch whose stores include a
+// moving window); without it the window code is absent from the kernel.
+template <int DIM, int ORDER, bool WIN>
 __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii, int jp, float* smem,
                              int* scnt) {
   constexpr int NG = ORDER + 1;  // gather taps per axis
@@ -413,7 +415,7 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
   bool strayed = false, bad = false, died = false;
   // moving window: ring origin of the x1 columns and whether the window
   // moves after this step (its back column is then discarded)
-  const bool win = g.window != 0;
+  const bool win = WIN && g.window != 0;
   int wo = 0;
   bool wshift = false;
   if (win) {
@@ -827,7 +829,7 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
   __syncthreads();
 }
 
-template <int DIM, int ORDER>
+template <int DIM, int ORDER, bool WIN>
 __global__ void __launch_bounds__(kBlock) gpd_kernel(const StoreDesc* __restrict__ stores, int nstores, int jp) {
   // 16-byte aligned: the int64 current tile inside it takes 8-byte LDS atomics
   extern __shared__ __align__(16) float smem[];
@@ -852,19 +854,22 @@ __global__ void __launch_bounds__(kBlock) gpd_kernel(const StoreDesc* __restrict
     const StoreDesc& S = stores[s];
     const int cur = s_cur[s];
     const Item it = S.items[cur][gi - s_pref[s]];
-    process_item<DIM, ORDER>(S, cur, it, gi - s_pref[s], jp, smem, s_cnt);
+    process_item<DIM, ORDER, WIN>(S, cur, it, gi - s_pref[s], jp, smem, s_cnt);
   }
 }
 
 template <int DIM, int ORDER>
-hipError_t prepare_one(size_t lds) {
-  return hipFuncSetAttribute((const void*)gpd_kernel<DIM, ORDER>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds);
+hipError_t prepare_one(bool win, size_t lds) {
+  const void* f = win ? (const void*)gpd_kernel<DIM, ORDER, true> : (const void*)gpd_kernel<DIM, ORDER, false>;
+  return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 template <int DIM, int ORDER>
-hipError_t launch_one(const StoreDesc* stores, int nstores, int grid, size_t lds, int jp, hipStream_t st) {
-  gpd_kernel<DIM, ORDER><<<dim3(grid), dim3(kBlock), lds, st>>>(stores, nstores, jp);
+hipError_t launch_one(bool win, const StoreDesc* stores, int nstores, int grid, size_t lds, int jp, hipStream_t st) {
+  if (win)
+    gpd_kernel<DIM, ORDER, true><<<dim3(grid), dim3(kBlock), lds, st>>>(stores, nstores, jp);
+  else
+    gpd_kernel<DIM, ORDER, false><<<dim3(grid), dim3(kBlock), lds, st>>>(stores, nstores, jp);
   return hipGetLastError();
 }
 
@@ -883,29 +888,29 @@ size_t pic_gpd_lds_bytes(const GridDesc& g) {
 int pic_gpd_block() { return kBlock; }
 int pic_gpd_max_group() { return kMaxGroup; }
 
-hipError_t pic_gpd_prepare(int dim, int order, size_t lds) {
+hipError_t pic_gpd_prepare(int dim, int order, bool window, size_t lds) {
   if (dim == 2) {
-    if (order == 1) return prepare_one<2, 1>(lds);
-    if (order == 2) return prepare_one<2, 2>(lds);
-    if (order == 3) return prepare_one<2, 3>(lds);
+    if (order == 1) return prepare_one<2, 1>(window, lds);
+    if (order == 2) return prepare_one<2, 2>(window, lds);
+    if (order == 3) return prepare_one<2, 3>(window, lds);
   } else if (dim == 3) {
-    if (order == 1) return prepare_one<3, 1>(lds);
-    if (order == 2) return prepare_one<3, 2>(lds);
-    if (order == 3) return prepare_one<3, 3>(lds);
+    if (order == 1) return prepare_one<3, 1>(window, lds);
+    if (order == 2) return prepare_one<3, 2>(window, lds);
+    if (order == 3) return prepare_one<3, 3>(window, lds);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t pic_launch_gpd(int dim, int order, const StoreDesc* d_stores, int nstores, int grid,
+hipError_t pic_launch_gpd(int dim, int order, bool window, const StoreDesc* d_stores, int nstores, int grid,
                           size_t lds, int parity, hipStream_t st) {
   if (dim == 2) {
-    if (order == 1) return launch_one<2, 1>(d_stores, nstores, grid, lds, parity, st);
-    if (order == 2) return launch_one<2, 2>(d_stores, nstores, grid, lds, parity, st);
-    if (order == 3) return launch_one<2, 3>(d_stores, nstores, grid, lds, parity, st);
+    if (order == 1) return launch_one<2, 1>(window, d_stores, nstores, grid, lds, parity, st);
+    if (order == 2) return launch_one<2, 2>(window, d_stores, nstores, grid, lds, parity, st);
+    if (order == 3) return launch_one<2, 3>(window, d_stores, nstores, grid, lds, parity, st);
   } else if (dim == 3) {
-    if (order == 1) return launch_one<3, 1>(d_stores, nstores, grid, lds, parity, st);
-    if (order == 2) return launch_one<3, 2>(d_stores, nstores, grid, lds, parity, st);
-    if (order == 3) return launch_one<3, 3>(d_stores, nstores, grid, lds, parity, st);
+    if (order == 1) return launch_one<3, 1>(window, d_stores, nstores, grid, lds, parity, st);
+    if (order == 2) return launch_one<3, 2>(window, d_stores, nstores, grid, lds, parity, st);
+    if (order == 3) return launch_one<3, 3>(window, d_stores, nstores, grid, lds, parity, st);
   }
   return hipErrorInvalidValue;
 }

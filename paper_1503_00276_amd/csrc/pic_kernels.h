@@ -9,9 +9,11 @@
 size_t pic_gpd_lds_bytes(const GridDesc& g);
 int pic_gpd_block();
 int pic_gpd_max_group();
-// allow the LDS size a group needs (call before launching or capturing)
-hipError_t pic_gpd_prepare(int dim, int order, size_t lds);
-hipError_t pic_launch_gpd(int dim, int order, const StoreDesc* d_stores, int nstores, int grid,
+// allow the LDS size a group needs (call before launching or capturing);
+// window: some store of the group has a moving window (selects the kernel
+// variant that carries the window logic)
+hipError_t pic_gpd_prepare(int dim, int order, bool window, size_t lds);
+hipError_t pic_launch_gpd(int dim, int order, bool window, const StoreDesc* d_stores, int nstores, int grid,
                           size_t lds, int parity, hipStream_t st);
 
 // Yee field solve (field.hip); instances in d_inst[0..ninst)

@@ -379,13 +379,14 @@ pic_status refresh_descriptors(Sim& S) {
           gr.max_tiles += I.g.ntiles;
           gr.max_blocks += (I.g.ntiles + PIC_REBIN_TILES - 1) / PIC_REBIN_TILES;
           gr.lds = std::max(gr.lds, pic_gpd_lds_bytes(I.g));
+          if (I.g.window) gr.window = true;
           gr.inject_max = std::max(gr.inject_max, sp.desc.inj_ppc[0] * sp.desc.inj_ppc[1] * sp.desc.inj_ppc[2] *
                                                       (I.g.ncell / I.g.nx[0]));
         }
       }
           if (gr.count > 0) {
         if (gr.count > pic_gpd_max_group()) return S.fail(PIC_E_INVALID, "too many stores in one group");
-        HIPCHK(S, pic_gpd_prepare(dim, order, gr.lds));
+        HIPCHK(S, pic_gpd_prepare(dim, order, gr.window, gr.lds));
         S.sgroups.push_back(gr);
       }
     }
@@ -527,7 +528,8 @@ pic_status launch_steps(Sim& S, int64_t first, int nsteps, bool end_with_check) 
     for (const Group& gr : S.sgroups) {
       int per_cu = std::max(1, std::min(8, (int)(kLdsMax / std::max<size_t>(gr.lds, 1))));
       int grid = std::max(1, std::min(gr.max_items, kNumCU * per_cu));
-      HIPCHK(S, pic_launch_gpd(gr.dim, gr.order, S.d_stores + gr.first, gr.count, grid, gr.lds, par, S.stream));
+      HIPCHK(S, pic_launch_gpd(gr.dim, gr.order, gr.window, S.d_stores + gr.first, gr.count, grid, gr.lds, par,
+                               S.stream));
     }
     prof_end(S, 0, e0);
     e0 = prof_begin(S);
