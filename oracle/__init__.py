@@ -23,4 +23,6 @@ from .oracle import (  # noqa: F401
     smooth_current,
     step_window,
     window_shifts,
+    step_cyl,
+    cyl_wall,
 )

@@ -45,6 +45,7 @@ class _Grid(C.Structure):
         ("smooth_level", C.c_int32 * 3),
         ("smooth_w", C.c_double * 72),
         ("window", C.c_int32),
+        ("cyl", C.c_int32),
     ]
 
 ISIS = 0
@@ -68,6 +69,7 @@ class Grid:
     window: int = 0       # 1: moving window along x1 (see step_window)
     inject_ppc: tuple = (1, 1, 1)  # moving window: injected particles per cell, per axis
     inject_w: float = 0.0          # moving window: weight of an injected particle
+    cyl: int = 0          # 1: 2D cylindrically symmetric r-z box (x1 = z, x2 = r; see step_cyl)
 
     def c(self) -> _Grid:
         g = _Grid()
@@ -87,6 +89,12 @@ class Grid:
             raise ValueError("TRISTAN deposit is defined for the linear shape only")
         g.deposit = int(self.deposit)
         g.window = int(self.window)
+        if self.cyl:
+            if self.dim != 2 or self.window or any(len(p) for p in self.smooth):
+                raise ValueError("the r-z geometry is 2D, without moving window or smoothing")
+            if float(xm[1]) != 0.0:
+                raise ValueError("in r-z the second coordinate is the radius (xmin[1] = 0)")
+        g.cyl = int(self.cyl)
         for ax, passes in enumerate(self.smooth):
             if len(passes) > 8:
                 raise ValueError("at most 8 smoothing passes per axis")
@@ -135,6 +143,9 @@ def _L():
         lib.orc_field_energy.argtypes = [G, P, P, P]
         lib.orc_particle_moments.argtypes = [G, C.c_int64, P, P, P, P]
         lib.orc_smooth_current.argtypes = [G, P]
+        lib.orc_yee_b_cyl.argtypes = [G, P, P, C.c_double]
+        lib.orc_yee_e_cyl.argtypes = [G, P, P, P, C.c_double]
+        lib.orc_particle_moments_cyl.argtypes = [G, C.c_int64, P, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -204,7 +215,7 @@ def yee_b(g: Grid, E, B, h):
     E = _f64(E).reshape(3, g.ncell)
     B = _f64(B).reshape(3, g.ncell).copy()
     gc = g.c()
-    _L().orc_yee_b(C.byref(gc), _p(E), _p(B), float(h))
+    (_L().orc_yee_b_cyl if g.cyl else _L().orc_yee_b)(C.byref(gc), _p(E), _p(B), float(h))
     return B
 
 
@@ -214,7 +225,7 @@ def yee_e(g: Grid, E, B, J, dt):
     B = _f64(B).reshape(3, g.ncell)
     J = _f64(J).reshape(3, g.ncell)
     gc = g.c()
-    _L().orc_yee_e(C.byref(gc), _p(E), _p(B), _p(J), float(dt))
+    (_L().orc_yee_e_cyl if g.cyl else _L().orc_yee_e)(C.byref(gc), _p(E), _p(B), _p(J), float(dt))
     return E
 
 
@@ -350,12 +361,35 @@ def field_energy(g: Grid, E, B):
     return out
 
 
-def particle_moments(g: Grid, u, w, qm):
+def particle_moments(g: Grid, u, w, qm, x=None):
+    """[kinetic energy, momentum (3)]; in r-z (x = (z, r) needed) [kinetic
+    energy, axial momentum, sum of radial momenta, angular momentum]."""
     u = _f64(u).reshape(-1, 3)
     n = u.shape[0]
     w = _f64(np.broadcast_to(w, (n,)))
     qm = _f64(np.broadcast_to(qm, (n,)))
     out = np.zeros(4)
     gc = g.c()
-    _L().orc_particle_moments(C.byref(gc), n, _p(u), _p(w), _p(qm), _p(out))
+    if g.cyl:
+        x = _f64(x).reshape(n, 2)
+        _L().orc_particle_moments_cyl(C.byref(gc), n, _p(x), _p(u), _p(w), _p(qm), _p(out))
+    else:
+        _L().orc_particle_moments(C.byref(gc), n, _p(u), _p(w), _p(qm), _p(out))
     return out
+
+
+def cyl_wall(g: Grid) -> float:
+    """Radius of the conducting wall of an r-z box: (nr - 1/2) dr."""
+    return (g.nx[1] - 0.5) * g.dx[1]
+
+
+def step_cyl(g: Grid, x, u, w, qm, E, B):
+    """One PIC step of an r-z box (Sec. 3.3); x = (z, r).  Particles that
+    reach the wall at r = (nr - 1/2) dr are removed after depositing their
+    current.  Returns (StepResult of the survivors, their w, their input
+    indices)."""
+    assert g.cyl == 1
+    r = step(g, x, u, w, qm, E, B)
+    w = _f64(np.broadcast_to(w, (len(r.x),))).copy()
+    keep = np.nonzero(r.x[:, 1] < cyl_wall(g))[0]
+    return StepResult(x=r.x[keep], u=r.u[keep], E=r.E, B=r.B, J=r.J), w[keep], keep

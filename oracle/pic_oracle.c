@@ -42,6 +42,38 @@
  * i0 + nx0*(i1 + nx1*i2); all boundaries periodic.  Particle positions are
  * absolute (x = xmin + xi*dx with xi in cell units).
  *
+ * 2D cylindrically symmetric geometry (cyl = 1, Sec. 3.3, Eqs.
+ * 2d-field-solve-cyl, 2d-field-solve-cyl-b1-axis, 2d-cyl-position-update-*):
+ *   - x1 = z (periodic), x2 = r; E1 E2 E3 = E_z E_r E_theta, B likewise,
+ *     J likewise; u = (u_z, u_r, u_theta) in the particle's local frame;
+ *   - the axis runs through the middle of the first cell: the rows of the
+ *     components on whole r-nodes (E_z, E_theta, B_r, J_z, J_theta, rho) sit
+ *     at r = (j - 1/2) dr, those half a cell up (E_r, B_z, B_theta, J_r) at
+ *     r = h dr; a particle at radius r has the cell coordinate r/dr + 1/2;
+ *   - below the axis every quantity is the mirror image of the one above:
+ *     z components and rho keep their sign, r and theta components change it
+ *     (so E_r, B_theta, J_r vanish on the axis); row 0 of the whole-node
+ *     components holds that image of row 1;
+ *   - B_z on the axis follows the integral form of Faraday's law over the
+ *     disc of radius dr/2; B_z and E_z elsewhere carry the r weights of the
+ *     cylindrical curl;
+ *   - r = (nr - 1/2) dr is a conducting wall: E_z, E_theta (and every other
+ *     value) beyond the last row are zero; a particle that reaches the wall
+ *     leaves the simulation (the caller removes it);
+ *   - the deposit is the Cartesian one in cell coordinates (it gives the
+ *     current of each ring particle); what lands below the axis is added to
+ *     the mirror row with the mirror sign (for J_r the axis row itself then
+ *     cancels), what lands beyond the wall is dropped, and the current
+ *     density is that current divided by the ring volume of its row,
+ *     2 pi r dr dz: the charge weight w of a particle is its charge over
+ *     2 pi dr^2 dz, so rho_j = sum_p w_p S / (r_j / dr);
+ *   - the position update is the straight 3D move followed by the rotation
+ *     back into the r-z plane: r' = |(r + dt v_r, dt v_theta)|,
+ *     u_r' = (u_r (r + dt v_r) + u_theta dt v_theta) / r',
+ *     u_theta' = u_theta r / r' (angular momentum);
+ *   - the out-of-plane (theta) current uses the velocity u_theta / gamma of
+ *     the push, before the rotation.
+ *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared -o liboracle.so pic_oracle.c -lm
  */
 #include <math.h>
@@ -64,6 +96,7 @@ typedef struct {
   int32_t window;    /* 1: moving window along x1 -- x1 is not periodic: grid values
                         beyond the first and last x1 cell are zero and currents
                         deposited there are dropped (Sec. 4.5 dynamic spaces) */
+  int32_t cyl;       /* 1: 2D cylindrically symmetric r-z geometry (Sec. 3.3) */
 } orc_grid;
 
 /* ------------------------------------------------------------------ */
@@ -93,6 +126,21 @@ static int64_t cidx(const orc_grid* g, int64_t i0, int64_t i1, int64_t i2) {
 /* Grid value at an index from cidx (zero beyond a moving window). */
 static double at(const double* F, int64_t c) { return c < 0 ? 0.0 : F[c]; }
 
+/* r-z: the stored row that holds the value of row 'row' of a component on
+ * half rows (half = 1) or whole rows (half = 0) and the sign of the mirror
+ * image (parallel = 1 for z components and rho); -1 at or beyond the wall. */
+static int64_t cyl_src(const orc_grid* g, int half, int parallel, int64_t row, double* sgn) {
+  *sgn = 1.0;
+  if (half ? row < 0 : row <= 0) {
+    row = half ? -row : 1 - row;
+    if (!parallel) *sgn = -1.0;
+  }
+  return row >= g->nx[1] ? -1 : row;
+}
+
+/* r-z: radius of a row in units of dr. */
+static double cyl_r(int half, int64_t row) { return half ? (double)row : (double)row - 0.5; }
+
 /* Staggered offset of field component comp (0..2) of E (kind 0), B (kind 1),
  * along axis d; J shares E's offsets and rho sits at the node. */
 static double stagger(int kind, int comp, int d) {
@@ -120,6 +168,7 @@ double orc_shape(int order, double t) {
 static void to_cells(const orc_grid* g, const double* x, double xi[3]) {
   xi[0] = xi[1] = xi[2] = 0.0;
   for (int d = 0; d < g->dim; d++) xi[d] = (x[d] - g->xmin[d]) / g->dx[d];
+  if (g->cyl) xi[1] = x[1] / g->dx[1] + 0.5;  /* r-z: x2 is the radius */
 }
 
 /* ------------------------------------------------------------------ */
@@ -147,6 +196,12 @@ static double gather_one(const orc_grid* g, const double* F, const double xi[3],
       for (int64_t i0 = lo[0]; i0 <= hi[0]; i0++) {
         double s0 = orc_shape(g->order, t[0] - (double)i0);
         if (s0 == 0.0) continue;
+        if (g->cyl) {
+          double sg;
+          int64_t row = cyl_src(g, stagger(kind, comp, 1) != 0.0, comp == 0, i1, &sg);
+          if (row >= 0) sum += s0 * s1 * sg * F[cidx(g, i0, row, 0)];
+          continue;
+        }
         sum += s0 * s1 * s2 * at(F, cidx(g, i0, i1, i2));
       }
     }
@@ -202,6 +257,22 @@ void orc_boris(int64_t n, double* u, const double* Ep, const double* Bp,
 /* ISIS deposit by enumeration of sub-move orderings (Sec. 3.2)        */
 /* ------------------------------------------------------------------ */
 
+/* Add v to component comp of the current at node (i0, i1, i2): periodic, or
+ * dropped beyond a moving window; in r-z what lands below the axis goes to
+ * the mirror row with the mirror sign (the axis row of J_r cancels itself)
+ * and what lands beyond the wall is dropped. */
+static void jadd(const orc_grid* g, double* J, int comp, int64_t i0, int64_t i1, int64_t i2, double v) {
+  if (g->cyl) {
+    if (comp == 1 && i1 == 0) return;
+    double sg;
+    i1 = cyl_src(g, comp == 1, comp == 0, i1, &sg);
+    if (i1 < 0) return;
+    v *= sg;
+  }
+  int64_t ci = cidx(g, i0, i1, i2);
+  if (ci >= 0) J[(int64_t)comp * ncells(g) + ci] += v;
+}
+
 /* One sub-move: coordinate k goes from p[k] to qk, the others stay at p.
  * Charge density change at node i is dq(i) = w [S(qk - i_k) - S(p_k - i_k)]
  * * prod_{d != k} S(p_d - i_d); the continuity equation along k fixes
@@ -210,7 +281,6 @@ void orc_boris(int64_t n, double* u, const double* Ep, const double* Bp,
 static void submove(const orc_grid* g, double* J, double w, const double p[3], int k,
                     double qk, double scale) {
   int dim = g->dim;
-  int64_t nc = ncells(g);
   int64_t lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
   for (int d = 0; d < dim; d++) {
     double a = p[d], b = (d == k) ? qk : p[d];
@@ -218,7 +288,6 @@ static void submove(const orc_grid* g, double* J, double w, const double p[3], i
     lo[d] = (int64_t)floor(mn) - 2;
     hi[d] = (int64_t)floor(mx) + 3;
   }
-  double* Jk = J + k * nc;
   /* loop over the lines along k */
   int o1 = (k == 0) ? 1 : 0;                 /* first transverse axis */
   int o2 = (k == 2) ? 1 : 2;                 /* second transverse axis (3D) */
@@ -239,8 +308,7 @@ static void submove(const orc_grid* g, double* J, double w, const double p[3], i
         ii[k] = ik;
         ii[o1] = j1;
         if (dim == 3) ii[o2] = j2;
-        int64_t ci = cidx(g, ii[0], ii[1], ii[2]);
-        if (ci >= 0) Jk[ci] += flux * scale;
+        jadd(g, J, k, ii[0], ii[1], ii[2], flux * scale);
       }
     }
   }
@@ -255,8 +323,6 @@ static const int perm3[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2},
  * The integrand is quadratic in t, so Simpson's rule is exact. */
 static void deposit_j3_2d(const orc_grid* g, double* J, double w, double v3,
                           const double a[3], const double b[3]) {
-  int64_t nc = ncells(g);
-  double* J3 = J + 2 * nc;
   int64_t lo[2], hi[2];
   for (int d = 0; d < 2; d++) {
     double mn = a[d] < b[d] ? a[d] : b[d], mx = a[d] < b[d] ? b[d] : a[d];
@@ -273,8 +339,7 @@ static void deposit_j3_2d(const orc_grid* g, double* J, double w, double v3,
       double fh = (0.5 * (s0a + s0b)) * (0.5 * (s1a + s1b));
       double f1 = s0b * s1b;
       double avg = (f0 + 4.0 * fh + f1) / 6.0;
-      int64_t ci = cidx(g, i0, i1, 0);
-      if (avg != 0.0 && ci >= 0) J3[ci] += w * v3 * avg;
+      if (avg != 0.0) jadd(g, J, 2, i0, i1, 0, w * v3 * avg);
     }
   }
 }
@@ -345,14 +410,34 @@ static void deposit_tristan(const orc_grid* g, double* J, double w, double v3, c
 void orc_deposit_cells(const orc_grid* g, int64_t n, const double* a, const double* b,
                        const double* w, const double* v3, double* J) {
   int dim = g->dim;
+  int64_t nc = ncells(g);
+  /* r-z: the ring currents go to a scratch array first, then each row is
+   * divided by its ring volume (in units of 2 pi dr^2 dz) */
+  double* I = J;
+  if (g->cyl) {
+    I = (double*)calloc(3 * (size_t)nc, sizeof(double));
+    if (!I) return;
+  }
   for (int64_t p = 0; p < n; p++) {
     const double* pa = a + p * dim;
     const double* pb = b + p * dim;
     double vz = v3 ? v3[p] : 0.0;
     if (g->deposit == 1)
-      deposit_tristan(g, J, w[p], vz, pa, pb);
+      deposit_tristan(g, I, w[p], vz, pa, pb);
     else
-      deposit_isis(g, J, w[p], vz, pa, pb);
+      deposit_isis(g, I, w[p], vz, pa, pb);
+  }
+  if (g->cyl) {
+    int nz = g->nx[0], nr = g->nx[1];
+    for (int c = 0; c < 3; c++) {
+      int half = c == 1;
+      for (int j = 1; j < nr; j++)
+        for (int i = 0; i < nz; i++) J[c * nc + (int64_t)j * nz + i] += I[c * nc + (int64_t)j * nz + i] / cyl_r(half, j);
+      /* row 0: the axis row of J_r (zero) or the mirror image of row 1 */
+      for (int i = 0; i < nz; i++)
+        J[c * nc + i] = half ? 0.0 : (c == 0 ? 1.0 : -1.0) * J[c * nc + nz + i];
+    }
+    free(I);
   }
 }
 
@@ -389,9 +474,18 @@ void orc_smooth_current(const orc_grid* g, double* J) {
   free(tmp);
 }
 
-/* Charge density of n particles at the rho nodes (accumulated). */
+/* Charge density of n particles at the rho nodes (accumulated).  In r-z the
+ * charge below the axis goes to the mirror row, charge beyond the wall is
+ * dropped and each row is divided by its ring volume (units 2 pi dr^2 dz);
+ * row 0 then holds the image of row 1. */
 void orc_rho(const orc_grid* g, int64_t n, const double* x, const double* w, double* rho) {
   int dim = g->dim;
+  int64_t nc = ncells(g);
+  double* out = rho;
+  if (g->cyl) {
+    rho = (double*)calloc((size_t)nc, sizeof(double));
+    if (!rho) return;
+  }
   for (int64_t p = 0; p < n; p++) {
     double xi[3];
     to_cells(g, x + p * dim, xi);
@@ -409,11 +503,24 @@ void orc_rho(const orc_grid* g, int64_t n, const double* x, const double* w, dou
         for (int64_t i0 = lo[0]; i0 <= hi[0]; i0++) {
           double s0 = orc_shape(g->order, xi[0] - (double)i0);
           if (s0 == 0.0) continue;
-          int64_t ci = cidx(g, i0, i1, i2);
+          int64_t r1 = i1;
+          if (g->cyl) {
+            double sg;
+            r1 = cyl_src(g, 0, 1, i1, &sg);
+            if (r1 < 0) continue;
+          }
+          int64_t ci = cidx(g, i0, r1, i2);
           if (ci >= 0) rho[ci] += w[p] * s0 * s1 * s2;
         }
       }
     }
+  }
+  if (g->cyl) {
+    int nz = g->nx[0], nr = g->nx[1];
+    for (int j = 1; j < nr; j++)
+      for (int i = 0; i < nz; i++) out[(int64_t)j * nz + i] += rho[(int64_t)j * nz + i] / cyl_r(0, j);
+    for (int i = 0; i < nz; i++) out[i] = out[nz + i];
+    free(rho);
   }
 }
 
@@ -473,6 +580,65 @@ void orc_yee_e(const orc_grid* g, double* E, const double* B, const double* J, d
       }
 }
 
+/* r-z Faraday half step B <- B - tau curl E (Sec. 3.3, Eqs. 2d-field-solve-cyl
+ * and 2d-field-solve-cyl-b1-axis); rows as described at the top.  E rows at
+ * and beyond the wall are zero. */
+void orc_yee_b_cyl(const orc_grid* g, const double* E, double* B, double tau) {
+  int64_t nc = ncells(g);
+  int nz = g->nx[0], nr = g->nx[1];
+  double dz = g->dx[0], dr = g->dx[1];
+  const double *Ez = E, *Er = E + nc, *Et = E + 2 * nc;
+  double *Bz = B, *Br = B + nc, *Bt = B + 2 * nc;
+#define RZ(j, i) ((int64_t)(j) * nz + (i))
+  for (int j = 0; j < nr; j++)
+    for (int i = 0; i < nz; i++) {
+      int ip = i + 1 == nz ? 0 : i + 1;
+      double et_up = j + 1 < nr ? Et[RZ(j + 1, i)] : 0.0;  /* E_theta at the whole row above half row j */
+      double ez_up = j + 1 < nr ? Ez[RZ(j + 1, i)] : 0.0;
+      /* B_r on whole row j >= 1: (curl E)_r = -dE_theta/dz */
+      if (j >= 1) Br[RZ(j, i)] -= tau * (-(Et[RZ(j, ip)] - Et[RZ(j, i)]) / dz);
+      /* B_theta on half row j: (curl E)_theta = dE_r/dz - dE_z/dr (zero on the axis) */
+      if (j >= 1)
+        Bt[RZ(j, i)] -= tau * ((Er[RZ(j, ip)] - Er[RZ(j, i)]) / dz - (ez_up - Ez[RZ(j, i)]) / dr);
+      else
+        Bt[RZ(j, i)] = 0.0;
+      /* B_z on half row j: (1/r) d(r E_theta)/dr; on the axis Faraday's law
+       * over the disc of radius dr/2 */
+      if (j >= 1)
+        Bz[RZ(j, i)] -= tau * ((j + 0.5) * et_up - (j - 0.5) * Et[RZ(j, i)]) / (j * dr);
+      else
+        Bz[RZ(j, i)] -= tau * 4.0 * et_up / dr;
+    }
+  for (int i = 0; i < nz; i++) Br[RZ(0, i)] = -Br[RZ(1, i)];
+}
+
+/* r-z Ampere step E <- E + dt (curl B - J) (Sec. 3.3, Eq. 2d-field-solve-cyl). */
+void orc_yee_e_cyl(const orc_grid* g, double* E, const double* B, const double* J, double dt) {
+  int64_t nc = ncells(g);
+  int nz = g->nx[0], nr = g->nx[1];
+  double dz = g->dx[0], dr = g->dx[1];
+  double *Ez = E, *Er = E + nc, *Et = E + 2 * nc;
+  const double *Bz = B, *Br = B + nc, *Bt = B + 2 * nc;
+  const double *Jz = J, *Jr = J + nc, *Jt = J + 2 * nc;
+  for (int j = 1; j < nr; j++)
+    for (int i = 0; i < nz; i++) {
+      int im = i == 0 ? nz - 1 : i - 1;
+      /* E_r on half row j: (curl B)_r = -dB_theta/dz */
+      Er[RZ(j, i)] += dt * (-(Bt[RZ(j, i)] - Bt[RZ(j, im)]) / dz - Jr[RZ(j, i)]);
+      /* E_theta on whole row j: (curl B)_theta = dB_r/dz - dB_z/dr */
+      Et[RZ(j, i)] += dt * ((Br[RZ(j, i)] - Br[RZ(j, im)]) / dz - (Bz[RZ(j, i)] - Bz[RZ(j - 1, i)]) / dr -
+                            Jt[RZ(j, i)]);
+      /* E_z on whole row j (radius (j - 1/2) dr): (1/r) d(r B_theta)/dr with
+       * B_theta on the half rows j (radius j dr) and j - 1 */
+      Ez[RZ(j, i)] += dt * ((j * Bt[RZ(j, i)] - (j - 1) * Bt[RZ(j - 1, i)]) / ((j - 0.5) * dr) - Jz[RZ(j, i)]);
+    }
+  for (int i = 0; i < nz; i++) {
+    Er[RZ(0, i)] = 0.0;
+    Ez[RZ(0, i)] = Ez[RZ(1, i)];
+    Et[RZ(0, i)] = -Et[RZ(1, i)];
+  }
+}
+
 /* ------------------------------------------------------------------ */
 /* one full step of the PIC loop (Sec. 3.1)                            */
 /* ------------------------------------------------------------------ */
@@ -500,7 +666,7 @@ int orc_step(const orc_grid* g, int64_t n, double* x, double* u, const double* w
   orc_boris(n, u, Ep, Bp, qm, g->dt);
   /* 3. advance positions with v = u / gamma (in-plane components only in 2D) */
   for (int64_t p = 0; p < n; p++) {
-    const double* up = u + p * 3;
+    double* up = u + p * 3;
     double gam = sqrt(1.0 + up[0] * up[0] + up[1] * up[1] + up[2] * up[2]);
     double xi[3];
     to_cells(g, x + p * dim, xi);
@@ -509,6 +675,22 @@ int orc_step(const orc_grid* g, int64_t n, double* x, double* u, const double* w
       b[p * dim + d] = xi[d] + g->dt * up[d] / gam / g->dx[d];
     }
     v3[p] = up[2] / gam;
+    if (g->cyl) {
+      /* r-z (Eqs. 2d-cyl-position-update-1..3): straight 3D move from
+       * (z, r, 0), then rotation into the r-z plane of the new position */
+      double r = x[p * dim + 1];
+      double y = r + g->dt * up[1] / gam, t = g->dt * up[2] / gam;
+      double rn = sqrt(y * y + t * t);
+      b[p * dim + 1] = rn / g->dx[1] + 0.5;
+      double ur = up[1], ut = up[2];
+      if (rn > 0.0) {
+        up[1] = (ur * y + ut * t) / rn;
+        up[2] = ut * r / rn;
+      } else {
+        up[1] = -ur;  /* landed on the axis: moving out on the other side */
+        up[2] = 0.0;
+      }
+    }
   }
   /* 4. deposit J^{n+1/2} from the old and new positions */
   memset(J, 0, sizeof(double) * 3 * (size_t)nc);
@@ -520,6 +702,10 @@ int orc_step(const orc_grid* g, int64_t n, double* x, double* u, const double* w
     for (int d = 0; d < dim; d++) {
       double xi = b[p * dim + d];
       double L = (double)g->nx[d];
+      if (g->cyl && d == 1) {
+        x[p * dim + 1] = (xi - 0.5) * g->dx[1];  /* the radius; not wrapped */
+        continue;
+      }
       if (!(g->window && d == 0)) {
         xi = fmod(xi, L);
         if (xi < 0.0) xi += L;
@@ -528,9 +714,15 @@ int orc_step(const orc_grid* g, int64_t n, double* x, double* u, const double* w
       x[p * dim + d] = g->xmin[d] + xi * g->dx[d];
     }
   /* 5. field solve: B half step, E full step, B half step */
-  orc_yee_b(g, E, B, 0.5 * g->dt);
-  orc_yee_e(g, E, B, J, g->dt);
-  orc_yee_b(g, E, B, 0.5 * g->dt);
+  if (g->cyl) {
+    orc_yee_b_cyl(g, E, B, 0.5 * g->dt);
+    orc_yee_e_cyl(g, E, B, J, g->dt);
+    orc_yee_b_cyl(g, E, B, 0.5 * g->dt);
+  } else {
+    orc_yee_b(g, E, B, 0.5 * g->dt);
+    orc_yee_e(g, E, B, J, g->dt);
+    orc_yee_b(g, E, B, 0.5 * g->dt);
+  }
   free(Ep); free(Bp); free(a); free(b); free(v3);
   return 0;
 }
@@ -539,10 +731,31 @@ int orc_step(const orc_grid* g, int64_t n, double* x, double* u, const double* w
 /* diagnostics                                                         */
 /* ------------------------------------------------------------------ */
 
-/* Gauss residual at the rho nodes: G = sum_d (E_d[i] - E_d[i-e_d])/dx_d - rho. */
+/* r-z divergence of a vector field V (J or E layout) at the whole-node rows
+ * j >= 1: dV_z/dz + (1/r) d(r V_r)/dr, V_r on the half rows j (radius j dr)
+ * and j - 1; row 0 gets the image of row 1. */
+static void cyl_div(const orc_grid* g, const double* V, double* D) {
+  int64_t nc = ncells(g);
+  int nz = g->nx[0], nr = g->nx[1];
+  for (int j = 1; j < nr; j++)
+    for (int i = 0; i < nz; i++) {
+      int im = i == 0 ? nz - 1 : i - 1;
+      D[RZ(j, i)] = (V[RZ(j, i)] - V[RZ(j, im)]) / g->dx[0] +
+                    (j * V[nc + RZ(j, i)] - (j - 1) * V[nc + RZ(j - 1, i)]) / ((j - 0.5) * g->dx[1]);
+    }
+  for (int i = 0; i < nz; i++) D[RZ(0, i)] = D[RZ(1, i)];
+}
+
+/* Gauss residual at the rho nodes: G = sum_d (E_d[i] - E_d[i-e_d])/dx_d - rho
+ * (r-z: the cylindrical divergence). */
 void orc_gauss_residual(const orc_grid* g, const double* E, const double* rho, double* G) {
   int64_t nc = ncells(g);
   int dim = g->dim;
+  if (g->cyl) {
+    cyl_div(g, E, G);
+    for (int64_t c = 0; c < nc; c++) G[c] -= rho[c];
+    return;
+  }
   int n2 = dim == 3 ? g->nx[2] : 1;
   for (int k = 0; k < n2; k++)
     for (int j = 0; j < g->nx[1]; j++)
@@ -560,6 +773,11 @@ void orc_charge_residual(const orc_grid* g, const double* rho0, const double* rh
                          const double* J, double* C) {
   int64_t nc = ncells(g);
   int dim = g->dim;
+  if (g->cyl) {
+    cyl_div(g, J, C);
+    for (int64_t c = 0; c < nc; c++) C[c] += (rho1[c] - rho0[c]) / g->dt;
+    return;
+  }
   int n2 = dim == 3 ? g->nx[2] : 1;
   for (int k = 0; k < n2; k++)
     for (int j = 0; j < g->nx[1]; j++)
@@ -578,9 +796,29 @@ void orc_field_energy(const orc_grid* g, const double* E, const double* B, doubl
   int64_t nc = ncells(g);
   double V = g->dx[0] * g->dx[1] * (g->dim == 3 ? g->dx[2] : 1.0);
   long double se = 0.0L, sb = 0.0L;
+  if (g->cyl) {
+    /* ring volumes: 2 pi r dr dz per row; the axis row of the half-row
+     * components holds the disc of radius dr/2; row 0 of the whole-row
+     * components is an image and counts nothing */
+    const double pi = 3.14159265358979323846;
+    int nz = g->nx[0], nr = g->nx[1];
+    const int half_e[3] = {0, 1, 0}, half_b[3] = {1, 0, 1};
+    for (int c = 0; c < 3; c++)
+      for (int j = 0; j < nr; j++) {
+        double ve = half_e[c] ? (j == 0 ? 0.25 * pi : 2.0 * pi * j) : (j == 0 ? 0.0 : 2.0 * pi * (j - 0.5));
+        double vb = half_b[c] ? (j == 0 ? 0.25 * pi : 2.0 * pi * j) : (j == 0 ? 0.0 : 2.0 * pi * (j - 0.5));
+        for (int i = 0; i < nz; i++) {
+          double e = E[c * nc + RZ(j, i)], b = B[c * nc + RZ(j, i)];
+          se += (long double)(ve * e * e);
+          sb += (long double)(vb * b * b);
+        }
+      }
+    V = g->dx[0] * g->dx[1] * g->dx[1];
+  } else {
   for (int64_t i = 0; i < 3 * nc; i++) {
     se += (long double)E[i] * E[i];
     sb += (long double)B[i] * B[i];
+  }
   }
   out[0] = (double)(0.5L * V * se);
   out[1] = (double)(0.5L * V * sb);
@@ -607,4 +845,29 @@ void orc_particle_moments(const orc_grid* g, int64_t n, const double* u, const d
   out[1] = (double)(V * px);
   out[2] = (double)(V * py);
   out[3] = (double)(V * pz);
+}
+
+/* r-z particle moments (Sec. 3.3): the charge of a ring particle is
+ * w 2 pi dr^2 dz; out[0] = kinetic energy sum Q rqm (gamma - 1), out[1] =
+ * axial momentum sum Q rqm u_z, out[2] = sum Q rqm u_r, out[3] = angular
+ * momentum about the axis sum Q rqm r u_theta.  x[n*2] = (z, r). */
+void orc_particle_moments_cyl(const orc_grid* g, int64_t n, const double* x, const double* u,
+                              const double* w, const double* qm, double out[4]) {
+  const double pi = 3.14159265358979323846;
+  double V = 2.0 * pi * g->dx[0] * g->dx[1] * g->dx[1];
+  long double ek = 0.0L, pz = 0.0L, pr = 0.0L, lz = 0.0L;
+  for (int64_t p = 0; p < n; p++) {
+    const double* up = u + p * 3;
+    double usq = up[0] * up[0] + up[1] * up[1] + up[2] * up[2];
+    double gm1 = usq / (sqrt(1.0 + usq) + 1.0);
+    double m = w[p] / qm[p];
+    ek += (long double)m * gm1;
+    pz += (long double)m * up[0];
+    pr += (long double)m * up[1];
+    lz += (long double)m * x[p * 2 + 1] * up[2];
+  }
+  out[0] = (double)(V * ek);
+  out[1] = (double)(V * pz);
+  out[2] = (double)(V * pr);
+  out[3] = (double)(V * lz);
 }

@@ -907,3 +907,220 @@ def test_window_continuity_away_from_the_ends(orc):
     assert orc.window_shifts(g, 1) == 0  # no shift in this step: only the removal acts
     r, w, keep = orc.step_window(g, 0, x, u, w, -1.0, E, B)
     assert list(keep) == [1] and len(r.x) == 1 and abs(r.x[0, 1] - 3.1 * dx[1]) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# 2D cylindrically symmetric r-z geometry (Sec. 3.3)
+# --------------------------------------------------------------------------
+
+
+def _cyl_fields(g, rng, scale=0.1):
+    """Random E, B with the structure the axis imposes: row 0 of the
+    whole-row components (E_z, E_theta, B_r) is the mirror image of row 1,
+    E_r and B_theta vanish on the axis."""
+    nz, nr = g.nx[0], g.nx[1]
+    E = rng.normal(0, scale, (3, nr, nz))
+    B = rng.normal(0, scale, (3, nr, nz))
+    E[0, 0] = E[0, 1]
+    E[2, 0] = -E[2, 1]
+    B[1, 0] = -B[1, 1]
+    E[1, 0] = 0.0
+    B[2, 0] = 0.0
+    return E.reshape(3, -1), B.reshape(3, -1)
+
+
+def _ring_flux_div_b(g, B):
+    """div B over each ring cell (z_i..z_i+1) x (r_lo..r_hi) around the half
+    rows (radius h dr), written as the flux through its faces over its volume."""
+    nz, nr = g.nx[0], g.nx[1]
+    dz, dr = g.dx[0], g.dx[1]
+    B = B.reshape(3, nr, nz)
+    out = np.zeros((nr, nz))
+    for h in range(nr):
+        r_lo, r_hi = max(h - 0.5, 0.0) * dr, (h + 0.5) * dr
+        area = math.pi * (r_hi ** 2 - r_lo ** 2)
+        for i in range(nz):
+            ip = (i + 1) % nz
+            br_hi = B[1, h + 1, i] if h + 1 < nr else 0.0
+            br_lo = B[1, h, i] if h >= 1 else 0.0
+            flux = area * (B[0, h, ip] - B[0, h, i]) + 2 * math.pi * dz * (r_hi * br_hi - r_lo * br_lo)
+            out[h, i] = flux / (area * dz)
+    return out
+
+
+def _ring_flux_div_e(g, E):
+    """div E over the ring cell ((j-1) dr .. j dr) around each whole row j >= 1."""
+    nz, nr = g.nx[0], g.nx[1]
+    dz, dr = g.dx[0], g.dx[1]
+    E = E.reshape(3, nr, nz)
+    out = np.zeros((nr, nz))
+    for j in range(1, nr):
+        r_lo, r_hi = (j - 1) * dr, j * dr
+        area = math.pi * (r_hi ** 2 - r_lo ** 2)
+        for i in range(nz):
+            flux = area * (E[0, j, i] - E[0, j, i - 1]) + 2 * math.pi * dz * (r_hi * E[1, j, i] - r_lo * E[1, j - 1, i])
+            out[j, i] = flux / (area * dz)
+    return out
+
+
+def test_cyl_free_ring_particle_follows_the_3d_straight_line(orc):
+    """Without fields a ring particle's point moves on a straight line in 3D:
+    after n steps r = |(r0 + t v_r0, t v_theta0)|, z = z0 + t v_z, and the
+    local-frame momenta are the constant 3D momentum projected on e_r and
+    e_theta of the new point (Eqs. 2d-cyl-position-update-1..3)."""
+    g = orc.Grid(dim=2, nx=(16, 64), dx=(0.2, 0.2), dt=0.1, order=2, cyl=1)
+    rng = np.random.default_rng(3)
+    n = 12
+    x0 = np.stack([rng.random(n) * 3.0, 0.05 + rng.random(n) * 4.0], axis=1)
+    u0 = rng.normal(0, 0.8, (n, 3))
+    u0[0] = [0.1, -2.0, 0.0]      # through the axis
+    u0[1] = [0.0, -0.5, 0.05]     # close to it
+    E = np.zeros((3, g.ncell))
+    B = np.zeros((3, g.ncell))
+    x, u = x0.copy(), u0.copy()
+    nsteps = 25
+    for _ in range(nsteps):
+        r = orc.step(g, x, u, np.zeros(n), -1.0, E, B)
+        x, u = r.x, r.u
+    t = nsteps * g.dt
+    gam = np.sqrt(1 + (u0 ** 2).sum(1))
+    px = x0[:, 1] + t * u0[:, 1] / gam
+    py = t * u0[:, 2] / gam
+    rr = np.hypot(px, py)
+    z = np.mod(x0[:, 0] + t * u0[:, 0] / gam, 16 * 0.2)
+    np.testing.assert_allclose(x[:, 1], rr, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(x[:, 0], z, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(u[:, 0], u0[:, 0], atol=1e-13)
+    np.testing.assert_allclose(u[:, 1], (u0[:, 1] * px + u0[:, 2] * py) / rr, atol=1e-11)
+    np.testing.assert_allclose(u[:, 2], (-u0[:, 1] * py + u0[:, 2] * px) / rr, atol=1e-11)
+    assert np.abs(E).max() == 0  # zero weights: no current, no field
+
+
+def test_cyl_yee_keeps_the_ring_flux_divergences(orc):
+    """In vacuum the r-z Yee scheme (Eq. 2d-field-solve-cyl, and the axis
+    update Eq. 2d-field-solve-cyl-b1-axis) changes neither div B nor div E,
+    each written here as the flux out of a ring cell over its volume, on the
+    axis cell included (a dropped r weight or a wrong axis factor fails)."""
+    g = orc.Grid(dim=2, nx=(10, 12), dx=(0.25, 0.2), dt=0.1, order=1, cyl=1)
+    rng = np.random.default_rng(11)
+    E, B = _cyl_fields(g, rng)
+    J = np.zeros((3, g.ncell))
+    db0, de0 = _ring_flux_div_b(g, B), _ring_flux_div_e(g, E)
+    for _ in range(40):
+        B = orc.yee_b(g, E, B, g.dt / 2)
+        E = orc.yee_e(g, E, B, J, g.dt)
+        B = orc.yee_b(g, E, B, g.dt / 2)
+    assert np.abs(E).max() > 0.01  # the fields did evolve
+    np.testing.assert_allclose(_ring_flux_div_b(g, B), db0, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(_ring_flux_div_e(g, E)[1:], de0[1:], rtol=0, atol=1e-12)
+    # the oracle's own Gauss operator is the same ring-flux divergence
+    G = orc.gauss_residual(g, E, np.zeros(g.ncell)).reshape(g.nx[1], g.nx[0])
+    np.testing.assert_allclose(G[1:], _ring_flux_div_e(g, E)[1:], rtol=0, atol=1e-12)
+
+
+def test_cyl_tm010_pillbox_frequency(orc):
+    """The lowest TM mode of a conducting cylinder of radius R (no z
+    dependence): E_z = J0(k r) cos(w t) with k = j01 / R and w = c k.  The
+    wall sits at (nr - 1/2) dr; the measured frequency agrees with w to the
+    scheme's second-order accuracy."""
+    special = pytest.importorskip("scipy.special")
+    nz, nr, dr = 4, 40, 0.1
+    g = orc.Grid(dim=2, nx=(nz, nr), dx=(0.1, dr), dt=0.05, order=1, cyl=1)
+    R = orc.cyl_wall(g)
+    k = special.jn_zeros(0, 1)[0] / R
+    r = (np.arange(nr) - 0.5) * dr
+    E = np.zeros((3, nr, nz))
+    E[0] = special.j0(k * np.abs(r))[:, None]
+    E = E.reshape(3, -1)
+    B = np.zeros((3, g.ncell))
+    J = np.zeros((3, g.ncell))
+    series = []
+    for _ in range(450):
+        B = orc.yee_b(g, E, B, g.dt / 2)
+        E = orc.yee_e(g, E, B, J, g.dt)
+        B = orc.yee_b(g, E, B, g.dt / 2)
+        series.append(E[0, nz * 1])
+    s = np.array(series)
+    t = (np.arange(len(s)) + 1) * g.dt
+    idx = np.nonzero(np.sign(s[1:]) != np.sign(s[:-1]))[0]
+    tz = t[idx] - s[idx] * (t[idx + 1] - t[idx]) / (s[idx + 1] - s[idx])
+    assert len(tz) >= 3
+    w_meas = math.pi / np.mean(np.diff(tz))
+    assert abs(w_meas / k - 1.0) < 3e-3, (w_meas, k)
+
+
+@pytest.mark.parametrize("order,dep", [(1, 0), (2, 0), (3, 0), (1, 1)])
+def test_cyl_deposit_conserves_charge_across_the_axis(orc, order, dep):
+    """Ring particles moving anywhere off the wall, the axis neighbourhood
+    included: the deposited current satisfies the cylindrical continuity
+    equation at every whole row, with rho from the particle positions."""
+    g = orc.Grid(dim=2, nx=(12, 14), dx=(0.2, 0.25), dt=0.1, order=order, deposit=dep, cyl=1)
+    rng = np.random.default_rng(100 + order + 10 * dep)
+    n = 300
+    a = np.stack([rng.random(n) * 12, 0.5 + rng.random(n) * 7.0], axis=1)
+    a[:60, 1] = 0.5 + rng.random(60) * 1.2  # within a cell of the axis
+    d = rng.uniform(-0.9, 0.9, (n, 2))
+    b = a + d
+    b[:, 1] = np.maximum(b[:, 1], 0.5 + 1e-3)
+    w = rng.normal(-0.2, 0.05, n)
+    v3 = rng.normal(0, 0.3, n)
+    J = orc.deposit_cells(g, a, b, w, v3)
+    xa = np.stack([a[:, 0] * g.dx[0], (a[:, 1] - 0.5) * g.dx[1]], 1)
+    xb = np.stack([np.mod(b[:, 0], 12) * g.dx[0], (b[:, 1] - 0.5) * g.dx[1]], 1)
+    r0, r1 = orc.rho(g, xa, w), orc.rho(g, xb, w)
+    C = orc.charge_residual(g, r0, r1, J).reshape(14, 12)
+    scale = np.abs(r1 - r0).max() / g.dt
+    assert scale > 1.0
+    assert np.abs(C[1:]).max() < 1e-12 * scale
+
+
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_cyl_fold_keeps_charge_and_theta_current_moment(orc, order):
+    """What a ring particle deposits below the axis belongs to the ring on
+    the other side: the total charge sum_j rho_j (r_j/dr) is the sum of the
+    weights, and the first moment of the theta current sum_j J_j (r_j/dr)^2
+    is sum_p w v_theta (r_p/dr), because B-spline shapes reproduce linear
+    functions (a wrong fold sign fails one of them)."""
+    g = orc.Grid(dim=2, nx=(8, 12), dx=(0.2, 0.2), dt=0.1, order=order, cyl=1)
+    rng = np.random.default_rng(7 + order)
+    n = 50
+    a = np.stack([rng.random(n) * 8, 0.5 + rng.random(n) * 2.5], axis=1)  # all near the axis
+    w = rng.normal(-0.3, 0.1, n)
+    v3 = rng.normal(0, 0.4, n)
+    x = np.stack([a[:, 0] * 0.2, (a[:, 1] - 0.5) * 0.2], 1)
+    rho = orc.rho(g, x, w).reshape(12, 8)
+    rj = np.arange(12) - 0.5
+    np.testing.assert_allclose((rho[1:] * rj[1:, None]).sum(), w.sum(), rtol=1e-13)
+    J = orc.deposit_cells(g, a, a, w, v3).reshape(3, 12, 8)  # no motion: only J_theta
+    assert np.abs(J[:2]).max() == 0
+    np.testing.assert_allclose((J[2, 1:] * (rj[1:, None] ** 2)).sum(), (w * v3 * (a[:, 1] - 0.5)).sum(),
+                               rtol=1e-12)
+    # the mirror rows hold the images
+    np.testing.assert_array_equal(rho[0], rho[1])
+    np.testing.assert_array_equal(J[2, 0], -J[2, 1])
+
+
+def test_cyl_uniform_plasma_has_uniform_density(orc):
+    """A uniform density loaded on a lattice with weights proportional to the
+    radius (equal charge per unit volume) gives rho = n exactly on every row
+    whose shape support stays off the axis (linear shape)."""
+    nz, nr = 6, 10
+    g = orc.Grid(dim=2, nx=(nz, nr), dx=(0.2, 0.2), dt=0.1, order=1, cyl=1)
+    m = 4
+    zz, rr = np.meshgrid((np.arange(nz * m) + 0.5) / m, (np.arange((nr - 2) * m) + 0.5) / m, indexing="ij")
+    x = np.stack([zz.ravel() * 0.2, rr.ravel() * 0.2], 1)
+    n0 = 0.7
+    w = n0 * rr.ravel() / (m * m)
+    rho = orc.rho(g, x, w).reshape(nr, nz)
+    np.testing.assert_allclose(rho[2:nr - 3], n0, rtol=1e-13)
+
+
+def test_cyl_step_removes_particles_at_the_wall(orc):
+    g = orc.Grid(dim=2, nx=(8, 6), dx=(0.2, 0.2), dt=0.1, order=2, cyl=1)
+    R = orc.cyl_wall(g)
+    x = np.array([[0.5, R - 0.01], [0.5, 0.4]])
+    u = np.array([[0.0, 2.0, 0.0], [0.0, 0.0, 0.0]])
+    E = np.zeros((3, g.ncell))
+    B = np.zeros((3, g.ncell))
+    r, w, keep = orc.step_cyl(g, x, u, np.array([-0.1, -0.1]), -1.0, E, B)
+    assert list(keep) == [1] and abs(r.x[0, 1] - 0.4) < 1e-15
