@@ -128,6 +128,28 @@ typedef struct {
   int32_t move_window;
   int32_t inject_ppc[3];
   double inject_w;
+  /* Geometry (PIC_GEOM_*).  PIC_GEOM_RZ (Sec. 3.3, 2D cylindrically
+   * symmetric): ndim = 2, x1 = z (periodic), x2 = r; E1 E2 E3 = E_z E_r
+   * E_theta (B, J likewise); u = (u_z, u_r, u_theta) in the particle's local
+   * frame.  The axis runs through the middle of the first cell: rows of
+   * E_z, E_theta, B_r, J_z, J_theta sit at r = (j - 1/2) dr, rows of E_r,
+   * B_z, B_theta, J_r at r = j dr; row 0 of the former is the mirror image
+   * of row 1 (z components keep their sign, r and theta components change
+   * it) and E_r, B_theta, J_r vanish on the axis.  B_z on the axis follows
+   * Faraday's law over the disc of radius dr/2 (Eq. 2d-field-solve-cyl-b1-axis),
+   * B_z and E_z elsewhere the r-weighted curl (Eq. 2d-field-solve-cyl).
+   * r = (nx[1] - 1/2) dr is a conducting wall: a particle that reaches it is
+   * removed after depositing its current.  A particle is a ring: its weight
+   * w is its charge over 2 pi dr^2 dz (so a density n loaded with ppc
+   * particles per cell takes w = n (r/dr) / ppc), and the current density
+   * of a row is the deposited ring current over the ring volume.  The push
+   * moves the particle on the straight 3D line and rotates position and
+   * momentum back into the r-z plane (Eqs. 2d-cyl-position-update-1..3).
+   * Positions loaded and exported are (z, r) with xmin[1] = 0; particles
+   * are exported in load order without the removed ones.  The sort
+   * interval is 1.  Not available with a moving window, smoothing or
+   * pic_autotune; diagnostics other than the exports are not available. */
+  int32_t geometry;
 } pic_config;
 
 #define PIC_MAX_SMOOTH 8
@@ -140,6 +162,12 @@ enum {
   PIC_DEPOSIT_TRISTAN = 1 /* Villasenor-Buneman: the straight path cut at the
                              cell faces it crosses, each piece depositing its
                              in-cell current; linear shape (shape_order 1) only */
+};
+
+/* Geometry of the box (pic_config.geometry). */
+enum {
+  PIC_GEOM_CARTESIAN = 0, /* 2D or 3D Cartesian, periodic */
+  PIC_GEOM_RZ = 1         /* 2D cylindrically symmetric r-z (Sec. 3.3) */
 };
 
 /* Flags for the load calls. */

@@ -51,6 +51,7 @@ __global__ void __launch_bounds__(kBlock) yee_step(const InstDesc* __restrict__ 
   __shared__ float sB[3][BZM * BYM * BXM];
   const InstDesc& I = inst[blockIdx.y];
   const GridDesc& g = I.g;
+  if (g.cyl) return;  // r-z instances take yee_step_rz
   const int ntx = (g.nx[0] + T::X - 1) / T::X;
   const int nty = (g.nx[1] + T::Y - 1) / T::Y;
   const int ntz = DIM == 3 ? (g.nx[2] + T::Z - 1) / T::Z : 1;
@@ -223,6 +224,155 @@ __global__ void __launch_bounds__(kBlock) yee_step(const InstDesc* __restrict__ 
   }
 }
 
+// The r-z field step (Sec. 3.3, Eqs. 2d-field-solve-cyl and
+// 2d-field-solve-cyl-b1-axis) on the 2D tiles, in the three parts of
+// yee_step.  E_z, E_theta, B_r (components 0, 2, 4) sit on whole rows at
+// r = (j - 1/2) dr, E_r, B_z, B_theta (1, 3, 5) on half rows at r = j dr.
+// Staged values below the axis are mirror images (z components keep the
+// sign, r and theta components change it), at and beyond the wall zero;
+// row 0 of the whole-row components is never read and is stored as zero;
+// E_r and B_theta stay zero on the axis, and B_z there follows Faraday's
+// law over the disc of radius dr/2, dB_z/dt = -4 E_theta(row 1) / dr.  The
+// accumulators hold the folded ring currents: each row is divided by its
+// ring volume (in units of 2 pi dr^2 dz) as it is read, and Jout keeps the
+// current density.
+__global__ void __launch_bounds__(kBlock) yee_step_rz(const InstDesc* __restrict__ inst, int par) {
+  using T = YeeTile<2>;
+  constexpr int EXM = T::X + 3, EYM = T::Y + 3;
+  constexpr int BXM = T::X + 2, BYM = T::Y + 2;
+  __shared__ float sE[3][EYM * EXM];
+  __shared__ float sB[3][BYM * BXM];
+  const InstDesc& I = inst[blockIdx.y];
+  const GridDesc& g = I.g;
+  if (!g.cyl) return;
+  const int ntx = (g.nx[0] + T::X - 1) / T::X;
+  const int nty = (g.nx[1] + T::Y - 1) / T::Y;
+  const int tile = blockIdx.x;
+  if (tile >= ntx * nty) return;
+  const int tx = threadIdx.x % T::X;
+  const int ty = threadIdx.x / T::X;
+  const int nc = g.ncell;
+  const int n0 = g.nx[0], n1 = g.nx[1];
+  const int o0 = (tile % ntx) * T::X;
+  const int o1 = (tile / ntx) * T::Y;
+  const int e0 = min(T::X, n0 - o0);
+  const int e1 = min(T::Y, n1 - o1);
+  const int EX = e0 + 3, EY = e1 + 3;
+  const int BX = e0 + 2, BY = e1 + 2;
+  // region node (x, y) is column o0 - 1 + x (periodic) and row o1 - 1 + y
+  const gfloat* F = (const gfloat*)I.F[par];
+  for (int y = ty; y < EY; y += T::Y)
+    for (int x = tx; x < EX; x += T::X) {
+      const int gx = wrap1(o0 - 1 + x, n0);
+      const int ry = o1 - 1 + y;
+      const int rw = ry <= 0 ? 1 - ry : ry;
+      const int rh = ry < 0 ? -ry : ry;
+      const float sw = ry <= 0 ? -1.0f : 1.0f, sh = ry < 0 ? -1.0f : 1.0f;
+      const bool iw = rw < n1, ih = rh < n1;
+      const int gw = gx + n0 * rw, gh = gx + n0 * rh;
+      const int r = x + EX * y;
+      sE[0][r] = iw ? F[gw] : 0.0f;
+      sE[1][r] = ih ? sh * F[nc + gh] : 0.0f;
+      sE[2][r] = iw ? sw * F[2 * nc + gw] : 0.0f;
+      if (x < BX && y < BY) {
+        const int rb = x + BX * y;
+        sB[0][rb] = ih ? F[3 * nc + gh] : 0.0f;
+        sB[1][rb] = iw ? sw * F[4 * nc + gw] : 0.0f;
+        sB[2][rb] = ih ? sh * F[5 * nc + gh] : 0.0f;
+      }
+    }
+  __syncthreads();
+  const float h = 0.5f * g.dt;
+  const float rz = g.rdx[0], rr = g.rdx[1];
+  // Bh on the B region (B_z, B_theta on half rows, B_r on whole rows); the
+  // general r weights also give the mirror rows below the axis their images
+  for (int y = ty; y < BY; y += T::Y)
+    for (int x = tx; x < BX; x += T::X) {
+      const int r = x + BX * y;
+      const int c = x + EX * y;
+      const int j = o1 - 1 + y;
+      sB[1][r] -= h * (-(sE[2][c + 1] - sE[2][c]) * rz);
+      sB[2][r] -= h * ((sE[1][c + 1] - sE[1][c]) * rz - (sE[0][c + EX] - sE[0][c]) * rr);
+      const float cz = j == 0 ? 4.0f * sE[2][c + EX] * rr
+                              : ((j + 0.5f) * sE[2][c + EX] - (j - 0.5f) * sE[2][c]) * rr / (float)j;
+      sB[0][r] -= h * cz;
+    }
+  __syncthreads();
+  // E' on the tile plus one node above (zero at and beyond the wall)
+  const int jp = par, jn = 1 - par;
+  const double jinv = (double)g.jinv;
+  for (int y = 1 + ty; y <= e1 + 1; y += T::Y)
+    for (int x = 1 + tx; x <= e0 + 1; x += T::X) {
+      const int ce = x + EX * y;
+      const int cb = x + BX * y;
+      const int j = o1 - 1 + y;
+      if (j >= n1) {
+        sE[0][ce] = 0.0f;
+        sE[1][ce] = 0.0f;
+        sE[2][ce] = 0.0f;
+        continue;
+      }
+      const int gi = wrap1(o0 - 1 + x, n0) + n0 * j;
+      float J1, J2, J3;
+      if (g.acc_mode == 2) {
+        J1 = (float)((double)(long long)I.J64[jp][gi] * jinv);
+        J2 = (float)((double)(long long)I.J64[jp][nc + gi] * jinv);
+        J3 = (float)((double)(long long)I.J64[jp][2 * nc + gi] * jinv);
+      } else {
+        const gfloat* Ja = (const gfloat*)I.Jacc[jp];
+        J1 = Ja[gi];
+        J2 = Ja[nc + gi];
+        J3 = Ja[2 * nc + gi];
+      }
+      // ring volumes of the row: whole rows (j - 1/2), half rows j
+      const float vw = j >= 1 ? 1.0f / ((float)j - 0.5f) : 0.0f;
+      const float vh = j >= 1 ? 1.0f / (float)j : 0.0f;
+      J1 *= vw;
+      J2 *= vh;
+      J3 *= vw;
+      sE[1][ce] = j == 0 ? 0.0f : sE[1][ce] + g.dt * (-(sB[2][cb] - sB[2][cb - 1]) * rz - J2);
+      sE[2][ce] += g.dt * ((sB[1][cb] - sB[1][cb - 1]) * rz - (sB[0][cb] - sB[0][cb - BX]) * rr - J3);
+      sE[0][ce] += g.dt * (((float)j * sB[2][cb] - (float)(j - 1) * sB[2][cb - BX]) * rr * vw - J1);
+      if (x <= e0 && y <= e1) {
+        gfloat* Jo = (gfloat*)I.Jout;
+        Jo[gi] = J1;
+        Jo[nc + gi] = J2;
+        Jo[2 * nc + gi] = J3;
+        if (g.acc_mode == 2) {
+          I.J64[jn][gi] = 0ull;
+          I.J64[jn][nc + gi] = 0ull;
+          I.J64[jn][2 * nc + gi] = 0ull;
+        } else {
+          gfloat* Jz = (gfloat*)I.Jacc[jn];
+          Jz[gi] = 0.0f;
+          Jz[nc + gi] = 0.0f;
+          Jz[2 * nc + gi] = 0.0f;
+        }
+      }
+    }
+  __syncthreads();
+  // B' on the tile, and write E', B' back
+  gfloat* Fw = (gfloat*)I.F[1 - par];
+  for (int y = 1 + ty; y <= e1; y += T::Y)
+    for (int x = 1 + tx; x <= e0; x += T::X) {
+      const int c = x + EX * y;
+      const int cb = x + BX * y;
+      const int j = o1 - 1 + y;
+      const int gi = wrap1(o0 - 1 + x, n0) + n0 * j;
+      const float cz = j == 0 ? 4.0f * sE[2][c + EX] * rr
+                              : ((j + 0.5f) * sE[2][c + EX] - (j - 0.5f) * sE[2][c]) * rr / (float)j;
+      const float br = sB[1][cb] - h * (-(sE[2][c + 1] - sE[2][c]) * rz);
+      const float bt = sB[2][cb] - h * ((sE[1][c + 1] - sE[1][c]) * rz - (sE[0][c + EX] - sE[0][c]) * rr);
+      const bool in = j >= 1;
+      Fw[gi] = in ? sE[0][c] : 0.0f;
+      Fw[nc + gi] = sE[1][c];
+      Fw[2 * nc + gi] = in ? sE[2][c] : 0.0f;
+      Fw[3 * nc + gi] = sB[0][cb] - h * cz;
+      Fw[4 * nc + gi] = in ? br : 0.0f;
+      Fw[5 * nc + gi] = in ? bt : 0.0f;
+    }
+}
+
 // One smoothing pass of the current along 'axis' (pass 'lev' of that axis)
 // for every instance that has it: J <- a J[i-1] + b J[i] + c J[i+1] with the
 // normalised weights, periodic.  The instance's first pass reads the
@@ -318,11 +468,12 @@ int pic_yee_tiles(int dim, const int nx[3]) {
          ((nx[2] + YeeTile<3>::Z - 1) / YeeTile<3>::Z);
 }
 
-hipError_t pic_launch_yee_step(const InstDesc* d_inst, int ninst, int max_tiles, int dim, int parity,
-                               hipStream_t st) {
-  if (dim == 2)
-    hipLaunchKernelGGL(yee_step<2>, dim3(max_tiles, ninst), dim3(kBlock), 0, st, d_inst, parity);
-  else
+hipError_t pic_launch_yee_step(const InstDesc* d_inst, int ninst, int max_tiles, int dim, bool cart, bool cyl,
+                               int parity, hipStream_t st) {
+  if (dim == 2) {
+    if (cart) hipLaunchKernelGGL(yee_step<2>, dim3(max_tiles, ninst), dim3(kBlock), 0, st, d_inst, parity);
+    if (cyl) hipLaunchKernelGGL(yee_step_rz, dim3(max_tiles, ninst), dim3(kBlock), 0, st, d_inst, parity);
+  } else
     hipLaunchKernelGGL(yee_step<3>, dim3(max_tiles, ninst), dim3(kBlock), 0, st, d_inst, parity);
   return hipGetLastError();
 }

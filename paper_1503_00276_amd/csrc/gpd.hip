@@ -352,13 +352,16 @@ __device__ __forceinline__ int wrap_fast(int v, int n) { return (unsigned)v < (u
 // one work item
 // ---------------------------------------------------------------------------
 
-// WIN: compiled with the moving-window logic (a launch whose stores include a
-// moving window); without it the window code is absent from the kernel.
-template <int DIM, int ORDER, bool WIN>
+// MODE selects the boundary logic compiled into the kernel: 0 periodic,
+// 1 moving window along x1 (a launch whose stores include a moving window),
+// 2 the 2D r-z geometry (x1 = z, x2 = r).  Without it the code is absent.
+template <int DIM, int ORDER, int MODE>
 __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii, int jp, float* smem,
                              int* scnt) {
   constexpr int NG = ORDER + 1;  // gather taps per axis
   constexpr int W = ORDER + 2;   // deposit window per axis
+  constexpr bool WIN = MODE == 1;
+  constexpr bool RZ = DIM == 2 && MODE == 2;
   const GridDesc& g = S.g;
   const int tid = threadIdx.x;
 
@@ -390,6 +393,25 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
     const gfloat* Fg = (const gfloat*)S.F[jp];
     for (int idx = tid; idx < fn; idx += blockDim.x, bw.advance(FR)) {
       int gx = wrap_fast(org[0] - flo[0] + bw.x, g.nx[0]);
+      if constexpr (RZ) {
+        // r-z: rows below the axis are mirror images (z components keep the
+        // sign, r and theta components change it); rows at and beyond the
+        // wall hold zero.  E_z, E_theta, B_r sit on whole rows, E_r, B_z,
+        // B_theta on half rows (the axis is half row 0).
+        const int ry = org[1] - flo[1] + bw.y;
+        const int rw = ry <= 0 ? 1 - ry : ry;
+        const int rh = ry < 0 ? -ry : ry;
+        const float sw = ry <= 0 ? -1.0f : 1.0f, sh = ry < 0 ? -1.0f : 1.0f;
+        const bool iw = rw < g.nx[1], ih = rh < g.nx[1];
+        const int gw = gx + g.nx[0] * rw, gh = gx + g.nx[0] * rh;
+        sF[idx] = iw ? Fg[gw] : 0.0f;
+        sF[fn + idx] = ih ? sh * Fg[(size_t)ncell + gh] : 0.0f;
+        sF[2 * fn + idx] = iw ? sw * Fg[(size_t)2 * ncell + gw] : 0.0f;
+        sF[3 * fn + idx] = ih ? Fg[(size_t)3 * ncell + gh] : 0.0f;
+        sF[4 * fn + idx] = iw ? sw * Fg[(size_t)4 * ncell + gw] : 0.0f;
+        sF[5 * fn + idx] = ih ? sh * Fg[(size_t)5 * ncell + gh] : 0.0f;
+        continue;
+      }
       int gy = wrap_fast(org[1] - flo[1] + bw.y, g.nx[1]);
       int gz = DIM == 3 ? wrap_fast(org[2] - flo[2] + bw.z, g.nx[2]) : 0;
       int gi = gx + g.nx[0] * (gy + g.nx[1] * gz);
@@ -427,7 +449,7 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
   // 3. particles
   for (int p = it.begin + tid; p < it.end; p += blockDim.x) {
     int cell = cellp[p];
-    if (win && cell < 0) continue;  // removed, awaiting the rebin
+    if ((win || RZ) && cell < 0) continue;  // removed, awaiting the rebin
     float e[3];
     e[0] = ep0[p];
     e[1] = ep1[p];
@@ -536,9 +558,32 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
     float uu[3] = {ux, uy, uz};
     float en[3];
     int mv[3] = {0, 0, 0};
+    float urn = uy, utn = uz;  // r-z: momenta in the frame of the new position
 #pragma unroll
     for (int d = 0; d < DIM; d++) {
-      float x = e[d] + g.dt * g.rdx[d] * (uu[d] * gi);
+      float x;
+      if (RZ && d == 1) {
+        // r-z (Eqs. 2d-cyl-position-update-1..3): the straight 3D move from
+        // radius r by (dt v_r, dt v_theta), in cells; the new radius rn and
+        // the change rn - r written without cancellation; momenta rotated
+        // into the new r-z plane (u_theta from the angular momentum)
+        const float r = (float)cc[1] + e[1] - 0.5f;
+        const float mr = g.dt * g.rdx[1] * (uy * gi);
+        const float mt = g.dt * g.rdx[1] * (uz * gi);
+        const float yr = r + mr;
+        const float rn = sqrtf(yr * yr + mt * mt);
+        const float den = rn + r;
+        x = e[1] + (den > 0.0f ? (mr * (r + yr) + mt * mt) / den : 0.0f);
+        if (rn > 0.0f) {
+          urn = (uy * yr + uz * mt) / rn;
+          utn = uz * r / rn;
+        } else {
+          urn = -uy;  // on the axis: moving out on the other side
+          utn = 0.0f;
+        }
+      } else {
+        x = e[d] + g.dt * g.rdx[d] * (uu[d] * gi);
+      }
       float f = floorf(x);
       int c = (int)f;
       float r = x - f;
@@ -758,6 +803,10 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
     }
 
     // ---- store the new state; count the particle's rebin slot
+    if constexpr (RZ) {
+      uy = urn;  // the deposit above used the push's u_theta
+      uz = utn;
+    }
     int nc[3] = {0, 0, 0};
     int dd[3] = {0, 0, 0};
 #pragma unroll
@@ -776,6 +825,11 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
     if (win) {
       const int wn = wcol + mv[0];
       dead = wn < 0 || wn >= g.nx[0] || (wshift && wn == 0);
+      died = died || dead;
+    }
+    if constexpr (RZ) {
+      // r-z: a particle that reached the wall is removed
+      dead = cc[1] + mv[1] >= g.nx[1];
       died = died || dead;
     }
     {
@@ -811,6 +865,25 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
   BoxWalk bj(tid, blockDim.x, JR);
   for (int idx = tid; idx < jn; idx += blockDim.x, bj.advance(JR)) {
     int gx = wrap_fast(org[0] - jlo[0] + bj.x, g.nx[0]);
+    if constexpr (RZ) {
+      // r-z: current below the axis goes to the mirror row with the mirror
+      // sign (J_z keeps it, J_r and J_theta change it; J_r on the axis
+      // cancels itself), current at and beyond the wall is dropped
+      const int ry = org[1] - jlo[1] + bj.y;
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        long long q = (long long)sJ[c * jn + idx];
+        const int row = c == 1 ? (ry < 0 ? -ry : ry) : (ry <= 0 ? 1 - ry : ry);
+        if (q == 0 || row >= g.nx[1] || (c == 1 && ry == 0)) continue;
+        if ((c == 1 && ry < 0) || (c == 2 && ry <= 0)) q = -q;
+        const size_t gi = (size_t)c * ncell + gx + g.nx[0] * row;
+        if (g.acc_mode == 2)
+          atomicAdd(S.J64[jp] + gi, (acc_t)q);
+        else
+          __builtin_amdgcn_global_atomic_fadd_f32((gfloat*)S.Jacc[jp] + gi, (float)((double)q * (double)g.jinv));
+      }
+      continue;
+    }
     int gy = wrap_fast(org[1] - jlo[1] + bj.y, g.nx[1]);
     int gz = DIM == 3 ? wrap_fast(org[2] - jlo[2] + bj.z, g.nx[2]) : 0;
     int gi = gx + g.nx[0] * (gy + g.nx[1] * gz);
@@ -829,7 +902,7 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
   __syncthreads();
 }
 
-template <int DIM, int ORDER, bool WIN>
+template <int DIM, int ORDER, int MODE>
 __global__ void __launch_bounds__(kBlock) gpd_kernel(const StoreDesc* __restrict__ stores, int nstores, int jp) {
   // 16-byte aligned: the int64 current tile inside it takes 8-byte LDS atomics
   extern __shared__ __align__(16) float smem[];
@@ -854,22 +927,35 @@ __global__ void __launch_bounds__(kBlock) gpd_kernel(const StoreDesc* __restrict
     const StoreDesc& S = stores[s];
     const int cur = s_cur[s];
     const Item it = S.items[cur][gi - s_pref[s]];
-    process_item<DIM, ORDER, WIN>(S, cur, it, gi - s_pref[s], jp, smem, s_cnt);
+    process_item<DIM, ORDER, MODE>(S, cur, it, gi - s_pref[s], jp, smem, s_cnt);
   }
 }
 
-template <int DIM, int ORDER>
-hipError_t prepare_one(bool win, size_t lds) {
-  const void* f = win ? (const void*)gpd_kernel<DIM, ORDER, true> : (const void*)gpd_kernel<DIM, ORDER, false>;
-  return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+template <int DIM, int ORDER, int MODE>
+hipError_t prepare_mode(size_t lds) {
+  return hipFuncSetAttribute((const void*)gpd_kernel<DIM, ORDER, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds);
 }
 
 template <int DIM, int ORDER>
-hipError_t launch_one(bool win, const StoreDesc* stores, int nstores, int grid, size_t lds, int jp, hipStream_t st) {
-  if (win)
-    gpd_kernel<DIM, ORDER, true><<<dim3(grid), dim3(kBlock), lds, st>>>(stores, nstores, jp);
+hipError_t prepare_one(int mode, size_t lds) {
+  if (mode == 1) return prepare_mode<DIM, ORDER, 1>(lds);
+  if constexpr (DIM == 2)
+    if (mode == 2) return prepare_mode<DIM, ORDER, 2>(lds);
+  if (mode == 0) return prepare_mode<DIM, ORDER, 0>(lds);
+  return hipErrorInvalidValue;
+}
+
+template <int DIM, int ORDER>
+hipError_t launch_one(int mode, const StoreDesc* stores, int nstores, int grid, size_t lds, int jp, hipStream_t st) {
+  if (mode == 1)
+    gpd_kernel<DIM, ORDER, 1><<<dim3(grid), dim3(kBlock), lds, st>>>(stores, nstores, jp);
+  else if (mode == 0)
+    gpd_kernel<DIM, ORDER, 0><<<dim3(grid), dim3(kBlock), lds, st>>>(stores, nstores, jp);
+  else if constexpr (DIM == 2)
+    gpd_kernel<DIM, ORDER, 2><<<dim3(grid), dim3(kBlock), lds, st>>>(stores, nstores, jp);
   else
-    gpd_kernel<DIM, ORDER, false><<<dim3(grid), dim3(kBlock), lds, st>>>(stores, nstores, jp);
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -888,29 +974,29 @@ size_t pic_gpd_lds_bytes(const GridDesc& g) {
 int pic_gpd_block() { return kBlock; }
 int pic_gpd_max_group() { return kMaxGroup; }
 
-hipError_t pic_gpd_prepare(int dim, int order, bool window, size_t lds) {
+hipError_t pic_gpd_prepare(int dim, int order, int mode, size_t lds) {
   if (dim == 2) {
-    if (order == 1) return prepare_one<2, 1>(window, lds);
-    if (order == 2) return prepare_one<2, 2>(window, lds);
-    if (order == 3) return prepare_one<2, 3>(window, lds);
+    if (order == 1) return prepare_one<2, 1>(mode, lds);
+    if (order == 2) return prepare_one<2, 2>(mode, lds);
+    if (order == 3) return prepare_one<2, 3>(mode, lds);
   } else if (dim == 3) {
-    if (order == 1) return prepare_one<3, 1>(window, lds);
-    if (order == 2) return prepare_one<3, 2>(window, lds);
-    if (order == 3) return prepare_one<3, 3>(window, lds);
+    if (order == 1) return prepare_one<3, 1>(mode, lds);
+    if (order == 2) return prepare_one<3, 2>(mode, lds);
+    if (order == 3) return prepare_one<3, 3>(mode, lds);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t pic_launch_gpd(int dim, int order, bool window, const StoreDesc* d_stores, int nstores, int grid,
+hipError_t pic_launch_gpd(int dim, int order, int mode, const StoreDesc* d_stores, int nstores, int grid,
                           size_t lds, int parity, hipStream_t st) {
   if (dim == 2) {
-    if (order == 1) return launch_one<2, 1>(window, d_stores, nstores, grid, lds, parity, st);
-    if (order == 2) return launch_one<2, 2>(window, d_stores, nstores, grid, lds, parity, st);
-    if (order == 3) return launch_one<2, 3>(window, d_stores, nstores, grid, lds, parity, st);
+    if (order == 1) return launch_one<2, 1>(mode, d_stores, nstores, grid, lds, parity, st);
+    if (order == 2) return launch_one<2, 2>(mode, d_stores, nstores, grid, lds, parity, st);
+    if (order == 3) return launch_one<2, 3>(mode, d_stores, nstores, grid, lds, parity, st);
   } else if (dim == 3) {
-    if (order == 1) return launch_one<3, 1>(window, d_stores, nstores, grid, lds, parity, st);
-    if (order == 2) return launch_one<3, 2>(window, d_stores, nstores, grid, lds, parity, st);
-    if (order == 3) return launch_one<3, 3>(window, d_stores, nstores, grid, lds, parity, st);
+    if (order == 1) return launch_one<3, 1>(mode, d_stores, nstores, grid, lds, parity, st);
+    if (order == 2) return launch_one<3, 2>(mode, d_stores, nstores, grid, lds, parity, st);
+    if (order == 3) return launch_one<3, 3>(mode, d_stores, nstores, grid, lds, parity, st);
   }
   return hipErrorInvalidValue;
 }

@@ -36,6 +36,7 @@ struct GridDesc {
   int deposit;        // 0: ISIS ordering average, 1: TRISTAN path cut at faces (linear shape)
   int window;         // 1: moving window along x1 (x1 open; grid stored as a ring, see WinCtl)
   double wa;          // moving window: c dt / dx1 (shifts after n steps: floor(n wa))
+  int cyl;            // 1: 2D r-z geometry (x1 = z, x2 = r; axis mid first cell, wall at the top)
   // LDS region geometry (nodes relative to the tile origin):
   // field region [-(slack+fa), e+slack+fb), current region [-(slack+ja), e+slack+jb)
   int fa, fb, ja, jb;

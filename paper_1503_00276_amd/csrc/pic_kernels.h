@@ -10,10 +10,10 @@ size_t pic_gpd_lds_bytes(const GridDesc& g);
 int pic_gpd_block();
 int pic_gpd_max_group();
 // allow the LDS size a group needs (call before launching or capturing);
-// window: some store of the group has a moving window (selects the kernel
-// variant that carries the window logic)
-hipError_t pic_gpd_prepare(int dim, int order, bool window, size_t lds);
-hipError_t pic_launch_gpd(int dim, int order, bool window, const StoreDesc* d_stores, int nstores, int grid,
+// mode: the boundary logic of the group's stores (0 periodic, 1 moving window
+// along x1, 2 the 2D r-z geometry), which selects the kernel variant
+hipError_t pic_gpd_prepare(int dim, int order, int mode, size_t lds);
+hipError_t pic_launch_gpd(int dim, int order, int mode, const StoreDesc* d_stores, int nstores, int grid,
                           size_t lds, int parity, hipStream_t st);
 
 // Yee field solve (field.hip); instances in d_inst[0..ninst)
@@ -21,8 +21,9 @@ int pic_yee_tiles(int dim, const int nx[3]);
 hipError_t pic_launch_window_advance(const InstDesc* d_inst, int ninst, hipStream_t st);
 hipError_t pic_launch_smooth_pass(const InstDesc* d_inst, int ninst, int max_ncell, int axis, int lev,
                                   int parity, hipStream_t st);
-hipError_t pic_launch_yee_step(const InstDesc* d_inst, int ninst, int max_tiles, int dim, int parity,
-                               hipStream_t st);
+// cart / cyl: the group holds Cartesian / r-z instances (each kernel skips the others)
+hipError_t pic_launch_yee_step(const InstDesc* d_inst, int ninst, int max_tiles, int dim, bool cart, bool cyl,
+                               int parity, hipStream_t st);
 
 // tile rebin (sort.hip); stores in d_stores[0..nstores)
 hipError_t pic_launch_rebin(const StoreDesc* d_stores, int nstores, int max_items, int total_tiles,

@@ -65,7 +65,12 @@ struct Group {
   int sm_max[3];  // most smoothing passes of any instance, per axis
   int inject_max; // moving window: most particles a store injects per shift
   bool window;    // some instance has a moving window
+  int mode = 0;   // stores: boundary logic of the fused kernel (0 periodic, 1 moving window, 2 r-z)
+  bool cyl = false, cart = false;  // instances: some are r-z / some are Cartesian
 };
+
+// Boundary logic an instance's stores need in the fused particle kernel.
+int kernel_mode(const GridDesc& g) { return g.window ? 1 : (g.cyl ? 2 : 0); }
 
 struct Sim {
   hipStream_t stream = nullptr;
@@ -162,6 +167,7 @@ pic_status setup_grid(Sim& S, const pic_config& c, int sort_interval, GridDesc& 
   g.acc_mode = c.accumulator;
   g.deposit = c.deposit;
   g.window = c.move_window;
+  g.cyl = c.geometry == PIC_GEOM_RZ;
   g.wa = c.dt / c.dx[0];
   g.jscale = 1.0f;
   g.jinv = 1.0f;
@@ -251,13 +257,24 @@ pic_status validate(Sim& S, const pic_config& c) {
   }
   for (int d = 0; d < 3; d++)
     if (!std::isfinite(c.e0[d]) || !std::isfinite(c.b0[d])) return S.fail(PIC_E_INVALID, "external field not finite");
+  if (c.geometry != PIC_GEOM_CARTESIAN && c.geometry != PIC_GEOM_RZ)
+    return S.fail(PIC_E_INVALID, "unknown geometry %d", c.geometry);
+  if (c.geometry == PIC_GEOM_RZ) {
+    if (c.ndim != 2) return S.fail(PIC_E_INVALID, "the r-z geometry is two-dimensional");
+    if (c.move_window) return S.fail(PIC_E_UNSUPPORTED, "the r-z geometry has no moving window");
+    if (c.smooth_level[0] || c.smooth_level[1]) return S.fail(PIC_E_UNSUPPORTED, "the r-z geometry has no smoothing");
+    if (c.xmin[1] != 0.0) return S.fail(PIC_E_INVALID, "in r-z x2 is the radius: xmin[1] must be 0");
+    if (c.nx[1] < 2) return S.fail(PIC_E_INVALID, "the r-z geometry needs at least 2 rows");
+    if (c.sort_interval > 1) return S.fail(PIC_E_INVALID, "the r-z geometry needs sort_interval 1 (or 0)");
+  }
   return PIC_OK;
 }
 
 int default_interval(const pic_config& c) {
   // 3D tiles are LDS-bound: keep the slack at one cell and check every step;
-  // a moving window removes and injects particles at every step's check
-  if (c.ndim == 3 || c.move_window) return 1;
+  // a moving window removes and injects particles at every step's check, and
+  // the r-z wall removes the particles that reach it at the step's check
+  if (c.ndim == 3 || c.move_window || c.geometry == PIC_GEOM_RZ) return 1;
   double vmax = 0.0;
   for (int d = 0; d < c.ndim; d++) vmax = std::max(vmax, c.dt / c.dx[d]);
   // largest interval whose slack stays at 2 cells
@@ -360,11 +377,13 @@ pic_status refresh_descriptors(Sim& S) {
   S.sgroups.clear();
   S.igroups.clear();
   for (int dim = 2; dim <= 3; dim++)
-    for (int order = 1; order <= 3; order++) {
+    for (int order = 1; order <= 3; order++)
+      for (int mode = 0; mode <= 2; mode++) {
       Group gr{dim, order, (int)stores.size(), 0, 0, 0, 0, 0, 0, false, {0, 0, 0}, 0, false};
+      gr.mode = mode;
       for (size_t i = 0; i < S.inst.size(); i++) {
         Instance& I = S.inst[i];
-        if (I.g.dim != dim || I.g.order != order) continue;
+        if (I.g.dim != dim || I.g.order != order || kernel_mode(I.g) != mode) continue;
         for (int s = 0; s < PIC_MAX_SPECIES; s++) {
           Species& sp = I.sp[s];
           if (!sp.used || sp.np == 0) continue;
@@ -386,7 +405,7 @@ pic_status refresh_descriptors(Sim& S) {
       }
           if (gr.count > 0) {
         if (gr.count > pic_gpd_max_group()) return S.fail(PIC_E_INVALID, "too many stores in one group");
-        HIPCHK(S, pic_gpd_prepare(dim, order, gr.window, gr.lds));
+        HIPCHK(S, pic_gpd_prepare(dim, order, gr.mode, gr.lds));
         S.sgroups.push_back(gr);
       }
     }
@@ -429,6 +448,10 @@ pic_status refresh_descriptors(Sim& S) {
         gr.window = true;
       }
       insts.push_back(id);
+      if (I.g.cyl)
+        gr.cyl = true;
+      else
+        gr.cart = true;
       if (I.g.acc_mode == PIC_ACC_FIXED64) gr.fixed64 = true;
       gr.count++;
       gr.max_ncell = std::max(gr.max_ncell, I.g.ncell);
@@ -528,7 +551,7 @@ pic_status launch_steps(Sim& S, int64_t first, int nsteps, bool end_with_check) 
     for (const Group& gr : S.sgroups) {
       int per_cu = std::max(1, std::min(8, (int)(kLdsMax / std::max<size_t>(gr.lds, 1))));
       int grid = std::max(1, std::min(gr.max_items, kNumCU * per_cu));
-      HIPCHK(S, pic_launch_gpd(gr.dim, gr.order, gr.window, S.d_stores + gr.first, gr.count, grid, gr.lds, par,
+      HIPCHK(S, pic_launch_gpd(gr.dim, gr.order, gr.mode, S.d_stores + gr.first, gr.count, grid, gr.lds, par,
                                S.stream));
     }
     prof_end(S, 0, e0);
@@ -538,7 +561,8 @@ pic_status launch_steps(Sim& S, int64_t first, int nsteps, bool end_with_check) 
         for (int lev = 0; lev < gr.sm_max[a]; lev++)
           HIPCHK(S, pic_launch_smooth_pass(S.d_inst + gr.first, gr.count, gr.max_ncell, a, lev, par, S.stream));
     for (const Group& gr : S.igroups)
-      HIPCHK(S, pic_launch_yee_step(S.d_inst + gr.first, gr.count, gr.max_tiles, gr.dim, par, S.stream));
+      HIPCHK(S, pic_launch_yee_step(S.d_inst + gr.first, gr.count, gr.max_tiles, gr.dim, gr.cart, gr.cyl, par,
+                                    S.stream));
     prof_end(S, 1, e0);
     if (end_with_check && k == nsteps - 1) {
       e0 = prof_begin(S);
@@ -621,8 +645,9 @@ pic_status sim_sync(Sim& S) {
       StoreCtl c{};
       HIPCHK(S, hipMemcpy(&c, sp.ctl, sizeof c, hipMemcpyDeviceToHost));
       if (c.bad) return S.fail(PIC_E_STATE, "a particle left the region staged for its tile");
-      if (I.cfg.move_window && c.nchecks > 0 && c.np != sp.np) {
-        // a moving window removed and injected particles
+      if ((I.cfg.move_window || I.g.cyl) && c.nchecks > 0 && c.np != sp.np) {
+        // a moving window removed and injected particles, or the r-z wall
+        // removed some
         sp.np = c.np;
         sp.desc.np = c.np;
         S.dirty = true;
@@ -841,15 +866,29 @@ pic_status sim_load(Sim& S, int inst, int32_t species, double rqm, int64_t n, co
   const bool win = I.cfg.move_window != 0;
   if (win && species != 0 && !I.sp[0].used)
     return S.fail(PIC_E_STATE, "with a moving window species 0 (the injected one) is loaded first");
+  const bool rz = I.g.cyl != 0;
   HostParticles h;
   if ((st = read_back(S, sp, dim, h)) != PIC_OK) return st;
   const size_t old = h.cell.size();
+  // ids continue after the largest one (the r-z wall may have removed some)
+  int64_t id0 = (int64_t)old;
+  if (rz) {
+    id0 = 0;
+    for (size_t q = 0; q < old; q++) id0 = std::max<int64_t>(id0, (int64_t)h.id[q] + 1);
+    if (id0 + n > 0x7fffff00LL) return S.fail(PIC_E_NOMEM, "particle ids exhausted");
+  }
   h.resize(old + n);
   for (int64_t p = 0; p < n; p++) {
     int c[3] = {0, 0, 0};
     for (int d = 0; d < dim; d++) {
       double L = (double)I.g.nx[d];
       double xi = (hx[p * dim + d] - I.cfg.xmin[d]) / I.cfg.dx[d];
+      if (rz && d == 1) {
+        // r-z: x2 is the radius; the cell coordinate is r/dr + 1/2
+        xi = hx[p * dim + 1] / I.cfg.dx[1] + 0.5;
+        if (!(hx[p * dim + 1] >= 0.0 && xi < L))
+          return S.fail(PIC_E_RANGE, "particle radius outside [0, (nr - 1/2) dr)");
+      }
       if (win && d == 0) {
         // window position, then ring column
         xi -= (double)wc.shifts;
@@ -871,7 +910,7 @@ pic_status sim_load(Sim& S, int inst, int32_t species, double rqm, int64_t n, co
       h.eps[d][old + p] = e;
     }
     h.cell[old + p] = pic_pack(I.g, c[0], c[1], c[2]);
-    h.id[old + p] = win ? (int)(wc.next_id + p) : (int)(old + p);
+    h.id[old + p] = win ? (int)(wc.next_id + p) : (int)(id0 + p);
     for (int k = 0; k < 3; k++) h.u[k][old + p] = (float)hu[p * 3 + k];
     h.w[old + p] = (float)hw[p];
   }
@@ -906,7 +945,7 @@ pic_status sim_load(Sim& S, int inst, int32_t species, double rqm, int64_t n, co
     HIPCHK(S, hipMemcpy(I.win, &wc, sizeof wc, hipMemcpyHostToDevice));
   }
   st = upload_binned(S, I, sp, h);
-  if (st == PIC_OK && win) {
+  if (st == PIC_OK && (win || rz)) {
     StoreCtl c{};
     HIPCHK(S, hipMemcpy(&c, sp.ctl, sizeof c, hipMemcpyDeviceToHost));
     c.np = (int)sp.np;
@@ -952,6 +991,16 @@ pic_status sim_load_fields(Sim& S, int inst, const double* e, const double* b, u
     if ((st = read_win(S, I, wc)) != PIC_OK) return st;
     ring_rotate(he.data(), 3, I.g, wc.origin, false);
     ring_rotate(hb.data(), 3, I.g, wc.origin, false);
+  }
+  if (I.g.cyl) {
+    // r-z row 0: the axis of E_r and B_theta (zero), the mirror row of
+    // E_z, E_theta, B_r (not stored); B_z on the axis is kept
+    const size_t nz = (size_t)I.g.nx[0], ncl = (size_t)I.g.ncell;
+    for (size_t i = 0; i < nz; i++) {
+      for (size_t c = 0; c < 3; c++) he[c * ncl + i] = 0.0;
+      hb[ncl + i] = 0.0;
+      hb[2 * ncl + i] = 0.0;
+    }
   }
   std::vector<float> f(2 * n);
   for (size_t i = 0; i < n; i++) {
@@ -1005,6 +1054,9 @@ pic_status sim_diag(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_byt
       for (void* p : v) (void)hipFree(p);
     }
   } fr{tmp};
+  if (g.cyl && kind != PIC_DIAG_EXPORT_STATE && kind != PIC_DIAG_EXPORT_FIELDS && kind != PIC_DIAG_EXPORT_CURRENT &&
+      kind != PIC_DIAG_COUNTS && kind != PIC_DIAG_KERNEL_TIMES)
+    return S.fail(PIC_E_UNSUPPORTED, "diagnostic %d is not available in the r-z geometry", (int)kind);
   switch (kind) {
     case PIC_DIAG_ENERGY:
     case PIC_DIAG_MOMENTUM: {
@@ -1102,9 +1154,10 @@ pic_status sim_diag(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_byt
         double* dbuf = nullptr;
         HIPCHK(S, hipMalloc(&dbuf, (size_t)sp.np * stride * sizeof(double)));
         tmp.push_back(dbuf);
-        if (I.cfg.move_window) {
+        if (I.cfg.move_window || g.cyl) {
           // rows in storage order with their ids; sorted by id here, x1 from
-          // the ring column to the lab position
+          // the ring column to the lab position (moving window), x2 from the
+          // cell coordinate to the radius (r-z)
           int* dids = nullptr;
           HIPCHK(S, hipMalloc(&dids, (size_t)sp.np * sizeof(int)));
           tmp.push_back(dids);
@@ -1126,6 +1179,11 @@ pic_status sim_diag(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_byt
             const double* r = rows.data() + (size_t)order[q] * stride;
             double* dst = o + q * stride;
             for (int c = 0; c < stride; c++) dst[c] = r[c];
+            if (g.cyl) {
+              dst[0] = I.cfg.xmin[0] + r[0] * I.cfg.dx[0];
+              dst[1] = (r[1] - 0.5) * I.cfg.dx[1];
+              continue;
+            }
             const double v = r[0];
             const double cr = std::floor(v);
             int wcol = (int)cr - wc.origin;
@@ -1158,6 +1216,18 @@ pic_status sim_diag(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_byt
         WinCtl wc;
         if ((st = read_win(S, I, wc)) != PIC_OK) return st;
         ring_rotate((double*)out, ncomp, g, wc.origin, true);
+      }
+      if (g.cyl) {
+        // r-z row 0: mirror images of row 1 for the whole-row components
+        // (E_z +, E_theta -, B_r -; J_z +, J_theta -); the half-row
+        // components keep their axis values
+        double* o = (double*)out;
+        const size_t nz = (size_t)g.nx[0];
+        const double sgn[6] = {1.0, 0.0, -1.0, 0.0, -1.0, 0.0};
+        const bool whole[6] = {true, false, true, false, true, false};
+        for (size_t c = 0; c < ncomp; c++)
+          if (whole[c])
+            for (size_t i = 0; i < nz; i++) o[c * nc + i] = sgn[c] * o[c * nc + nz + i];
       }
       return PIC_OK;
     }
@@ -1561,7 +1631,8 @@ pic_status sim_autotune(Sim& S, pic_tune* io) {
   if (io->what < 0 || io->what > 7) return S.fail(PIC_E_INVALID, "unknown PIC_TUNE bits");
   const int what = io->what ? io->what : 7;
   for (const Instance& I : S.inst)
-    if (I.cfg.move_window) return S.fail(PIC_E_UNSUPPORTED, "the autotuner does not handle a moving window");
+    if (I.cfg.move_window || I.g.cyl)
+      return S.fail(PIC_E_UNSUPPORTED, "the autotuner does not handle a moving window or the r-z geometry");
   pic_status st = refresh_descriptors(S);
   if (st != PIC_OK) return st;
   if (S.sgroups.empty()) return S.fail(PIC_E_STATE, "autotune needs loaded particles");

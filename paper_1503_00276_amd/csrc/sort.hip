@@ -226,9 +226,9 @@ __global__ void __launch_bounds__(kScanBlock) rebin_fold(const StoreDesc* __rest
       S.ioff[nxt][S.g.ntiles] = carry_b;
       S.ctl->n_items[nxt] = min(carry_b, S.max_items);
       S.ctl->np = carry_a;
-      // without a window the count is fixed; with one it changes (removal,
-      // injection) but never exceeds the capacity
-      if (carry_b > S.max_items || (S.g.window ? carry_a > S.cap : carry_a != S.np)) S.ctl->bad |= 4;
+      // in a periodic box the count is fixed; a moving window (removal,
+      // injection) or the r-z wall (removal) change it within the capacity
+      if (carry_b > S.max_items || ((S.g.window || S.g.cyl) ? carry_a > S.cap : carry_a != S.np)) S.ctl->bad |= 4;
     }
   }
   if (threadIdx.x == 0) {

@@ -31,6 +31,9 @@ PIC_ACC_FIXED64 = 2
 PIC_DEPOSIT_ISIS = 0
 PIC_DEPOSIT_TRISTAN = 1
 
+PIC_GEOM_CARTESIAN = 0
+PIC_GEOM_RZ = 1
+
 PIC_DEVICE_PTRS = 1
 
 PIC_DIAG_ENERGY = 0
@@ -80,6 +83,7 @@ class pic_config(C.Structure):
         ("move_window", C.c_int32),
         ("inject_ppc", C.c_int32 * 3),
         ("inject_w", C.c_double),
+        ("geometry", C.c_int32),
     ]
 
 
@@ -187,6 +191,7 @@ class Config:
     move_window: int = 0   # 1: the window moves along +x1 at c
     inject_ppc: Sequence[int] = (1, 1, 1)  # moving window: injected particles per cell per axis
     inject_w: float = 0.0  # moving window: weight of an injected particle
+    geometry: int = 0      # PIC_GEOM_CARTESIAN, or PIC_GEOM_RZ (x1 = z, x2 = r)
 
     def c(self) -> pic_config:
         c = pic_config()
@@ -210,6 +215,7 @@ class Config:
         for i in range(3):
             c.inject_ppc[i] = int(self.inject_ppc[i]) if i < len(self.inject_ppc) else 1
         c.inject_w = float(self.inject_w)
+        c.geometry = int(self.geometry)
         for ax, passes in enumerate(self.smooth):
             c.smooth_level[ax] = len(passes)
             for p, wts in enumerate(passes[:8]):
@@ -323,8 +329,8 @@ class Pic(_Base):
 
     def state(self):
         """(x [n, ndim], u [n, 3], w [n]) of all species in load order."""
-        if self.cfg.move_window:
-            self.sync()  # the window removes and injects particles
+        if self.cfg.move_window or self.cfg.geometry == PIC_GEOM_RZ:
+            self.sync()  # the window removes and injects particles, the r-z wall removes some
         n = self.nparticles()
         d = self.cfg.ndim
         a = self.diag(PIC_DIAG_EXPORT_STATE, n * (d + 4)).reshape(n, d + 4)
