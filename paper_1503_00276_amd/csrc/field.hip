@@ -42,7 +42,9 @@ __device__ __forceinline__ int wrap1(int v, int n) {
   return v >= n ? v - n : v;
 }
 
-template <int DIM>
+// WIN: compiled with the moving-window terms (launched for groups that hold a
+// moving window).
+template <int DIM, bool WIN>
 __global__ void __launch_bounds__(kBlock) yee_step(const InstDesc* __restrict__ inst, int par) {
   using T = YeeTile<DIM>;
   constexpr int EXM = T::X + 3, EYM = T::Y + 3, EZM = DIM == 3 ? T::Z + 3 : 1;
@@ -75,7 +77,7 @@ __global__ void __launch_bounds__(kBlock) yee_step(const InstDesc* __restrict__ 
     // moving window: the window column of region x index x (the x1 neighbour
     // beyond the window's front or back is zero), and whether the window
     // moves after this step (its back column then becomes the new, empty front)
-    const bool win = g.window != 0;
+    const bool win = WIN && g.window != 0;
     int wo = 0;
     bool wshift = false;
     if (win) {
@@ -469,11 +471,16 @@ int pic_yee_tiles(int dim, const int nx[3]) {
 }
 
 hipError_t pic_launch_yee_step(const InstDesc* d_inst, int ninst, int max_tiles, int dim, bool cart, bool cyl,
-                               int parity, hipStream_t st) {
+                               bool window, int parity, hipStream_t st) {
+  const dim3 grid(max_tiles, ninst);
   if (dim == 2) {
-    if (cart) hipLaunchKernelGGL(yee_step<2>, dim3(max_tiles, ninst), dim3(kBlock), 0, st, d_inst, parity);
-    if (cyl) hipLaunchKernelGGL(yee_step_rz, dim3(max_tiles, ninst), dim3(kBlock), 0, st, d_inst, parity);
-  } else
-    hipLaunchKernelGGL(yee_step<3>, dim3(max_tiles, ninst), dim3(kBlock), 0, st, d_inst, parity);
+    if (cart && window) hipLaunchKernelGGL((yee_step<2, true>), grid, dim3(kBlock), 0, st, d_inst, parity);
+    if (cart && !window) hipLaunchKernelGGL((yee_step<2, false>), grid, dim3(kBlock), 0, st, d_inst, parity);
+    if (cyl) hipLaunchKernelGGL(yee_step_rz, grid, dim3(kBlock), 0, st, d_inst, parity);
+  } else if (window) {
+    hipLaunchKernelGGL((yee_step<3, true>), grid, dim3(kBlock), 0, st, d_inst, parity);
+  } else {
+    hipLaunchKernelGGL((yee_step<3, false>), grid, dim3(kBlock), 0, st, d_inst, parity);
+  }
   return hipGetLastError();
 }

@@ -355,8 +355,10 @@ __device__ __forceinline__ int wrap_fast(int v, int n) { return (unsigned)v < (u
 // MODE selects the boundary logic compiled into the kernel: 0 periodic,
 // 1 moving window along x1 (a launch whose stores include a moving window),
 // 2 the 2D r-z geometry (x1 = z, x2 = r).  Without it the code is absent.
+// kstep: steps done since the last rebin check (0 for the first step of a
+// sort cycle).
 template <int DIM, int ORDER, int MODE>
-__device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii, int jp, float* smem,
+__device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii, int jp, int kstep, float* smem,
                              int* scnt) {
   constexpr int NG = ORDER + 1;  // gather taps per axis
   constexpr int W = ORDER + 2;   // deposit window per axis
@@ -367,16 +369,28 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
 
   int tc[3];
   pic_tile_coords(g, it.tile, tc);
+  // How far a particle can be outside its tile at the start of this step:
+  // 0 after a check that re-sorted (or a load), flag_slack after one that
+  // did not, plus what kstep steps can cover along each axis; never more
+  // than the last step of a cycle, for which the LDS is sized.  Only that
+  // much halo is staged and flushed.
+  // (the values are uniform: kept in scalar registers, so the per-particle
+  // code keeps its vector registers)
+  const int s0 = __builtin_amdgcn_readfirstlane(S.ctl->sorted) ? 0 : g.flag_slack;
+  int sl[3];
+#pragma unroll
+  for (int d = 0; d < 3; d++)
+    sl[d] = d < DIM ? __builtin_amdgcn_readfirstlane(min(s0 + (int)ceilf((float)kstep * g.vstep[d]), g.slk[d])) : 0;
   int org[3], ext[3], FR[3], JR[3], flo[3], jlo[3];
 #pragma unroll
   for (int d = 0; d < 3; d++) {
     if (d < DIM) {
       org[d] = tc[d] * g.tile[d];
       ext[d] = min(g.tile[d], g.nx[d] - org[d]);
-      flo[d] = g.slack + g.fa;  // region-relative index of tile node 0
-      jlo[d] = g.slack + g.ja;
-      FR[d] = ext[d] + 2 * g.slack + g.fa + g.fb;
-      JR[d] = ext[d] + 2 * g.slack + g.ja + g.jb;
+      flo[d] = sl[d] + g.fa;  // region-relative index of tile node 0
+      jlo[d] = sl[d] + g.ja;
+      FR[d] = ext[d] + 2 * sl[d] + g.fa + g.fb;
+      JR[d] = ext[d] + 2 * sl[d] + g.ja + g.jb;
     } else {
       org[d] = 0; ext[d] = 1; flo[d] = 0; jlo[d] = 0; FR[d] = 1; JR[d] = 1;
     }
@@ -463,7 +477,7 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
 #pragma unroll
     for (int d = 0; d < DIM; d++) {
       l[d] = pic_local(cc[d], org[d], ext[d], g.nx[d]);
-      ok = ok && (l[d] >= -g.slack) && (l[d] < ext[d] + g.slack);
+      ok = ok && (l[d] >= -sl[d]) && (l[d] < ext[d] + sl[d]);
     }
     if (!ok) {
       bad = true;
@@ -903,7 +917,7 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
 }
 
 template <int DIM, int ORDER, int MODE>
-__global__ void __launch_bounds__(kBlock) gpd_kernel(const StoreDesc* __restrict__ stores, int nstores, int jp) {
+__device__ __forceinline__ void gpd_body(const StoreDesc* __restrict__ stores, int nstores, int jp, int kstep) {
   // 16-byte aligned: the int64 current tile inside it takes 8-byte LDS atomics
   extern __shared__ __align__(16) float smem[];
   __shared__ int s_pref[kMaxGroup + 1];
@@ -927,14 +941,32 @@ __global__ void __launch_bounds__(kBlock) gpd_kernel(const StoreDesc* __restrict
     const StoreDesc& S = stores[s];
     const int cur = s_cur[s];
     const Item it = S.items[cur][gi - s_pref[s]];
-    process_item<DIM, ORDER, MODE>(S, cur, it, gi - s_pref[s], jp, smem, s_cnt);
+    process_item<DIM, ORDER, MODE>(S, cur, it, gi - s_pref[s], jp, kstep, smem, s_cnt);
   }
+}
+
+// (Holding the 2D kernels to the registers of five waves per SIMD was
+// measured: faster on small tiles, slower on the larger tiles the autotuner
+// picks, so the compiler keeps its choice.)
+template <int DIM, int ORDER, int MODE>
+__global__ void __launch_bounds__(kBlock) gpd_kernel(const StoreDesc* __restrict__ stores, int nstores, int jp,
+                                                     int kstep) {
+  gpd_body<DIM, ORDER, MODE>(stores, nstores, jp, kstep);
+}
+
+template <int DIM, int ORDER, int MODE>
+const void* gpd_entry() {
+  return (const void*)gpd_kernel<DIM, ORDER, MODE>;
 }
 
 template <int DIM, int ORDER, int MODE>
 hipError_t prepare_mode(size_t lds) {
-  return hipFuncSetAttribute((const void*)gpd_kernel<DIM, ORDER, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds);
+  return hipFuncSetAttribute(gpd_entry<DIM, ORDER, MODE>(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <int DIM, int ORDER, int MODE>
+void launch_mode(const StoreDesc* stores, int nstores, int grid, size_t lds, int jp, int kstep, hipStream_t st) {
+  gpd_kernel<DIM, ORDER, MODE><<<dim3(grid), dim3(kBlock), lds, st>>>(stores, nstores, jp, kstep);
 }
 
 template <int DIM, int ORDER>
@@ -947,13 +979,14 @@ hipError_t prepare_one(int mode, size_t lds) {
 }
 
 template <int DIM, int ORDER>
-hipError_t launch_one(int mode, const StoreDesc* stores, int nstores, int grid, size_t lds, int jp, hipStream_t st) {
+hipError_t launch_one(int mode, const StoreDesc* stores, int nstores, int grid, size_t lds, int jp, int kstep,
+                      hipStream_t st) {
   if (mode == 1)
-    gpd_kernel<DIM, ORDER, 1><<<dim3(grid), dim3(kBlock), lds, st>>>(stores, nstores, jp);
+    launch_mode<DIM, ORDER, 1>(stores, nstores, grid, lds, jp, kstep, st);
   else if (mode == 0)
-    gpd_kernel<DIM, ORDER, 0><<<dim3(grid), dim3(kBlock), lds, st>>>(stores, nstores, jp);
+    launch_mode<DIM, ORDER, 0>(stores, nstores, grid, lds, jp, kstep, st);
   else if constexpr (DIM == 2)
-    gpd_kernel<DIM, ORDER, 2><<<dim3(grid), dim3(kBlock), lds, st>>>(stores, nstores, jp);
+    launch_mode<DIM, ORDER, 2>(stores, nstores, grid, lds, jp, kstep, st);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -965,8 +998,8 @@ hipError_t launch_one(int mode, const StoreDesc* stores, int nstores, int grid, 
 size_t pic_gpd_lds_bytes(const GridDesc& g) {
   size_t fn = 1, jn = 1;
   for (int d = 0; d < g.dim; d++) {
-    fn *= (size_t)(g.tile[d] + 2 * g.slack + g.fa + g.fb);
-    jn *= (size_t)(g.tile[d] + 2 * g.slack + g.ja + g.jb);
+    fn *= (size_t)(g.tile[d] + 2 * g.slk[d] + g.fa + g.fb);
+    jn *= (size_t)(g.tile[d] + 2 * g.slk[d] + g.ja + g.jb);
   }
   return ((6 * fn + 1) & ~(size_t)1) * sizeof(float) + 3 * jn * sizeof(unsigned long long);
 }
@@ -987,16 +1020,39 @@ hipError_t pic_gpd_prepare(int dim, int order, int mode, size_t lds) {
   return hipErrorInvalidValue;
 }
 
-hipError_t pic_launch_gpd(int dim, int order, int mode, const StoreDesc* d_stores, int nstores, int grid,
-                          size_t lds, int parity, hipStream_t st) {
+template <int DIM, int ORDER>
+int resident_one(int mode, size_t lds) {
+  int n = 0;
+  const void* f = mode == 1 ? gpd_entry<DIM, ORDER, 1>() : gpd_entry<DIM, ORDER, 0>();
+  if constexpr (DIM == 2)
+    if (mode == 2) f = gpd_entry<DIM, ORDER, 2>();
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kBlock, lds) != hipSuccess) return 1;
+  return n < 1 ? 1 : n;
+}
+
+int pic_gpd_resident(int dim, int order, int mode, size_t lds) {
   if (dim == 2) {
-    if (order == 1) return launch_one<2, 1>(mode, d_stores, nstores, grid, lds, parity, st);
-    if (order == 2) return launch_one<2, 2>(mode, d_stores, nstores, grid, lds, parity, st);
-    if (order == 3) return launch_one<2, 3>(mode, d_stores, nstores, grid, lds, parity, st);
+    if (order == 1) return resident_one<2, 1>(mode, lds);
+    if (order == 2) return resident_one<2, 2>(mode, lds);
+    if (order == 3) return resident_one<2, 3>(mode, lds);
   } else if (dim == 3) {
-    if (order == 1) return launch_one<3, 1>(mode, d_stores, nstores, grid, lds, parity, st);
-    if (order == 2) return launch_one<3, 2>(mode, d_stores, nstores, grid, lds, parity, st);
-    if (order == 3) return launch_one<3, 3>(mode, d_stores, nstores, grid, lds, parity, st);
+    if (order == 1) return resident_one<3, 1>(mode, lds);
+    if (order == 2) return resident_one<3, 2>(mode, lds);
+    if (order == 3) return resident_one<3, 3>(mode, lds);
+  }
+  return 1;
+}
+
+hipError_t pic_launch_gpd(int dim, int order, int mode, const StoreDesc* d_stores, int nstores, int grid,
+                          size_t lds, int parity, int kstep, hipStream_t st) {
+  if (dim == 2) {
+    if (order == 1) return launch_one<2, 1>(mode, d_stores, nstores, grid, lds, parity, kstep, st);
+    if (order == 2) return launch_one<2, 2>(mode, d_stores, nstores, grid, lds, parity, kstep, st);
+    if (order == 3) return launch_one<2, 3>(mode, d_stores, nstores, grid, lds, parity, kstep, st);
+  } else if (dim == 3) {
+    if (order == 1) return launch_one<3, 1>(mode, d_stores, nstores, grid, lds, parity, kstep, st);
+    if (order == 2) return launch_one<3, 2>(mode, d_stores, nstores, grid, lds, parity, kstep, st);
+    if (order == 3) return launch_one<3, 3>(mode, d_stores, nstores, grid, lds, parity, kstep, st);
   }
   return hipErrorInvalidValue;
 }

@@ -19,7 +19,9 @@ struct GridDesc {
   int ntiles;         // product of ntile
   int sh1, sh2;       // bit shifts of the packed cell index (c0 | c1<<sh1 | c2<<sh2)
   int m0, m1;         // masks of c0 and c1
-  int slack;          // cells a particle may stray outside its tile at a step start
+  int slack;          // cells a particle may stray outside its tile at a step start (max of slk)
+  int slk[3];         // per axis: the stray bound of the last step of a sort cycle
+  float vstep[3];     // per axis: cells a particle can move in one step (c dt / dx, rounded up)
   int flag_slack;     // stray distance (cells) beyond which a rebin is requested
   int ncell;          // product of nx
   float dx[3];        // cell size
@@ -57,7 +59,7 @@ struct StoreCtl {
   int nchecks;      // rebin checks performed
   int force;        // set by the host: rebin at every check (autotuner trials)
   int np;           // particles in the current set after the last rebin (moving window)
-  int pad;
+  int sorted;       // 1: every particle sits in its own tile (loaded, or re-sorted at the last check)
 };
 
 __host__ __device__ inline int pic_cur(const StoreCtl& c) { return c.cur ^ c.pending; }

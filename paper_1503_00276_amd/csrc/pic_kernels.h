@@ -13,17 +13,23 @@ int pic_gpd_max_group();
 // mode: the boundary logic of the group's stores (0 periodic, 1 moving window
 // along x1, 2 the 2D r-z geometry), which selects the kernel variant
 hipError_t pic_gpd_prepare(int dim, int order, int mode, size_t lds);
+// workgroups of the variant that are resident on one CU at once with 'lds'
+// bytes of dynamic LDS (after pic_gpd_prepare)
+int pic_gpd_resident(int dim, int order, int mode, size_t lds);
+// kstep: steps done since the last rebin check (bounds the staged halo)
 hipError_t pic_launch_gpd(int dim, int order, int mode, const StoreDesc* d_stores, int nstores, int grid,
-                          size_t lds, int parity, hipStream_t st);
+                          size_t lds, int parity, int kstep, hipStream_t st);
 
 // Yee field solve (field.hip); instances in d_inst[0..ninst)
 int pic_yee_tiles(int dim, const int nx[3]);
 hipError_t pic_launch_window_advance(const InstDesc* d_inst, int ninst, hipStream_t st);
 hipError_t pic_launch_smooth_pass(const InstDesc* d_inst, int ninst, int max_ncell, int axis, int lev,
                                   int parity, hipStream_t st);
-// cart / cyl: the group holds Cartesian / r-z instances (each kernel skips the others)
+// cart / cyl: the group holds Cartesian / r-z instances (each kernel skips the
+// others); window: some instance has a moving window (selects the variant
+// with the window terms)
 hipError_t pic_launch_yee_step(const InstDesc* d_inst, int ninst, int max_tiles, int dim, bool cart, bool cyl,
-                               int parity, hipStream_t st);
+                               bool window, int parity, hipStream_t st);
 
 // tile rebin (sort.hip); stores in d_stores[0..nstores)
 hipError_t pic_launch_rebin(const StoreDesc* d_stores, int nstores, int max_items, int total_tiles,

@@ -66,6 +66,7 @@ struct Group {
   int inject_max; // moving window: most particles a store injects per shift
   bool window;    // some instance has a moving window
   int mode = 0;   // stores: boundary logic of the fused kernel (0 periodic, 1 moving window, 2 r-z)
+  int resident = 1;  // stores: fused-kernel workgroups resident per CU (the grid is one full wave of them)
   bool cyl = false, cart = false;  // instances: some are r-z / some are Cartesian
 };
 
@@ -73,6 +74,7 @@ struct Group {
 int kernel_mode(const GridDesc& g) { return g.window ? 1 : (g.cyl ? 2 : 0); }
 
 struct Sim {
+  int num_cu = kNumCU;  // compute units of the device
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::vector<Instance> inst;
@@ -151,7 +153,6 @@ pic_status setup_grid(Sim& S, const pic_config& c, int sort_interval, GridDesc& 
   memset(&g, 0, sizeof g);
   g.dim = c.ndim;
   g.order = c.shape_order;
-  double vmax = 0.0;
   for (int d = 0; d < 3; d++) {
     g.nx[d] = d < c.ndim ? c.nx[d] : 1;
     g.dxd[d] = d < c.ndim ? c.dx[d] : 1.0;
@@ -160,7 +161,6 @@ pic_status setup_grid(Sim& S, const pic_config& c, int sort_interval, GridDesc& 
     g.cdt[d] = (float)(g.dxd[d] / c.dt);
     g.e0[d] = (float)c.e0[d];
     g.b0[d] = (float)c.b0[d];
-    if (d < c.ndim) vmax = std::max(vmax, c.dt / c.dx[d]);
   }
   g.dt = (float)c.dt;
   g.dtd = c.dt;
@@ -172,10 +172,20 @@ pic_status setup_grid(Sim& S, const pic_config& c, int sort_interval, GridDesc& 
   g.jscale = 1.0f;
   g.jinv = 1.0f;
   g.flag_slack = 1;
-  int extra = (int)std::ceil((sort_interval - 1) * vmax - 1e-12);
-  g.slack = g.flag_slack + std::max(0, extra);
+  // Stray bound per axis.  After a check a particle sits in its tile (the
+  // check re-sorted) or within flag_slack cells of it; each step moves it
+  // less than c dt / dx_d cells along axis d.  The staged regions are sized
+  // for the last step of a cycle; each launch stages only what its own step
+  // needs (see the fused kernel).
+  g.slack = 0;
+  for (int d = 0; d < 3; d++) {
+    const double v = d < c.ndim ? c.dt / c.dx[d] : 0.0;
+    g.vstep[d] = std::nextafter((float)v, 2.0f);
+    const int extra = d < c.ndim ? (int)std::ceil((sort_interval - 1) * v - 1e-12) : 0;
+    g.slk[d] = d < c.ndim ? g.flag_slack + std::max(0, extra) : 0;
+    g.slack = std::max(g.slack, g.slk[d]);
+  }
   region_guards(g.order, g.fa, g.fb, g.ja, g.jb);
-  const int need = g.slack + 2;
   g.ntiles = 1;
   for (int d = 0; d < 3; d++) {
     if (d >= c.ndim) {
@@ -183,6 +193,7 @@ pic_status setup_grid(Sim& S, const pic_config& c, int sort_interval, GridDesc& 
       g.ntile[d] = 1;
       continue;
     }
+    const int need = g.slk[d] + 2;
     int t = c.tile[d];
     if (t == 0) t = pick_tile(g.nx[d], c.ndim == 2 ? 16 : 8, need);
     if (!tile_ok(g.nx[d], t, need))
@@ -205,6 +216,7 @@ pic_status setup_grid(Sim& S, const pic_config& c, int sort_interval, GridDesc& 
     for (int d = 1; d < c.ndim; d++)
       if (g.tile[d] > g.tile[dmax]) dmax = d;
     int t = g.tile[dmax] / 2;
+    const int need = g.slk[dmax] + 2;
     if (c.tile[dmax] != 0 || t < need) return S.fail(PIC_E_INVALID, "tile needs more LDS than a workgroup has");
     while (t >= need && !tile_ok(g.nx[dmax], t, need)) t--;
     if (t < need) return S.fail(PIC_E_INVALID, "no tile fits the LDS");
@@ -406,6 +418,7 @@ pic_status refresh_descriptors(Sim& S) {
           if (gr.count > 0) {
         if (gr.count > pic_gpd_max_group()) return S.fail(PIC_E_INVALID, "too many stores in one group");
         HIPCHK(S, pic_gpd_prepare(dim, order, gr.mode, gr.lds));
+        gr.resident = pic_gpd_resident(dim, order, gr.mode, gr.lds);
         S.sgroups.push_back(gr);
       }
     }
@@ -544,15 +557,18 @@ pic_status prof_collect(Sim& S) {
 
 // Launch nsteps steps starting at global step 'first' (whose parity picks
 // the current accumulator of each step).
-pic_status launch_steps(Sim& S, int64_t first, int nsteps, bool end_with_check) {
+// 'first' only sets the parity of each step; phase0 is the number of steps
+// done since the last rebin check when the first of them starts.
+pic_status launch_steps(Sim& S, int64_t first, int nsteps, bool end_with_check, int phase0) {
   for (int k = 0; k < nsteps; k++) {
     const int par = (int)((first + k) & 1);
     hipEvent_t e0 = prof_begin(S);
     for (const Group& gr : S.sgroups) {
-      int per_cu = std::max(1, std::min(8, (int)(kLdsMax / std::max<size_t>(gr.lds, 1))));
-      int grid = std::max(1, std::min(gr.max_items, kNumCU * per_cu));
+      // one full wave of resident workgroups: a partial second wave would
+      // leave the kernel's tail to a fraction of the chip
+      int grid = std::max(1, std::min(gr.max_items, S.num_cu * gr.resident));
       HIPCHK(S, pic_launch_gpd(gr.dim, gr.order, gr.mode, S.d_stores + gr.first, gr.count, grid, gr.lds, par,
-                               S.stream));
+                               phase0 + k, S.stream));
     }
     prof_end(S, 0, e0);
     e0 = prof_begin(S);
@@ -561,8 +577,8 @@ pic_status launch_steps(Sim& S, int64_t first, int nsteps, bool end_with_check) 
         for (int lev = 0; lev < gr.sm_max[a]; lev++)
           HIPCHK(S, pic_launch_smooth_pass(S.d_inst + gr.first, gr.count, gr.max_ncell, a, lev, par, S.stream));
     for (const Group& gr : S.igroups)
-      HIPCHK(S, pic_launch_yee_step(S.d_inst + gr.first, gr.count, gr.max_tiles, gr.dim, gr.cart, gr.cyl, par,
-                                    S.stream));
+      HIPCHK(S, pic_launch_yee_step(S.d_inst + gr.first, gr.count, gr.max_tiles, gr.dim, gr.cart, gr.cyl,
+                                    gr.window, par, S.stream));
     prof_end(S, 1, e0);
     if (end_with_check && k == nsteps - 1) {
       e0 = prof_begin(S);
@@ -582,7 +598,7 @@ pic_status capture_cycle(Sim& S, int par) {
   if (S.cycle_exec[par]) return PIC_OK;
   hipGraph_t graph = nullptr;
   HIPCHK(S, hipStreamBeginCapture(S.stream, hipStreamCaptureModeThreadLocal));
-  pic_status st = launch_steps(S, par, S.sort_interval, true);
+  pic_status st = launch_steps(S, par, S.sort_interval, true, 0);  // a cycle starts after a check
   hipError_t e = hipStreamEndCapture(S.stream, &graph);
   if (st != PIC_OK) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -620,7 +636,7 @@ pic_status sim_step(Sim& S, int64_t nsteps) {
     }
     int64_t run = std::min<int64_t>(left, SI - phase);
     bool check = (phase + run == SI);
-    st = launch_steps(S, S.steps, (int)run, check);
+    st = launch_steps(S, S.steps, (int)run, check, (int)phase);
     if (st != PIC_OK) return st;
     S.steps += run;
     done += run;
@@ -795,6 +811,7 @@ pic_status upload_bins(Sim& S, Species& sp, const Binned& B) {
   c.bad = 0;
   c.n_items[0] = (int)B.items.size();
   c.n_items[1] = 0;
+  c.sorted = 1;  // binned exactly: every particle in its own tile
   HIPCHK(S, hipMemcpy(sp.ctl, &c, sizeof c, hipMemcpyHostToDevice));
   sp.np = (int64_t)n;
   sp.desc.np = (int)n;
@@ -1309,6 +1326,12 @@ pic_status sim_create(Sim& S, const pic_config* cfgs, int n, void* stream) {
   }
   S.sort_interval = SI;
   S.stream = (hipStream_t)stream;
+  {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+      S.num_cu = ncu;
+  }
   if (!S.stream) {
     // graph capture needs a stream of our own when the caller gives none
     HIPCHK(S, hipStreamCreateWithFlags(&S.stream, hipStreamNonBlocking));
@@ -1469,9 +1492,8 @@ std::vector<int> tile_ladder(int n, int need) {
 // CU; g carries the slack of the sort interval in question.
 void tile_for_cells(const GridDesc& g0, double cells, int aspect, int out[3]) {
   GridDesc g = g0;
-  const int need = g.slack + 2;
   std::vector<int> lad[3];
-  for (int d = 0; d < 3; d++) lad[d] = d < g.dim ? tile_ladder(g.nx[d], need) : std::vector<int>{1};
+  for (int d = 0; d < 3; d++) lad[d] = d < g.dim ? tile_ladder(g.nx[d], g.slk[d] + 2) : std::vector<int>{1};
   double best = 1e300;
   out[0] = g0.tile[0];
   out[1] = g0.tile[1];

@@ -240,6 +240,9 @@ __global__ void __launch_bounds__(kScanBlock) rebin_fold(const StoreDesc* __rest
     c->flag = 0;
     c->nchecks += 1;
     c->nsorts += act;
+    // after this check every particle sits in its own tile (re-sorted), or
+    // within flag_slack cells of it (no particle strayed further)
+    c->sorted = act;
   }
 }
 
