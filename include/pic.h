@@ -147,8 +147,13 @@ typedef struct {
    * momentum back into the r-z plane (Eqs. 2d-cyl-position-update-1..3).
    * Positions loaded and exported are (z, r) with xmin[1] = 0; particles
    * are exported in load order without the removed ones.  The sort
-   * interval is 1.  Not available with a moving window, smoothing or
-   * pic_autotune; diagnostics other than the exports are not available. */
+   * interval is 1.  The diagnostics use the ring volumes: RHO is
+   * ion_density + (charge below the axis folded to its mirror row) / (r/dr),
+   * the residuals use the cylindrical divergence, ENERGY weighs each value
+   * by the volume 2 pi r dr dz of its ring (pi dr^2 dz / 4 for the axis
+   * disc), and MOMENTUM is (P_z, sum of the radial momenta, angular momentum
+   * about the axis sum Q r u_theta m/q), with Q = w 2 pi dr^2 dz.  Not
+   * available with a moving window, smoothing or pic_autotune. */
   int32_t geometry;
 } pic_config;
 

@@ -63,7 +63,16 @@ __global__ void __launch_bounds__(kBlock) rho64(const StoreDesc* __restrict__ sp
     for (int k = 0; k < nz; k++) {
       int gz = g.dim == 3 ? pic_wrap(c[2] + bz + k, g.nx[2]) : 0;
       for (int j = 0; j < no; j++) {
-        int gy = pic_wrap(c[1] + by + j, g.nx[1]);
+        int gy;
+        if (g.cyl) {
+          // r-z: charge below the axis belongs to the mirror row, beyond the
+          // wall it is dropped (rows are divided by their ring volume later)
+          const int ry = c[1] + by + j;
+          gy = ry <= 0 ? 1 - ry : ry;
+          if (gy >= g.nx[1]) continue;
+        } else {
+          gy = pic_wrap(c[1] + by + j, g.nx[1]);
+        }
         for (int i = 0; i < no; i++) {
           if (g.window && (unsigned)(wc + bx + i) >= (unsigned)g.nx[0]) continue;  // beyond the window
           int gx = pic_wrap(c[0] + bx + i, g.nx[0]);
@@ -74,6 +83,19 @@ __global__ void __launch_bounds__(kBlock) rho64(const StoreDesc* __restrict__ sp
   }
 }
 
+// r-z: rho = ion density + (folded ring charge) / (r_j / dr) on the rows
+// j >= 1; row 0 holds the image of row 1.
+__global__ void rz_rho_finish(double* rho, int nz, int nr, double ion) {
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nz * nr; c += gridDim.x * blockDim.x) {
+    const int j = c / nz;
+    if (j >= 1) rho[c] = ion + rho[c] / ((double)j - 0.5);
+  }
+}
+
+__global__ void rz_rho_mirror(double* rho, int nz) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nz; i += gridDim.x * blockDim.x) rho[i] = rho[nz + i];
+}
+
 __global__ void fill64(double* p, double v, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
@@ -81,8 +103,20 @@ __global__ void fill64(double* p, double v, size_t n) {
 // Backward-difference divergence of a 3-component staggered field at node c.
 template <typename T>
 // wo: ring origin of a moving window (-1 without one); the x1 neighbour
-// behind the window's back column is zero.
+// behind the window's back column is zero.  r-z: the cylindrical divergence
+// dV_z/dz + (1/r) d(r V_r)/dr on the rows j >= 1 (V_r on the half rows j and
+// j - 1, radii j dr and (j - 1) dr; the row radius (j - 1/2) dr); row 0
+// takes the value of row 1.
 __device__ __forceinline__ double div_at(const GridDesc& g, const T* V, int nc, int c, int dim, int wo = -1) {
+  if (g.cyl) {
+    if (c < g.nx[0]) c += g.nx[0];
+    const int i = c % g.nx[0];
+    const int j = c / g.nx[0];
+    const int cxm = (i > 0) ? c - 1 : c + g.nx[0] - 1;
+    return ((double)V[c] - (double)V[cxm]) / g.dxd[0] +
+           ((double)j * (double)V[nc + c] - (double)(j - 1) * (double)V[nc + c - g.nx[0]]) /
+               (((double)j - 0.5) * g.dxd[1]);
+  }
   int i = c % g.nx[0];
   int r = c / g.nx[0];
   int j = r % g.nx[1];
@@ -198,11 +232,22 @@ __global__ void __launch_bounds__(kBlock) field_sums(const InstDesc* __restrict_
   const int nc = I.g.ncell;
   Pair v[2] = {{0.0, 0.0}, {0.0, 0.0}};
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
+    // r-z: each value weighted by its ring volume in units of dz dr^2:
+    // 2 pi r / dr off the axis, pi / 4 for the disc of the half rows on the
+    // axis, 0 for the image row 0 of the whole-row components
+    double vw = 1.0, vh = 1.0;
+    if (I.g.cyl) {
+      const int j = c / I.g.nx[0];
+      const double two_pi = 6.283185307179586;
+      vw = j == 0 ? 0.0 : two_pi * ((double)j - 0.5);
+      vh = j == 0 ? 0.25 * 3.141592653589793 : two_pi * (double)j;
+    }
     for (int k = 0; k < 3; k++) {
       const float* F = I.F[fpar];
       double e = F[(size_t)k * nc + c], b = F[(size_t)(3 + k) * nc + c];
-      neumaier(v[0], e * e);
-      neumaier(v[1], b * b);
+      // whole rows: E_z, E_theta (k = 0, 2), B_r (k = 1); half rows the others
+      neumaier(v[0], (k == 1 ? vh : vw) * e * e);
+      neumaier(v[1], (k == 1 ? vw : vh) * b * b);
     }
   }
   block_reduce_store<2>(v, partial);
@@ -222,7 +267,14 @@ __global__ void __launch_bounds__(kBlock) particle_sums(const StoreDesc* __restr
     neumaier(v[0], m * (usq / (sqrt(1.0 + usq) + 1.0)));
     neumaier(v[1], m * ux);
     neumaier(v[2], m * uy);
-    neumaier(v[3], m * uz);
+    if (S.g.cyl) {
+      // r-z: angular momentum about the axis, r u_theta
+      const int row = (S.cell[cur][p] >> S.g.sh1) & S.g.m1;
+      const double r = ((double)row + (double)S.eps[cur][1][p] - 0.5) * S.g.dxd[1];
+      neumaier(v[3], m * r * uz);
+    } else {
+      neumaier(v[3], m * uz);
+    }
   }
   block_reduce_store<4>(v, partial);
 }
@@ -280,6 +332,12 @@ int pic_reduce_blocks() { return kRedBlocks; }
 
 hipError_t pic_launch_rho64(const StoreDesc* d_store, int np_max, double* rho, hipStream_t st) {
   hipLaunchKernelGGL(rho64, dim3(grid_for(np_max)), dim3(kBlock), 0, st, d_store, rho);
+  return hipGetLastError();
+}
+
+hipError_t pic_launch_rz_rho_finish(double* rho, int nz, int nr, double ion, hipStream_t st) {
+  hipLaunchKernelGGL(rz_rho_finish, dim3(grid_for((size_t)nz * nr)), dim3(kBlock), 0, st, rho, nz, nr, ion);
+  hipLaunchKernelGGL(rz_rho_mirror, dim3(grid_for((size_t)nz)), dim3(kBlock), 0, st, rho, nz);
   return hipGetLastError();
 }
 

@@ -14,6 +14,8 @@
 //
 // Positions are stored as a packed integer cell plus an FP32 offset in [0,1)
 // per axis; all arithmetic is FP32.
+#include <hip/hip_ext.h>
+
 #include "pic_dev.h"
 #include "pic_kernels.h"
 
@@ -965,8 +967,14 @@ hipError_t prepare_mode(size_t lds) {
 }
 
 template <int DIM, int ORDER, int MODE>
-void launch_mode(const StoreDesc* stores, int nstores, int grid, size_t lds, int jp, int kstep, hipStream_t st) {
-  gpd_kernel<DIM, ORDER, MODE><<<dim3(grid), dim3(kBlock), lds, st>>>(stores, nstores, jp, kstep);
+void launch_mode(const StoreDesc* stores, int nstores, int grid, size_t lds, int jp, int kstep, hipStream_t st,
+                 hipEvent_t ev0, hipEvent_t ev1) {
+  if (ev0 || ev1)
+    // the command processor stamps the events at the kernel's own start and end
+    hipExtLaunchKernelGGL(gpd_kernel<DIM, ORDER, MODE>, dim3(grid), dim3(kBlock), (std::uint32_t)lds, st, ev0, ev1, 0,
+                          stores, nstores, jp, kstep);
+  else
+    gpd_kernel<DIM, ORDER, MODE><<<dim3(grid), dim3(kBlock), lds, st>>>(stores, nstores, jp, kstep);
 }
 
 template <int DIM, int ORDER>
@@ -980,13 +988,13 @@ hipError_t prepare_one(int mode, size_t lds) {
 
 template <int DIM, int ORDER>
 hipError_t launch_one(int mode, const StoreDesc* stores, int nstores, int grid, size_t lds, int jp, int kstep,
-                      hipStream_t st) {
+                      hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (mode == 1)
-    launch_mode<DIM, ORDER, 1>(stores, nstores, grid, lds, jp, kstep, st);
+    launch_mode<DIM, ORDER, 1>(stores, nstores, grid, lds, jp, kstep, st, ev0, ev1);
   else if (mode == 0)
-    launch_mode<DIM, ORDER, 0>(stores, nstores, grid, lds, jp, kstep, st);
+    launch_mode<DIM, ORDER, 0>(stores, nstores, grid, lds, jp, kstep, st, ev0, ev1);
   else if constexpr (DIM == 2)
-    launch_mode<DIM, ORDER, 2>(stores, nstores, grid, lds, jp, kstep, st);
+    launch_mode<DIM, ORDER, 2>(stores, nstores, grid, lds, jp, kstep, st, ev0, ev1);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -1044,15 +1052,15 @@ int pic_gpd_resident(int dim, int order, int mode, size_t lds) {
 }
 
 hipError_t pic_launch_gpd(int dim, int order, int mode, const StoreDesc* d_stores, int nstores, int grid,
-                          size_t lds, int parity, int kstep, hipStream_t st) {
+                          size_t lds, int parity, int kstep, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (dim == 2) {
-    if (order == 1) return launch_one<2, 1>(mode, d_stores, nstores, grid, lds, parity, kstep, st);
-    if (order == 2) return launch_one<2, 2>(mode, d_stores, nstores, grid, lds, parity, kstep, st);
-    if (order == 3) return launch_one<2, 3>(mode, d_stores, nstores, grid, lds, parity, kstep, st);
+    if (order == 1) return launch_one<2, 1>(mode, d_stores, nstores, grid, lds, parity, kstep, st, ev0, ev1);
+    if (order == 2) return launch_one<2, 2>(mode, d_stores, nstores, grid, lds, parity, kstep, st, ev0, ev1);
+    if (order == 3) return launch_one<2, 3>(mode, d_stores, nstores, grid, lds, parity, kstep, st, ev0, ev1);
   } else if (dim == 3) {
-    if (order == 1) return launch_one<3, 1>(mode, d_stores, nstores, grid, lds, parity, kstep, st);
-    if (order == 2) return launch_one<3, 2>(mode, d_stores, nstores, grid, lds, parity, kstep, st);
-    if (order == 3) return launch_one<3, 3>(mode, d_stores, nstores, grid, lds, parity, kstep, st);
+    if (order == 1) return launch_one<3, 1>(mode, d_stores, nstores, grid, lds, parity, kstep, st, ev0, ev1);
+    if (order == 2) return launch_one<3, 2>(mode, d_stores, nstores, grid, lds, parity, kstep, st, ev0, ev1);
+    if (order == 3) return launch_one<3, 3>(mode, d_stores, nstores, grid, lds, parity, kstep, st, ev0, ev1);
   }
   return hipErrorInvalidValue;
 }

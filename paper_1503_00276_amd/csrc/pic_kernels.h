@@ -16,9 +16,10 @@ hipError_t pic_gpd_prepare(int dim, int order, int mode, size_t lds);
 // workgroups of the variant that are resident on one CU at once with 'lds'
 // bytes of dynamic LDS (after pic_gpd_prepare)
 int pic_gpd_resident(int dim, int order, int mode, size_t lds);
-// kstep: steps done since the last rebin check (bounds the staged halo)
+// kstep: steps done since the last rebin check (bounds the staged halo);
+// ev0 / ev1 (may be null): events stamped at the kernel's start / end
 hipError_t pic_launch_gpd(int dim, int order, int mode, const StoreDesc* d_stores, int nstores, int grid,
-                          size_t lds, int parity, int kstep, hipStream_t st);
+                          size_t lds, int parity, int kstep, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
 
 // Yee field solve (field.hip); instances in d_inst[0..ninst)
 int pic_yee_tiles(int dim, const int nx[3]);
@@ -38,6 +39,8 @@ hipError_t pic_launch_rebin(const StoreDesc* d_stores, int nstores, int max_item
 // diagnostics (diag.hip)
 hipError_t pic_launch_rho64(const StoreDesc* d_store, int np_max, double* rho, hipStream_t st);
 hipError_t pic_launch_fill64(double* p, double v, size_t n, hipStream_t st);
+// r-z: rho = ion + folded charge / (r_j/dr) on rows j >= 1, row 0 = row 1
+hipError_t pic_launch_rz_rho_finish(double* rho, int nz, int nr, double ion, hipStream_t st);
 hipError_t pic_launch_gauss64(const InstDesc* d_inst, const double* rho, double* G, int ncell, int dim,
                               int fpar, hipStream_t st);
 hipError_t pic_launch_charge64(const InstDesc* d_inst, const double* rho0, const double* rho1,

@@ -562,16 +562,25 @@ pic_status prof_collect(Sim& S) {
 pic_status launch_steps(Sim& S, int64_t first, int nsteps, bool end_with_check, int phase0) {
   for (int k = 0; k < nsteps; k++) {
     const int par = (int)((first + k) & 1);
-    hipEvent_t e0 = prof_begin(S);
-    for (const Group& gr : S.sgroups) {
+    // profiling: the particle family's events are stamped at the start of its
+    // first kernel and the end of its last one
+    hipEvent_t p0 = nullptr, p1 = nullptr;
+    if (S.profiling && !S.sgroups.empty()) {
+      p0 = take_event(S);
+      p1 = take_event(S);
+      if (!p0 || !p1) p0 = p1 = nullptr;
+    }
+    for (size_t q = 0; q < S.sgroups.size(); q++) {
+      const Group& gr = S.sgroups[q];
       // one full wave of resident workgroups: a partial second wave would
       // leave the kernel's tail to a fraction of the chip
       int grid = std::max(1, std::min(gr.max_items, S.num_cu * gr.resident));
       HIPCHK(S, pic_launch_gpd(gr.dim, gr.order, gr.mode, S.d_stores + gr.first, gr.count, grid, gr.lds, par,
-                               phase0 + k, S.stream));
+                               phase0 + k, S.stream, q == 0 ? p0 : nullptr,
+                               q + 1 == S.sgroups.size() ? p1 : nullptr));
     }
-    prof_end(S, 0, e0);
-    e0 = prof_begin(S);
+    if (p0) S.ev_pending[0].push_back({p0, p1});
+    hipEvent_t e0 = prof_begin(S);
     for (const Group& gr : S.igroups)
       for (int a = 0; a < gr.dim; a++)
         for (int lev = 0; lev < gr.sm_max[a]; lev++)
@@ -1042,13 +1051,15 @@ pic_status need(Sim& S, size_t want, size_t out_bytes, size_t* written) {
 
 pic_status compute_rho(Sim& S, int i, double* d_rho) {
   Instance& I = S.inst[i];
-  HIPCHK(S, pic_launch_fill64(d_rho, I.cfg.ion_density, (size_t)I.g.ncell, S.stream));
+  // r-z: the folded ring charge first, then the ring volumes and the ions
+  HIPCHK(S, pic_launch_fill64(d_rho, I.g.cyl ? 0.0 : I.cfg.ion_density, (size_t)I.g.ncell, S.stream));
   for (int s = 0; s < PIC_MAX_SPECIES; s++) {
     if (!I.sp[s].used || I.sp[s].np == 0) continue;
     int k = store_desc_index(S, i, s);
     if (k < 0) return S.fail(PIC_E_STATE, "species descriptor missing");
     HIPCHK(S, pic_launch_rho64(S.d_stores + k, (int)I.sp[s].np, d_rho, S.stream));
   }
+  if (I.g.cyl) HIPCHK(S, pic_launch_rz_rho_finish(d_rho, I.g.nx[0], I.g.nx[1], I.cfg.ion_density, S.stream));
   return PIC_OK;
 }
 
@@ -1071,9 +1082,6 @@ pic_status sim_diag(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_byt
       for (void* p : v) (void)hipFree(p);
     }
   } fr{tmp};
-  if (g.cyl && kind != PIC_DIAG_EXPORT_STATE && kind != PIC_DIAG_EXPORT_FIELDS && kind != PIC_DIAG_EXPORT_CURRENT &&
-      kind != PIC_DIAG_COUNTS && kind != PIC_DIAG_KERNEL_TIMES)
-    return S.fail(PIC_E_UNSUPPORTED, "diagnostic %d is not available in the r-z geometry", (int)kind);
   switch (kind) {
     case PIC_DIAG_ENERGY:
     case PIC_DIAG_MOMENTUM: {
@@ -1094,15 +1102,19 @@ pic_status sim_diag(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_byt
         for (int q = 0; q < 4; q++) pm[q] += r[q];
       }
       double* o = (double*)out;
+      // r-z: the field sums carry the ring volumes in units of dz dr^2, and a
+      // particle's charge is w 2 pi dr^2 dz
+      const double Vf = g.cyl ? g.dxd[0] * g.dxd[1] * g.dxd[1] : V;
+      const double Vp = g.cyl ? 6.283185307179586 * g.dxd[0] * g.dxd[1] * g.dxd[1] : V;
       if (kind == PIC_DIAG_ENERGY) {
-        o[0] = 0.5 * V * fe[0];
-        o[1] = 0.5 * V * fe[1];
-        o[2] = V * pm[0];
+        o[0] = 0.5 * Vf * fe[0];
+        o[1] = 0.5 * Vf * fe[1];
+        o[2] = Vp * pm[0];
         o[3] = o[0] + o[1] + o[2];
       } else {
-        o[0] = V * pm[1];
-        o[1] = V * pm[2];
-        o[2] = V * pm[3];
+        o[0] = Vp * pm[1];
+        o[1] = Vp * pm[2];
+        o[2] = Vp * pm[3];
       }
       return PIC_OK;
     }

@@ -118,33 +118,29 @@ __device__ __forceinline__ void block_scan2(int a, int b, int& ea, int& eb, int&
   __syncthreads();
 }
 
-// --- 1. per source tile: running slot counts over the tile's items ----------
+// --- 1. per source tile and slot: running counts over the tile's items ------
+// One thread per (tile, slot): consecutive threads read and write
+// consecutive words of the slot-major count rows.
 __global__ void __launch_bounds__(kBlock) rebin_count(const StoreDesc* __restrict__ stores, int nstores,
                                                       int total_tiles) {
   __shared__ int t0[kMaxGroup];
   for (int i = threadIdx.x; i < nstores; i += blockDim.x) t0[i] = stores[i].tile0;
   __syncthreads();
-  for (int gt = blockIdx.x * blockDim.x + threadIdx.x; gt < total_tiles; gt += gridDim.x * blockDim.x) {
+  const int total = total_tiles * PIC_NSLOT;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < total; q += gridDim.x * blockDim.x) {
+    const int gt = q / PIC_NSLOT, sl = q - gt * PIC_NSLOT;
     const StoreDesc& S = stores[store_of(t0, nstores, gt)];
     if (!(S.ctl->flag | S.ctl->force) && !win_shift_now(S)) continue;
     const int cur = pic_cur(*S.ctl);
     const int t = gt - S.tile0;
     const int i0 = S.ioff[cur][t], i1 = S.ioff[cur][t + 1];
-    int run[PIC_NSLOT];
-#pragma unroll
-    for (int sl = 0; sl < PIC_NSLOT; sl++) run[sl] = 0;
+    int run = 0;
     for (int i = i0; i < i1; i++) {
-      int c[PIC_NSLOT];
-#pragma unroll
-      for (int sl = 0; sl < PIC_NSLOT; sl++) c[sl] = S.cnt[i * PIC_NSLOT + sl];
-#pragma unroll
-      for (int sl = 0; sl < PIC_NSLOT; sl++) {
-        S.pre[i * PIC_NSLOT + sl] = run[sl];
-        run[sl] += c[sl];
-      }
+      const int c = S.cnt[i * PIC_NSLOT + sl];
+      S.pre[i * PIC_NSLOT + sl] = run;
+      run += c;
     }
-#pragma unroll
-    for (int sl = 0; sl < PIC_NSLOT; sl++) S.tot[t * PIC_NSLOT + sl] = run[sl];
+    S.tot[t * PIC_NSLOT + sl] = run;
   }
 }
 
@@ -429,8 +425,8 @@ int cap_grid(long n, int per) {
 hipError_t pic_launch_rebin(const StoreDesc* d_stores, int nstores, int max_items, int total_tiles,
                             int total_blocks, int inject_max, hipStream_t st) {
   if (nstores > kMaxGroup || nstores < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(rebin_count, dim3(cap_grid(total_tiles, kBlock)), dim3(kBlock), 0, st, d_stores, nstores,
-                     total_tiles);
+  hipLaunchKernelGGL(rebin_count, dim3(cap_grid((long)total_tiles * PIC_NSLOT, kBlock)), dim3(kBlock), 0, st,
+                     d_stores, nstores, total_tiles);
   hipLaunchKernelGGL(rebin_dest, dim3(total_blocks), dim3(kBlock), 0, st, d_stores, nstores);
   hipLaunchKernelGGL(rebin_fold, dim3(nstores), dim3(kScanBlock), 0, st, d_stores);
   hipLaunchKernelGGL(rebin_offsets, dim3(total_blocks), dim3(kBlock), 0, st, d_stores, nstores);

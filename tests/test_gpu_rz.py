@@ -171,8 +171,51 @@ def test_rz_rejects_unsupported_combinations():
     x = np.array([[0.5, 0.3]])
     sim.load_particles(x, np.zeros((1, 3)), np.array([-0.1]), rqm=-1.0)
     with pytest.raises(pic.PicError):
-        sim.energy()
-    with pytest.raises(pic.PicError):
         sim.load_particles(np.array([[0.5, -0.1]]), np.zeros((1, 3)), np.array([-0.1]), rqm=-1.0)
     with pytest.raises(pic.PicError):
         sim.load_particles(np.array([[0.5, 3.11]]), np.zeros((1, 3)), np.array([-0.1]), rqm=-1.0)
+
+
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_rz_fp64_diagnostics_match_the_oracle(orc, order):
+    """rho with the axis fold and ring volumes, the Gauss residual with the
+    cylindrical divergence, energies with ring volumes and the moments
+    (axial momentum, angular momentum) against the oracle; then the charge
+    residual after one GPU step vanishes (cylindrical continuity) on every
+    row the wall does not touch."""
+    pic = _pic()
+    nz, nr, dz, dr = 24, 20, 0.2, 0.2
+    rng = np.random.default_rng(200 + order)
+    n = nz * 12 * 3
+    x = np.stack([rng.random(n) * nz * dz, rng.random(n) * 12 * dr], 1)  # away from the wall
+    x[: n // 5, 1] = rng.random(n // 5) * 1.2 * dr
+    u = rng.normal(0, 0.2, (n, 3))
+    w = -(x[:, 1] / dr) / 3
+    cfg = pic.Config(ndim=2, nx=(nz, nr), dx=(dz, dr), dt=0.1, shape_order=order, tile=(8, 10), sort_interval=1,
+                     geometry=pic.PIC_GEOM_RZ, ion_density=0.7)
+    sim = pic.Pic(cfg)
+    sim.load_particles(x, u, w, rqm=-1.0)
+    E, B = _rz_fields(nz, nr, 21)
+    sim.load_fields(E, B)
+    g = oracle_grid(orc, cfg)
+    xs, us, ws = sim.state()
+    Eg, Bg = sim.fields()
+    rho_ref = orc.rho(g, xs, ws) + 0.7
+    rho = sim.rho()
+    np.testing.assert_allclose(rho, rho_ref, rtol=0, atol=1e-12 * np.abs(rho_ref).max())
+    G = sim.gauss_residual()
+    G_ref = orc.gauss_residual(g, Eg, rho_ref)
+    np.testing.assert_allclose(G, G_ref, rtol=0, atol=1e-9 * np.abs(G_ref).max())
+    en = sim.energy()
+    fe = orc.field_energy(g, Eg, Bg)
+    pm = orc.particle_moments(g, us, ws, -1.0, x=xs)
+    np.testing.assert_allclose(en[:3], [fe[0], fe[1], pm[0]], rtol=1e-10)
+    mo = sim.momentum()
+    np.testing.assert_allclose(mo, [pm[1], pm[2], pm[3]], rtol=1e-10, atol=1e-12)
+    # continuity after one step, rows 1 .. nr - 4 (the particles stay below row 14)
+    sim.rho_snapshot()
+    r0 = sim.rho()
+    sim.step(1)
+    C = sim.charge_residual().reshape(nr, nz)
+    scale = np.abs(r0 - 0.7).max() / cfg.dt
+    assert np.abs(C[1:nr - 4]).max() <= 1e-6 * scale
