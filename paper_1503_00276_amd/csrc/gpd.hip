@@ -1012,6 +1012,19 @@ size_t pic_gpd_lds_bytes(const GridDesc& g) {
   return ((6 * fn + 1) & ~(size_t)1) * sizeof(float) + 3 * jn * sizeof(unsigned long long);
 }
 
+// LDS the step kstep of a sort cycle needs: its stray bound with the largest
+// base the kernel can read (flag_slack, after a check that did not re-sort),
+// computed with the same float arithmetic as the kernel's.
+size_t pic_gpd_lds_bytes_step(const GridDesc& g, int kstep) {
+  size_t fn = 1, jn = 1;
+  for (int d = 0; d < g.dim; d++) {
+    const int sl = min(g.flag_slack + (int)ceilf((float)kstep * g.vstep[d]), g.slk[d]);
+    fn *= (size_t)(g.tile[d] + 2 * sl + g.fa + g.fb);
+    jn *= (size_t)(g.tile[d] + 2 * sl + g.ja + g.jb);
+  }
+  return ((6 * fn + 1) & ~(size_t)1) * sizeof(float) + 3 * jn * sizeof(unsigned long long);
+}
+
 int pic_gpd_block() { return kBlock; }
 int pic_gpd_max_group() { return kMaxGroup; }
 

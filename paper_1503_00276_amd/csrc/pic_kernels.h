@@ -7,6 +7,8 @@
 
 // fused gather + push + deposit (gpd.hip)
 size_t pic_gpd_lds_bytes(const GridDesc& g);
+// LDS of step kstep of a sort cycle (at most pic_gpd_lds_bytes)
+size_t pic_gpd_lds_bytes_step(const GridDesc& g, int kstep);
 int pic_gpd_block();
 int pic_gpd_max_group();
 // allow the LDS size a group needs (call before launching or capturing);

@@ -67,6 +67,10 @@ struct Group {
   bool window;    // some instance has a moving window
   int mode = 0;   // stores: boundary logic of the fused kernel (0 periodic, 1 moving window, 2 r-z)
   int resident = 1;  // stores: fused-kernel workgroups resident per CU (the grid is one full wave of them)
+  // stores, per step of a sort cycle: the LDS that step stages (its halo
+  // grows with the steps since the check) and the workgroups resident with it
+  std::vector<size_t> lds_k;
+  std::vector<int> res_k;
   bool cyl = false, cart = false;  // instances: some are r-z / some are Cartesian
 };
 
@@ -419,6 +423,17 @@ pic_status refresh_descriptors(Sim& S) {
         if (gr.count > pic_gpd_max_group()) return S.fail(PIC_E_INVALID, "too many stores in one group");
         HIPCHK(S, pic_gpd_prepare(dim, order, gr.mode, gr.lds));
         gr.resident = pic_gpd_resident(dim, order, gr.mode, gr.lds);
+        gr.lds_k.assign(std::max(1, S.sort_interval), 0);
+        gr.res_k.assign(gr.lds_k.size(), 1);
+        for (size_t k = 0; k < gr.lds_k.size(); k++) {
+          for (size_t i = 0; i < S.inst.size(); i++) {
+            const Instance& I = S.inst[i];
+            if (I.g.dim != dim || I.g.order != order || kernel_mode(I.g) != mode) continue;
+            gr.lds_k[k] = std::max(gr.lds_k[k], pic_gpd_lds_bytes_step(I.g, (int)k));
+          }
+          gr.lds_k[k] = std::min(gr.lds_k[k], gr.lds);
+          gr.res_k[k] = pic_gpd_resident(dim, order, gr.mode, gr.lds_k[k]);
+        }
         S.sgroups.push_back(gr);
       }
     }
@@ -573,9 +588,13 @@ pic_status launch_steps(Sim& S, int64_t first, int nsteps, bool end_with_check, 
     for (size_t q = 0; q < S.sgroups.size(); q++) {
       const Group& gr = S.sgroups[q];
       // one full wave of resident workgroups: a partial second wave would
-      // leave the kernel's tail to a fraction of the chip
-      int grid = std::max(1, std::min(gr.max_items, S.num_cu * gr.resident));
-      HIPCHK(S, pic_launch_gpd(gr.dim, gr.order, gr.mode, S.d_stores + gr.first, gr.count, grid, gr.lds, par,
+      // leave the kernel's tail to a fraction of the chip.  The step's LDS
+      // (and with it the workgroups per CU) follows its halo.
+      const int kk = std::min<int>(phase0 + k, (int)gr.lds_k.size() - 1);
+      const size_t lds = gr.lds_k.empty() ? gr.lds : gr.lds_k[kk];
+      const int res = gr.res_k.empty() ? gr.resident : gr.res_k[kk];
+      int grid = std::max(1, std::min(gr.max_items, S.num_cu * res));
+      HIPCHK(S, pic_launch_gpd(gr.dim, gr.order, gr.mode, S.d_stores + gr.first, gr.count, grid, lds, par,
                                phase0 + k, S.stream, q == 0 ? p0 : nullptr,
                                q + 1 == S.sgroups.size() ? p1 : nullptr));
     }
