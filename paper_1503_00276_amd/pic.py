@@ -435,8 +435,13 @@ class PicBatch(_Base):
         return out[:count]
 
     def state(self, inst: int):
-        n = self._np[inst]
-        d = self.cfgs[inst].ndim
+        cfg = self.cfgs[inst]
+        if cfg.move_window or cfg.geometry == PIC_GEOM_RZ:
+            self.sync()  # the window or the r-z wall changed the count
+            n = int(sum(self.info(inst).nparticles))
+        else:
+            n = self._np[inst]
+        d = cfg.ndim
         a = self.diag(inst, PIC_DIAG_EXPORT_STATE, n * (d + 4)).reshape(n, d + 4)
         return a[:, :d].copy(), a[:, d:d + 3].copy(), a[:, d + 3].copy()
 

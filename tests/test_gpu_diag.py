@@ -205,3 +205,51 @@ def test_nonfinite_and_capacity_errors():
     with pytest.raises(pic.PicError):
         sim.charge_residual()  # no snapshot yet
     sim.close()
+
+
+def test_mixed_batch_equals_plain_bitwise():
+    """A batch mixing the boundary kinds -- periodic 2D, a moving window, the
+    r-z geometry and periodic 3D -- runs each with its own fused-kernel and
+    field-solve variant in one step, bitwise like each run alone (int64
+    current fold), removals and injections included."""
+    pic = _pic()
+    cfgs = [
+        pic.Config(ndim=2, nx=(32, 16), dx=(0.2, 0.25), dt=0.1, shape_order=2, tile=(8, 8), sort_interval=1,
+                   accumulator=pic.PIC_ACC_FIXED64),
+        pic.Config(ndim=2, nx=(24, 16), dx=(0.2, 0.2), dt=0.1, shape_order=2, tile=(8, 8), sort_interval=1,
+                   accumulator=pic.PIC_ACC_FIXED64, move_window=1, inject_ppc=(2, 2, 1), inject_w=-0.25),
+        pic.Config(ndim=2, nx=(24, 16), dx=(0.2, 0.2), dt=0.1, shape_order=2, tile=(8, 8), sort_interval=1,
+                   accumulator=pic.PIC_ACC_FIXED64, geometry=pic.PIC_GEOM_RZ),
+        pic.Config(ndim=3, nx=(8, 8, 8), dx=(0.2, 0.2, 0.2), dt=0.08, shape_order=1, tile=(4, 4, 4),
+                   sort_interval=1, accumulator=pic.PIC_ACC_FIXED64),
+    ]
+    parts = []
+    for k, cfg in enumerate(cfgs):
+        nx = cfg.nx[:cfg.ndim]
+        x, u, w = _thermal(cfg.ndim, nx, cfg.dx[:cfg.ndim], 3, 0.3, 70 + k)
+        if cfg.geometry == pic.PIC_GEOM_RZ:
+            x[:, 1] = np.minimum(x[:, 1], (nx[1] - 0.5) * cfg.dx[1] - 1e-3)  # inside the wall
+            u[:8, 1] = 3.0  # some reach the wall
+            x[:8, 1] = (nx[1] - 0.7) * cfg.dx[1]
+            w = -(x[:, 1] / cfg.dx[1]) / 3
+        parts.append((x, u, w))
+    batch = pic.PicBatch(cfgs)
+    for k, (x, u, w) in enumerate(parts):
+        batch.load_particles(k, x, u, w, rqm=-1.0)
+    batch.step(7)
+    for k, cfg in enumerate(cfgs):
+        sim = pic.Pic(cfg)
+        sim.load_particles(*parts[k], rqm=-1.0)
+        sim.step(7)
+        xb, ub, wb = batch.state(k)
+        xs, us, ws = sim.state()
+        assert xb.shape == xs.shape, (k, xb.shape, xs.shape)
+        assert np.array_equal(xb, xs) and np.array_equal(ub, us) and np.array_equal(wb, ws), k
+        assert np.array_equal(batch.current(k), sim.current()), k
+        Eb, Bb = batch.fields(k)
+        Es, Bs = sim.fields()
+        assert np.array_equal(Eb, Es) and np.array_equal(Bb, Bs), k
+        if k == 2:
+            assert len(xs) < len(parts[k][2])  # the wall removed some
+        sim.close()
+    batch.close()
