@@ -354,6 +354,58 @@ __device__ __forceinline__ int wrap_fast(int v, int n) { return (unsigned)v < (u
 // one work item
 // ---------------------------------------------------------------------------
 
+// One axis of the 3D current in Esirkepov's closed form, split into the core
+// of the old support (K = ORDER+1 nodes from window position p0) and the one
+// node (S-type: old shape S, change D) or face (P-type: the prefix current P
+// along the axis) outside it, which is nonzero only when the support widened.
+template <int K>
+struct DepAxis {
+  float S[K], D[K];
+  float P[K - 1];
+  float Se, De, Pe;
+  int oS, oP;  // node offsets of the extras from the core origin
+  bool wide;
+};
+
+// Component A of the current (flow along axis A; B, C the other axes) on one
+// block of nodes: core or extra along each axis (EA, EB, EC).  The value is
+// P_A * (S_B S_C + (D_B S_C + S_B D_C)/2 + D_B D_C/3).
+template <int K, int A, bool EA, bool EB, bool EC>
+__device__ __forceinline__ void dep3_part(acc_t* J, int cb, const int st[3], const DepAxis<K> (&ax)[3]) {
+  constexpr int B = (A + 1) % 3, C = (A + 2) % 3;
+  constexpr int NA = EA ? 1 : K - 1, NB = EB ? 1 : K, NC = EC ? 1 : K;
+#pragma unroll
+  for (int kc = 0; kc < NC; kc++) {
+    const float sc = EC ? ax[C].Se : ax[C].S[kc], dc = EC ? ax[C].De : ax[C].D[kc];
+    const int oc = (EC ? ax[C].oS : kc) * st[C];
+#pragma unroll
+    for (int kb = 0; kb < NB; kb++) {
+      const float sb = EB ? ax[B].Se : ax[B].S[kb], db = EB ? ax[B].De : ax[B].D[kb];
+      const float T = sb * sc + 0.5f * (db * sc + sb * dc) + (1.0f / 3.0f) * db * dc;
+      const int ob = cb + oc + (EB ? ax[B].oS : kb) * st[B];
+#pragma unroll
+      for (int ka = 0; ka < NA; ka++) {
+        const float pa = EA ? ax[A].Pe : ax[A].P[ka];
+        lds_add_any(J + ob + (EA ? ax[A].oP : ka) * st[A], pa * T);
+      }
+    }
+  }
+}
+
+template <int K, int A>
+__device__ __forceinline__ void dep3_comp(acc_t* J, int cb, const int st[3], const DepAxis<K> (&ax)[3]) {
+  constexpr int B = (A + 1) % 3, C = (A + 2) % 3;
+  const bool wa = ax[A].wide, wb = ax[B].wide, wc = ax[C].wide;
+  dep3_part<K, A, false, false, false>(J, cb, st, ax);
+  if (wa) dep3_part<K, A, true, false, false>(J, cb, st, ax);
+  if (wb) dep3_part<K, A, false, true, false>(J, cb, st, ax);
+  if (wc) dep3_part<K, A, false, false, true>(J, cb, st, ax);
+  if (wa && wb) dep3_part<K, A, true, true, false>(J, cb, st, ax);
+  if (wa && wc) dep3_part<K, A, true, false, true>(J, cb, st, ax);
+  if (wb && wc) dep3_part<K, A, false, true, true>(J, cb, st, ax);
+  if (wa && wb && wc) dep3_part<K, A, true, true, true>(J, cb, st, ax);
+}
+
 // MODE selects the boundary logic compiled into the kernel: 0 periodic,
 // 1 moving window along x1 (a launch whose stores include a moving window),
 // 2 the 2D r-z geometry (x1 = z, x2 = r).  Without it the code is absent.
@@ -760,59 +812,49 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
           lds_add_any(J2 + cb + eyp + exS, Pye * X2e);
         }
       } else {
-        int jz = jlo[2] + l[2] + wb[2];
-        float q3 = -wq * g.cdt[2] * js;
-        float P3[W - 1];
-        {
-          float a = 0.0f;
+        // 3D: per axis the core of ORDER+1 nodes of the old support plus one
+        // extra node (or face) that only a widened support reaches, as in 2D;
+        // core adds are unconditional, each extra block is one branch.  A
+        // particle that did not move deposits nothing.
+        const bool moved = mv[0] != 0 || mv[1] != 0 || mv[2] != 0 || en[0] != e[0] || en[1] != e[1] ||
+                           en[2] != e[2];
+        if (moved) {
+          int jz = jlo[2] + l[2] + wb[2];
+          float q3 = -wq * g.cdt[2] * js;
+          float P3[W - 1];
+          {
+            float a = 0.0f;
   #pragma unroll
-          for (int k = 0; k < W - 1; k++) {
-            a += D[2][k];
-            P3[k] = q3 * a;
+            for (int k = 0; k < W - 1; k++) {
+              a += D[2][k];
+              P3[k] = q3 * a;
+            }
           }
-        }
-        const float th = 1.0f / 3.0f;
-        // J1: P1[i] * T1[k][j]
+          constexpr int K = ORDER + 1;
+          DepAxis<K> ax[3];
+          const float* Pw[3] = {P1, P2, P3};
   #pragma unroll
-        for (int k = 0; k < W; k++) {
+          for (int d = 0; d < 3; d++) {
+            const bool pd = p0[d] != 0;
   #pragma unroll
-          for (int j = 0; j < W; j++) {
-            float T = S0[1][j] * S0[2][k] + 0.5f * (D[1][j] * S0[2][k] + S0[1][j] * D[2][k]) +
-                      th * D[1][j] * D[2][k];
-            acc_t* r = J1 + ((jz + k) * JR[1] + (jy + j)) * JR[0] + jx;
+            for (int k = 0; k < K; k++) {
+              ax[d].S[k] = pd ? S0[d][k + 1] : S0[d][k];
+              ax[d].D[k] = pd ? D[d][k + 1] : D[d][k];
+            }
   #pragma unroll
-            for (int i = 0; i < W - 1; i++) lds_add(r + i, P1[i] * T);
+            for (int k = 0; k < K - 1; k++) ax[d].P[k] = pd ? Pw[d][k + 1] : Pw[d][k];
+            ax[d].Se = pd ? S0[d][0] : S0[d][K];
+            ax[d].De = pd ? D[d][0] : D[d][K];
+            ax[d].Pe = wide[d] ? (pd ? Pw[d][0] : Pw[d][K - 1]) : 0.0f;
+            ax[d].oS = pd ? -1 : K;
+            ax[d].oP = pd ? -1 : K - 1;
+            ax[d].wide = wide[d];
           }
-        }
-        // J2: P2[j] * T2[k][i]
-  #pragma unroll
-        for (int k = 0; k < W; k++) {
-          float Tk[W];
-  #pragma unroll
-          for (int i = 0; i < W; i++)
-            Tk[i] = S0[0][i] * S0[2][k] + 0.5f * (D[0][i] * S0[2][k] + S0[0][i] * D[2][k]) +
-                    th * D[0][i] * D[2][k];
-  #pragma unroll
-          for (int j = 0; j < W - 1; j++) {
-            acc_t* r = J2 + ((jz + k) * JR[1] + (jy + j)) * JR[0] + jx;
-  #pragma unroll
-            for (int i = 0; i < W; i++) lds_add(r + i, P2[j] * Tk[i]);
-          }
-        }
-        // J3: P3[k] * T3[j][i]
-  #pragma unroll
-        for (int j = 0; j < W; j++) {
-          float Tj[W];
-  #pragma unroll
-          for (int i = 0; i < W; i++)
-            Tj[i] = S0[0][i] * S0[1][j] + 0.5f * (D[0][i] * S0[1][j] + S0[0][i] * D[1][j]) +
-                    th * D[0][i] * D[1][j];
-  #pragma unroll
-          for (int k = 0; k < W - 1; k++) {
-            acc_t* r = J3 + ((jz + k) * JR[1] + (jy + j)) * JR[0] + jx;
-  #pragma unroll
-            for (int i = 0; i < W; i++) lds_add(r + i, P3[k] * Tj[i]);
-          }
+          const int st[3] = {1, JR[0], JR[0] * JR[1]};
+          const int cb = ((jz + p0[2]) * JR[1] + (jy + p0[1])) * JR[0] + jx + p0[0];
+          dep3_comp<K, 0>(J1, cb, st, ax);
+          dep3_comp<K, 1>(J2, cb, st, ax);
+          dep3_comp<K, 2>(J3, cb, st, ax);
         }
       }
 
