@@ -90,8 +90,8 @@ class Grid:
         g.deposit = int(self.deposit)
         g.window = int(self.window)
         if self.cyl:
-            if self.dim != 2 or self.window or any(len(p) for p in self.smooth):
-                raise ValueError("the r-z geometry is 2D, without moving window or smoothing")
+            if self.dim != 2 or any(len(p) for p in self.smooth):
+                raise ValueError("the r-z geometry is 2D, without smoothing")
             if float(xm[1]) != 0.0:
                 raise ValueError("in r-z the second coordinate is the radius (xmin[1] = 0)")
         g.cyl = int(self.cyl)
@@ -286,12 +286,19 @@ def step_window(g: Grid, n: int, x, u, w, qm, E, B) -> StepResult:
          weight inject_w, cells in increasing linear index, lattice points
          with axis 1 fastest.
     Returns x, u, w of the survivors (in input order) followed by the
-    injected particles, E, B, J, and 'keep', the survivors' input indices."""
+    injected particles, E, B, J, and 'keep', the survivors' input indices.
+    In the r-z geometry (x = (z, r)) particles that reach the wall are
+    removed too, and the injected lattice is the same in cell coordinates
+    without its points below the axis (cell coordinate < 1/2), each with
+    weight inject_w * r / dr (a uniform density)."""
     assert g.window == 1
     r = step(g, x, u, w, qm, E, B)
     w = _f64(np.broadcast_to(w, (len(r.x),))).copy()
     L1 = g.nx[0] * g.dx[0]
-    keep = np.nonzero((r.x[:, 0] >= 0.0) & (r.x[:, 0] < L1))[0]
+    inside = (r.x[:, 0] >= 0.0) & (r.x[:, 0] < L1)
+    if g.cyl:
+        inside &= r.x[:, 1] < cyl_wall(g)
+    keep = np.nonzero(inside)[0]
     x1, u1, w1 = r.x[keep], r.u[keep], w[keep]
     E1, B1, J1 = r.E, r.B, r.J
     if window_shifts(g, n + 1) > window_shifts(g, n):
@@ -327,9 +334,16 @@ def step_window(g: Grid, n: int, x, u, w, qm, E, B) -> StepResult:
                 for j in range(g.nx[1]):
                     cells.append((g.nx[0] - 1, j, k))
         newx = np.concatenate([(np.asarray(c, dtype=float) + offs) * np.asarray(g.dx[:d]) for c in cells])
+        neww = np.full(len(newx), float(g.inject_w))
+        if g.cyl:
+            # cell coordinate r/dr + 1/2: drop the points below the axis
+            newx[:, 1] -= 0.5 * g.dx[1]
+            ok = newx[:, 1] >= 0.0
+            newx = newx[ok]
+            neww = float(g.inject_w) * newx[:, 1] / g.dx[1]
         x1 = np.concatenate([x1, newx])
         u1 = np.concatenate([u1, np.zeros((len(newx), 3))])
-        w1 = np.concatenate([w1, np.full(len(newx), float(g.inject_w))])
+        w1 = np.concatenate([w1, neww])
     return StepResult(x=x1, u=u1, E=E1, B=B1, J=J1), w1, keep
 
 

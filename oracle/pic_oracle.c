@@ -44,7 +44,8 @@
  *
  * 2D cylindrically symmetric geometry (cyl = 1, Sec. 3.3, Eqs.
  * 2d-field-solve-cyl, 2d-field-solve-cyl-b1-axis, 2d-cyl-position-update-*):
- *   - x1 = z (periodic), x2 = r; E1 E2 E3 = E_z E_r E_theta, B likewise,
+ *   - x1 = z (periodic, or a moving window), x2 = r; E1 E2 E3 = E_z E_r
+ *     E_theta, B likewise,
  *     J likewise; u = (u_z, u_r, u_theta) in the particle's local frame;
  *   - the axis runs through the middle of the first cell: the rows of the
  *     components on whole r-nodes (E_z, E_theta, B_r, J_z, J_theta, rho) sit
@@ -199,7 +200,7 @@ static double gather_one(const orc_grid* g, const double* F, const double xi[3],
         if (g->cyl) {
           double sg;
           int64_t row = cyl_src(g, stagger(kind, comp, 1) != 0.0, comp == 0, i1, &sg);
-          if (row >= 0) sum += s0 * s1 * sg * F[cidx(g, i0, row, 0)];
+          if (row >= 0) sum += s0 * s1 * sg * at(F, cidx(g, i0, row, 0));
           continue;
         }
         sum += s0 * s1 * s2 * at(F, cidx(g, i0, i1, i2));
@@ -583,6 +584,18 @@ void orc_yee_e(const orc_grid* g, double* E, const double* B, const double* J, d
 /* r-z Faraday half step B <- B - tau curl E (Sec. 3.3, Eqs. 2d-field-solve-cyl
  * and 2d-field-solve-cyl-b1-axis); rows as described at the top.  E rows at
  * and beyond the wall are zero. */
+/* r-z: value of row j at z column i + di (di = -1 or +1): periodic, or zero
+ * beyond the ends of a moving window */
+static double zn(const orc_grid* g, const double* F, int j, int i, int di) {
+  int nz = g->nx[0];
+  int k = i + di;
+  if (k < 0 || k >= nz) {
+    if (g->window) return 0.0;
+    k = k < 0 ? k + nz : k - nz;
+  }
+  return F[(int64_t)j * nz + k];
+}
+
 void orc_yee_b_cyl(const orc_grid* g, const double* E, double* B, double tau) {
   int64_t nc = ncells(g);
   int nz = g->nx[0], nr = g->nx[1];
@@ -592,14 +605,13 @@ void orc_yee_b_cyl(const orc_grid* g, const double* E, double* B, double tau) {
 #define RZ(j, i) ((int64_t)(j) * nz + (i))
   for (int j = 0; j < nr; j++)
     for (int i = 0; i < nz; i++) {
-      int ip = i + 1 == nz ? 0 : i + 1;
       double et_up = j + 1 < nr ? Et[RZ(j + 1, i)] : 0.0;  /* E_theta at the whole row above half row j */
       double ez_up = j + 1 < nr ? Ez[RZ(j + 1, i)] : 0.0;
       /* B_r on whole row j >= 1: (curl E)_r = -dE_theta/dz */
-      if (j >= 1) Br[RZ(j, i)] -= tau * (-(Et[RZ(j, ip)] - Et[RZ(j, i)]) / dz);
+      if (j >= 1) Br[RZ(j, i)] -= tau * (-(zn(g, Et, j, i, 1) - Et[RZ(j, i)]) / dz);
       /* B_theta on half row j: (curl E)_theta = dE_r/dz - dE_z/dr (zero on the axis) */
       if (j >= 1)
-        Bt[RZ(j, i)] -= tau * ((Er[RZ(j, ip)] - Er[RZ(j, i)]) / dz - (ez_up - Ez[RZ(j, i)]) / dr);
+        Bt[RZ(j, i)] -= tau * ((zn(g, Er, j, i, 1) - Er[RZ(j, i)]) / dz - (ez_up - Ez[RZ(j, i)]) / dr);
       else
         Bt[RZ(j, i)] = 0.0;
       /* B_z on half row j: (1/r) d(r E_theta)/dr; on the axis Faraday's law
@@ -622,11 +634,10 @@ void orc_yee_e_cyl(const orc_grid* g, double* E, const double* B, const double* 
   const double *Jz = J, *Jr = J + nc, *Jt = J + 2 * nc;
   for (int j = 1; j < nr; j++)
     for (int i = 0; i < nz; i++) {
-      int im = i == 0 ? nz - 1 : i - 1;
       /* E_r on half row j: (curl B)_r = -dB_theta/dz */
-      Er[RZ(j, i)] += dt * (-(Bt[RZ(j, i)] - Bt[RZ(j, im)]) / dz - Jr[RZ(j, i)]);
+      Er[RZ(j, i)] += dt * (-(Bt[RZ(j, i)] - zn(g, Bt, j, i, -1)) / dz - Jr[RZ(j, i)]);
       /* E_theta on whole row j: (curl B)_theta = dB_r/dz - dB_z/dr */
-      Et[RZ(j, i)] += dt * ((Br[RZ(j, i)] - Br[RZ(j, im)]) / dz - (Bz[RZ(j, i)] - Bz[RZ(j - 1, i)]) / dr -
+      Et[RZ(j, i)] += dt * ((Br[RZ(j, i)] - zn(g, Br, j, i, -1)) / dz - (Bz[RZ(j, i)] - Bz[RZ(j - 1, i)]) / dr -
                             Jt[RZ(j, i)]);
       /* E_z on whole row j (radius (j - 1/2) dr): (1/r) d(r B_theta)/dr with
        * B_theta on the half rows j (radius j dr) and j - 1 */
@@ -739,8 +750,7 @@ static void cyl_div(const orc_grid* g, const double* V, double* D) {
   int nz = g->nx[0], nr = g->nx[1];
   for (int j = 1; j < nr; j++)
     for (int i = 0; i < nz; i++) {
-      int im = i == 0 ? nz - 1 : i - 1;
-      D[RZ(j, i)] = (V[RZ(j, i)] - V[RZ(j, im)]) / g->dx[0] +
+      D[RZ(j, i)] = (V[RZ(j, i)] - zn(g, V, j, i, -1)) / g->dx[0] +
                     (j * V[nc + RZ(j, i)] - (j - 1) * V[nc + RZ(j - 1, i)]) / ((j - 0.5) * g->dx[1]);
     }
   for (int i = 0; i < nz; i++) D[RZ(0, i)] = D[RZ(1, i)];

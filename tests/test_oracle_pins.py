@@ -1124,3 +1124,106 @@ def test_cyl_step_removes_particles_at_the_wall(orc):
     B = np.zeros((3, g.ncell))
     r, w, keep = orc.step_cyl(g, x, u, np.array([-0.1, -0.1]), -1.0, E, B)
     assert list(keep) == [1] and abs(r.x[0, 1] - 0.4) < 1e-15
+
+
+def _cyl_lattice(nz, nr, ppc, dz, dr, inject_w):
+    """The injection lattice of an r-z window over the whole box: cell
+    coordinates (i + (k+1/2)/ppc) without the points below the axis, weight
+    inject_w * r / dr."""
+    zz, rr = np.meshgrid((np.arange(nz * ppc[0]) + 0.5) / ppc[0], (np.arange(nr * ppc[1]) + 0.5) / ppc[1],
+                         indexing="ij")
+    x = np.stack([zz.ravel() * dz, (rr.ravel() - 0.5) * dr], 1)
+    x = x[(x[:, 1] >= 0.0) & (x[:, 1] < (nr - 0.5) * dr)]
+    return x, inject_w * x[:, 1] / dr
+
+
+@pytest.mark.parametrize("ppc_r", [1, 2, 3])
+def test_cyl_window_keeps_a_resting_plasma_fixed_in_the_lab(orc, ppc_r):
+    """r-z with a moving window: a resting cold ring plasma with weights
+    proportional to the radius (uniform density) stays on its lab lattice
+    over 40 steps and 29 shifts; each new front column brings exactly the
+    rings the back column took away, and no field or current appears."""
+    nz, nr, dz, dr, dt = 12, 6, 0.2, 0.25, 0.15
+    ppc = (2, ppc_r)
+    g = orc.Grid(dim=2, nx=(nz, nr), dx=(dz, dr), dt=dt, order=2, window=1, inject_ppc=ppc, inject_w=-0.3, cyl=1)
+    x, w = _cyl_lattice(nz, nr, ppc, dz, dr, -0.3)
+    u = np.zeros((len(x), 3))
+    E = np.zeros((3, g.ncell))
+    B = np.zeros((3, g.ncell))
+    n0 = len(x)
+    for n in range(40):
+        r, w, keep = orc.step_window(g, n, x, u, w, -1.0, E, B)
+        x, u, E, B = r.x, r.u, r.E, r.B
+        assert len(x) == n0
+        assert np.abs(E).max() == 0 and np.abs(B).max() == 0 and np.abs(r.J).max() == 0
+    s = orc.window_shifts(g, 40)
+    assert s == int(np.floor(40 * (dt / dz))) and s >= 29
+    lab = x.copy()
+    lab[:, 0] += s * dz
+    k0 = lab[:, 0] / (dz / ppc[0]) - 0.5
+    assert np.abs(k0 - np.round(k0)).max() < 1e-9
+    np.testing.assert_allclose(w, -0.3 * x[:, 1] / dr, rtol=1e-15)
+    # the same set of rings as the lattice of the moved window
+    ref, _ = _cyl_lattice(nz, nr, ppc, dz, dr, -0.3)
+    key = lambda a: sorted(map(tuple, np.round(a / np.array([dz / ppc[0], dr / (2 * ppc[1])]) * 4).astype(int)))
+    assert key(x) == key(ref)
+
+
+def test_cyl_window_conserves_charge_inside(orc):
+    """r-z with a window: the step's current satisfies the cylindrical
+    continuity equation on every row and column away from the window's ends
+    and the wall, with particles crossing the axis region."""
+    nz, nr = 14, 10
+    g = orc.Grid(dim=2, nx=(nz, nr), dx=(0.2, 0.2), dt=0.1, order=2, window=1, inject_ppc=(1, 1), cyl=1)
+    rng = np.random.default_rng(5)
+    n = 200
+    x = np.stack([(3 + rng.random(n) * 8) * 0.2, rng.random(n) * 6 * 0.2], 1)
+    u = rng.normal(0, 0.5, (n, 3))
+    w = rng.normal(-0.2, 0.05, n)
+    E = np.zeros((3, g.ncell))
+    B = np.zeros((3, g.ncell))
+    assert orc.window_shifts(g, 1) == 0
+    r0 = orc.rho(g, x, w)
+    res, w1, keep = orc.step_window(g, 0, x, u, w, -1.0, E, B)
+    assert len(keep) == n
+    r1 = orc.rho(g, res.x, w1)
+    C = orc.charge_residual(g, r0, r1, res.J).reshape(nr, nz)
+    scale = np.abs(r1 - r0).max() / g.dt
+    assert np.abs(C[1:nr - 2, 2:nz - 2]).max() < 1e-12 * scale
+
+
+def test_cyl_window_field_solve_is_the_periodic_one_with_zero_guard_columns(orc):
+    """The r-z field solve of a moving window equals the periodic r-z solve of
+    a box two columns longer whose two extra columns are held at zero (the
+    window's ends are open: nothing beyond them)."""
+    nz, nr = 10, 8
+    gw = orc.Grid(dim=2, nx=(nz, nr), dx=(0.25, 0.2), dt=0.1, order=1, window=1, cyl=1)
+    gp = orc.Grid(dim=2, nx=(nz + 2, nr), dx=(0.25, 0.2), dt=0.1, order=1, cyl=1)
+    rng = np.random.default_rng(17)
+    E, B = _cyl_fields(gw, rng)
+    J = rng.normal(0, 0.05, (3, nr, nz))
+    J[1, 0] = 0.0
+
+    def pad(F):
+        P = np.zeros((3, nr, nz + 2))
+        P[:, :, 1:nz + 1] = F.reshape(3, nr, nz)
+        return P.reshape(3, -1)
+
+    def guard0(F):
+        F = F.reshape(3, nr, nz + 2).copy()
+        F[:, :, 0] = 0.0
+        F[:, :, nz + 1] = 0.0
+        return F.reshape(3, -1)
+
+    Ew, Bw = E.copy(), B.copy()
+    Ep, Bp, Jp = pad(E), pad(B), pad(J.reshape(3, -1))
+    for _ in range(5):
+        Bw = orc.yee_b(gw, Ew, Bw, gw.dt / 2)
+        Ew = orc.yee_e(gw, Ew, Bw, J.reshape(3, -1), gw.dt)
+        Bw = orc.yee_b(gw, Ew, Bw, gw.dt / 2)
+        Bp = guard0(orc.yee_b(gp, Ep, Bp, gp.dt / 2))
+        Ep = guard0(orc.yee_e(gp, Ep, Bp, Jp, gp.dt))
+        Bp = guard0(orc.yee_b(gp, Ep, Bp, gp.dt / 2))
+    np.testing.assert_allclose(Ew.reshape(3, nr, nz), Ep.reshape(3, nr, nz + 2)[:, :, 1:nz + 1], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(Bw.reshape(3, nr, nz), Bp.reshape(3, nr, nz + 2)[:, :, 1:nz + 1], rtol=0, atol=1e-14)
+    assert np.abs(Ew).max() > 0.01
