@@ -152,8 +152,11 @@ typedef struct {
    * the residuals use the cylindrical divergence, ENERGY weighs each value
    * by the volume 2 pi r dr dz of its ring (pi dr^2 dz / 4 for the axis
    * disc), and MOMENTUM is (P_z, sum of the radial momenta, angular momentum
-   * about the axis sum Q r u_theta m/q), with Q = w 2 pi dr^2 dz.  Not
-   * available with a moving window, smoothing or pic_autotune. */
+   * about the axis sum Q r u_theta m/q), with Q = w 2 pi dr^2 dz.  With a
+   * moving window (along z) the injected lattice leaves out its points
+   * below the axis (cell coordinate under 1/2) and an injected ring at
+   * radius r takes weight inject_w r / dr (a uniform density).  Not
+   * available with smoothing or pic_autotune. */
   int32_t geometry;
 } pic_config;
 

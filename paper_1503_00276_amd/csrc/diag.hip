@@ -113,7 +113,8 @@ __device__ __forceinline__ double div_at(const GridDesc& g, const T* V, int nc, 
     const int i = c % g.nx[0];
     const int j = c / g.nx[0];
     const int cxm = (i > 0) ? c - 1 : c + g.nx[0] - 1;
-    return ((double)V[c] - (double)V[cxm]) / g.dxd[0] +
+    const double vxm = (wo >= 0 && i == wo) ? 0.0 : (double)V[cxm];
+    return ((double)V[c] - vxm) / g.dxd[0] +
            ((double)j * (double)V[nc + c] - (double)(j - 1) * (double)V[nc + c - g.nx[0]]) /
                (((double)j - 0.5) * g.dxd[1]);
   }

@@ -261,6 +261,21 @@ __global__ void __launch_bounds__(kBlock) yee_step_rz(const InstDesc* __restrict
   const int e1 = min(T::Y, n1 - o1);
   const int EX = e0 + 3, EY = e1 + 3;
   const int BX = e0 + 2, BY = e1 + 2;
+  // moving window along z: the window column of region column x; the z
+  // neighbours beyond the window's front and back are zero, and the back
+  // column is discarded (becomes the empty front) after a shift
+  const bool win = g.window != 0;
+  int wo = 0;
+  bool wshift = false;
+  if (win) {
+    const WinCtl wc = *I.win;
+    wo = wc.origin;
+    wshift = pic_win_shifts(g.wa, wc.step + 1) > pic_win_shifts(g.wa, wc.step);
+  }
+  auto wcol = [&](int x) {
+    int r = wrap1(o0 - 1 + x, n0) - wo;
+    return r < 0 ? r + n0 : r;
+  };
   // region node (x, y) is column o0 - 1 + x (periodic) and row o1 - 1 + y
   const gfloat* F = (const gfloat*)I.F[par];
   for (int y = ty; y < EY; y += T::Y)
@@ -293,8 +308,9 @@ __global__ void __launch_bounds__(kBlock) yee_step_rz(const InstDesc* __restrict
       const int r = x + BX * y;
       const int c = x + EX * y;
       const int j = o1 - 1 + y;
-      sB[1][r] -= h * (-(sE[2][c + 1] - sE[2][c]) * rz);
-      sB[2][r] -= h * ((sE[1][c + 1] - sE[1][c]) * rz - (sE[0][c + EX] - sE[0][c]) * rr);
+      const bool front = win && wcol(x) == n0 - 1;
+      sB[1][r] -= h * (-((front ? 0.0f : sE[2][c + 1]) - sE[2][c]) * rz);
+      sB[2][r] -= h * (((front ? 0.0f : sE[1][c + 1]) - sE[1][c]) * rz - (sE[0][c + EX] - sE[0][c]) * rr);
       const float cz = j == 0 ? 4.0f * sE[2][c + EX] * rr
                               : ((j + 0.5f) * sE[2][c + EX] - (j - 0.5f) * sE[2][c]) * rr / (float)j;
       sB[0][r] -= h * cz;
@@ -332,14 +348,17 @@ __global__ void __launch_bounds__(kBlock) yee_step_rz(const InstDesc* __restrict
       J1 *= vw;
       J2 *= vh;
       J3 *= vw;
-      sE[1][ce] = j == 0 ? 0.0f : sE[1][ce] + g.dt * (-(sB[2][cb] - sB[2][cb - 1]) * rz - J2);
-      sE[2][ce] += g.dt * ((sB[1][cb] - sB[1][cb - 1]) * rz - (sB[0][cb] - sB[0][cb - BX]) * rr - J3);
+      const bool back = win && wcol(x) == 0;
+      const float bt_m = back ? 0.0f : sB[2][cb - 1], br_m = back ? 0.0f : sB[1][cb - 1];
+      sE[1][ce] = j == 0 ? 0.0f : sE[1][ce] + g.dt * (-(sB[2][cb] - bt_m) * rz - J2);
+      sE[2][ce] += g.dt * ((sB[1][cb] - br_m) * rz - (sB[0][cb] - sB[0][cb - BX]) * rr - J3);
       sE[0][ce] += g.dt * (((float)j * sB[2][cb] - (float)(j - 1) * sB[2][cb - BX]) * rr * vw - J1);
       if (x <= e0 && y <= e1) {
         gfloat* Jo = (gfloat*)I.Jout;
-        Jo[gi] = J1;
-        Jo[nc + gi] = J2;
-        Jo[2 * nc + gi] = J3;
+        const float keep = (back && wshift) ? 0.0f : 1.0f;  // discarded column
+        Jo[gi] = J1 * keep;
+        Jo[nc + gi] = J2 * keep;
+        Jo[2 * nc + gi] = J3 * keep;
         if (g.acc_mode == 2) {
           I.J64[jn][gi] = 0ull;
           I.J64[jn][nc + gi] = 0ull;
@@ -363,15 +382,19 @@ __global__ void __launch_bounds__(kBlock) yee_step_rz(const InstDesc* __restrict
       const int gi = wrap1(o0 - 1 + x, n0) + n0 * j;
       const float cz = j == 0 ? 4.0f * sE[2][c + EX] * rr
                               : ((j + 0.5f) * sE[2][c + EX] - (j - 0.5f) * sE[2][c]) * rr / (float)j;
-      const float br = sB[1][cb] - h * (-(sE[2][c + 1] - sE[2][c]) * rz);
-      const float bt = sB[2][cb] - h * ((sE[1][c + 1] - sE[1][c]) * rz - (sE[0][c + EX] - sE[0][c]) * rr);
+      const int wx = win ? wcol(x) : 1;
+      const bool front = win && wx == n0 - 1;
+      const float br = sB[1][cb] - h * (-((front ? 0.0f : sE[2][c + 1]) - sE[2][c]) * rz);
+      const float bt = sB[2][cb] - h * (((front ? 0.0f : sE[1][c + 1]) - sE[1][c]) * rz - (sE[0][c + EX] - sE[0][c]) * rr);
       const bool in = j >= 1;
-      Fw[gi] = in ? sE[0][c] : 0.0f;
-      Fw[nc + gi] = sE[1][c];
-      Fw[2 * nc + gi] = in ? sE[2][c] : 0.0f;
-      Fw[3 * nc + gi] = sB[0][cb] - h * cz;
-      Fw[4 * nc + gi] = in ? br : 0.0f;
-      Fw[5 * nc + gi] = in ? bt : 0.0f;
+      // the window's back column becomes its empty front after a shift
+      const float keep = (win && wshift && wx == 0) ? 0.0f : 1.0f;
+      Fw[gi] = in ? sE[0][c] * keep : 0.0f;
+      Fw[nc + gi] = sE[1][c] * keep;
+      Fw[2 * nc + gi] = in ? sE[2][c] * keep : 0.0f;
+      Fw[3 * nc + gi] = (sB[0][cb] - h * cz) * keep;
+      Fw[4 * nc + gi] = in ? br * keep : 0.0f;
+      Fw[5 * nc + gi] = in ? bt * keep : 0.0f;
     }
 }
 

@@ -408,7 +408,8 @@ __device__ __forceinline__ void dep3_comp(acc_t* J, int cb, const int st[3], con
 
 // MODE selects the boundary logic compiled into the kernel: 0 periodic,
 // 1 moving window along x1 (a launch whose stores include a moving window),
-// 2 the 2D r-z geometry (x1 = z, x2 = r).  Without it the code is absent.
+// 2 the 2D r-z geometry (x1 = z, x2 = r), 3 both.  Without it the code is
+// absent.
 // kstep: steps done since the last rebin check (0 for the first step of a
 // sort cycle).
 template <int DIM, int ORDER, int MODE>
@@ -416,8 +417,8 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
                              int* scnt) {
   constexpr int NG = ORDER + 1;  // gather taps per axis
   constexpr int W = ORDER + 2;   // deposit window per axis
-  constexpr bool WIN = MODE == 1;
-  constexpr bool RZ = DIM == 2 && MODE == 2;
+  constexpr bool WIN = MODE == 1 || MODE == 3;
+  constexpr bool RZ = DIM == 2 && (MODE == 2 || MODE == 3);
   const GridDesc& g = S.g;
   const int tid = threadIdx.x;
 
@@ -887,7 +888,7 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
     }
     if constexpr (RZ) {
       // r-z: a particle that reached the wall is removed
-      dead = cc[1] + mv[1] >= g.nx[1];
+      dead = dead || cc[1] + mv[1] >= g.nx[1];
       died = died || dead;
     }
     {
@@ -1022,8 +1023,10 @@ void launch_mode(const StoreDesc* stores, int nstores, int grid, size_t lds, int
 template <int DIM, int ORDER>
 hipError_t prepare_one(int mode, size_t lds) {
   if (mode == 1) return prepare_mode<DIM, ORDER, 1>(lds);
-  if constexpr (DIM == 2)
+  if constexpr (DIM == 2) {
     if (mode == 2) return prepare_mode<DIM, ORDER, 2>(lds);
+    if (mode == 3) return prepare_mode<DIM, ORDER, 3>(lds);
+  }
   if (mode == 0) return prepare_mode<DIM, ORDER, 0>(lds);
   return hipErrorInvalidValue;
 }
@@ -1035,10 +1038,14 @@ hipError_t launch_one(int mode, const StoreDesc* stores, int nstores, int grid, 
     launch_mode<DIM, ORDER, 1>(stores, nstores, grid, lds, jp, kstep, st, ev0, ev1);
   else if (mode == 0)
     launch_mode<DIM, ORDER, 0>(stores, nstores, grid, lds, jp, kstep, st, ev0, ev1);
-  else if constexpr (DIM == 2)
-    launch_mode<DIM, ORDER, 2>(stores, nstores, grid, lds, jp, kstep, st, ev0, ev1);
-  else
+  else if constexpr (DIM == 2) {
+    if (mode == 2)
+      launch_mode<DIM, ORDER, 2>(stores, nstores, grid, lds, jp, kstep, st, ev0, ev1);
+    else
+      launch_mode<DIM, ORDER, 3>(stores, nstores, grid, lds, jp, kstep, st, ev0, ev1);
+  } else {
     return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -1087,8 +1094,10 @@ template <int DIM, int ORDER>
 int resident_one(int mode, size_t lds) {
   int n = 0;
   const void* f = mode == 1 ? gpd_entry<DIM, ORDER, 1>() : gpd_entry<DIM, ORDER, 0>();
-  if constexpr (DIM == 2)
+  if constexpr (DIM == 2) {
     if (mode == 2) f = gpd_entry<DIM, ORDER, 2>();
+    if (mode == 3) f = gpd_entry<DIM, ORDER, 3>();
+  }
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kBlock, lds) != hipSuccess) return 1;
   return n < 1 ? 1 : n;
 }

@@ -75,7 +75,7 @@ struct Group {
 };
 
 // Boundary logic an instance's stores need in the fused particle kernel.
-int kernel_mode(const GridDesc& g) { return g.window ? 1 : (g.cyl ? 2 : 0); }
+int kernel_mode(const GridDesc& g) { return g.window ? (g.cyl ? 3 : 1) : (g.cyl ? 2 : 0); }
 
 struct Sim {
   int num_cu = kNumCU;  // compute units of the device
@@ -277,7 +277,6 @@ pic_status validate(Sim& S, const pic_config& c) {
     return S.fail(PIC_E_INVALID, "unknown geometry %d", c.geometry);
   if (c.geometry == PIC_GEOM_RZ) {
     if (c.ndim != 2) return S.fail(PIC_E_INVALID, "the r-z geometry is two-dimensional");
-    if (c.move_window) return S.fail(PIC_E_UNSUPPORTED, "the r-z geometry has no moving window");
     if (c.smooth_level[0] || c.smooth_level[1]) return S.fail(PIC_E_UNSUPPORTED, "the r-z geometry has no smoothing");
     if (c.xmin[1] != 0.0) return S.fail(PIC_E_INVALID, "in r-z x2 is the radius: xmin[1] must be 0");
     if (c.nx[1] < 2) return S.fail(PIC_E_INVALID, "the r-z geometry needs at least 2 rows");
@@ -394,7 +393,7 @@ pic_status refresh_descriptors(Sim& S) {
   S.igroups.clear();
   for (int dim = 2; dim <= 3; dim++)
     for (int order = 1; order <= 3; order++)
-      for (int mode = 0; mode <= 2; mode++) {
+      for (int mode = 0; mode <= 3; mode++) {
       Group gr{dim, order, (int)stores.size(), 0, 0, 0, 0, 0, 0, false, {0, 0, 0}, 0, false};
       gr.mode = mode;
       for (size_t i = 0; i < S.inst.size(); i++) {
@@ -982,7 +981,9 @@ pic_status sim_load(Sim& S, int inst, int32_t species, double rqm, int64_t n, co
   if (win && species == 0) {
     for (int a = 0; a < 3; a++) sp.desc.inj_ppc[a] = a < dim ? I.cfg.inject_ppc[a] : 1;
     sp.desc.inj_w = (float)I.cfg.inject_w;
-    I.wmax[0] = std::max(I.wmax[0], std::fabs(I.cfg.inject_w));
+    // r-z: injected weights grow with the radius, up to (nr - 1/2) inject_w
+    const double wi = std::fabs(I.cfg.inject_w) * (rz ? (double)I.g.nx[1] - 0.5 : 1.0);
+    I.wmax[0] = std::max(I.wmax[0], wi);
   }
   set_current_scale(I);
   if (win) {
@@ -1227,17 +1228,17 @@ pic_status sim_diag(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_byt
             const double* r = rows.data() + (size_t)order[q] * stride;
             double* dst = o + q * stride;
             for (int c = 0; c < stride; c++) dst[c] = r[c];
-            if (g.cyl) {
+            if (I.cfg.move_window) {
+              const double v = r[0];
+              const double cr = std::floor(v);
+              int wcol = (int)cr - wc.origin;
+              if (wcol < 0) wcol += g.nx[0];
+              dst[0] = I.cfg.xmin[0] + ((double)wc.shifts + (double)wcol + (v - cr)) * I.cfg.dx[0];
+            } else {
               dst[0] = I.cfg.xmin[0] + r[0] * I.cfg.dx[0];
-              dst[1] = (r[1] - 0.5) * I.cfg.dx[1];
-              continue;
             }
-            const double v = r[0];
-            const double cr = std::floor(v);
-            int wcol = (int)cr - wc.origin;
-            if (wcol < 0) wcol += g.nx[0];
-            dst[0] = I.cfg.xmin[0] + ((double)wc.shifts + (double)wcol + (v - cr)) * I.cfg.dx[0];
             for (int d = 1; d < g.dim; d++) dst[d] = I.cfg.xmin[d] + r[d] * I.cfg.dx[d];
+            if (g.cyl) dst[1] = (r[1] - 0.5) * I.cfg.dx[1];  // r-z: the radius
           }
         } else {
           HIPCHK(S, pic_launch_export_state(S.d_stores + k, (int)sp.np, dbuf, nullptr, S.stream));

@@ -62,7 +62,10 @@ __device__ __forceinline__ int win_inject_count(const StoreDesc& S, int d) {
   if (o < org0 || o >= org0 + min(g.tile[0], g.nx[0] - org0)) return 0;
   int cells = 1;
   for (int k = 1; k < g.dim; k++) cells *= min(g.tile[k], g.nx[k] - tc[k] * g.tile[k]);
-  return cells * S.inj_ppc[0] * S.inj_ppc[1] * S.inj_ppc[2];
+  int n = cells * S.inj_ppc[0] * S.inj_ppc[1] * S.inj_ppc[2];
+  // r-z: the lattice points of the axis row below the axis are not injected
+  if (g.cyl && tc[1] == 0) n -= S.inj_ppc[0] * (S.inj_ppc[1] / 2);
+  return n;
 }
 
 // Slot of a particle with packed cell 'cell' that is stored in tile t
@@ -388,15 +391,19 @@ __global__ void __launch_bounds__(kBlock) rebin_inject(const StoreDesc* __restri
   const int total = ppc * ny * nz;
   const int o = S.win->origin;
   const long long id0 = S.win->next_id;
+  // r-z: lattice points below the axis (axis-row offsets under 1/2) are
+  // skipped; the others of the tile holding the axis row move up in rank
+  const int nex = g.cyl ? p1 / 2 : 0;
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < total; k += gridDim.x * blockDim.x) {
     const int cidx = k / ppc, li = k - cidx * ppc;
     const int cy = cidx % ny, cz = cidx / ny;
     const int l0 = li % p0, l1 = (li / p0) % p1, l2 = li / (p0 * p1);
+    if (cy == 0 && l1 < nex) continue;
     const int ty = cy / g.tile[1], tz = g.dim == 3 ? cz / g.tile[2] : 0;
     const int t = pic_tile_index(g, o / g.tile[0], ty, tz);
     const int oy = ty * g.tile[1], oz = tz * g.tile[2];
     const int ey = min(g.tile[1], ny - oy);
-    const int rank = ((cy - oy) + ey * (cz - oz)) * ppc + li;
+    const int rank = ((cy - oy) + ey * (cz - oz)) * ppc + li - (oy == 0 ? p0 * nex : 0);
     const int pos = S.toff[nxt][t] + S.dcount[t] - win_inject_count(S, t) + rank;
     if (pos < 0 || pos >= S.cap) {
       atomicOr(&S.ctl->bad, 2);
@@ -409,7 +416,8 @@ __global__ void __launch_bounds__(kBlock) rebin_inject(const StoreDesc* __restri
     S.u[nxt][0][pos] = 0.0f;
     S.u[nxt][1][pos] = 0.0f;
     S.u[nxt][2][pos] = 0.0f;
-    S.w[nxt][pos] = S.inj_w;
+    // r-z: a uniform density takes a weight proportional to the radius
+    S.w[nxt][pos] = g.cyl ? S.inj_w * ((float)cy + ((float)l1 + 0.5f) / (float)p1 - 0.5f) : S.inj_w;
     S.id[nxt][pos] = (int)(id0 + k);
   }
 }

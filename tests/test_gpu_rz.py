@@ -163,8 +163,7 @@ def test_rz_free_rings_follow_their_3d_lines():
 def test_rz_rejects_unsupported_combinations():
     pic = _pic()
     base = dict(ndim=2, nx=(16, 16), dx=(0.2, 0.2), dt=0.1, shape_order=1, tile=(8, 8), geometry=pic.PIC_GEOM_RZ)
-    for extra in ({"move_window": 1, "inject_ppc": (1, 1, 1)}, {"smooth": (((1, 2, 1),), ())},
-                  {"xmin": (0.0, 1.0, 0.0)}, {"sort_interval": 2}):
+    for extra in ({"smooth": (((1, 2, 1),), ())}, {"xmin": (0.0, 1.0, 0.0)}, {"sort_interval": 2}):
         with pytest.raises(pic.PicError):
             pic.Pic(pic.Config(**{**base, **extra}))
     sim = pic.Pic(pic.Config(**base))
@@ -219,3 +218,35 @@ def test_rz_fp64_diagnostics_match_the_oracle(orc, order):
     C = sim.charge_residual().reshape(nr, nz)
     scale = np.abs(r0 - 0.7).max() / cfg.dt
     assert np.abs(C[1:nr - 4]).max() <= 1e-6 * scale
+
+
+@pytest.mark.parametrize("order,ippc_r,acc", [(1, 1, 0), (2, 2, 0), (3, 3, 2)])
+def test_rz_window_step_parity(orc, order, ippc_r, acc):
+    """r-z with a moving window along z: each step against the oracle's
+    window step in the r-z geometry across shifts, with rings near the axis,
+    rings leaving through the wall and the back, and the ring lattice the
+    window injects (weights proportional to the radius)."""
+    from test_gpu_window import window_step_parity
+
+    pic = _pic()
+    nz, nr, dz, dr = 32, 16, 0.2, 0.25
+    x, u, w = _ring_plasma(nz, nr, dz, dr, 3, 0.3, 300 + order)
+    cfg = pic.Config(ndim=2, nx=(nz, nr), dx=(dz, dr), dt=0.1, shape_order=order, tile=(8, 8), sort_interval=1,
+                     geometry=pic.PIC_GEOM_RZ, move_window=1, inject_ppc=(2, ippc_r, 1), inject_w=-0.2,
+                     accumulator=acc, xmin=(0.5, 0.0, 0.0))
+    sim = pic.Pic(cfg)
+    sim.load_particles(x + np.array([0.5, 0.0]), u, w, rqm=-1.0)
+    E, B = _rz_fields(nz, nr, 23)
+    sim.load_fields(E, B)
+    shifts = removed = 0
+    for n in range(7):
+        err = window_step_parity(orc, sim, cfg, n)
+        print(n, err, flush=True)
+        assert err["inside"]
+        assert err["pos"] <= POS_TOL and err["mom"] <= MOM_TOL
+        assert err["w"] <= 1e-6
+        assert err["J"] <= J_TOL
+        assert err["E"] <= F_TOL and err["B"] <= F_TOL
+        shifts += err["shift"]
+        removed += err["removed"]
+    assert shifts >= 3 and removed > 0
