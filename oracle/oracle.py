@@ -90,8 +90,8 @@ class Grid:
         g.deposit = int(self.deposit)
         g.window = int(self.window)
         if self.cyl:
-            if self.dim != 2 or any(len(p) for p in self.smooth):
-                raise ValueError("the r-z geometry is 2D, without smoothing")
+            if self.dim != 2:
+                raise ValueError("the r-z geometry is 2D")
             if float(xm[1]) != 0.0:
                 raise ValueError("in r-z the second coordinate is the radius (xmin[1] = 0)")
         g.cyl = int(self.cyl)

@@ -73,7 +73,9 @@
  *     u_r' = (u_r (r + dt v_r) + u_theta dt v_theta) / r',
  *     u_theta' = u_theta r / r' (angular momentum);
  *   - the out-of-plane (theta) current uses the velocity u_theta / gamma of
- *     the push, before the rotation.
+ *     the push, before the rotation;
+ *   - current smoothing filters the current density; along r it takes the
+ *     mirror images below the axis and zero beyond the wall.
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared -o liboracle.so pic_oracle.c -lm
  */
@@ -457,6 +459,30 @@ void orc_smooth_current(const orc_grid* g, double* J) {
     for (int pass = 0; pass < g->smooth_level[ax]; pass++) {
       double a = g->smooth_w[ax][pass][0], b = g->smooth_w[ax][pass][1], c = g->smooth_w[ax][pass][2];
       double s = a + b + c;
+      if (g->cyl && ax == 1) {
+        /* r-z along r: the neighbours below the axis are mirror images, those
+         * at and beyond the wall zero; J_r stays zero on the axis and row 0
+         * of J_z, J_theta keeps the image of row 1 */
+        int nz = g->nx[0], nr = g->nx[1];
+        for (int comp = 0; comp < 3; comp++) {
+          double* V = J + comp * nc;
+          int half = comp == 1;
+          for (int j = 0; j < nr; j++)
+            for (int i = 0; i < nz; i++) {
+              double v[3];
+              for (int d = -1; d <= 1; d++) {
+                double sg;
+                int64_t src = cyl_src(g, half, comp == 0, (int64_t)j + d, &sg);
+                v[d + 1] = src < 0 ? 0.0 : sg * V[src * nz + i];
+              }
+              tmp[(int64_t)j * nz + i] = (a * v[0] + b * v[1] + c * v[2]) / s;
+            }
+          for (int i = 0; i < nz; i++)
+            tmp[i] = half ? 0.0 : (comp == 0 ? 1.0 : -1.0) * tmp[nz + i];
+          memcpy(V, tmp, sizeof(double) * (size_t)nc);
+        }
+        continue;
+      }
       for (int comp = 0; comp < 3; comp++) {
         double* V = J + comp * nc;
         for (int64_t q = 0; q < nc; q++) {

@@ -1227,3 +1227,28 @@ def test_cyl_window_field_solve_is_the_periodic_one_with_zero_guard_columns(orc)
     np.testing.assert_allclose(Ew.reshape(3, nr, nz), Ep.reshape(3, nr, nz + 2)[:, :, 1:nz + 1], rtol=0, atol=1e-14)
     np.testing.assert_allclose(Bw.reshape(3, nr, nz), Bp.reshape(3, nr, nz + 2)[:, :, 1:nz + 1], rtol=0, atol=1e-14)
     assert np.abs(Ew).max() > 0.01
+
+
+@pytest.mark.parametrize("weights", [(1.0, 2.0, 1.0), (-1.0, 6.0, -1.0)])
+def test_cyl_smoothing_along_r_has_the_mirror_and_wall_eigenmodes(orc, weights):
+    """Smoothing along r in r-z filters the current density with the axis
+    mirror and the wall: J_z = cos(k (j - 1/2)) (even, zero at the wall row),
+    J_theta = sin(k (j - 1/2)) and J_r = sin(k h) (odd, zero at the wall)
+    are eigenvectors of a symmetric 3-point pass with the eigenvalue of the
+    infinite line, (2 a cos k + b) / (2 a + b)."""
+    nz, nr = 4, 12
+    a, b, c = weights
+    g = orc.Grid(dim=2, nx=(nz, nr), dx=(0.2, 0.2), dt=0.1, order=1, cyl=1, smooth=((), ((a, b, c),)))
+    j = np.arange(nr)
+    for m in (1, 3):
+        kz = math.pi * (m + 0.5) / (nr - 0.5)
+        kt = math.pi * m / (nr - 0.5)
+        kr = math.pi * m / nr
+        J = np.zeros((3, nr, nz))
+        J[0] = np.cos(kz * (j - 0.5))[:, None]
+        J[1] = np.sin(kr * j)[:, None]
+        J[2] = np.sin(kt * (j - 0.5))[:, None]
+        S = orc.smooth_current(g, J.reshape(3, -1)).reshape(3, nr, nz)
+        for comp, k in ((0, kz), (1, kr), (2, kt)):
+            lam = (2 * a * math.cos(k) + b) / (2 * a + b)
+            np.testing.assert_allclose(S[comp], lam * J[comp], rtol=0, atol=1e-13, err_msg=f"comp {comp} m {m}")
