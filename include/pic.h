@@ -155,8 +155,11 @@ typedef struct {
    * about the axis sum Q r u_theta m/q), with Q = w 2 pi dr^2 dz.  With a
    * moving window (along z) the injected lattice leaves out its points
    * below the axis (cell coordinate under 1/2) and an injected ring at
-   * radius r takes weight inject_w r / dr (a uniform density).  Not
-   * available with smoothing or pic_autotune. */
+   * radius r takes weight inject_w r / dr (a uniform density).  Current
+   * smoothing filters the current density (after the division by the ring
+   * volumes); along r the neighbours below the axis are the mirror images
+   * and those at and beyond the wall zero, J_r stays zero on the axis.  Not
+   * available with pic_autotune. */
   int32_t geometry;
 } pic_config;
 

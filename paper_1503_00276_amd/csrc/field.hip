@@ -332,22 +332,30 @@ __global__ void __launch_bounds__(kBlock) yee_step_rz(const InstDesc* __restrict
       }
       const int gi = wrap1(o0 - 1 + x, n0) + n0 * j;
       float J1, J2, J3;
-      if (g.acc_mode == 2) {
-        J1 = (float)((double)(long long)I.J64[jp][gi] * jinv);
-        J2 = (float)((double)(long long)I.J64[jp][nc + gi] * jinv);
-        J3 = (float)((double)(long long)I.J64[jp][2 * nc + gi] * jinv);
-      } else {
-        const gfloat* Ja = (const gfloat*)I.Jacc[jp];
-        J1 = Ja[gi];
-        J2 = Ja[nc + gi];
-        J3 = Ja[2 * nc + gi];
-      }
       // ring volumes of the row: whole rows (j - 1/2), half rows j
       const float vw = j >= 1 ? 1.0f / ((float)j - 0.5f) : 0.0f;
       const float vh = j >= 1 ? 1.0f / (float)j : 0.0f;
-      J1 *= vw;
-      J2 *= vh;
-      J3 *= vw;
+      if (I.sm_npass > 0) {  // the smoothed current is a density already
+        const gfloat* Js = (const gfloat*)I.Jsm[(I.sm_npass - 1) & 1];
+        const float on = j >= 1 ? 1.0f : 0.0f;
+        J1 = on * Js[gi];
+        J2 = on * Js[nc + gi];
+        J3 = on * Js[2 * nc + gi];
+      } else {
+        if (g.acc_mode == 2) {
+          J1 = (float)((double)(long long)I.J64[jp][gi] * jinv);
+          J2 = (float)((double)(long long)I.J64[jp][nc + gi] * jinv);
+          J3 = (float)((double)(long long)I.J64[jp][2 * nc + gi] * jinv);
+        } else {
+          const gfloat* Ja = (const gfloat*)I.Jacc[jp];
+          J1 = Ja[gi];
+          J2 = Ja[nc + gi];
+          J3 = Ja[2 * nc + gi];
+        }
+        J1 *= vw;
+        J2 *= vh;
+        J3 *= vw;
+      }
       const bool back = win && wcol(x) == 0;
       const float bt_m = back ? 0.0f : sB[2][cb - 1], br_m = back ? 0.0f : sB[1][cb - 1];
       sE[1][ce] = j == 0 ? 0.0f : sE[1][ce] + g.dt * (-(sB[2][cb] - bt_m) * rz - J2);
@@ -402,6 +410,74 @@ __global__ void __launch_bounds__(kBlock) yee_step_rz(const InstDesc* __restrict
 // for every instance that has it: J <- a J[i-1] + b J[i] + c J[i+1] with the
 // normalised weights, periodic.  The instance's first pass reads the
 // accumulator of the step's parity; later passes read the other buffer.
+// One smoothing pass of an r-z instance.  The filtered quantity is the
+// current density (the deposit divided by the ring volume of its row: radius
+// (j - 1/2) dr for the whole rows of J_z, J_theta, j dr for the half rows of
+// J_r).  Neighbours below the axis are the mirror images (J_z even, J_r and
+// J_theta odd), those at and beyond the wall zero.  Row 0 keeps the axis
+// value of J_r (zero) and the image of row 1 for J_z, J_theta, so the row-0
+// entries of the passes are never read as sources.
+__device__ __forceinline__ void smooth_pass_rz(const InstDesc& I, int axis, float a, float b, float c,
+                                               gfloat* dst, const gfloat* src, bool first, bool fixed,
+                                               double jinv, int par) {
+  const GridDesc& g = I.g;
+  const int nc = g.ncell;
+  const int n0 = g.nx[0], n1 = g.nx[1];
+  // the density of component comp at (row, column): mirror and wall rules,
+  // raw deposit divided by the ring volume on the first pass
+  auto load = [&](int comp, int row, int col) -> float {
+    const bool half = comp == 1;
+    float sg = 1.0f;
+    if (half ? row < 0 : row <= 0) {
+      row = half ? -row : 1 - row;
+      if (comp != 0) sg = -1.0f;
+    }
+    if (row >= n1) return 0.0f;
+    const int q = comp * nc + col + n0 * row;
+    if (!first) return sg * src[q];
+    const float rv = half ? (float)row : (float)row - 0.5f;
+    if (rv <= 0.0f) return 0.0f;  // J_r on the axis
+    float v;
+    if (fixed)
+      v = (float)((double)(long long)I.J64[par][q] * jinv);
+    else
+      v = ((const gfloat*)I.Jacc[par])[q];
+    return sg * v / rv;
+  };
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < 3 * nc; e += gridDim.x * blockDim.x) {
+    const int comp = e / nc;
+    const int q = e - comp * nc;
+    const int i = q % n0;
+    int j = q / n0;
+    float out;
+    if (axis == 0) {
+      // along z: periodic, or zero beyond the ends of a moving window
+      float am = a, cp = c;
+      if (g.window) {
+        int wr = i - I.win->origin;
+        if (wr < 0) wr += n0;
+        if (wr == 0) am = 0.0f;
+        if (wr == n0 - 1) cp = 0.0f;
+      }
+      const int im = i == 0 ? n0 - 1 : i - 1;
+      const int ip = i == n0 - 1 ? 0 : i + 1;
+      out = am * load(comp, j, im) + b * load(comp, j, i) + cp * load(comp, j, ip);
+    } else {
+      float sg = 1.0f;
+      if (j == 0) {  // axis row: J_r zero, J_z and J_theta the image of row 1
+        if (comp == 1) {
+          dst[e] = 0.0f;
+          continue;
+        }
+        j = 1;
+        sg = comp == 0 ? 1.0f : -1.0f;
+      }
+      out = sg * (a * load(comp, j - 1, i) + b * load(comp, j, i) + c * load(comp, j + 1, i));
+    }
+    dst[e] = out;
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) smooth_pass(const InstDesc* __restrict__ inst, int axis, int lev,
                                                       int par) {
   const InstDesc& I = inst[blockIdx.y];
@@ -417,6 +493,10 @@ __global__ void __launch_bounds__(kBlock) smooth_pass(const InstDesc* __restrict
   const bool first = k == 0;
   const bool fixed = g.acc_mode == 2;
   const double jinv = (double)g.jinv;
+  if (g.cyl) {
+    smooth_pass_rz(I, axis, a, b, c, dst, src, first, fixed, jinv, par);
+    return;
+  }
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < 3 * nc; e += gridDim.x * blockDim.x) {
     const int comp = e / nc;
     const int q = e - comp * nc;

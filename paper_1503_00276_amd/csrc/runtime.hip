@@ -277,7 +277,6 @@ pic_status validate(Sim& S, const pic_config& c) {
     return S.fail(PIC_E_INVALID, "unknown geometry %d", c.geometry);
   if (c.geometry == PIC_GEOM_RZ) {
     if (c.ndim != 2) return S.fail(PIC_E_INVALID, "the r-z geometry is two-dimensional");
-    if (c.smooth_level[0] || c.smooth_level[1]) return S.fail(PIC_E_UNSUPPORTED, "the r-z geometry has no smoothing");
     if (c.xmin[1] != 0.0) return S.fail(PIC_E_INVALID, "in r-z x2 is the radius: xmin[1] must be 0");
     if (c.nx[1] < 2) return S.fail(PIC_E_INVALID, "the r-z geometry needs at least 2 rows");
     if (c.sort_interval > 1) return S.fail(PIC_E_INVALID, "the r-z geometry needs sort_interval 1 (or 0)");

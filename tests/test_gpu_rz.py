@@ -104,6 +104,41 @@ def test_rz_step_parity(orc, case):
     assert removed > 0  # the wall removed the outgoing particles
 
 
+SMOOTH_CASES = [
+    # order, accumulator, passes along z, passes along r
+    (2, 0, ((1, 2, 1),), ((1, 2, 1), (-1, 6, -1))),     # both axes, compensated along r
+    (1, 2, (), ((0.25, 0.5, 0.25),)),                    # r only (first pass along r), int64 fold
+    (3, 0, ((1, 2, 1), (1, 2, 1)), ()),                  # z only
+]
+
+
+@pytest.mark.parametrize("case", SMOOTH_CASES, ids=lambda c: f"o{c[0]}_acc{c[1]}_z{len(c[2])}_r{len(c[3])}")
+def test_rz_smoothed_step_parity(orc, case):
+    """Current smoothing in r-z: the filtered current density (mirror
+    neighbours below the axis, zero at the wall) and the fields it drives,
+    step by step against the oracle, with rings near the axis and the wall."""
+    pic = _pic()
+    order, acc, sz, sr = case
+    nz, nr, dz, dr = 32, 20, 0.2, 0.2
+    x, u, w = _ring_plasma(nz, nr, dz, dr, 3, 0.3, 500 + order)
+    cfg = pic.Config(ndim=2, nx=(nz, nr), dx=(dz, dr), dt=0.1, shape_order=order, tile=(8, 8), sort_interval=1,
+                     geometry=pic.PIC_GEOM_RZ, accumulator=acc, ion_density=1.0, smooth=(sz, sr))
+    sim = pic.Pic(cfg)
+    sim.load_particles(x, u, w, rqm=-1.0)
+    E, B = _rz_fields(nz, nr, 17)
+    sim.load_fields(E, B)
+    print(f"case {case}", flush=True)
+    for k in range(4):
+        err = rz_step_parity(orc, sim, cfg)
+        print(k, err, flush=True)
+        assert err["pos"] <= POS_TOL and err["mom"] <= MOM_TOL
+        assert err["w"] == 0.0
+        assert err["J"] <= J_TOL
+        assert err["E"] <= F_TOL and err["B"] <= F_TOL
+    J = sim.current().reshape(3, nr, nz)
+    assert np.abs(J[1, 0]).max() == 0.0  # J_r on the axis
+
+
 def test_rz_pillbox_fields_match_the_oracle_over_many_steps(orc):
     """The vacuum TM010 pillbox mode for 200 steps: the FP32 r-z field solve
     against the FP64 oracle (no particles)."""
@@ -163,7 +198,7 @@ def test_rz_free_rings_follow_their_3d_lines():
 def test_rz_rejects_unsupported_combinations():
     pic = _pic()
     base = dict(ndim=2, nx=(16, 16), dx=(0.2, 0.2), dt=0.1, shape_order=1, tile=(8, 8), geometry=pic.PIC_GEOM_RZ)
-    for extra in ({"smooth": (((1, 2, 1),), ())}, {"xmin": (0.0, 1.0, 0.0)}, {"sort_interval": 2}):
+    for extra in ({"xmin": (0.0, 1.0, 0.0)}, {"sort_interval": 2}):
         with pytest.raises(pic.PicError):
             pic.Pic(pic.Config(**{**base, **extra}))
     sim = pic.Pic(pic.Config(**base))
@@ -220,12 +255,14 @@ def test_rz_fp64_diagnostics_match_the_oracle(orc, order):
     assert np.abs(C[1:nr - 4]).max() <= 1e-6 * scale
 
 
-@pytest.mark.parametrize("order,ippc_r,acc", [(1, 1, 0), (2, 2, 0), (3, 3, 2)])
-def test_rz_window_step_parity(orc, order, ippc_r, acc):
+@pytest.mark.parametrize("order,ippc_r,acc,smooth", [(1, 1, 0, ()), (2, 2, 0, ()), (3, 3, 2, ()),
+                                                     (2, 2, 0, (((1, 2, 1),), ((1, 2, 1),)))])
+def test_rz_window_step_parity(orc, order, ippc_r, acc, smooth):
     """r-z with a moving window along z: each step against the oracle's
     window step in the r-z geometry across shifts, with rings near the axis,
     rings leaving through the wall and the back, and the ring lattice the
-    window injects (weights proportional to the radius)."""
+    window injects (weights proportional to the radius); last case with the
+    current smoothed along z (zero beyond the window's ends) and r."""
     from test_gpu_window import window_step_parity
 
     pic = _pic()
@@ -233,7 +270,7 @@ def test_rz_window_step_parity(orc, order, ippc_r, acc):
     x, u, w = _ring_plasma(nz, nr, dz, dr, 3, 0.3, 300 + order)
     cfg = pic.Config(ndim=2, nx=(nz, nr), dx=(dz, dr), dt=0.1, shape_order=order, tile=(8, 8), sort_interval=1,
                      geometry=pic.PIC_GEOM_RZ, move_window=1, inject_ppc=(2, ippc_r, 1), inject_w=-0.2,
-                     accumulator=acc, xmin=(0.5, 0.0, 0.0))
+                     accumulator=acc, xmin=(0.5, 0.0, 0.0), smooth=smooth)
     sim = pic.Pic(cfg)
     sim.load_particles(x + np.array([0.5, 0.0]), u, w, rqm=-1.0)
     E, B = _rz_fields(nz, nr, 23)
