@@ -422,6 +422,16 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
   const GridDesc& g = S.g;
   const int tid = threadIdx.x;
 
+  const int set = cur;
+  gint* __restrict__ cellp = (gint*)S.cell[set];
+  gfloat* __restrict__ ep0 = (gfloat*)S.eps[set][0];
+  gfloat* __restrict__ ep1 = (gfloat*)S.eps[set][1];
+  gfloat* __restrict__ ep2 = (gfloat*)S.eps[set][2];
+  gfloat* __restrict__ up0 = (gfloat*)S.u[set][0];
+  gfloat* __restrict__ up1 = (gfloat*)S.u[set][1];
+  gfloat* __restrict__ up2 = (gfloat*)S.u[set][2];
+  const gfloat* __restrict__ wp = (const gfloat*)S.w[set];
+
   int tc[3];
   pic_tile_coords(g, it.tile, tc);
   // How far a particle can be outside its tile at the start of this step:
@@ -455,6 +465,22 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
   float* sF = smem;                                     // [6][fn]
   acc_t* sJ = (acc_t*)(smem + ((6 * fn + 1) & ~1));     // [3][jn], 8-byte aligned
 
+  // the state of each thread's first particle is requested here, after the
+  // control word above has arrived and before the fields are staged, so its
+  // latency overlaps the staging
+  int n_cell = 0;
+  float n_e0 = 0.0f, n_e1 = 0.0f, n_e2 = 0.0f, n_ux = 0.0f, n_uy = 0.0f, n_uz = 0.0f, n_w = 0.0f;
+  if (it.begin + tid < it.end) {
+    const int p = it.begin + tid;
+    n_cell = cellp[p];
+    n_e0 = ep0[p];
+    n_e1 = ep1[p];
+    if (DIM == 3) n_e2 = ep2[p];
+    n_ux = up0[p];
+    n_uy = up1[p];
+    n_uz = up2[p];
+    n_w = wp[p];
+  }
   // 1. stage E, B with periodic wrap
   const int ncell = g.ncell;
   {
@@ -481,11 +507,34 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
         sF[5 * fn + idx] = ih ? sh * Fg[(size_t)5 * ncell + gh] : 0.0f;
         continue;
       }
+      // two nodes per round: the loads of both are in flight together
+      const int idx2 = idx + blockDim.x;
       int gy = wrap_fast(org[1] - flo[1] + bw.y, g.nx[1]);
       int gz = DIM == 3 ? wrap_fast(org[2] - flo[2] + bw.z, g.nx[2]) : 0;
-      int gi = gx + g.nx[0] * (gy + g.nx[1] * gz);
+      const int gi = gx + g.nx[0] * (gy + g.nx[1] * gz);
+      bw.advance(FR);
+      const bool two = idx2 < fn;
+      int gi2 = gi;
+      if (two) {
+        const int gx2 = wrap_fast(org[0] - flo[0] + bw.x, g.nx[0]);
+        const int gy2 = wrap_fast(org[1] - flo[1] + bw.y, g.nx[1]);
+        const int gz2 = DIM == 3 ? wrap_fast(org[2] - flo[2] + bw.z, g.nx[2]) : 0;
+        gi2 = gx2 + g.nx[0] * (gy2 + g.nx[1] * gz2);
+      }
+      float v1[6], v2[6];
 #pragma unroll
-      for (int c = 0; c < 6; c++) sF[c * fn + idx] = Fg[(size_t)c * ncell + gi];
+      for (int c = 0; c < 6; c++) v1[c] = Fg[(size_t)c * ncell + gi];
+      if (two) {
+#pragma unroll
+        for (int c = 0; c < 6; c++) v2[c] = Fg[(size_t)c * ncell + gi2];
+      }
+#pragma unroll
+      for (int c = 0; c < 6; c++) sF[c * fn + idx] = v1[c];
+      if (two) {
+#pragma unroll
+        for (int c = 0; c < 6; c++) sF[c * fn + idx2] = v2[c];
+      }
+      idx = idx2;  // the loop step takes it (and the walker) one node further
     }
   }
   // 2. clear the current tile and the rebin slot counters
@@ -493,15 +542,6 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
   if (tid < PIC_NSLOT) scnt[tid] = 0;
   __syncthreads();
 
-  const int set = cur;
-  gint* __restrict__ cellp = (gint*)S.cell[set];
-  gfloat* __restrict__ ep0 = (gfloat*)S.eps[set][0];
-  gfloat* __restrict__ ep1 = (gfloat*)S.eps[set][1];
-  gfloat* __restrict__ ep2 = (gfloat*)S.eps[set][2];
-  gfloat* __restrict__ up0 = (gfloat*)S.u[set][0];
-  gfloat* __restrict__ up1 = (gfloat*)S.u[set][1];
-  gfloat* __restrict__ up2 = (gfloat*)S.u[set][2];
-  const gfloat* __restrict__ wp = (const gfloat*)S.w[set];
   const float h = 0.5f * S.qm * g.dt;
   bool strayed = false, bad = false, died = false;
   // moving window: ring origin of the x1 columns and whether the window
@@ -515,16 +555,30 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
     wshift = pic_win_shifts(g.wa, wc.step + 1) > pic_win_shifts(g.wa, wc.step);
   }
 
-  // 3. particles
+  // 3. particles; the next particle's state is loaded while this one is
+  // processed (hides the global-load latency at the top of the loop)
   for (int p = it.begin + tid; p < it.end; p += blockDim.x) {
-    int cell = cellp[p];
-    if ((win || RZ) && cell < 0) continue;  // removed, awaiting the rebin
+    int cell = n_cell;
     float e[3];
-    e[0] = ep0[p];
-    e[1] = ep1[p];
-    e[2] = DIM == 3 ? ep2[p] : 0.0f;
-    float ux = up0[p], uy = up1[p], uz = up2[p];
-    float wq = wp[p];
+    e[0] = n_e0;
+    e[1] = n_e1;
+    e[2] = DIM == 3 ? n_e2 : 0.0f;
+    float ux = n_ux, uy = n_uy, uz = n_uz;
+    float wq = n_w;
+    {
+      const int pn = p + blockDim.x;
+      if (pn < it.end) {
+        n_cell = cellp[pn];
+        n_e0 = ep0[pn];
+        n_e1 = ep1[pn];
+        if (DIM == 3) n_e2 = ep2[pn];
+        n_ux = up0[pn];
+        n_uy = up1[pn];
+        n_uz = up2[pn];
+        n_w = wp[pn];
+      }
+    }
+    if ((win || RZ) && cell < 0) continue;  // removed, awaiting the rebin
     int cc[3];
     pic_unpack(g, cell, cc);
     int l[3] = {0, 0, 0};
@@ -536,7 +590,13 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
     }
     if (!ok) {
       bad = true;
-      continue;
+      if constexpr (WIN || RZ) continue;
+      // periodic: the step is reported as failed; the lane still runs,
+      // clamped into the staged region, so that every path through the loop
+      // body ends in the stores and the wait for the next particle's loads
+      // at the loop's end does not wait for this particle's stores too
+#pragma unroll
+      for (int d = 0; d < DIM; d++) l[d] = min(max(l[d], -sl[d]), ext[d] + sl[d] - 1);
     }
 
     // ---- gather: weights at offset 0 and 1/2 per axis
