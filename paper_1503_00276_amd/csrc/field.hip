@@ -96,21 +96,49 @@ __global__ void __launch_bounds__(kBlock) yee_step(const InstDesc* __restrict__ 
       return gx + n0 * (gy + n1 * gz);
     };
     const gfloat* F = (const gfloat*)I.F[par];
-    for (int z = (DIM == 3 ? tz : 0); z < EZ; z += T::Z)
-      for (int y = ty; y < EY; y += T::Y)
-        for (int x = tx; x < EX; x += T::X) {
-          int r = x + EX * (y + EY * z);
-          int gi = gidx(x, y, z);
-          sE[0][r] = F[gi];
-          sE[1][r] = F[nc + gi];
-          sE[2][r] = F[2 * nc + gi];
-          if (x < BX && y < BY && z < BZ) {
-            int rb = x + BX * (y + BY * z);
-            sB[0][rb] = F[3 * nc + gi];
-            sB[1][rb] = F[4 * nc + gi];
-            sB[2][rb] = F[5 * nc + gi];
+    // staging: the region's nodes in flat order, U per thread and round,
+    // every load of a round issued before its first LDS write (so a thread
+    // waits for memory once per round, not once per node and field)
+    {
+      constexpr int U = DIM == 3 ? 4 : 2;
+      const int EN = EX * EY * EZ;
+      for (int q0 = threadIdx.x; q0 < EN; q0 += U * kBlock) {
+        float v[U][6];
+        int rb[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          const int q = q0 + u * kBlock;
+          rb[u] = -2;  // -2: no node, -1: node outside the B region
+          if (q < EN) {
+            const int x = q % EX, y = (q / EX) % EY, z = DIM == 3 ? q / (EX * EY) : 0;
+            const int gi = gidx(x, y, z);
+            v[u][0] = F[gi];
+            v[u][1] = F[nc + gi];
+            v[u][2] = F[2 * nc + gi];
+            rb[u] = -1;
+            if (x < BX && y < BY && z < BZ) {
+              rb[u] = x + BX * (y + BY * z);
+              v[u][3] = F[3 * nc + gi];
+              v[u][4] = F[4 * nc + gi];
+              v[u][5] = F[5 * nc + gi];
+            }
           }
         }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          const int q = q0 + u * kBlock;  // region index x + EX (y + EY z)
+          if (rb[u] == -2) continue;
+          sE[0][q] = v[u][0];
+          sE[1][q] = v[u][1];
+          sE[2][q] = v[u][2];
+          if (rb[u] >= 0) {
+            sB[0][rb[u]] = v[u][3];
+            sB[1][rb[u]] = v[u][4];
+            sB[2][rb[u]] = v[u][5];
+          }
+        }
+      }
+    }
     __syncthreads();
     const float h = 0.5f * g.dt;
     const float r0 = g.rdx[0], r1 = g.rdx[1], r2 = g.rdx[2];

@@ -1050,11 +1050,15 @@ __device__ __forceinline__ void gpd_body(const StoreDesc* __restrict__ stores, i
   }
 }
 
-// (Holding the 2D kernels to the registers of five waves per SIMD was
-// measured: faster on small tiles, slower on the larger tiles the autotuner
-// picks, so the compiler keeps its choice.)
+// The periodic 2D kernels of orders 1 and 2 are held to the registers of
+// five waves per SIMD (96 VGPRs, no spills): where the LDS of a tile allows
+// five workgroups per CU this is up to 8 % faster (16x8 tiles, the batched
+// parameter scan); where LDS allows only four (32x8 tiles late in a sort
+// cycle) it changes nothing.  The other variants would spill; they keep the
+// compiler's choice.
 template <int DIM, int ORDER, int MODE>
-__global__ void __launch_bounds__(kBlock) gpd_kernel(const StoreDesc* __restrict__ stores, int nstores, int jp,
+__global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu(DIM == 2 && ORDER <= 2 && MODE == 0 ? 5 : 1))) gpd_kernel(const StoreDesc* __restrict__ stores, int nstores, int jp,
                                                      int kstep) {
   gpd_body<DIM, ORDER, MODE>(stores, nstores, jp, kstep);
 }
