@@ -230,8 +230,9 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=48)  # whole cycles of every sort interval searched
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2_097_152)
-    ap.add_argument("--tune-steps", type=int, default=10,
-                    help="steps the autotuner times per candidate layout (0: no autotune)")
+    ap.add_argument("--tune-steps", type=int, default=24,
+                    help="steps the autotuner times per candidate layout, rounded up to whole sort "
+                         "cycles (0: no autotune); 24 holds whole cycles of every interval searched")
     ap.add_argument("--tune-after", type=int, default=100,
                     help="untimed steps run before the autotuner, so it tunes the developed state")
     ap.add_argument("--tile", type=int, nargs="+", default=None, help="tile extents (default: automatic)")
