@@ -57,7 +57,8 @@ struct StoreCtl {
   int bad;          // a particle was found outside its staged region (skipped)
   int nsorts;       // rebins performed
   int nchecks;      // rebin checks performed
-  int force;        // set by the host: rebin at every check (autotuner trials)
+  int force;        // set by the host for autotuner trials: k > 0 rebins at
+                    // every k-th check (nchecks % k == 0), flagged or not
   int np;           // particles in the current set after the last rebin (moving window)
   int sorted;       // 1: every particle sits in its own tile (loaded, or re-sorted at the last check)
 };

@@ -1640,13 +1640,13 @@ pic_status set_force(Sim& S, int v) {
   return PIC_OK;
 }
 
-// Milliseconds per step of the installed layout, with a rebin at every check
-// (the steady state of a plasma whose particles cross tiles; the loaded state
-// may not have reached it): two warm-up cycles (graph capture of both
-// parities), then 'trial' steps rounded up to whole cycles.
-pic_status time_layout(Sim& S, int trial, double* ms) {
+// Milliseconds per step of the installed layout, with a rebin forced at
+// every 'every'-th check (besides the checks that find strayed particles):
+// two warm-up cycles (graph capture of both parities), then 'trial' steps
+// rounded up to whole cycles.
+pic_status time_layout(Sim& S, int trial, int every, double* ms) {
   const int SI = S.sort_interval;
-  pic_status fs = set_force(S, 1);
+  pic_status fs = set_force(S, every);
   if (fs != PIC_OK) return fs;
   int64_t phase = S.steps % SI;
   pic_status st = sim_step(S, (SI - phase) % SI + 2 * SI);
@@ -1690,6 +1690,24 @@ pic_status sim_autotune(Sim& S, pic_tune* io) {
   if (st != PIC_OK) return st;
   if (S.sgroups.empty()) return S.fail(PIC_E_STATE, "autotune needs loaded particles");
   if ((st = sim_sync(S)) != PIC_OK) return st;
+  // Trials rebin at the rate this run's checks have rebinned so far (a
+  // forced rebin every round(checks / rebins)-th check; none if no check
+  // has rebinned), so a layout is timed with the rebin cost it will meet.
+  // Without a history (tuned right after loading) every check is forced:
+  // the loaded state may be quieter than the plasma it becomes.
+  int every = 1;
+  {
+    int64_t checks = 0, sorts = 0;
+    for (Instance& I : S.inst)
+      for (Species& sp : I.sp) {
+        if (!sp.used || !sp.ctl) continue;
+        StoreCtl c{};
+        HIPCHK(S, hipMemcpy(&c, sp.ctl, sizeof c, hipMemcpyDeviceToHost));
+        checks += c.nchecks;
+        sorts += c.nsorts;
+      }
+    if (checks > 0) every = sorts == 0 ? 0 : std::max<int>(1, (int)std::lround((double)checks / (double)sorts));
+  }
   const bool was_profiling = S.profiling;
   if ((st = prof_collect(S)) != PIC_OK) return st;
   S.profiling = false;
@@ -1733,7 +1751,7 @@ pic_status sim_autotune(Sim& S, pic_tune* io) {
   int tried = 0;
   auto trial = [&](const Layout& L, const std::vector<pic_config>& c, double* ms) -> pic_status {
     pic_status r = apply_layout(S, c, L.si, snap);
-    if (r == PIC_OK) r = time_layout(S, io->trial_steps, ms);
+    if (r == PIC_OK) r = time_layout(S, io->trial_steps, every, ms);
     tried++;
     return r;
   };

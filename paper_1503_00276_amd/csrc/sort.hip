@@ -16,8 +16,9 @@
 //   fold    (per store)             scan of the block sums; control words
 //   offsets (per destination tile)  tile offsets, item offsets, item list
 //   scatter (per source item)       stable scatter into the other buffer set
-// Only stores whose fused kernel raised the flag (or whose host set 'force')
-// do any work; for the others every launch returns at once.
+// Only stores whose fused kernel raised the flag (or whose check the host
+// forces, in autotuner trials) do any work; for the others every launch
+// returns at once.
 #include "pic_dev.h"
 #include "pic_kernels.h"
 
@@ -32,6 +33,14 @@ static_assert(kTB == kBlock, "one destination tile per thread of the planner");
 
 // Store of a flat index over the stores of a group, given per-store starts
 // (pref[0..n-1], increasing) in LDS.
+// Whether the host forces this check to rebin (autotuner trials: every
+// force-th check).  nchecks only changes at the end of a check (in the fold),
+// so every kernel of one check takes the same decision.
+__device__ __forceinline__ bool forced_check(const StoreCtl* c) {
+  const int k = c->force;
+  return k > 0 && c->nchecks % k == 0;
+}
+
 __device__ __forceinline__ int store_of(const int* pref, int n, int x) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
@@ -133,7 +142,7 @@ __global__ void __launch_bounds__(kBlock) rebin_count(const StoreDesc* __restric
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < total; q += gridDim.x * blockDim.x) {
     const int gt = q / PIC_NSLOT, sl = q - gt * PIC_NSLOT;
     const StoreDesc& S = stores[store_of(t0, nstores, gt)];
-    if (!(S.ctl->flag | S.ctl->force) && !win_shift_now(S)) continue;
+    if (!(S.ctl->flag || forced_check(S.ctl)) && !win_shift_now(S)) continue;
     const int cur = pic_cur(*S.ctl);
     const int t = gt - S.tile0;
     const int i0 = S.ioff[cur][t], i1 = S.ioff[cur][t + 1];
@@ -153,7 +162,7 @@ __global__ void __launch_bounds__(kBlock) rebin_dest(const StoreDesc* __restrict
   for (int i = threadIdx.x; i < nstores; i += blockDim.x) b0[i] = stores[i].blk0;
   __syncthreads();
   const StoreDesc& S = stores[store_of(b0, nstores, blockIdx.x)];
-  if (!(S.ctl->flag | S.ctl->force) && !win_shift_now(S)) return;
+  if (!(S.ctl->flag || forced_check(S.ctl)) && !win_shift_now(S)) return;
   const int blk = blockIdx.x - S.blk0;
   const int d = blk * kTB + threadIdx.x;
   int acc = 0, ni = 0;
@@ -188,7 +197,7 @@ __global__ void __launch_bounds__(kScanBlock) rebin_fold(const StoreDesc* __rest
   if (threadIdx.x == 0) {
     const StoreCtl c = *S.ctl;
     s_cur = c.cur ^ c.pending;
-    s_act = (c.flag | c.force || win_shift_now(S)) ? 1 : 0;
+    s_act = (c.flag || forced_check(&c) || win_shift_now(S)) ? 1 : 0;
   }
   __syncthreads();
   const int cur = s_cur;
