@@ -290,9 +290,13 @@ pic_status pic_get_info(const pic_ctx* ctx, pic_info* out);
  *                         long work item).
  * Each candidate re-bins the particles, runs two warm-up rebin cycles and
  * times trial_steps steps (rounded up to whole cycles) with HIP events on
- * the context's stream, with a rebin at every check (the steady state of a
- * plasma whose particles cross tiles, which the loaded state may not have
- * reached yet).  The state is restored before every candidate and
+ * the context's stream.  Trials rebin at the rate this context's checks
+ * have rebinned since the particles were loaded or the layout last
+ * changed (a previous pic_autotune): every
+ * round(checks / rebins)-th check is forced to rebin (besides the checks
+ * that find strayed particles), none if no check has rebinned, and every
+ * check when no step has run yet (the loaded state may be quieter than the
+ * plasma it becomes).  The state is restored before every candidate and
  * after the search: particles (in load order), fields, the last current and
  * the step count are exactly those before the call; only the layout (tile,
  * sort interval, chunk, order of particles inside a tile) changes, and the

@@ -1690,11 +1690,12 @@ pic_status sim_autotune(Sim& S, pic_tune* io) {
   if (st != PIC_OK) return st;
   if (S.sgroups.empty()) return S.fail(PIC_E_STATE, "autotune needs loaded particles");
   if ((st = sim_sync(S)) != PIC_OK) return st;
-  // Trials rebin at the rate this run's checks have rebinned so far (a
-  // forced rebin every round(checks / rebins)-th check; none if no check
-  // has rebinned), so a layout is timed with the rebin cost it will meet.
-  // Without a history (tuned right after loading) every check is forced:
-  // the loaded state may be quieter than the plasma it becomes.
+  // Trials rebin at the rate the checks have rebinned since the particles
+  // were loaded or the layout last changed (a forced rebin every
+  // round(checks / rebins)-th check; none if no check has rebinned), so a
+  // layout is timed with the rebin cost it will meet.  Without a history
+  // (tuned right after loading) every check is forced: the loaded state may
+  // be quieter than the plasma it becomes.
   int every = 1;
   {
     int64_t checks = 0, sorts = 0;
