@@ -103,22 +103,31 @@ def test_thermal_64x64_full_parity_and_energy_history(orc):
     sim.close()
 
 
-def test_lwfa_full_size_parity_in_bench_layout(orc):
+@pytest.mark.parametrize("layout", [None, (32, 8, 8, 1024)], ids=["autotuned", "32x8_si8_chunk1024"])
+def test_lwfa_full_size_parity_in_bench_layout(orc, layout):
     """Workload 2 (2,097,152 electrons, quadratic, laser): the autotuned
-    layout, 40 steps into the run (the wake has formed, particles cross cells
-    and tiles, rebins have run), then every particle, current and field value
-    for two steps."""
+    layout, or the layout the benchmark's autotuner settles on (32x8 tiles,
+    sort interval 8, chunk 1024); 40-45 steps into the run (the wake has
+    formed, particles cross cells and tiles, rebins have run), then every
+    particle, current and field value for two steps (late in a sort cycle
+    for the fixed layout, where the staged halo is widest)."""
     from paper_1503_00276_amd import workloads as W
 
     pic = _pic()
     wl = W.workload2()
-    cfg, sim = _sim(pic, wl)
-    tune = sim.autotune(trial_steps=4)
+    if layout is None:
+        cfg, sim = _sim(pic, wl)
+        tune = sim.autotune(trial_steps=4)
+        nsteps = 40
+    else:
+        cfg, sim = _sim(pic, wl, tile=layout[:2], sort_interval=layout[2], chunk=layout[3])
+        tune = None
+        nsteps = 45  # the next two steps are steps 5 and 6 of an 8-step cycle
     info = sim.info()
     print("layout", list(info.tile), info.sort_interval, info.chunk, tune, flush=True)
-    sim.step(40)
+    sim.step(nsteps)
     for k in range(2):
-        _check(step_parity(orc, sim, cfg), f"cfg2 step {41 + k}")
+        _check(step_parity(orc, sim, cfg), f"cfg2 step {nsteps + 1 + k}")
     assert sim.counts()[2] > 0  # rebins happened
     sim.close()
 
