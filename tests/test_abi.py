@@ -126,3 +126,15 @@ def test_tristan_needs_linear_shape():
     pic, _ = _lib()
     assert _create_status(pic, shape_order=2, deposit=pic.PIC_DEPOSIT_TRISTAN) == pic.PIC_E_INVALID
     assert _create_status(pic, shape_order=1, deposit=7) == pic.PIC_E_INVALID
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py is a one-GPU benchmark: --gpus above 1 exits before touching a
+    GPU, with a message."""
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
