@@ -60,7 +60,7 @@ typedef enum {
   PIC_E_HIP = -3,         /* a HIP runtime call failed */
   PIC_E_STATE = -4,       /* call not valid in the current state */
   PIC_E_RANGE = -5,       /* non-finite input, or output buffer too small */
-  PIC_E_UNSUPPORTED = -6  /* valid request this build does not implement */
+  PIC_E_UNSUPPORTED = -6  /* valid request the library does not implement */
 } pic_status;
 
 /* Accumulation of the current.  Every particle's FP32 contribution is
