@@ -16,6 +16,8 @@
 // per axis; all arithmetic is FP32.
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include "pic_dev.h"
 #include "pic_kernels.h"
 
@@ -226,6 +228,16 @@ __device__ __forceinline__ void lds_add_any(acc_t* p, float v) {
   __hip_atomic_fetch_add(p, (acc_t)(long long)(int)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// The tile of the two-phase 3D kernel: v is in units of the work item's own
+// fixed point (chosen so that every single contribution stays below 2^30),
+// rounded to the nearest integer and summed exactly in int64.
+struct acc_rn {
+  acc_t v;
+};
+__device__ __forceinline__ void lds_add_any(acc_rn* p, float v) {
+  __hip_atomic_fetch_add(&p->v, (acc_t)(long long)(int)rintf(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // TRISTAN (Villasenor-Buneman) current of one particle for the linear shape
 // (Sec. 3.2): the straight move from offset e in the old cell by dl cells
 // (|dl| < 1 per axis) is cut where it crosses cell faces; each piece lies in
@@ -370,8 +382,8 @@ struct DepAxis {
 // Component A of the current (flow along axis A; B, C the other axes) on one
 // block of nodes: core or extra along each axis (EA, EB, EC).  The value is
 // P_A * (S_B S_C + (D_B S_C + S_B D_C)/2 + D_B D_C/3).
-template <int K, int A, bool EA, bool EB, bool EC>
-__device__ __forceinline__ void dep3_part(acc_t* J, int cb, const int st[3], const DepAxis<K> (&ax)[3]) {
+template <int K, int A, bool EA, bool EB, bool EC, typename Acc>
+__device__ __forceinline__ void dep3_part(Acc* J, int cb, const int st[3], const DepAxis<K> (&ax)[3]) {
   constexpr int B = (A + 1) % 3, C = (A + 2) % 3;
   constexpr int NA = EA ? 1 : K - 1, NB = EB ? 1 : K, NC = EC ? 1 : K;
 #pragma unroll
@@ -392,8 +404,8 @@ __device__ __forceinline__ void dep3_part(acc_t* J, int cb, const int st[3], con
   }
 }
 
-template <int K, int A>
-__device__ __forceinline__ void dep3_comp(acc_t* J, int cb, const int st[3], const DepAxis<K> (&ax)[3]) {
+template <int K, int A, typename Acc>
+__device__ __forceinline__ void dep3_comp(Acc* J, int cb, const int st[3], const DepAxis<K> (&ax)[3]) {
   constexpr int B = (A + 1) % 3, C = (A + 2) % 3;
   const bool wa = ax[A].wide, wb = ax[B].wide, wc = ax[C].wide;
   dep3_part<K, A, false, false, false>(J, cb, st, ax);
@@ -1021,6 +1033,393 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
   __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// periodic 3D work item in two phases
+// ---------------------------------------------------------------------------
+//
+// Phase A stages E and B of the tile and pushes every particle of the item
+// (up to kSplitR per thread), keeping what the deposit needs in registers.
+// Phase B clears the int64 current tile in the same LDS and deposits into it.
+// Field tile and current tile never coexist, so a workgroup needs the larger
+// of the two instead of their sum, and more workgroups share a CU.  The
+// regions carry only the guards the shapes reach (see the host's region
+// guards of this variant).
+//
+// The fixed point of the tile is chosen per work item from the particles
+// just pushed.  A contribution of particle p to one node is at most
+// |w_p| |v_p|: the charge fraction that crosses a face in one step is at most
+// the displacement in cells (the prefix of the shape change along the axis
+// is 1-Lipschitz), and the transverse weight (a time average of products of
+// shape values) is at most one.  With Q = 2^e and Q max_p |w_p| |v_p| < 2^29
+// every contribution converts to an int32 (with a factor 2 to spare for the
+// FP32 rounding of the shape differences) and the int64 sums are exact; the
+// rounding unit follows the item's fastest particle instead of the speed of
+// light, so a slow or cold plasma keeps its relative precision.
+
+constexpr int kSplitR = 2;  // particles per thread per work item
+
+template <int ORDER>
+__device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii, int jp, int kstep, float* smem,
+                              int* scnt, float* sred) {
+  constexpr int NG = ORDER + 1;  // gather taps per axis
+  constexpr int K = ORDER + 1;   // deposit core per axis
+  constexpr int W = ORDER + 2;   // deposit window per axis
+  constexpr int R = kSplitR;
+  const GridDesc& g = S.g;
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;
+
+  const int set = cur;
+  gint* __restrict__ cellp = (gint*)S.cell[set];
+  gfloat* __restrict__ ep0 = (gfloat*)S.eps[set][0];
+  gfloat* __restrict__ ep1 = (gfloat*)S.eps[set][1];
+  gfloat* __restrict__ ep2 = (gfloat*)S.eps[set][2];
+  gfloat* __restrict__ up0 = (gfloat*)S.u[set][0];
+  gfloat* __restrict__ up1 = (gfloat*)S.u[set][1];
+  gfloat* __restrict__ up2 = (gfloat*)S.u[set][2];
+  const gfloat* __restrict__ wp = (const gfloat*)S.w[set];
+
+  int tc[3];
+  pic_tile_coords(g, it.tile, tc);
+  // stray bound of this step (as in the one-phase kernel)
+  const int s0 = __builtin_amdgcn_readfirstlane(S.ctl->sorted) ? 0 : g.flag_slack;
+  int sl[3], org[3], ext[3], FR[3], JR[3], flo[3], jlo[3];
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    sl[d] = __builtin_amdgcn_readfirstlane(min(s0 + (int)ceilf((float)kstep * g.vstep[d]), g.slk[d]));
+    org[d] = tc[d] * g.tile[d];
+    ext[d] = min(g.tile[d], g.nx[d] - org[d]);
+    flo[d] = sl[d] + g.fa;
+    jlo[d] = sl[d] + g.ja;
+    FR[d] = ext[d] + 2 * sl[d] + g.fa + g.fb;
+    JR[d] = ext[d] + 2 * sl[d] + g.ja + g.jb;
+  }
+  const int fn = FR[0] * FR[1] * FR[2];
+  const int jn = JR[0] * JR[1] * JR[2];
+  float* sF = smem;            // phase A: [6][fn]
+  acc_rn* sJ = (acc_rn*)smem;  // phase B: [3][jn]
+
+  // this thread's particles: requested before the fields are staged
+  int pc[R];
+  float pe[R][3], pu[R][3], pw[R];
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    const int p = it.begin + tid + r * nthr;
+    pc[r] = -1;
+    pe[r][0] = pe[r][1] = pe[r][2] = 0.0f;
+    pu[r][0] = pu[r][1] = pu[r][2] = 0.0f;
+    pw[r] = 0.0f;
+    if (p < it.end) {
+      pc[r] = cellp[p];
+      pe[r][0] = ep0[p];
+      pe[r][1] = ep1[p];
+      pe[r][2] = ep2[p];
+      pu[r][0] = up0[p];
+      pu[r][1] = up1[p];
+      pu[r][2] = up2[p];
+      pw[r] = wp[p];
+    }
+  }
+
+  // 1. stage E, B with periodic wrap: four nodes per thread per batch, every
+  // load of a batch in flight before its LDS writes
+  const int ncell = g.ncell;
+  {
+    const gfloat* Fg = (const gfloat*)S.F[jp];
+    BoxWalk bw(tid, nthr, FR);
+    for (int base = 0; base < fn; base += 4 * nthr) {
+      float v[4][6];
+      int gi[4];
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const int gx = wrap_fast(org[0] - flo[0] + bw.x, g.nx[0]);
+        const int gy = wrap_fast(org[1] - flo[1] + bw.y, g.nx[1]);
+        const int gz = wrap_fast(org[2] - flo[2] + bw.z, g.nx[2]);
+        gi[q] = gx + g.nx[0] * (gy + g.nx[1] * gz);
+        bw.advance(FR);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        if (base + q * nthr + tid < fn) {
+#pragma unroll
+          for (int c = 0; c < 6; c++) v[q][c] = Fg[(size_t)c * ncell + gi[q]];
+        }
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const int idx = base + q * nthr + tid;
+        if (idx < fn) {
+#pragma unroll
+          for (int c = 0; c < 6; c++) sF[c * fn + idx] = v[q][c];
+        }
+      }
+    }
+  }
+  if (tid < PIC_NSLOT) scnt[tid] = 0;
+  __syncthreads();
+
+  // 2. phase A: gather, Boris push, advance; store the new state
+  const float h = 0.5f * S.qm * g.dt;
+  bool strayed = false, bad = false;
+  float bmax = 0.0f;
+  // kept for the deposit: old and new offsets, the move, the weight and the
+  // old cell in current-region coordinates (-1: no particle)
+  float se0[R][3], sen[R][3], swq[R];
+  int smv[R], sjc[R];
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    const int p = it.begin + tid + r * nthr;
+    smv[r] = 0;
+    sjc[r] = -1;
+    swq[r] = 0.0f;
+#pragma unroll
+    for (int d = 0; d < 3; d++) se0[r][d] = sen[r][d] = 0.0f;
+    int dd[3] = {0, 0, 0};
+    bool live = p < it.end;
+    if (live) {
+      int cc[3];
+      pic_unpack(g, pc[r], cc);
+      int l[3];
+      bool ok = true;
+#pragma unroll
+      for (int d = 0; d < 3; d++) {
+        l[d] = pic_local(cc[d], org[d], ext[d], g.nx[d]);
+        ok = ok && (l[d] >= -sl[d]) && (l[d] < ext[d] + sl[d]);
+      }
+      if (!ok) {
+        // reported as a failed step; the particle is clamped into the
+        // staged region so that every access stays inside it
+        bad = true;
+#pragma unroll
+        for (int d = 0; d < 3; d++) l[d] = min(max(l[d], -sl[d]), ext[d] + sl[d] - 1);
+      }
+      const float e[3] = {pe[r][0], pe[r][1], pe[r][2]};
+      // ---- gather: weights at offset 0 and 1/2 per axis
+      int b0[3], bh[3];
+      float w0[3][NG], wh[3][NG];
+#pragma unroll
+      for (int d = 0; d < 3; d++) {
+        gather_weights<ORDER>(e[d], false, b0[d], w0[d]);
+        gather_weights<ORDER>(e[d], true, bh[d], wh[d]);
+      }
+      float Fp[6];
+#pragma unroll
+      for (int c = 0; c < 6; c++) {
+        // component c: E_c staggered half along axis c, B_c half along the others
+        const bool hx = (c < 3) ? (c == 0) : (c != 3);
+        const bool hy = (c < 3) ? (c == 1) : (c != 4);
+        const bool hz = (c < 3) ? (c == 2) : (c != 5);
+        const float* wx = hx ? wh[0] : w0[0];
+        const float* wy = hy ? wh[1] : w0[1];
+        const float* wz = hz ? wh[2] : w0[2];
+        const int sx = flo[0] + l[0] + (hx ? bh[0] : b0[0]);
+        const int sy = flo[1] + l[1] + (hy ? bh[1] : b0[1]);
+        const int sz = flo[2] + l[2] + (hz ? bh[2] : b0[2]);
+        const float* Fc = sF + c * fn + (sz * FR[1] + sy) * FR[0] + sx;
+        float acc = 0.0f;
+#pragma unroll
+        for (int k = 0; k < NG; k++) {
+          float pl = 0.0f;
+#pragma unroll
+          for (int j = 0; j < NG; j++) {
+            const float* row = Fc + (k * FR[1] + j) * FR[0];
+            float rr = 0.0f;
+#pragma unroll
+            for (int i = 0; i < NG; i++) rr += wx[i] * row[i];
+            pl += wy[j] * rr;
+          }
+          acc += wz[k] * pl;
+        }
+        Fp[c] = acc;
+      }
+      const float Ex = Fp[0] + g.e0[0], Ey = Fp[1] + g.e0[1], Ez = Fp[2] + g.e0[2];
+      const float Bx = Fp[3] + g.b0[0], By = Fp[4] + g.b0[1], Bz = Fp[5] + g.b0[2];
+      // ---- Boris push (Sec. 3.2, Eq. momentum-update)
+      float ux = pu[r][0], uy = pu[r][1], uz = pu[r][2];
+      const float mx = ux + h * Ex, my = uy + h * Ey, mz = uz + h * Ez;
+      const float gim = rsqrtf(1.0f + mx * mx + my * my + mz * mz);
+      const float tx = h * Bx * gim, ty = h * By * gim, tz = h * Bz * gim;
+      const float sfac = 2.0f * __builtin_amdgcn_rcpf(1.0f + tx * tx + ty * ty + tz * tz);
+      const float px = mx + (my * tz - mz * ty);
+      const float py = my + (mz * tx - mx * tz);
+      const float pz = mz + (mx * ty - my * tx);
+      const float sx_ = sfac * tx, sy_ = sfac * ty, sz_ = sfac * tz;
+      ux = mx + (py * sz_ - pz * sy_) + h * Ex;
+      uy = my + (pz * sx_ - px * sz_) + h * Ey;
+      uz = mz + (px * sy_ - py * sx_) + h * Ez;
+      // ---- advance (Eq. 2d-position-update, all three axes)
+      const float uu2 = ux * ux + uy * uy + uz * uz;
+      const float gi = rsqrtf(1.0f + uu2);
+      const float uu[3] = {ux, uy, uz};
+      int mv[3];
+      float en[3];
+#pragma unroll
+      for (int d = 0; d < 3; d++) {
+        const float x = e[d] + g.dt * g.rdx[d] * (uu[d] * gi);
+        const float f = floorf(x);
+        int c = (int)f;
+        float rr = x - f;
+        if (rr >= 1.0f) {  // rounding edge: keep the offset in [0,1)
+          rr = 0.0f;
+          c += 1;
+        }
+        // the Courant condition keeps |move| below one cell
+        if (c > 1) {
+          c = 1;
+          rr = 0.99999994f;
+        } else if (c < -1) {
+          c = -1;
+          rr = 0.0f;
+        }
+        en[d] = rr;
+        mv[d] = c;
+      }
+      // ---- store the new state
+      int nc[3];
+#pragma unroll
+      for (int d = 0; d < 3; d++) {
+        nc[d] = cc[d] + mv[d];
+        if (nc[d] < 0) nc[d] += g.nx[d];
+        if (nc[d] >= g.nx[d]) nc[d] -= g.nx[d];
+        const int ln = pic_local(nc[d], org[d], ext[d], g.nx[d]);
+        strayed = strayed || ln < -g.flag_slack || ln >= ext[d] + g.flag_slack;
+        dd[d] = ln < 0 ? -1 : (ln >= ext[d] ? 1 : 0);
+      }
+      cellp[p] = pic_pack(g, nc[0], nc[1], nc[2]);
+      ep0[p] = en[0];
+      ep1[p] = en[1];
+      ep2[p] = en[2];
+      up0[p] = ux;
+      up1[p] = uy;
+      up2[p] = uz;
+      // ---- what the deposit needs
+      const bool moved = mv[0] != 0 || mv[1] != 0 || mv[2] != 0 || en[0] != e[0] || en[1] != e[1] || en[2] != e[2];
+      if (moved) {
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+          se0[r][d] = e[d];
+          sen[r][d] = en[d];
+        }
+        smv[r] = (mv[0] + 1) | ((mv[1] + 1) << 2) | ((mv[2] + 1) << 4);
+        sjc[r] = ((jlo[2] + l[2]) * JR[1] + jlo[1] + l[1]) * JR[0] + jlo[0] + l[0];
+        swq[r] = pw[r];
+        bmax = fmaxf(bmax, fabsf(pw[r]) * (sqrtf(uu2) * gi));
+      }
+    }
+    {
+      // wave-aggregated count per rebin slot (almost every particle is in slot 13)
+      const int slt = live ? pic_slot(dd[0], dd[1], dd[2]) : -1;
+      unsigned long long todo = __ballot(slt >= 0);
+      while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int ls = __shfl(slt, leader);
+        const unsigned long long m = __ballot(slt == ls);
+        if ((int)(threadIdx.x & 63) == leader) atomicAdd(&scnt[ls], (int)__popcll(m));
+        todo &= ~m;
+      }
+    }
+  }
+  // the item's bound on a single contribution: max of |w| |v| over its particles
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) bmax = fmaxf(bmax, __shfl_xor(bmax, off));
+  if ((tid & 63) == 0) sred[tid >> 6] = bmax;
+  const int any_strayed = __syncthreads_or(strayed ? 1 : 0);  // also: phase A done, fields dead
+  const int any_bad = __syncthreads_or(bad ? 1 : 0);
+  float btop = 0.0f;
+  for (int k = 0; k < (nthr >> 6); k++) btop = fmaxf(btop, sred[k]);
+  // fixed point of the tile: Q = 2^e with Q btop < 2^29
+  int ex = 0;
+  (void)frexpf(btop, &ex);
+  const int e_item = btop > 0.0f ? min(100, max(-100, 29 - ex)) : 0;
+  const float Q = ldexpf(1.0f, e_item);
+
+  // 3. clear the current tile (over the staged fields)
+  for (int idx = tid; idx < 3 * jn; idx += nthr) sJ[idx].v = 0ull;
+  if (tid == 0) {
+    if (any_strayed) S.ctl->flag = 1;
+    if (any_bad) S.ctl->bad = 1;
+  }
+  if (tid < PIC_NSLOT) S.cnt[ii * PIC_NSLOT + tid] = scnt[tid];
+  __syncthreads();
+
+  // 4. phase B: ISIS ordering average in Esirkepov's closed form, core of the
+  // old support unconditional, each extra block under one branch
+  const int st[3] = {1, JR[0], JR[0] * JR[1]};
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    if (sjc[r] < 0) continue;
+    const int mv[3] = {(smv[r] & 3) - 1, ((smv[r] >> 2) & 3) - 1, ((smv[r] >> 4) & 3) - 1};
+    int wb[3], p0[3];
+    bool wide[3];
+    float S0[3][W], D[3][W];
+#pragma unroll
+    for (int d = 0; d < 3; d++) deposit_shape<ORDER>(se0[r][d], sen[r][d], mv[d], wb[d], p0[d], wide[d], S0[d], D[d]);
+    DepAxis<K> ax[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      const float qd = -swq[r] * g.cdt[d] * Q;
+      float P[W - 1];
+      float a = 0.0f;
+#pragma unroll
+      for (int k = 0; k < W - 1; k++) {
+        a += D[d][k];
+        P[k] = qd * a;
+      }
+      const bool pd = p0[d] != 0;
+#pragma unroll
+      for (int k = 0; k < K; k++) {
+        ax[d].S[k] = pd ? S0[d][k + 1] : S0[d][k];
+        ax[d].D[k] = pd ? D[d][k + 1] : D[d][k];
+      }
+#pragma unroll
+      for (int k = 0; k < K - 1; k++) ax[d].P[k] = pd ? P[k + 1] : P[k];
+      ax[d].Se = pd ? S0[d][0] : S0[d][K];
+      ax[d].De = pd ? D[d][0] : D[d][K];
+      ax[d].Pe = wide[d] ? (pd ? P[0] : P[K - 1]) : 0.0f;
+      ax[d].oS = pd ? -1 : K;
+      ax[d].oP = pd ? -1 : K - 1;
+      ax[d].wide = wide[d];
+    }
+    const int cb = sjc[r] + (wb[0] + p0[0]) + (wb[1] + p0[1]) * st[1] + (wb[2] + p0[2]) * st[2];
+    dep3_comp<K, 0>(sJ, cb, st, ax);
+    dep3_comp<K, 1>(sJ + jn, cb, st, ax);
+    dep3_comp<K, 2>(sJ + 2 * jn, cb, st, ax);
+  }
+  __syncthreads();
+
+  // 5. fold the tile into the global current (periodic wrap); the int64 mode
+  // converts the item's units to the instance's fixed point exactly (a left
+  // shift) or rounds to it (a right shift), so its sums stay order-free
+  const float qinv = ldexpf(1.0f, -e_item);
+  int eg = 0;
+  (void)frexpf(g.jscale, &eg);
+  const int sh = (eg - 1) - e_item;  // jscale = 2^(eg-1)
+  BoxWalk bj(tid, nthr, JR);
+  for (int idx = tid; idx < jn; idx += nthr, bj.advance(JR)) {
+    const int gx = wrap_fast(org[0] - jlo[0] + bj.x, g.nx[0]);
+    const int gy = wrap_fast(org[1] - jlo[1] + bj.y, g.nx[1]);
+    const int gz = wrap_fast(org[2] - jlo[2] + bj.z, g.nx[2]);
+    const int gidx = gx + g.nx[0] * (gy + g.nx[1] * gz);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      const long long q = (long long)sJ[c * jn + idx].v;
+      if (q != 0) {
+        if (g.acc_mode == 2) {
+          long long v = q;
+          if (sh >= 0)
+            v = v << sh;
+          else
+            v = -sh > 62 ? 0 : ((v + (1ll << (-sh - 1))) >> (-sh));
+          if (v != 0) atomicAdd(S.J64[jp] + (size_t)c * ncell + gidx, (acc_t)v);
+        } else {
+          __builtin_amdgcn_global_atomic_fadd_f32((gfloat*)S.Jacc[jp] + (size_t)c * ncell + gidx,
+                                                  (float)((double)q * (double)qinv));
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
 template <int DIM, int ORDER, int MODE>
 __device__ __forceinline__ void gpd_body(const StoreDesc* __restrict__ stores, int nstores, int jp, int kstep) {
   // 16-byte aligned: the int64 current tile inside it takes 8-byte LDS atomics
@@ -1028,6 +1427,7 @@ __device__ __forceinline__ void gpd_body(const StoreDesc* __restrict__ stores, i
   __shared__ int s_pref[kMaxGroup + 1];
   __shared__ int s_cur[kMaxGroup];
   __shared__ int s_cnt[PIC_NSLOT];
+  __shared__ float s_red[kBlock / 64];
   if (threadIdx.x == 0) {
     int acc = 0;
     for (int s = 0; s < nstores; s++) {
@@ -1040,14 +1440,32 @@ __device__ __forceinline__ void gpd_body(const StoreDesc* __restrict__ stores, i
   }
   __syncthreads();
   const int total = s_pref[nstores];
+  // Items are listed in tile order.  Workgroup b runs on XCD b % 8 (the
+  // dispatcher deals workgroups to the eight XCDs in turn), so a plain
+  // grid-stride walk would scatter neighbouring tiles, whose staged halos
+  // overlap, over eight separate L2 caches.  With a grid that is a multiple
+  // of 8, the workgroups of each XCD walk one contiguous eighth of the list
+  // (two-phase 3D kernel only; the 2D kernels keep the plain walk).
+  int lo = 0, hi = total, first = blockIdx.x, stride = gridDim.x;
+  if (MODE == 4 && (gridDim.x & 7) == 0 && total >= (int)gridDim.x) {
+    const int per = (total + 7) >> 3;
+    lo = min(total, (int)(blockIdx.x & 7) * per);
+    hi = min(total, lo + per);
+    first = lo + (int)(blockIdx.x >> 3);
+    stride = gridDim.x >> 3;
+  }
   int s = 0;
-  for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
+  for (int gi = first; gi < hi; gi += stride) {
     while (gi >= s_pref[s + 1]) s++;
     const StoreDesc& S = stores[s];
     const int cur = s_cur[s];
     const Item it = S.items[cur][gi - s_pref[s]];
-    process_item<DIM, ORDER, MODE>(S, cur, it, gi - s_pref[s], jp, kstep, smem, s_cnt);
+    if constexpr (MODE == 4)
+      process_item3<ORDER>(S, cur, it, gi - s_pref[s], jp, kstep, smem, s_cnt, s_red);
+    else
+      process_item<DIM, ORDER, MODE>(S, cur, it, gi - s_pref[s], jp, kstep, smem, s_cnt);
   }
+  (void)lo;
 }
 
 // The periodic 2D kernels of orders 1 and 2 are held to the registers of
@@ -1090,6 +1508,8 @@ hipError_t prepare_one(int mode, size_t lds) {
   if constexpr (DIM == 2) {
     if (mode == 2) return prepare_mode<DIM, ORDER, 2>(lds);
     if (mode == 3) return prepare_mode<DIM, ORDER, 3>(lds);
+  } else {
+    if (mode == 4) return prepare_mode<DIM, ORDER, 4>(lds);
   }
   if (mode == 0) return prepare_mode<DIM, ORDER, 0>(lds);
   return hipErrorInvalidValue;
@@ -1108,7 +1528,8 @@ hipError_t launch_one(int mode, const StoreDesc* stores, int nstores, int grid, 
     else
       launch_mode<DIM, ORDER, 3>(stores, nstores, grid, lds, jp, kstep, st, ev0, ev1);
   } else {
-    return hipErrorInvalidValue;
+    if (mode != 4) return hipErrorInvalidValue;
+    launch_mode<DIM, ORDER, 4>(stores, nstores, grid, lds, jp, kstep, st, ev0, ev1);
   }
   return hipGetLastError();
 }
@@ -1122,6 +1543,7 @@ size_t pic_gpd_lds_bytes(const GridDesc& g) {
     fn *= (size_t)(g.tile[d] + 2 * g.slk[d] + g.fa + g.fb);
     jn *= (size_t)(g.tile[d] + 2 * g.slk[d] + g.ja + g.jb);
   }
+  if (pic_gpd_split(g)) return std::max(6 * fn * sizeof(float), 3 * jn * sizeof(unsigned long long));
   return ((6 * fn + 1) & ~(size_t)1) * sizeof(float) + 3 * jn * sizeof(unsigned long long);
 }
 
@@ -1135,8 +1557,12 @@ size_t pic_gpd_lds_bytes_step(const GridDesc& g, int kstep) {
     fn *= (size_t)(g.tile[d] + 2 * sl + g.fa + g.fb);
     jn *= (size_t)(g.tile[d] + 2 * sl + g.ja + g.jb);
   }
+  if (pic_gpd_split(g)) return std::max(6 * fn * sizeof(float), 3 * jn * sizeof(unsigned long long));
   return ((6 * fn + 1) & ~(size_t)1) * sizeof(float) + 3 * jn * sizeof(unsigned long long);
 }
+
+// Particles one work item of the two-phase 3D kernel can hold.
+int pic_gpd_split_chunk() { return kSplitR * kBlock; }
 
 int pic_gpd_block() { return kBlock; }
 int pic_gpd_max_group() { return kMaxGroup; }
@@ -1161,6 +1587,8 @@ int resident_one(int mode, size_t lds) {
   if constexpr (DIM == 2) {
     if (mode == 2) f = gpd_entry<DIM, ORDER, 2>();
     if (mode == 3) f = gpd_entry<DIM, ORDER, 3>();
+  } else {
+    if (mode == 4) f = gpd_entry<DIM, ORDER, 4>();
   }
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kBlock, lds) != hipSuccess) return 1;
   return n < 1 ? 1 : n;

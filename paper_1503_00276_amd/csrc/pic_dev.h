@@ -78,6 +78,13 @@ struct WinCtl {
   int pad[2];
 };
 
+// The periodic 3D ISIS variant of the fused kernel runs each work item in two
+// phases whose field and current tiles share one LDS region (fused-kernel
+// MODE 4); every other box takes the one-phase kernel.
+__host__ __device__ inline bool pic_gpd_split(const GridDesc& g) {
+  return g.dim == 3 && !g.window && !g.cyl && g.deposit == 0;
+}
+
 // Shifts after n steps of a window moving at c.
 __host__ __device__ inline int pic_win_shifts(double wa, long long n) { return (int)floor((double)n * wa); }
 

@@ -26,7 +26,10 @@
 
 namespace {
 
-constexpr int kLdsMax = 160 * 1024;
+// dynamic LDS a fused-kernel workgroup may request: the CU's 160 KiB less
+// 4 KiB for the kernel's static LDS (its item prefix, slot counters and
+// reduction slots; a build test checks that they fit)
+constexpr int kLdsMax = 160 * 1024 - 4096;
 constexpr int kNumCU = 256;
 
 struct Species {
@@ -75,7 +78,16 @@ struct Group {
 };
 
 // Boundary logic an instance's stores need in the fused particle kernel.
-int kernel_mode(const GridDesc& g) { return g.window ? (g.cyl ? 3 : 1) : (g.cyl ? 2 : 0); }
+int kernel_mode(const GridDesc& g) {
+  if (pic_gpd_split(g)) return 4;
+  return g.window ? (g.cyl ? 3 : 1) : (g.cyl ? 2 : 0);
+}
+
+// Particles per work item a store of this box uses: the two-phase 3D kernel
+// holds at most pic_gpd_split_chunk() per item.
+int store_chunk(const GridDesc& g, int chunk) {
+  return pic_gpd_split(g) ? std::min(chunk, pic_gpd_split_chunk()) : chunk;
+}
 
 struct Sim {
   int num_cu = kNumCU;  // compute units of the device
@@ -190,6 +202,14 @@ pic_status setup_grid(Sim& S, const pic_config& c, int sort_interval, GridDesc& 
     g.slack = std::max(g.slack, g.slk[d]);
   }
   region_guards(g.order, g.fa, g.fb, g.ja, g.jb);
+  if (pic_gpd_split(g)) {
+    // the two-phase kernel stages only what the shapes reach, one node less
+    // above than the one-phase kernel: gather taps reach cell offsets
+    // [-fa, fb] (orders 1/2/3: [-1,1], [-1,2], [-2,2]) and the deposit
+    // window [-ja, jb] ([-1,2], [-2,3], [-2,3]) of the particle's cell
+    g.fb -= 1;
+    g.jb -= 1;
+  }
   g.ntiles = 1;
   for (int d = 0; d < 3; d++) {
     if (d >= c.ndim) {
@@ -199,7 +219,10 @@ pic_status setup_grid(Sim& S, const pic_config& c, int sort_interval, GridDesc& 
     }
     const int need = g.slk[d] + 2;
     int t = c.tile[d];
-    if (t == 0) t = pick_tile(g.nx[d], c.ndim == 2 ? 16 : 8, need);
+    // default extents: 16 in 2D; in 3D 4 for the two-phase kernel (a tile of
+    // 4x4x4 cells holds the 256-512 particles of one work item at 4-8 per
+    // cell), 8 otherwise
+    if (t == 0) t = pick_tile(g.nx[d], c.ndim == 2 ? 16 : (pic_gpd_split(g) ? 4 : 8), need);
     if (!tile_ok(g.nx[d], t, need))
       return S.fail(PIC_E_INVALID, "tile[%d]=%d does not suit nx=%d (needs >= %d cells per tile and per remainder)",
                     d, t, g.nx[d], need);
@@ -339,8 +362,8 @@ pic_status alloc_species(Sim& S, Instance& I, Species& sp, int64_t cap, int chun
   StoreDesc& d = sp.desc;
   memset(&d, 0, sizeof d);
   d.g = g;
-  d.chunk = chunk;
-  d.max_items = (int)std::min<int64_t>((int64_t)g.ntiles + cap / chunk + 1, 0x7fffffff);
+  d.chunk = store_chunk(g, chunk);
+  d.max_items = (int)std::min<int64_t>((int64_t)g.ntiles + cap / d.chunk + 1, 0x7fffffff);
   sp.max_items = d.max_items;
   pic_status st;
 #define AL(ptr, n) \
@@ -392,7 +415,7 @@ pic_status refresh_descriptors(Sim& S) {
   S.igroups.clear();
   for (int dim = 2; dim <= 3; dim++)
     for (int order = 1; order <= 3; order++)
-      for (int mode = 0; mode <= 3; mode++) {
+      for (int mode = 0; mode <= 4; mode++) {
       Group gr{dim, order, (int)stores.size(), 0, 0, 0, 0, 0, 0, false, {0, 0, 0}, 0, false};
       gr.mode = mode;
       for (size_t i = 0; i < S.inst.size(); i++) {
@@ -1592,7 +1615,7 @@ pic_status apply_layout(Sim& S, const std::vector<pic_config>& cfgs, int si, con
   std::vector<Binned> bins((size_t)ni * PIC_MAX_SPECIES);
   parallel_for(ni * PIC_MAX_SPECIES, [&](int k) {
     const int i = k / PIC_MAX_SPECIES, s = k % PIC_MAX_SPECIES;
-    if (S.inst[i].sp[s].used) bin_particles(gs[i], cfgs[i].chunk, snap.parts[i][s], bins[k]);
+    if (S.inst[i].sp[s].used) bin_particles(gs[i], store_chunk(gs[i], cfgs[i].chunk), snap.parts[i][s], bins[k]);
   });
   for (int i = 0; i < ni; i++) {
     Instance& I = S.inst[i];
