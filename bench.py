@@ -4,14 +4,17 @@
 Metric: particle pushes per second (one push = gather + Boris push + advance +
 charge-conserving deposit of one particle), whole step included (the Yee
 field solve and the rebin checks run inside the timed region), inputs already
-resident in HBM.  Workload (default): the 2D3V laser-wakefield case, 1024x256
-cells, 2,097,152 electrons, quadratic shape, with the layout the autotuner
-picks.  A second leg times the batched scan (64 independent 2D thermal
-instances of uneven grids and particle counts advanced by the batched step)
-against the same instances run plain one after another.  Prints one JSON line.
+resident in HBM.  Headline workload (default): the 3D3V uniform thermal
+plasma of 512x256x256 cells, 134,217,728 electrons, cubic shape, timed after
+100 untimed steps in the layout the autotuner picks for it.  Further legs:
+the 2D3V laser wakefield (1024x256 cells, 2,097,152 electrons, quadratic,
+autotuned in the run), the batched scan (64 independent 2D thermal instances
+of uneven grids and particle counts advanced by the batched step) against the
+same instances run plain one after another, and the FP64 CPU oracle on the
+host's cores.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload lwfa2d|thermal2d|beam3d|cubic3d]
-                  [--no-batched] [--no-cpu-baseline] [--tune-steps T]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cubic3d|lwfa2d|thermal2d|beam3d]
+                  [--no-lwfa] [--no-batched] [--no-cpu-baseline] [--tune-steps T] [--tune-headline]
 """
 from __future__ import annotations
 
@@ -62,63 +65,97 @@ def bytes_per_push(wl):
     return particle + 36.0 / ppc
 
 
-def cpu_baseline(wl, max_particles, min_seconds=10.0, max_steps=20):
-    """Time the FP64 oracle (single thread, as it stands) on consecutive full
-    steps of a bounded sample of the workload's particles, until about
-    min_seconds of CPU work."""
+def _host_cpu():
+    """Host CPU model and core counts as the OS reports them."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"model": model, "nproc": os.cpu_count() or 1, "usable": usable}
+
+
+def _oracle_steps(job):
+    """One worker of the CPU baseline: the FP64 oracle as it stands, stepped on
+    its own share of the particles over its own copy of the grid; returns
+    (particles, steps, seconds spent inside the oracle's step)."""
+    import numpy as np
+    import oracle
+
+    dim, nx, dx, dt, order, x, u, w, qm, steps = job
+    g = oracle.Grid(dim=dim, nx=nx, dx=dx, dt=dt, order=order)
+    E = np.zeros((3, g.ncell))
+    B = np.zeros((3, g.ncell))
+    t = 0.0
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        r = oracle.step(g, x, u, w, qm, E, B)
+        t += time.perf_counter() - t0
+        x, u, E, B = r.x, r.u, r.E, r.B
+    return len(w), steps, t
+
+
+def cpu_baseline(wl, target_s=10.0, max_workers=16):
+    """The FP64 oracle (as it stands, no tuning) on a bounded random sample of
+    the workload's particles, on its own grid: first one thread, then one
+    process per usable host core (at most max_workers), each stepping its own
+    disjoint sample.  Each leg is sized to about target_s of work."""
+    import multiprocessing as mp
+
     import numpy as np
     import oracle
 
     oracle.build(force=False)
-    g = oracle.Grid(dim=wl.ndim, nx=wl.nx, dx=wl.dx, dt=wl.dt, order=wl.order)
-    n = min(wl.n, max_particles)
-    idx = np.arange(wl.n) if n == wl.n else np.random.default_rng(0).choice(wl.n, n, replace=False)
-    x, u, w = wl.x[idx], wl.u[idx], wl.w[idx]
-    E = wl.E if wl.E is not None else np.zeros((3, wl.ncell))
-    B = wl.B if wl.B is not None else np.zeros((3, wl.ncell))
-    t = 0.0
-    steps = 0
-    while steps < max_steps and (steps == 0 or t < min_seconds):
-        t0 = time.perf_counter()
-        r = oracle.step(g, x, u, w, 1.0 / wl.rqm, E, B)
-        t += time.perf_counter() - t0
-        x, u, E, B = r.x, r.u, r.E, r.B
-        steps += 1
-    what = "all" if n == wl.n else "a random sample of"
+    rng = np.random.default_rng(0)
+    qm = 1.0 / wl.rqm
+    spec = (wl.ndim, wl.nx, wl.dx, wl.dt, wl.order)
+
+    def sample(n):
+        return np.sort(rng.choice(wl.n, n, replace=False))
+
+    # calibrate the cost per particle-step on a small sample
+    n0 = min(wl.n, 4096)
+    idx = sample(n0)
+    _, _, t0 = _oracle_steps(spec + (wl.x[idx], wl.u[idx], wl.w[idx], qm, 1))
+    per = max(t0 / n0, 1e-9)
+    n1 = int(min(wl.n, max(n0, target_s / per)))
+    idx = sample(n1)
+    n, k, t1 = _oracle_steps(spec + (wl.x[idx], wl.u[idx], wl.w[idx], qm, 1))
+    single = n * k / t1
+
+    host = _host_cpu()
+    P = max(1, min(max_workers, host["usable"]))
+    share = int(min(n1, wl.n // P))
+    perm = rng.permutation(wl.n)[: share * P]
+    jobs = []
+    for j in range(P):
+        ix = np.sort(perm[j * share:(j + 1) * share])
+        jobs.append(spec + (wl.x[ix], wl.u[ix], wl.w[ix], qm, 1))
+    ctx = mp.get_context("spawn")  # fresh interpreters: no GPU state is inherited
+    with ctx.Pool(P) as pool:
+        res = pool.map(_oracle_steps, jobs, chunksize=1)
+    tmax = max(r[2] for r in res)
+    multi = sum(r[0] * r[1] for r in res) / tmax
     return {
-        "value": n * steps / t,
+        "value": multi,
         "unit": "particle pushes/s",
-        "cores": 1,
+        "cores": P,
         "kind": "oracle",
-        "sample": f"{steps} consecutive FP64 oracle steps (gather, push, deposit, field solve) of {what} {n} "
-                  f"particles of the workload, single thread, {t:.1f} s",
+        "sample": f"FP64 oracle step (gather, push, deposit, field solve on the {'x'.join(map(str, wl.nx))} grid) "
+                  f"of random particle samples of the workload: {P} processes, each stepping its own "
+                  f"{share} particles once ({tmax:.1f} s for the slowest); single thread: {n1} particles, "
+                  f"{t1:.1f} s",
+        "single_thread_value": single,
+        "host": host,
     }
-
-
-def measured_traffic(wl, info, kernel_avg_s):
-    """HBM traffic of the particle kernel in GB/s from the committed counter
-    record (rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by
-    what the same counter reads for a plain device copy of known size), or
-    None when no record matches this workload and layout or the kernel's
-    source changed since the counters were taken."""
-    import hashlib
-
-    path = os.path.join(ROOT, "profiles", "gpd_lwfa2d_1024x256_counters.json")
-    if not os.path.exists(path):
-        return None
-    rec = json.load(open(path))
-    h = hashlib.sha256()
-    for f in ["gpd.hip", "pic_dev.h"]:
-        with open(os.path.join(ROOT, "paper_1503_00276_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    if rec.get("source_sha256") != h.hexdigest() or rec.get("workload_name") != wl.name:
-        return None
-    for e in rec.get("layouts", []):
-        if (list(e["tile"]) == list(info.tile)[:wl.ndim] and e["sort_interval"] == info.sort_interval
-                and e["chunk"] == info.chunk):
-            kib = e["fetch_kib_per_dispatch"] * rec["fetch_scale"] + e["write_kib_per_dispatch"] * rec["write_scale"]
-            return kib * 1024.0 / kernel_avg_s / 1e9
-    return None
 
 
 def algorithmic_bytes(n, ndim, ncell):
@@ -221,23 +258,174 @@ def run_batched(args, pic, stream):
     }
 
 
+# Layout of the headline workload when the benchmark does not tune it: the
+# one pic_autotune picked for it (profiles/ holds the search), since a search
+# over 134 M particles re-bins them on the host for every candidate and takes
+# minutes.  --tune-headline runs the search instead.
+DEFAULT_LAYOUT = {
+    "cubic3d": {"tile": [4, 4, 4], "sort_interval": 1, "chunk": 512},
+}
+
+
+def counter_record(wl, info):
+    """The committed rocprofv3 counter record of the particle kernel for this
+    workload and layout (FETCH_SIZE, WRITE_SIZE and SQ_INSTS_VALU per
+    dispatch), or None when there is none or the kernel's source changed
+    since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"gpd_{wl.name}_counters.json")
+    if not os.path.exists(path):
+        return None, None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in ["gpd.hip", "pic_dev.h"]:
+        with open(os.path.join(ROOT, "paper_1503_00276_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if rec.get("source_sha256") != h.hexdigest() or rec.get("workload_name") != wl.name:
+        return rec, None
+    for e in rec.get("layouts", []):
+        if (list(e["tile"]) == list(info.tile)[:wl.ndim] and e["sort_interval"] == info.sort_interval
+                and e["chunk"] == info.chunk):
+            return rec, e
+    return rec, None
+
+
+def roofline(wl, info, gpd_avg_s):
+    """HBM roofline of the particle kernel (algorithmic bytes over its average
+    launch time) with the counter-measured traffic and, for the kernels whose
+    arithmetic bounds them, the VALU issue fraction: measured VALU wave
+    instructions per launch against one wave instruction per cycle per CU
+    (256 CUs at 2.4 GHz; packed FP32 is not used, so this is 78.6 TFLOP/s of
+    FMA)."""
+    bpp = bytes_per_push(wl)
+    achieved = wl.n * bpp / gpd_avg_s / 1e9
+    rec, e = counter_record(wl, info)
+    traffic = valu = None
+    if e is not None:
+        kib = e["fetch_kib_per_dispatch"] * rec["fetch_scale"] + e["write_kib_per_dispatch"] * rec["write_scale"]
+        traffic = kib * 1024.0 / gpd_avg_s / 1e9
+        if "valu_insts_per_dispatch" in e:
+            issue = e["valu_insts_per_dispatch"] / gpd_avg_s
+            peak = 256 * 2.4e9
+            valu = {"insts_per_launch": e["valu_insts_per_dispatch"], "achieved_insts_per_s": issue,
+                    "peak_insts_per_s": peak, "frac": issue / peak,
+                    "insts_per_push": e["valu_insts_per_dispatch"] * 64.0 / wl.n}
+    return {
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": traffic,
+        "kernel": "gpd_kernel (fused gather+push+deposit)",
+        "bytes_per_push": bpp,
+        "kernel_avg_us": gpd_avg_s * 1e6,
+        "kernel_pushes_per_s": wl.n / gpd_avg_s,
+        "valu": valu,
+    }
+
+
+def plain_leg(args, pic, stream, name, steps, layout=None, tune=True):
+    """One workload on the plain single-instance path: load, untimed steps,
+    optionally the autotuner, then 'steps' timed steps and a profiled run."""
+    log(f"[{name}] generating")
+    wl = make_workload(name)
+    lay = layout or {}
+    tile = list(lay.get("tile", []))
+    cfg = pic.Config(ndim=wl.ndim, nx=wl.nx, dx=wl.dx, dt=wl.dt, shape_order=wl.order,
+                     ion_density=wl.ion_density, tile=tuple(tile + [0] * (3 - len(tile))),
+                     chunk=lay.get("chunk", 0), sort_interval=lay.get("sort_interval", 0))
+    sim = pic.Pic(cfg, stream=stream)
+    log(f"[{name}] loading {wl.n} particles")
+    sim.load_particles(wl.x, wl.u, wl.w, rqm=wl.rqm)
+    if wl.E is not None:
+        sim.load_fields(wl.E, wl.B)
+    sim.step(args.warmup)
+    sim.sync()
+    # tuned (and timed) on a developed state: the loaded state is quieter than
+    # the run it starts (the wake, its density spikes, particles strayed from
+    # their tiles)
+    sim.step(args.tune_after)
+    sim.sync()
+    tuned = None
+    if tune and args.tune_steps > 0:
+        log(f"[{name}] autotune")
+        tuned = sim.autotune(trial_steps=args.tune_steps)
+        sim.step(args.warmup)
+        sim.sync()
+    info = sim.info()
+    log(f"[{name}] timing {steps} steps")
+    elapsed = timed_steps(sim, stream, steps)
+    log(f"[{name}] profiling {args.profile_steps} steps")
+    sim.profile(2)
+    sim.step(args.profile_steps)
+    kt = sim.kernel_times()
+    sim.profile(0)
+    sim.sync()
+    gpd_avg_s = kt["particle"][0] / max(kt["particle"][1], 1) / 1000.0
+    counts = sim.counts()
+    # charge conservation of the benched layout, from the GPU's FP64
+    # diagnostics: max|C| dt / max|rho_e| over one step
+    sim.rho_snapshot()
+    rho_e = sim.rho() - wl.ion_density
+    sim.step(1)
+    C = sim.charge_residual()
+    import numpy as np
+
+    charge_rel = float(np.abs(C).max() * wl.dt / max(np.abs(rho_e).max(), 1e-300))
+    sim.close()
+    rec = {
+        "value": wl.n * steps / elapsed,
+        "unit": "particle pushes/s",
+        "ms_per_step": elapsed * 1000.0 / steps,
+        "steps": steps,
+        "config": {
+            "workload": wl.name,
+            "cells": list(wl.nx),
+            "particles": wl.n,
+            "shape_order": wl.order,
+            "dt": wl.dt,
+            "dx": list(wl.dx),
+            "tile": list(info.tile)[:wl.ndim],
+            "sort_interval": info.sort_interval,
+            "chunk": info.chunk,
+            "slack": info.slack,
+            "lds_bytes": int(info.lds_bytes),
+            "autotune": tuned,
+            "layout_from": "autotuned in this run" if tuned else (
+                "the autotuner's pick for this workload (fixed)" if layout else "library defaults"),
+            "rebins_done": int(counts[2]),
+            "rebin_checks": int(counts[3]),
+        },
+        "roofline": roofline(wl, info, gpd_avg_s),
+        "kernel_times_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in kt.items()},
+        "charge_residual_rel": charge_rel,
+    }
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="lwfa2d")
-    ap.add_argument("--profile-steps", type=int, default=48)  # whole cycles of every sort interval searched
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="cubic3d")
+    ap.add_argument("--profile-steps", type=int, default=24)  # whole cycles of every sort interval searched
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=2_097_152)
     ap.add_argument("--tune-steps", type=int, default=24,
                     help="steps the autotuner times per candidate layout, rounded up to whole sort "
                          "cycles (0: no autotune); 24 holds whole cycles of every interval searched")
     ap.add_argument("--tune-after", type=int, default=100,
-                    help="untimed steps run before the autotuner, so it tunes the developed state")
-    ap.add_argument("--tile", type=int, nargs="+", default=None, help="tile extents (default: automatic)")
+                    help="untimed steps run before the autotuner (and the timing), so it tunes the "
+                         "developed state")
+    ap.add_argument("--tune-headline", action="store_true",
+                    help="run the autotuner on the headline workload too (slow on 134 M particles)")
+    ap.add_argument("--tile", type=int, nargs="+", default=None, help="headline tile extents")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--sort-interval", type=int, default=0)
+    ap.add_argument("--no-lwfa", action="store_true", help="skip the 2D laser-wakefield leg")
+    ap.add_argument("--lwfa-steps", type=int, default=200)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--only-batched", action="store_true",
                     help="run only the batched leg and print its record (for profiling)")
@@ -263,47 +451,13 @@ def main():
         print(json.dumps(run_batched(args, pic, stream)), flush=True)
         return
 
-    log(f"generating workload {args.workload}")
-    wl = make_workload(args.workload)
-    cfg = pic.Config(ndim=wl.ndim, nx=wl.nx, dx=wl.dx, dt=wl.dt, shape_order=wl.order,
-                     ion_density=wl.ion_density, tile=tuple((args.tile or []) + [0] * (3 - len(args.tile or []))),
-                     chunk=args.chunk, sort_interval=args.sort_interval)
-    sim = pic.Pic(cfg, stream=stream)
-    log(f"loading {wl.n} particles")
-    sim.load_particles(wl.x, wl.u, wl.w, rqm=wl.rqm)
-    if wl.E is not None:
-        sim.load_fields(wl.E, wl.B)
-    log(f"warmup {args.warmup} steps")
-    sim.step(args.warmup)
-    sim.sync()
-    tune = None
-    if args.tune_steps > 0:
-        # tuned on a developed state (the loaded state of a driven plasma is
-        # quieter than the run it starts: the wake, its density spikes and the
-        # face crossings come later)
-        sim.step(args.tune_after)
-        log("autotune")
-        tune = sim.autotune(trial_steps=args.tune_steps)
-        sim.step(args.warmup)
-        sim.sync()
-    info = sim.info()
-
-    log(f"timing {args.steps} steps")
-    elapsed = timed_steps(sim, stream, args.steps)
-    value = wl.n * args.steps / elapsed
-
-    # per-kernel times: the same steps launched one by one with HIP events
-    log(f"profiling {args.profile_steps} steps")
-    sim.profile(2)
-    sim.step(args.profile_steps)
-    kt = sim.kernel_times()
-    sim.profile(0)
-    sim.sync()
-    gpd_ms, gpd_n = kt["particle"]
-    gpd_avg_s = gpd_ms / max(gpd_n, 1) / 1000.0
-    bpp = bytes_per_push(wl)
-    achieved = wl.n * bpp / gpd_avg_s / 1e9
-    counts = sim.counts()
+    layout = None
+    if args.tile or args.chunk or args.sort_interval:
+        layout = {"tile": args.tile or [], "chunk": args.chunk, "sort_interval": args.sort_interval}
+    elif not args.tune_headline:
+        layout = DEFAULT_LAYOUT.get(args.workload)
+    head = plain_leg(args, pic, stream, args.workload, args.steps, layout,
+                     tune=args.tune_headline or (layout is None and args.workload not in DEFAULT_LAYOUT))
 
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * 1024 * 1024 // 4
@@ -314,7 +468,9 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    sim.close()
+    lwfa = None
+    if not args.no_lwfa and args.workload != "lwfa2d":
+        lwfa = plain_leg(args, pic, stream, "lwfa2d", args.lwfa_steps, None, tune=True)
     batched = None
     if not args.no_batched:
         batched = run_batched(args, pic, stream)
@@ -322,49 +478,29 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
-        cpu = cpu_baseline(wl, args.cpu_sample)
+        cwl = make_workload("cubic3d_sub" if args.workload == "cubic3d" else args.workload)
+        cpu = cpu_baseline(cwl)
+        if args.workload == "cubic3d":
+            cpu["sample"] += " (the 64^3 sub-run of the workload: same density, shape, cell and time step)"
 
     out = {
         "metric": "particle pushes/sec (gather+push+deposit) and % HBM roofline, plain vs batched, 1 GPU",
-        "value": value,
+        "value": head["value"],
         "unit": "particle pushes/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed * 1000.0 / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {
-            "workload": wl.name,
-            "cells": list(wl.nx),
-            "particles": wl.n,
-            "shape_order": wl.order,
-            "dt": wl.dt,
-            "dx": list(wl.dx),
-            "tile": list(info.tile)[:wl.ndim],
-            "sort_interval": info.sort_interval,
-            "chunk": info.chunk,
-            "slack": info.slack,
-            "autotune": tune,
-            "rebins_done": int(counts[2]),
-            "rebin_checks": int(counts[3]),
-        },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(wl, info, gpd_avg_s),
-            "kernel": "gpd_kernel (fused gather+push+deposit)",
-            "bytes_per_push": bpp,
-            "kernel_avg_us": gpd_avg_s * 1e6,
-            "kernel_pushes_per_s": wl.n / gpd_avg_s,
-        },
-        "kernel_times_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in kt.items()},
+        "config": head["config"],
+        "roofline": head["roofline"],
+        "kernel_times_ms_per_step": head["kernel_times_ms_per_step"],
+        "charge_residual_rel": head["charge_residual_rel"],
+        "lwfa2d": lwfa,
         "batched": batched,
         "cpu_baseline": cpu,
     }

@@ -118,9 +118,10 @@ typedef struct {
    * removed.  After every step that brings c t past the next whole cell
    * (floor(n dt / dx1) shifts after n steps) the window moves by one cell:
    * the back cell column is discarded with its particles, and the new front
-   * column starts with E = B = 0 and a cold plasma of species 0:
+   * column starts with E = B = 0 and a plasma of species 0:
    * inject_ppc[d] particles per cell per axis on a regular sub-lattice
-   * ((k + 1/2) / inject_ppc[d] of the cell), u = 0, weight inject_w.  The
+   * ((k + 1/2) / inject_ppc[d] of the cell), weight inject_w, at rest or, with
+   * inject_uth > 0, thermal (see inject_uth below).  The
    * sort interval is 1.  Positions exported and loaded are lab positions
    * (xmin1 + shifts dx1 + window position); grid arrays exported and loaded
    * are in window order (index 0 at the back).  Species 0 must be loaded
@@ -161,6 +162,18 @@ typedef struct {
    * and those at and beyond the wall zero, J_r stays zero on the axis.  Not
    * available with pic_autotune. */
   int32_t geometry;
+  /* Thermal injection at the moving window's front (Sec. 4.5: the new
+   * region is initialised thermal): each component of an injected
+   * particle's momentum is inject_uth times a standard normal deviate drawn
+   * from its id, u_c = inject_uth sqrt(-2 ln U1) cos(2 pi U2) (Box-Muller)
+   * with U1 = (floor(o(8 id + 2c + 1) / 2^11) + 1) 2^-53 and
+   * U2 = floor(o(8 id + 2c + 2) / 2^11) 2^-53, where o(n) is the n-th output
+   * of the SplitMix64 generator (Steele, Lea and Flood 2014) seeded with
+   * inject_seed, computed in FP64.  Injected ids
+   * continue after the loaded ones, one per lattice point of each new
+   * column (points below the r-z axis included).  0: a cold plasma. */
+  double inject_uth;
+  uint64_t inject_seed;
 } pic_config;
 
 #define PIC_MAX_SMOOTH 8

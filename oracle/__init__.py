@@ -23,6 +23,8 @@ from .oracle import (  # noqa: F401
     smooth_current,
     step_window,
     window_shifts,
+    splitmix64,
+    thermal_normal,
     step_cyl,
     cyl_wall,
 )

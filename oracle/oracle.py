@@ -1,9 +1,12 @@
 """ctypes loader for the FP64 C oracle ``pic_oracle.c``.
 
 TEST INFRASTRUCTURE ONLY: only ``tests/``, ``__graft_entry__.smoke()`` and the
-``cpu_baseline`` leg of ``bench.py`` may use it.  Every function here is
-argument marshalling around the C routine of the same name; the arithmetic
-lives in ``pic_oracle.c`` (which cites the dissertation's Ch. 3 passages).
+``cpu_baseline`` leg of ``bench.py`` may use it.  Most functions here are
+argument marshalling around the C routine of the same name, whose arithmetic
+lives in ``pic_oracle.c`` (which cites the dissertation's Ch. 3 passages);
+the moving window's bookkeeping (``step_window``: removal, shift, injection)
+and the generator of thermally injected momenta (``splitmix64``,
+``thermal_normal``) are written here in numpy.
 """
 from __future__ import annotations
 
@@ -69,6 +72,8 @@ class Grid:
     window: int = 0       # 1: moving window along x1 (see step_window)
     inject_ppc: tuple = (1, 1, 1)  # moving window: injected particles per cell, per axis
     inject_w: float = 0.0          # moving window: weight of an injected particle
+    inject_uth: float = 0.0        # moving window: thermal spread of the injected momenta (0: at rest)
+    inject_seed: int = 0           # moving window: seed of their generator (see thermal_normal)
     cyl: int = 0          # 1: 2D cylindrically symmetric r-z box (x1 = z, x2 = r; see step_cyl)
 
     def c(self) -> _Grid:
@@ -271,7 +276,33 @@ def window_shifts(g: Grid, n: int) -> int:
     return int(math.floor(n * (g.dt / g.dx[0])))
 
 
-def step_window(g: Grid, n: int, x, u, w, qm, E, B) -> StepResult:
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+
+
+def splitmix64(seed: int, n) -> np.ndarray:
+    """Outputs n (>= 1, array) of the SplitMix64 generator seeded with 'seed'
+    (Steele, Lea and Flood, "Fast splittable pseudorandom number generators",
+    OOPSLA 2014): state_n = seed + n * 0x9e3779b97f4a7c15 (mod 2^64), output
+    the state mixed by two xor-shift-multiply rounds and a final xor-shift."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + np.asarray(n, dtype=np.uint64) * _GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def thermal_normal(seed: int, ids, c: int) -> np.ndarray:
+    """Standard normal deviates for component c of particles 'ids' by the
+    Box-Muller transform (1958) of U1 in (0, 1] and U2 in [0, 1), the top 53
+    bits of SplitMix64 outputs 8 id + 2c + 1 and 8 id + 2c + 2."""
+    ids = np.asarray(ids, dtype=np.uint64)
+    n = np.uint64(8) * ids + np.uint64(2 * c)
+    u1 = ((splitmix64(seed, n + np.uint64(1)) >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
+    u2 = (splitmix64(seed, n + np.uint64(2)) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * math.pi * u2)
+
+
+def step_window(g: Grid, n: int, x, u, w, qm, E, B, id0: int = 0) -> StepResult:
     """One PIC step of a box whose window moves along x1 at c (Sec. 4.5).
 
     x are positions relative to the window's current lower corner.  The step
@@ -281,10 +312,12 @@ def step_window(g: Grid, n: int, x, u, w, qm, E, B) -> StepResult:
       2. if the window moves after this step (n -> n+1), every grid array
          moves down by one x1 cell, the new front cell column gets zero E, B
          (and J), particles move by -dx1 and those that fall behind the window
-         are removed, and a cold plasma is initialised in the front column:
-         inject_ppc per axis on a regular sub-lattice of each cell, u = 0,
-         weight inject_w, cells in increasing linear index, lattice points
-         with axis 1 fastest.
+         are removed, and a plasma is initialised in the front column:
+         inject_ppc per axis on a regular sub-lattice of each cell, weight
+         inject_w, cells in increasing linear index, lattice points with
+         axis 1 fastest; the injected particles take ids id0, id0 + 1, ...
+         in that order and momenta inject_uth * thermal_normal(inject_seed,
+         id, c) per component (u = 0 for inject_uth = 0: a cold plasma).
     Returns x, u, w of the survivors (in input order) followed by the
     injected particles, E, B, J, and 'keep', the survivors' input indices.
     In the r-z geometry (x = (z, r)) particles that reach the wall are
@@ -335,14 +368,20 @@ def step_window(g: Grid, n: int, x, u, w, qm, E, B) -> StepResult:
                     cells.append((g.nx[0] - 1, j, k))
         newx = np.concatenate([(np.asarray(c, dtype=float) + offs) * np.asarray(g.dx[:d]) for c in cells])
         neww = np.full(len(newx), float(g.inject_w))
+        ids = int(id0) + np.arange(len(newx))
         if g.cyl:
             # cell coordinate r/dr + 1/2: drop the points below the axis
             newx[:, 1] -= 0.5 * g.dx[1]
             ok = newx[:, 1] >= 0.0
             newx = newx[ok]
+            ids = ids[ok]
             neww = float(g.inject_w) * newx[:, 1] / g.dx[1]
+        newu = np.zeros((len(newx), 3))
+        if g.inject_uth > 0.0:
+            for c in range(3):
+                newu[:, c] = g.inject_uth * thermal_normal(g.inject_seed, ids, c)
         x1 = np.concatenate([x1, newx])
-        u1 = np.concatenate([u1, np.zeros((len(newx), 3))])
+        u1 = np.concatenate([u1, newu])
         w1 = np.concatenate([w1, neww])
     return StepResult(x=x1, u=u1, E=E1, B=B1, J=J1), w1, keep
 

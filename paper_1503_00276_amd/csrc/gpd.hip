@@ -89,9 +89,10 @@ __device__ __forceinline__ void gather_weights(float eps, bool half, int& base, 
 // Old shape S0 on a window of ORDER+2 nodes starting at node 'base' (relative
 // to the particle's old cell) and the change D = S1 - S0 on that window, for
 // a move from offset e0 in the old cell to offset e1 in the cell c (-1,0,1)
-// cells away.  When no knot of the shape is crossed D is formed from factored
-// differences (proportional to the displacement), keeping full FP32 relative
-// accuracy for small moves; otherwise D = S1 - S0 directly.
+// cells away.  D is formed from factored differences (proportional to the
+// displacement, or, for a move across a knot of the shape, to the distances
+// on either side of the knot), keeping full FP32 relative accuracy for short
+// moves.
 // p0 (0 or 1) is the window position of the old shape's first node and wide
 // is true when the new shape's support is shifted by one node (the union
 // then fills all ORDER+2 window positions; otherwise D vanishes outside the
@@ -156,18 +157,24 @@ __device__ __forceinline__ void deposit_shape(float e0, float e1, int c, int& ba
       } else {
         D[1] = v0; D[2] = v1; D[3] = v2;
       }
+    } else if (n1 > n0) {
+      // the move crosses the half-node x_k = n0 + 1/2, a knot of every node's
+      // spline in the window: each difference is taken on the two pieces on
+      // either side of x_k, factored by the distances a = x_k - x0 and
+      // b = x1 - x_k (exact near the crossing), so a short move keeps its
+      // relative precision
+      const float a = 0.5f - t0, b = t1 + 0.5f;
+      D[0] = -0.5f * a * a;
+      D[1] = -a * (0.5f + t0) - 0.5f * b * (2.0f - b);
+      D[2] = 0.5f * a * (1.5f + t0) + b * (1.0f - b);
+      D[3] = 0.5f * b * b;
     } else {
-      int p1 = n1 - 1 - base;
-      float a1 = 0.5f - t1, b1 = 0.5f + t1;
-      float u0 = 0.5f * a1 * a1, u1 = 0.75f - t1 * t1, u2 = 0.5f * b1 * b1;
-      float S1[W] = {0.0f, 0.0f, 0.0f, 0.0f};
-      if (p1 == 0) {
-        S1[0] = u0; S1[1] = u1; S1[2] = u2;
-      } else {
-        S1[1] = u0; S1[2] = u1; S1[3] = u2;
-      }
-#pragma unroll
-      for (int k = 0; k < W; k++) D[k] = S1[k] - S0[k];
+      // mirror image: crossing x_k = n0 - 1/2 to the left
+      const float a = t0 + 0.5f, b = 0.5f - t1;
+      D[0] = 0.5f * b * b;
+      D[1] = 0.5f * a * (1.5f - t0) + b * (1.0f - b);
+      D[2] = -a * (0.5f - t0) - 0.5f * b * (2.0f - b);
+      D[3] = -0.5f * a * a;
     }
   } else {
     // old nodes -1..2 (floor = 0), new nodes c-1..c+2
@@ -192,19 +199,24 @@ __device__ __forceinline__ void deposit_shape(float e0, float e1, int c, int& ba
       D[1] = d * (0.5f * q - s);
       D[2] = (0.5f * d) * (1.0f + s - q);
       D[3] = (d * s6) * q;
+    } else if (c > 0) {
+      // the move crosses the cell face x_k = 1, a knot of every node's spline
+      // in the window: each difference is taken on the pieces on either side
+      // of it, factored by a = 1 - e0 and b = e1 (exact near the crossing)
+      const float a = 1.0f - e0, b = e1;
+      D[0] = -(a * a * a) * s6;
+      D[1] = -0.5f * a * (1.0f + a - a * a) - b * (3.0f - 3.0f * b + b * b) * s6;
+      D[2] = 0.5f * a * a * (2.0f - a) - 0.5f * b * b * (2.0f - b);
+      D[3] = a * (3.0f - 3.0f * a + a * a) * s6 + 0.5f * b * (1.0f + b - b * b);
+      D[4] = b * b * b * s6;
     } else {
-      int p1 = c - 1 - base;
-      float g1 = 1.0f - e1, h2 = e1 * e1, h3 = h2 * e1;
-      float u0 = g1 * g1 * g1 * s6, u1 = (4.0f - 6.0f * h2 + 3.0f * h3) * s6;
-      float u2 = (1.0f + 3.0f * e1 + 3.0f * h2 - 3.0f * h3) * s6, u3 = h3 * s6;
-      float S1[W] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-      if (p1 == 0) {
-        S1[0] = u0; S1[1] = u1; S1[2] = u2; S1[3] = u3;
-      } else {
-        S1[1] = u0; S1[2] = u1; S1[3] = u2; S1[4] = u3;
-      }
-#pragma unroll
-      for (int k = 0; k < W; k++) D[k] = S1[k] - S0[k];
+      // mirror image: crossing the face x_k = 0 to the left, a = e0, b = 1 - e1
+      const float a = e0, b = 1.0f - e1;
+      D[0] = b * b * b * s6;
+      D[1] = a * (3.0f - 3.0f * a + a * a) * s6 + 0.5f * b * (1.0f + b - b * b);
+      D[2] = 0.5f * a * a * (2.0f - a) - 0.5f * b * b * (2.0f - b);
+      D[3] = -0.5f * a * (1.0f + a - a * a) - b * (3.0f - 3.0f * b + b * b) * s6;
+      D[4] = -(a * a * a) * s6;
     }
   }
 }
@@ -215,28 +227,53 @@ __device__ __forceinline__ void deposit_shape(float e0, float e1, int c, int& ba
 // in units of 1/scale (|v*scale| < 2^30) and summed exactly in int64.
 typedef unsigned long long acc_t;
 
-// v is already in units of the fixed point (the scale is folded into the
-// per-particle prefactors); the conversion truncates (error < 1 unit).
+// floor(x + 1/2) as an int32 in one instruction (round half up)
+__device__ __forceinline__ int cvt_rpi(float x) {
+  int r;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
+// v is already in units of the fixed point (the instance's, or the work
+// item's in the two-phase 3D kernel; the scale is folded into the
+// per-particle prefactors); it is rounded to the nearest unit.
 __device__ __forceinline__ void lds_add(acc_t* p, float v) {
-  int q = (int)v;
+  const int q = cvt_rpi(v);
   if (q != 0)
     __hip_atomic_fetch_add(p, (acc_t)(long long)q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Unconditional add (for nodes whose contribution is rarely zero).
 __device__ __forceinline__ void lds_add_any(acc_t* p, float v) {
-  __hip_atomic_fetch_add(p, (acc_t)(long long)(int)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  __hip_atomic_fetch_add(p, (acc_t)(long long)cvt_rpi(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+
+// Fixed point of one work item's int64 current tile: Q = 2^e with Q b < 2^29
+// for a bound b on any single contribution (a factor 2 to spare for the FP32
+// rounding of the shape differences), so that every contribution converts
+// to an int32; e = 0 when nothing can be deposited.
+__device__ __forceinline__ int item_exponent(float b) {
+  int ex = 0;
+  (void)frexpf(b, &ex);
+  return b > 0.0f ? min(100, max(-100, 29 - ex)) : 0;
+}
+
+// An int64 node sum times its unit, as FP32.  The low word is taken signed
+// (q = hi 2^32 + lo, lo in [-2^31, 2^31)), so a sum below 2^31 in magnitude
+// converts with a single FP32 rounding (an unsigned low word of a small
+// negative sum would sit near 2^32 and cancel against hi = -1).
+__device__ __forceinline__ float item_sum_f32(long long q, float unit) {
+  const int lo = (int)(unsigned)(q & 0xffffffffll);
+  const long long hi = (q - (long long)lo) >> 32;
+  return fmaf((float)hi, 4294967296.0f, (float)lo) * unit;
+}
+
+
 
 // The tile of the two-phase 3D kernel: v is in units of the work item's own
 // fixed point (chosen so that every single contribution stays below 2^30),
 // rounded to the nearest integer and summed exactly in int64.
-struct acc_rn {
-  acc_t v;
-};
-__device__ __forceinline__ void lds_add_any(acc_rn* p, float v) {
-  __hip_atomic_fetch_add(&p->v, (acc_t)(long long)(int)rintf(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
+
 
 // TRISTAN (Villasenor-Buneman) current of one particle for the linear shape
 // (Sec. 3.2): the straight move from offset e in the old cell by dl cells
@@ -336,17 +373,24 @@ __device__ __forceinline__ void deposit_tristan(acc_t* sJ, int jn, const int JR[
 // Coordinates of a flat index over a box of extents R[3] that advances by a
 // fixed step: kept up to date by additions, so the staging and flush loops
 // divide only once per workgroup.
+// n / d for 0 <= n < 2^20 and d >= 1 through the FP32 reciprocal: the
+// quotient (n + 1/2) / d sits at least 1/(2d) from an integer, farther than
+// the reciprocal's error of a few 2^-24 relative reaches below 2^20.
+__device__ __forceinline__ int small_div(int n, int d) {
+  return (int)(((float)n + 0.5f) * __builtin_amdgcn_rcpf((float)d));
+}
+
 struct BoxWalk {
   int x, y, z, sx, sy, sz;
   __device__ BoxWalk(int start, int step, const int R[3]) {
-    x = start % R[0];
-    int r = start / R[0];
-    y = r % R[1];
-    z = r / R[1];
-    sx = step % R[0];
-    r = step / R[0];
-    sy = r % R[1];
-    sz = r / R[1];
+    int r = small_div(start, R[0]);
+    x = start - r * R[0];
+    z = small_div(r, R[1]);
+    y = r - z * R[1];
+    r = small_div(step, R[0]);
+    sx = step - r * R[0];
+    sz = small_div(r, R[1]);
+    sy = r - sz * R[1];
   }
   __device__ void advance(const int R[3]) {
     x += sx;
@@ -370,30 +414,33 @@ __device__ __forceinline__ int wrap_fast(int v, int n) { return (unsigned)v < (u
 // of the old support (K = ORDER+1 nodes from window position p0) and the one
 // node (S-type: old shape S, change D) or face (P-type: the prefix current P
 // along the axis) outside it, which is nonzero only when the support widened.
+// The transverse factor S_B S_C + (D_B S_C + S_B D_C)/2 + D_B D_C/3 of the
+// closed form equals H_B H_C + G_B G_C with H = S + D/2 and G = D/sqrt(12),
+// so each axis carries H and G instead of S and D.
 template <int K>
 struct DepAxis {
-  float S[K], D[K];
+  float H[K], G[K];
   float P[K - 1];
-  float Se, De, Pe;
+  float He, Ge, Pe;
   int oS, oP;  // node offsets of the extras from the core origin
   bool wide;
 };
 
 // Component A of the current (flow along axis A; B, C the other axes) on one
 // block of nodes: core or extra along each axis (EA, EB, EC).  The value is
-// P_A * (S_B S_C + (D_B S_C + S_B D_C)/2 + D_B D_C/3).
+// P_A * (H_B H_C + G_B G_C).
 template <int K, int A, bool EA, bool EB, bool EC, typename Acc>
 __device__ __forceinline__ void dep3_part(Acc* J, int cb, const int st[3], const DepAxis<K> (&ax)[3]) {
   constexpr int B = (A + 1) % 3, C = (A + 2) % 3;
   constexpr int NA = EA ? 1 : K - 1, NB = EB ? 1 : K, NC = EC ? 1 : K;
 #pragma unroll
   for (int kc = 0; kc < NC; kc++) {
-    const float sc = EC ? ax[C].Se : ax[C].S[kc], dc = EC ? ax[C].De : ax[C].D[kc];
+    const float hc = EC ? ax[C].He : ax[C].H[kc], gc = EC ? ax[C].Ge : ax[C].G[kc];
     const int oc = (EC ? ax[C].oS : kc) * st[C];
 #pragma unroll
     for (int kb = 0; kb < NB; kb++) {
-      const float sb = EB ? ax[B].Se : ax[B].S[kb], db = EB ? ax[B].De : ax[B].D[kb];
-      const float T = sb * sc + 0.5f * (db * sc + sb * dc) + (1.0f / 3.0f) * db * dc;
+      const float hb = EB ? ax[B].He : ax[B].H[kb], gb = EB ? ax[B].Ge : ax[B].G[kb];
+      const float T = fmaf(hb, hc, gb * gc);
       const int ob = cb + oc + (EB ? ax[B].oS : kb) * st[B];
 #pragma unroll
       for (int ka = 0; ka < NA; ka++) {
@@ -511,9 +558,12 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
         const float sw = ry <= 0 ? -1.0f : 1.0f, sh = ry < 0 ? -1.0f : 1.0f;
         const bool iw = rw < g.nx[1], ih = rh < g.nx[1];
         const int gw = gx + g.nx[0] * rw, gh = gx + g.nx[0] * rh;
-        sF[idx] = iw ? Fg[gw] : 0.0f;
-        sF[fn + idx] = ih ? sh * Fg[(size_t)ncell + gh] : 0.0f;
-        sF[2 * fn + idx] = iw ? sw * Fg[(size_t)2 * ncell + gw] : 0.0f;
+        const float ez = iw ? Fg[gw] : 0.0f;
+        const float er = ih ? sh * Fg[(size_t)ncell + gh] : 0.0f;
+        const float et = iw ? sw * Fg[(size_t)2 * ncell + gw] : 0.0f;
+        sF[idx] = ez;
+        sF[fn + idx] = er;
+        sF[2 * fn + idx] = et;
         sF[3 * fn + idx] = ih ? Fg[(size_t)3 * ncell + gh] : 0.0f;
         sF[4 * fn + idx] = iw ? sw * Fg[(size_t)4 * ncell + gw] : 0.0f;
         sF[5 * fn + idx] = ih ? sh * Fg[(size_t)5 * ncell + gh] : 0.0f;
@@ -553,6 +603,9 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
   for (int idx = tid; idx < 3 * jn; idx += blockDim.x) sJ[idx] = 0ull;
   if (tid < PIC_NSLOT) scnt[tid] = 0;
   __syncthreads();
+  // the instance's fixed point (see the host's current scale); the two-phase
+  // 3D kernel below chooses one per work item instead
+  const float Qi = g.jscale;
 
   const float h = 0.5f * S.qm * g.dt;
   bool strayed = false, bad = false, died = false;
@@ -748,7 +801,7 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
     // ---- deposit
     if (ORDER == 1 && g.deposit == 1) {
       // TRISTAN: the straight move cut at the faces it crosses
-      const float js = g.jscale;
+      const float js = Qi;
       float dl[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int d = 0; d < DIM; d++) dl[d] = (float)mv[d] + en[d] - e[d];
@@ -767,7 +820,7 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
       acc_t* J1 = sJ;
       acc_t* J2 = sJ + jn;
       acc_t* J3 = sJ + 2 * jn;
-      const float js = g.jscale;
+      const float js = Qi;
       float q1 = -wq * g.cdt[0] * js, q2 = -wq * g.cdt[1] * js;
       float P1[W - 1], P2[W - 1];
       {
@@ -911,13 +964,17 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
             const bool pd = p0[d] != 0;
   #pragma unroll
             for (int k = 0; k < K; k++) {
-              ax[d].S[k] = pd ? S0[d][k + 1] : S0[d][k];
-              ax[d].D[k] = pd ? D[d][k + 1] : D[d][k];
+              const float sk = pd ? S0[d][k + 1] : S0[d][k], dk = pd ? D[d][k + 1] : D[d][k];
+              ax[d].H[k] = fmaf(0.5f, dk, sk);
+              ax[d].G[k] = 0.28867513f * dk;  // 1/sqrt(12)
             }
   #pragma unroll
             for (int k = 0; k < K - 1; k++) ax[d].P[k] = pd ? Pw[d][k + 1] : Pw[d][k];
-            ax[d].Se = pd ? S0[d][0] : S0[d][K];
-            ax[d].De = pd ? D[d][0] : D[d][K];
+            {
+              const float se = pd ? S0[d][0] : S0[d][K], de = pd ? D[d][0] : D[d][K];
+              ax[d].He = fmaf(0.5f, de, se);
+              ax[d].Ge = 0.28867513f * de;
+            }
             ax[d].Pe = wide[d] ? (pd ? Pw[d][0] : Pw[d][K - 1]) : 0.0f;
             ax[d].oS = pd ? -1 : K;
             ax[d].oP = pd ? -1 : K - 1;
@@ -992,7 +1049,9 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
   }
   if (tid < PIC_NSLOT) S.cnt[ii * PIC_NSLOT + tid] = scnt[tid];
 
-  // 4. fold the LDS current into the global current (periodic wrap)
+  // 4. fold the LDS current into the global current (periodic wrap): FP32
+  // atomics of the sums times the unit, or int64 atomics of the sums
+  const float qinv = g.jinv;
   BoxWalk bj(tid, blockDim.x, JR);
   for (int idx = tid; idx < jn; idx += blockDim.x, bj.advance(JR)) {
     int gx = wrap_fast(org[0] - jlo[0] + bj.x, g.nx[0]);
@@ -1011,7 +1070,7 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
         if (g.acc_mode == 2)
           atomicAdd(S.J64[jp] + gi, (acc_t)q);
         else
-          __builtin_amdgcn_global_atomic_fadd_f32((gfloat*)S.Jacc[jp] + gi, (float)((double)q * (double)g.jinv));
+          __builtin_amdgcn_global_atomic_fadd_f32((gfloat*)S.Jacc[jp] + gi, item_sum_f32(q, qinv));
       }
       continue;
     }
@@ -1026,7 +1085,7 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
           atomicAdd(S.J64[jp] + (size_t)c * ncell + gi, (acc_t)q);
         else
           __builtin_amdgcn_global_atomic_fadd_f32((gfloat*)S.Jacc[jp] + (size_t)c * ncell + gi,
-                                                  (float)((double)q * (double)g.jinv));
+                                                  item_sum_f32(q, qinv));
       }
     }
   }
@@ -1056,9 +1115,12 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
 // rounding unit follows the item's fastest particle instead of the speed of
 // light, so a slow or cold plasma keeps its relative precision.
 
-constexpr int kSplitR = 2;  // particles per thread per work item
+constexpr int kSplitR = 3;  // particles per thread per work item
 
-template <int ORDER>
+// FIXED: the LDS strides are the 12-node rows and 144-node planes that 4x4xN
+// tiles take (every shape order, stray bound 1), as compile-time constants,
+// so that the taps and adds address LDS through instruction offsets.
+template <int ORDER, bool FIXED>
 __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii, int jp, int kstep, float* smem,
                               int* scnt, float* sred) {
   constexpr int NG = ORDER + 1;  // gather taps per axis
@@ -1094,10 +1156,16 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
     FR[d] = ext[d] + 2 * sl[d] + g.fa + g.fb;
     JR[d] = ext[d] + 2 * sl[d] + g.ja + g.jb;
   }
+  // LDS layout: padded row and plane strides (fixed for the box, sized for
+  // the largest region of a sort cycle); fn / jn count the region's nodes
   const int fn = FR[0] * FR[1] * FR[2];
   const int jn = JR[0] * JR[1] * JR[2];
-  float* sF = smem;            // phase A: [6][fn]
-  acc_rn* sJ = (acc_rn*)smem;  // phase B: [3][jn]
+  const int fs0 = FIXED ? 12 : g.fs0, fs01 = FIXED ? 144 : g.fs01;
+  const int js0 = FIXED ? 12 : g.js0, js01 = FIXED ? 144 : g.js01;
+  const int fpl = fs01 * FR[2];  // one field component
+  const int jpl = js01 * JR[2];  // one current component
+  float* sF = smem;            // phase A: [6][fpl]
+  acc_t* sJ = (acc_t*)smem;    // phase B: [3][jpl]
 
   // this thread's particles: requested before the fields are staged
   int pc[R];
@@ -1130,12 +1198,14 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
     for (int base = 0; base < fn; base += 4 * nthr) {
       float v[4][6];
       int gi[4];
+      int li[4];
 #pragma unroll
       for (int q = 0; q < 4; q++) {
         const int gx = wrap_fast(org[0] - flo[0] + bw.x, g.nx[0]);
         const int gy = wrap_fast(org[1] - flo[1] + bw.y, g.nx[1]);
         const int gz = wrap_fast(org[2] - flo[2] + bw.z, g.nx[2]);
         gi[q] = gx + g.nx[0] * (gy + g.nx[1] * gz);
+        li[q] = bw.x + bw.y * fs0 + bw.z * fs01;
         bw.advance(FR);
       }
 #pragma unroll
@@ -1146,10 +1216,9 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
         }
 #pragma unroll
       for (int q = 0; q < 4; q++) {
-        const int idx = base + q * nthr + tid;
-        if (idx < fn) {
+        if (base + q * nthr + tid < fn) {
 #pragma unroll
-          for (int c = 0; c < 6; c++) sF[c * fn + idx] = v[q][c];
+          for (int c = 0; c < 6; c++) sF[c * fpl + li[q]] = v[q][c];
         }
       }
     }
@@ -1214,14 +1283,14 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
         const int sx = flo[0] + l[0] + (hx ? bh[0] : b0[0]);
         const int sy = flo[1] + l[1] + (hy ? bh[1] : b0[1]);
         const int sz = flo[2] + l[2] + (hz ? bh[2] : b0[2]);
-        const float* Fc = sF + c * fn + (sz * FR[1] + sy) * FR[0] + sx;
+        const float* Fc = sF + c * fpl + sz * fs01 + sy * fs0 + sx;
         float acc = 0.0f;
 #pragma unroll
         for (int k = 0; k < NG; k++) {
           float pl = 0.0f;
 #pragma unroll
           for (int j = 0; j < NG; j++) {
-            const float* row = Fc + (k * FR[1] + j) * FR[0];
+            const float* row = Fc + k * fs01 + j * fs0;
             float rr = 0.0f;
 #pragma unroll
             for (int i = 0; i < NG; i++) rr += wx[i] * row[i];
@@ -1300,7 +1369,7 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
           sen[r][d] = en[d];
         }
         smv[r] = (mv[0] + 1) | ((mv[1] + 1) << 2) | ((mv[2] + 1) << 4);
-        sjc[r] = ((jlo[2] + l[2]) * JR[1] + jlo[1] + l[1]) * JR[0] + jlo[0] + l[0];
+        sjc[r] = (jlo[2] + l[2]) * js01 + (jlo[1] + l[1]) * js0 + jlo[0] + l[0];
         swq[r] = pw[r];
         bmax = fmaxf(bmax, fabsf(pw[r]) * (sqrtf(uu2) * gi));
       }
@@ -1326,14 +1395,14 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
   const int any_bad = __syncthreads_or(bad ? 1 : 0);
   float btop = 0.0f;
   for (int k = 0; k < (nthr >> 6); k++) btop = fmaxf(btop, sred[k]);
-  // fixed point of the tile: Q = 2^e with Q btop < 2^29
-  int ex = 0;
-  (void)frexpf(btop, &ex);
-  const int e_item = btop > 0.0f ? min(100, max(-100, 29 - ex)) : 0;
-  const float Q = ldexpf(1.0f, e_item);
+  // (the int64 mode: the instance's own fixed point, as in the one-phase kernel)
+  int eg = 0;
+  (void)frexpf(g.jscale, &eg);  // jscale = 2^(eg-1)
+  const int e_item = __builtin_amdgcn_readfirstlane(g.acc_mode == 2 ? eg - 1 : item_exponent(btop));
+  const float Q = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(ldexpf(1.0f, e_item))));
 
   // 3. clear the current tile (over the staged fields)
-  for (int idx = tid; idx < 3 * jn; idx += nthr) sJ[idx].v = 0ull;
+  for (int idx = tid; idx < 3 * jpl; idx += nthr) sJ[idx] = 0ull;
   if (tid == 0) {
     if (any_strayed) S.ctl->flag = 1;
     if (any_bad) S.ctl->bad = 1;
@@ -1343,7 +1412,7 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
 
   // 4. phase B: ISIS ordering average in Esirkepov's closed form, core of the
   // old support unconditional, each extra block under one branch
-  const int st[3] = {1, JR[0], JR[0] * JR[1]};
+  const int st[3] = {1, js0, js01};
 #pragma unroll
   for (int r = 0; r < R; r++) {
     if (sjc[r] < 0) continue;
@@ -1367,13 +1436,17 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
       const bool pd = p0[d] != 0;
 #pragma unroll
       for (int k = 0; k < K; k++) {
-        ax[d].S[k] = pd ? S0[d][k + 1] : S0[d][k];
-        ax[d].D[k] = pd ? D[d][k + 1] : D[d][k];
+        const float sk = pd ? S0[d][k + 1] : S0[d][k], dk = pd ? D[d][k + 1] : D[d][k];
+        ax[d].H[k] = fmaf(0.5f, dk, sk);
+        ax[d].G[k] = 0.28867513f * dk;  // 1/sqrt(12)
       }
 #pragma unroll
       for (int k = 0; k < K - 1; k++) ax[d].P[k] = pd ? P[k + 1] : P[k];
-      ax[d].Se = pd ? S0[d][0] : S0[d][K];
-      ax[d].De = pd ? D[d][0] : D[d][K];
+      {
+        const float se = pd ? S0[d][0] : S0[d][K], de = pd ? D[d][0] : D[d][K];
+        ax[d].He = fmaf(0.5f, de, se);
+        ax[d].Ge = 0.28867513f * de;
+      }
       ax[d].Pe = wide[d] ? (pd ? P[0] : P[K - 1]) : 0.0f;
       ax[d].oS = pd ? -1 : K;
       ax[d].oP = pd ? -1 : K - 1;
@@ -1381,8 +1454,8 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
     }
     const int cb = sjc[r] + (wb[0] + p0[0]) + (wb[1] + p0[1]) * st[1] + (wb[2] + p0[2]) * st[2];
     dep3_comp<K, 0>(sJ, cb, st, ax);
-    dep3_comp<K, 1>(sJ + jn, cb, st, ax);
-    dep3_comp<K, 2>(sJ + 2 * jn, cb, st, ax);
+    dep3_comp<K, 1>(sJ + jpl, cb, st, ax);
+    dep3_comp<K, 2>(sJ + 2 * jpl, cb, st, ax);
   }
   __syncthreads();
 
@@ -1390,29 +1463,22 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
   // converts the item's units to the instance's fixed point exactly (a left
   // shift) or rounds to it (a right shift), so its sums stay order-free
   const float qinv = ldexpf(1.0f, -e_item);
-  int eg = 0;
-  (void)frexpf(g.jscale, &eg);
-  const int sh = (eg - 1) - e_item;  // jscale = 2^(eg-1)
   BoxWalk bj(tid, nthr, JR);
   for (int idx = tid; idx < jn; idx += nthr, bj.advance(JR)) {
     const int gx = wrap_fast(org[0] - jlo[0] + bj.x, g.nx[0]);
     const int gy = wrap_fast(org[1] - jlo[1] + bj.y, g.nx[1]);
     const int gz = wrap_fast(org[2] - jlo[2] + bj.z, g.nx[2]);
     const int gidx = gx + g.nx[0] * (gy + g.nx[1] * gz);
+    const int lj = bj.x + bj.y * js0 + bj.z * js01;
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-      const long long q = (long long)sJ[c * jn + idx].v;
+      const long long q = (long long)sJ[c * jpl + lj];
       if (q != 0) {
         if (g.acc_mode == 2) {
-          long long v = q;
-          if (sh >= 0)
-            v = v << sh;
-          else
-            v = -sh > 62 ? 0 : ((v + (1ll << (-sh - 1))) >> (-sh));
-          if (v != 0) atomicAdd(S.J64[jp] + (size_t)c * ncell + gidx, (acc_t)v);
+          atomicAdd(S.J64[jp] + (size_t)c * ncell + gidx, (acc_t)q);
         } else {
           __builtin_amdgcn_global_atomic_fadd_f32((gfloat*)S.Jacc[jp] + (size_t)c * ncell + gidx,
-                                                  (float)((double)q * (double)qinv));
+                                                  item_sum_f32(q, qinv));
         }
       }
     }
@@ -1447,7 +1513,7 @@ __device__ __forceinline__ void gpd_body(const StoreDesc* __restrict__ stores, i
   // of 8, the workgroups of each XCD walk one contiguous eighth of the list
   // (two-phase 3D kernel only; the 2D kernels keep the plain walk).
   int lo = 0, hi = total, first = blockIdx.x, stride = gridDim.x;
-  if (MODE == 4 && (gridDim.x & 7) == 0 && total >= (int)gridDim.x) {
+  if (MODE >= 4 && (gridDim.x & 7) == 0 && total >= (int)gridDim.x) {
     const int per = (total + 7) >> 3;
     lo = min(total, (int)(blockIdx.x & 7) * per);
     hi = min(total, lo + per);
@@ -1457,13 +1523,20 @@ __device__ __forceinline__ void gpd_body(const StoreDesc* __restrict__ stores, i
   int s = 0;
   for (int gi = first; gi < hi; gi += stride) {
     while (gi >= s_pref[s + 1]) s++;
+    // the store, its buffer set and the item are the workgroup's own: read
+    // into scalar registers, so the descriptor's fields load as scalars
+    s = __builtin_amdgcn_readfirstlane(s);
     const StoreDesc& S = stores[s];
-    const int cur = s_cur[s];
-    const Item it = S.items[cur][gi - s_pref[s]];
-    if constexpr (MODE == 4)
-      process_item3<ORDER>(S, cur, it, gi - s_pref[s], jp, kstep, smem, s_cnt, s_red);
+    const int cur = __builtin_amdgcn_readfirstlane(s_cur[s]);
+    const int ii = __builtin_amdgcn_readfirstlane(gi - s_pref[s]);
+    Item it = S.items[cur][ii];
+    it.tile = __builtin_amdgcn_readfirstlane(it.tile);
+    it.begin = __builtin_amdgcn_readfirstlane(it.begin);
+    it.end = __builtin_amdgcn_readfirstlane(it.end);
+    if constexpr (MODE >= 4)
+      process_item3<ORDER, MODE == 5>(S, cur, it, ii, jp, kstep, smem, s_cnt, s_red);
     else
-      process_item<DIM, ORDER, MODE>(S, cur, it, gi - s_pref[s], jp, kstep, smem, s_cnt);
+      process_item<DIM, ORDER, MODE>(S, cur, it, ii, jp, kstep, smem, s_cnt);
   }
   (void)lo;
 }
@@ -1476,7 +1549,7 @@ __device__ __forceinline__ void gpd_body(const StoreDesc* __restrict__ stores, i
 // compiler's choice.
 template <int DIM, int ORDER, int MODE>
 __global__ void __launch_bounds__(kBlock)
-    __attribute__((amdgpu_waves_per_eu(DIM == 2 && ORDER <= 2 && MODE == 0 ? 5 : 1))) gpd_kernel(const StoreDesc* __restrict__ stores, int nstores, int jp,
+    __attribute__((amdgpu_waves_per_eu(DIM == 2 && ORDER <= 2 && MODE == 0 ? 5 : (MODE >= 4 ? 4 : 1)))) gpd_kernel(const StoreDesc* __restrict__ stores, int nstores, int jp,
                                                      int kstep) {
   gpd_body<DIM, ORDER, MODE>(stores, nstores, jp, kstep);
 }
@@ -1510,6 +1583,7 @@ hipError_t prepare_one(int mode, size_t lds) {
     if (mode == 3) return prepare_mode<DIM, ORDER, 3>(lds);
   } else {
     if (mode == 4) return prepare_mode<DIM, ORDER, 4>(lds);
+    if (mode == 5) return prepare_mode<DIM, ORDER, 5>(lds);
   }
   if (mode == 0) return prepare_mode<DIM, ORDER, 0>(lds);
   return hipErrorInvalidValue;
@@ -1528,8 +1602,12 @@ hipError_t launch_one(int mode, const StoreDesc* stores, int nstores, int grid, 
     else
       launch_mode<DIM, ORDER, 3>(stores, nstores, grid, lds, jp, kstep, st, ev0, ev1);
   } else {
-    if (mode != 4) return hipErrorInvalidValue;
-    launch_mode<DIM, ORDER, 4>(stores, nstores, grid, lds, jp, kstep, st, ev0, ev1);
+    if (mode == 4)
+      launch_mode<DIM, ORDER, 4>(stores, nstores, grid, lds, jp, kstep, st, ev0, ev1);
+    else if (mode == 5)
+      launch_mode<DIM, ORDER, 5>(stores, nstores, grid, lds, jp, kstep, st, ev0, ev1);
+    else
+      return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
@@ -1537,13 +1615,70 @@ hipError_t launch_one(int mode, const StoreDesc* stores, int nstores, int grid, 
 }  // namespace
 
 // LDS bytes one workgroup of the fused kernel needs for a grid.
+// Padded LDS strides of the two-phase kernel's regions.  The lanes of a
+// wavefront hold one particle of each of 64 consecutive cells of the tile
+// (the binning interleaves the cells, x fastest), and every lane of an LDS
+// instruction reads or adds at the same offset from its own cell, so the
+// banks the lanes hit are set by the row and plane strides.  Among strides
+// up to 8 nodes above the region's extents, take the one whose 64 addresses
+// spread best over 64 four-byte banks (field reads) or over 32 eight-byte
+// bank pairs per half-wave (int64 current adds), then the smallest plane.
+static void split_stride_pick(const GridDesc& g, int ex, int ey, bool wide8, int& s0, int& s01) {
+  int lx[64], ly[64], lz[64];
+  const int vol = g.tile[0] * g.tile[1] * g.tile[2];
+  for (int c = 0; c < 64; c++) {
+    const int k = c % vol;
+    lx[c] = k % g.tile[0];
+    ly[c] = (k / g.tile[0]) % g.tile[1];
+    lz[c] = k / (g.tile[0] * g.tile[1]);
+  }
+  int best = 1 << 30;
+  s0 = ex;
+  s01 = ex * ey;
+  for (int a = ex; a < ex + 8; a++)
+    for (int b = ey; b < ey + 8; b++) {
+      int cost = 0;
+      for (int h = 0; h < (wide8 ? 2 : 1); h++) {
+        int cnt[64] = {0};
+        const int n = wide8 ? 32 : 64, m = wide8 ? 32 : 64;
+        for (int c = h * n; c < h * n + n; c++) {
+          const int addr = lx[c] + ly[c] * a + lz[c] * a * b;
+          cost = std::max(cost, ++cnt[addr % m]);
+        }
+      }
+      const int key = cost * (1 << 20) + a * b;
+      if (key < best) {
+        best = key;
+        s0 = a;
+        s01 = a * b;
+      }
+    }
+}
+
+void pic_gpd_split_strides(GridDesc& g) {
+  split_stride_pick(g, g.tile[0] + 2 * g.slk[0] + g.fa + g.fb, g.tile[1] + 2 * g.slk[1] + g.fa + g.fb, false, g.fs0,
+                    g.fs01);
+  split_stride_pick(g, g.tile[0] + 2 * g.slk[0] + g.ja + g.jb, g.tile[1] + 2 * g.slk[1] + g.ja + g.jb, true, g.js0,
+                    g.js01);
+}
+
+// LDS of the two-phase kernel: six field planes or three int64 current
+// planes over the padded strides of the largest region of a sort cycle.
+static size_t split_lds_bytes(const GridDesc& g0) {
+  GridDesc g = g0;
+  pic_gpd_split_strides(g);
+  const size_t f2 = (size_t)(g.tile[2] + 2 * g.slk[2] + g.fa + g.fb);
+  const size_t j2 = (size_t)(g.tile[2] + 2 * g.slk[2] + g.ja + g.jb);
+  return std::max(6 * (size_t)g.fs01 * f2 * sizeof(float), 3 * (size_t)g.js01 * j2 * sizeof(unsigned long long));
+}
+
 size_t pic_gpd_lds_bytes(const GridDesc& g) {
   size_t fn = 1, jn = 1;
   for (int d = 0; d < g.dim; d++) {
     fn *= (size_t)(g.tile[d] + 2 * g.slk[d] + g.fa + g.fb);
     jn *= (size_t)(g.tile[d] + 2 * g.slk[d] + g.ja + g.jb);
   }
-  if (pic_gpd_split(g)) return std::max(6 * fn * sizeof(float), 3 * jn * sizeof(unsigned long long));
+  if (pic_gpd_split(g)) return split_lds_bytes(g);
   return ((6 * fn + 1) & ~(size_t)1) * sizeof(float) + 3 * jn * sizeof(unsigned long long);
 }
 
@@ -1557,7 +1692,7 @@ size_t pic_gpd_lds_bytes_step(const GridDesc& g, int kstep) {
     fn *= (size_t)(g.tile[d] + 2 * sl + g.fa + g.fb);
     jn *= (size_t)(g.tile[d] + 2 * sl + g.ja + g.jb);
   }
-  if (pic_gpd_split(g)) return std::max(6 * fn * sizeof(float), 3 * jn * sizeof(unsigned long long));
+  if (pic_gpd_split(g)) return split_lds_bytes(g);
   return ((6 * fn + 1) & ~(size_t)1) * sizeof(float) + 3 * jn * sizeof(unsigned long long);
 }
 
@@ -1589,6 +1724,7 @@ int resident_one(int mode, size_t lds) {
     if (mode == 3) f = gpd_entry<DIM, ORDER, 3>();
   } else {
     if (mode == 4) f = gpd_entry<DIM, ORDER, 4>();
+    if (mode == 5) f = gpd_entry<DIM, ORDER, 5>();
   }
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kBlock, lds) != hipSuccess) return 1;
   return n < 1 ? 1 : n;

@@ -42,6 +42,10 @@ struct GridDesc {
   // LDS region geometry (nodes relative to the tile origin):
   // field region [-(slack+fa), e+slack+fb), current region [-(slack+ja), e+slack+jb)
   int fa, fb, ja, jb;
+  // two-phase 3D kernel: LDS strides (nodes) of a field-region row and plane
+  // and of a current-region row and plane, padded so that the lanes of a
+  // wavefront, one particle per cell of the tile, spread over the LDS banks
+  int fs0, fs01, js0, js01;
 };
 
 // Control words of one particle store.  The buffer set holding the particles
@@ -124,6 +128,8 @@ struct StoreDesc {
   WinCtl* win;               // moving window state of the instance (null without a window)
   int inj_ppc[3];            // moving window: injected particles per cell per axis
   float inj_w;               // moving window: weight of an injected particle
+  double inj_uth;            // moving window: thermal spread of the injected momenta (0: at rest)
+  unsigned long long inj_seed;  // moving window: seed of their generator
   const int* nsrc;           // [ntiles][27] tile - delta_s (periodic), per instance
   const int* ndst;           // [ntiles][27] tile + delta_s (periodic), per instance
   StoreCtl* ctl;

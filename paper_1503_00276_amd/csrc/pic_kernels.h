@@ -12,11 +12,14 @@ size_t pic_gpd_lds_bytes_step(const GridDesc& g, int kstep);
 int pic_gpd_block();
 // particles a work item of the two-phase 3D variant can hold (its chunk limit)
 int pic_gpd_split_chunk();
+// padded LDS strides of the two-phase variant for g's tile and stray bound
+void pic_gpd_split_strides(GridDesc& g);
 int pic_gpd_max_group();
 // allow the LDS size a group needs (call before launching or capturing);
 // mode: the boundary logic of the group's stores (0 periodic, 1 moving window
 // along x1, 2 the 2D r-z geometry, 3 r-z with a moving window, 4 periodic 3D
-// in two phases), which selects the kernel variant
+// in two phases, 5 the same with the compile-time LDS strides of 4x4xN
+// tiles), which selects the kernel variant
 hipError_t pic_gpd_prepare(int dim, int order, int mode, size_t lds);
 // workgroups of the variant that are resident on one CU at once with 'lds'
 // bytes of dynamic LDS (after pic_gpd_prepare)

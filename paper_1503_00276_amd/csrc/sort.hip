@@ -389,6 +389,25 @@ __global__ void __launch_bounds__(kBlock) rebin_scatter(const StoreDesc* __restr
 // of a cell with axis 1 fastest) goes to its tile's range after the incoming
 // particles, at its rank among the tile's injected particles; ids continue
 // from the window's counter.
+// Output n >= 1 of the SplitMix64 generator seeded with s (Steele, Lea and
+// Flood, "Fast splittable pseudorandom number generators", 2014): the state
+// advances by the golden-ratio increment, the output mixes it.
+__device__ unsigned long long splitmix64_output(unsigned long long s, unsigned long long n) {
+  unsigned long long z = s + n * 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+// Standard normal deviate of component c of the particle with id 'id':
+// Box-Muller (1958) on U1 in (0, 1] and U2 in [0, 1), 53 bits each.
+__device__ double thermal_normal(unsigned long long seed, long long id, int c) {
+  const unsigned long long n = 8ull * (unsigned long long)id + 2ull * (unsigned long long)c;
+  const double u1 = (double)((splitmix64_output(seed, n + 1) >> 11) + 1) * 0x1.0p-53;
+  const double u2 = (double)(splitmix64_output(seed, n + 2) >> 11) * 0x1.0p-53;
+  return sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+
 __global__ void __launch_bounds__(kBlock) rebin_inject(const StoreDesc* __restrict__ stores, int nstores) {
   const StoreDesc& S = stores[blockIdx.y];
   if (!S.g.window || !S.ctl->active || !win_shift_now(S)) return;
@@ -422,9 +441,12 @@ __global__ void __launch_bounds__(kBlock) rebin_inject(const StoreDesc* __restri
     S.eps[nxt][0][pos] = ((float)l0 + 0.5f) / (float)p0;
     S.eps[nxt][1][pos] = ((float)l1 + 0.5f) / (float)p1;
     if (g.dim == 3) S.eps[nxt][2][pos] = ((float)l2 + 0.5f) / (float)p2;
-    S.u[nxt][0][pos] = 0.0f;
-    S.u[nxt][1][pos] = 0.0f;
-    S.u[nxt][2][pos] = 0.0f;
+    // at rest, or thermal: a Box-Muller normal deviate per component from
+    // the SplitMix64 outputs 8 id + 2c + 1 and 8 id + 2c + 2 (FP64)
+    const long long id = id0 + k;
+#pragma unroll
+    for (int c = 0; c < 3; c++)
+      S.u[nxt][c][pos] = S.inj_uth > 0.0 ? (float)(S.inj_uth * thermal_normal(S.inj_seed, id, c)) : 0.0f;
     // r-z: a uniform density takes a weight proportional to the radius
     S.w[nxt][pos] = g.cyl ? S.inj_w * ((float)cy + ((float)l1 + 0.5f) / (float)p1 - 0.5f) : S.inj_w;
     S.id[nxt][pos] = (int)(id0 + k);

@@ -84,6 +84,8 @@ class pic_config(C.Structure):
         ("inject_ppc", C.c_int32 * 3),
         ("inject_w", C.c_double),
         ("geometry", C.c_int32),
+        ("inject_uth", C.c_double),
+        ("inject_seed", C.c_uint64),
     ]
 
 
@@ -127,6 +129,14 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1503_00276_amd.build`")
+        # torch first when it is installed: its HIP runtime (the same soname
+        # the library needs) is then the only one in the process; loading the
+        # library first would bring in the system's copy beside torch's, and
+        # torch's device initialisation then fails
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         P, V, I64, I32, U32, D, SZ = (C.POINTER(C.c_double), C.c_void_p, C.c_int64, C.c_int32,
                                       C.c_uint32, C.c_double, C.c_size_t)
@@ -192,6 +202,8 @@ class Config:
     inject_ppc: Sequence[int] = (1, 1, 1)  # moving window: injected particles per cell per axis
     inject_w: float = 0.0  # moving window: weight of an injected particle
     geometry: int = 0      # PIC_GEOM_CARTESIAN, or PIC_GEOM_RZ (x1 = z, x2 = r)
+    inject_uth: float = 0.0  # moving window: thermal spread of the injected momenta (0: cold)
+    inject_seed: int = 0     # moving window: seed of the injected momenta's generator
 
     def c(self) -> pic_config:
         c = pic_config()
@@ -216,6 +228,8 @@ class Config:
             c.inject_ppc[i] = int(self.inject_ppc[i]) if i < len(self.inject_ppc) else 1
         c.inject_w = float(self.inject_w)
         c.geometry = int(self.geometry)
+        c.inject_uth = float(self.inject_uth)
+        c.inject_seed = int(self.inject_seed) & 0xFFFFFFFFFFFFFFFF
         for ax, passes in enumerate(self.smooth):
             c.smooth_level[ax] = len(passes)
             for p, wts in enumerate(passes[:8]):

@@ -23,7 +23,8 @@ def oracle_grid(orc, cfg):
                     order=cfg.shape_order, xmin=tuple(cfg.xmin), e0=tuple(cfg.e0), b0=tuple(cfg.b0),
                     deposit=getattr(cfg, "deposit", 0), smooth=tuple(tuple(p) for p in getattr(cfg, "smooth", ())),
                     window=getattr(cfg, "move_window", 0), inject_ppc=tuple(getattr(cfg, "inject_ppc", (1, 1, 1))),
-                    inject_w=getattr(cfg, "inject_w", 0.0), cyl=int(getattr(cfg, "geometry", 0) == 1))
+                    inject_w=getattr(cfg, "inject_w", 0.0), inject_uth=getattr(cfg, "inject_uth", 0.0),
+                    inject_seed=getattr(cfg, "inject_seed", 0), cyl=int(getattr(cfg, "geometry", 0) == 1))
 
 
 def periodic_dx(a, b, L):

@@ -255,14 +255,16 @@ def test_rz_fp64_diagnostics_match_the_oracle(orc, order):
     assert np.abs(C[1:nr - 4]).max() <= 1e-6 * scale
 
 
-@pytest.mark.parametrize("order,ippc_r,acc,smooth", [(1, 1, 0, ()), (2, 2, 0, ()), (3, 3, 2, ()),
-                                                     (2, 2, 0, (((1, 2, 1),), ((1, 2, 1),)))])
-def test_rz_window_step_parity(orc, order, ippc_r, acc, smooth):
+@pytest.mark.parametrize("order,ippc_r,acc,smooth,uth", [(1, 1, 0, (), 0.0), (2, 2, 0, (), 0.0), (3, 3, 2, (), 0.0),
+                                                         (2, 2, 0, (((1, 2, 1),), ((1, 2, 1),)), 0.0),
+                                                         (2, 3, 0, (), 0.1)])
+def test_rz_window_step_parity(orc, order, ippc_r, acc, smooth, uth):
     """r-z with a moving window along z: each step against the oracle's
     window step in the r-z geometry across shifts, with rings near the axis,
     rings leaving through the wall and the back, and the ring lattice the
-    window injects (weights proportional to the radius); last case with the
-    current smoothed along z (zero beyond the window's ends) and r."""
+    window injects (weights proportional to the radius); one case with the
+    current smoothed along z (zero beyond the window's ends) and r, one with
+    thermally injected rings."""
     from test_gpu_window import window_step_parity
 
     pic = _pic()
@@ -270,14 +272,14 @@ def test_rz_window_step_parity(orc, order, ippc_r, acc, smooth):
     x, u, w = _ring_plasma(nz, nr, dz, dr, 3, 0.3, 300 + order)
     cfg = pic.Config(ndim=2, nx=(nz, nr), dx=(dz, dr), dt=0.1, shape_order=order, tile=(8, 8), sort_interval=1,
                      geometry=pic.PIC_GEOM_RZ, move_window=1, inject_ppc=(2, ippc_r, 1), inject_w=-0.2,
-                     accumulator=acc, xmin=(0.5, 0.0, 0.0), smooth=smooth)
+                     accumulator=acc, xmin=(0.5, 0.0, 0.0), smooth=smooth, inject_uth=uth, inject_seed=99)
     sim = pic.Pic(cfg)
     sim.load_particles(x + np.array([0.5, 0.0]), u, w, rqm=-1.0)
     E, B = _rz_fields(nz, nr, 23)
     sim.load_fields(E, B)
     shifts = removed = 0
     for n in range(7):
-        err = window_step_parity(orc, sim, cfg, n)
+        err = window_step_parity(orc, sim, cfg, n, nload=len(x))
         print(n, err, flush=True)
         assert err["inside"]
         assert err["pos"] <= POS_TOL and err["mom"] <= MOM_TOL

@@ -1,7 +1,8 @@
 """GPU parity of the moving window (Sec. 4.5, dynamic simulation spaces): each
 step of the HIP path against one step of the FP64 oracle's window step from
 the same (GPU-exported) state, across steps that shift the window, remove
-particles and inject the cold plasma of the new front column.  Positions are
+particles and inject the plasma of the new front column (cold, or thermal
+with momenta drawn from the injected particles' ids).  Positions are
 compared in window coordinates (lab x1 minus the window's travel), particles
 by identity (survivors in load order, then the injected ones in injection
 order), grid arrays in window order."""
@@ -38,13 +39,17 @@ def _to_window(cfg, x_lab, shifts):
     return x
 
 
-def window_step_parity(orc, sim, cfg, n, qm=-1.0):
-    """Step n -> n+1 on both sides from the GPU's state; return the errors."""
+def window_step_parity(orc, sim, cfg, n, qm=-1.0, nload=0):
+    """Step n -> n+1 on both sides from the GPU's state; return the errors.
+    nload: particles loaded before the first step (the injected ids follow
+    them, one per lattice point of every new column)."""
     g = dataclasses.replace(oracle_grid(orc, cfg), xmin=(0.0, 0.0, 0.0))
     x0, u0, w0 = sim.state()
     E0, B0 = sim.fields()
     s0 = orc.window_shifts(g, n)
-    ref, wref, keep = orc.step_window(g, n, _to_window(cfg, x0, s0), u0, w0, qm, E0, B0)
+    per_shift = int(np.prod(cfg.inject_ppc[:cfg.ndim])) * (int(np.prod(cfg.nx[:cfg.ndim])) // cfg.nx[0])
+    ref, wref, keep = orc.step_window(g, n, _to_window(cfg, x0, s0), u0, w0, qm, E0, B0,
+                                      id0=nload + s0 * per_shift)
     sim.step(1)
     x1, u1, w1 = sim.state()
     E1, B1 = sim.fields()
@@ -77,6 +82,9 @@ CASES = [
      {"smooth": ((0.25, 0.5, 0.25), (-0.25, 1.5, -0.25))}),                          # smoothed current
     (3, (16, 8, 8), (0.2, 0.2, 0.2), 0.08, 1, (8, 4, 4), 2, (1, 2, 1), {}),
     (3, (12, 10, 8), (0.2, 0.2, 0.25), 0.08, 2, (4, 5, 4), 2, (2, 1, 1), {}),
+    # thermal injection (Sec. 4.5: the new region initialised thermal)
+    (2, (32, 16), (0.2, 0.25), 0.1, 2, (8, 8), 3, (2, 2), {"inject_uth": 0.05, "inject_seed": 150300276}),
+    (3, (16, 8, 8), (0.2, 0.2, 0.2), 0.08, 3, (8, 4, 4), 2, (1, 2, 1), {"inject_uth": 0.2, "inject_seed": 7}),
 ]
 
 
@@ -109,7 +117,7 @@ def test_window_step_parity(orc, case):
     print(f"case {_ident(case)}", flush=True)
     shifts = removed = 0
     for n in range(7):  # several window shifts (c dt / dx1 = 0.4 or 0.5)
-        err = window_step_parity(orc, sim, cfg, n)
+        err = window_step_parity(orc, sim, cfg, n, nload=len(x))
         print(n, err, flush=True)
         assert err["inside"]
         assert err["pos"] <= POS_TOL

@@ -909,6 +909,67 @@ def test_window_continuity_away_from_the_ends(orc):
     assert list(keep) == [1] and len(r.x) == 1 and abs(r.x[0, 1] - 3.1 * dx[1]) < 1e-12
 
 
+def test_splitmix64_published_outputs(orc):
+    """The first outputs of SplitMix64 seeded with 0, as published with the
+    generator's reference implementation (Steele, Lea, Flood 2014; the seeding
+    generator of xoshiro/xoroshiro): 0xe220a8397b1dcdaf, 0x6e789e6aa1b965f4,
+    0x06c45d188009454f."""
+    out = orc.splitmix64(0, np.array([1, 2, 3], dtype=np.uint64))
+    assert [int(v) for v in out] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_thermal_normal_is_standard_normal_and_keyed_by_id(orc):
+    """Box-Muller deviates drawn per (seed, id, component): mean 0, variance
+    1, Kolmogorov-Smirnov against the standard normal, no correlation between
+    components, and the value depends on the id alone (not on the order or
+    the batch it is drawn in)."""
+    from scipy import stats
+
+    n = 200_000
+    ids = np.arange(n, dtype=np.int64) + 12345
+    z = np.stack([orc.thermal_normal(150300276, ids, c) for c in range(3)])
+    assert np.all(np.isfinite(z))
+    for c in range(3):
+        assert abs(z[c].mean()) < 5.0 / math.sqrt(n)
+        assert abs(z[c].var() - 1.0) < 5.0 * math.sqrt(2.0 / n)
+        assert stats.kstest(z[c], "norm").pvalue > 1e-4
+    cc = np.corrcoef(z)
+    assert np.abs(cc - np.eye(3)).max() < 5.0 / math.sqrt(n)
+    perm = np.random.default_rng(1).permutation(n)[:1000]
+    assert np.array_equal(orc.thermal_normal(150300276, ids[perm], 1), z[1, perm])
+    assert not np.array_equal(orc.thermal_normal(150300277, ids[:1000], 1), z[1, :1000])
+
+
+def test_window_thermal_injection_temperature(orc):
+    """A field-free window that injects a thermal plasma (inject_uth): over
+    many shifts the injected momenta have the requested spread per component,
+    zero mean, and the injected ids run on from id0 without a gap, so no two
+    injected particles share their momenta."""
+    nx, dx, dt = (8, 16), (0.2, 0.2), 0.2  # one shift per step
+    uth = 0.05
+    g = orc.Grid(dim=2, nx=nx, dx=dx, dt=dt, order=1, window=1, inject_ppc=(2, 2), inject_w=0.0,
+                 inject_uth=uth, inject_seed=7)
+    x = np.zeros((0, 2))
+    u = np.zeros((0, 3))
+    w = np.zeros(0)
+    E = np.zeros((3, g.ncell))
+    B = np.zeros((3, g.ncell))
+    per_shift = 4 * nx[1]
+    new_u = []
+    for n in range(60):
+        s0 = orc.window_shifts(g, n)
+        r, w, keep = orc.step_window(g, n, x, u, w, -1.0, E, B, id0=s0 * per_shift)
+        assert orc.window_shifts(g, n + 1) == s0 + 1
+        new_u.append(r.u[len(keep):])
+        x, u, E, B = r.x, r.u, r.E, r.B
+    un = np.concatenate(new_u)
+    assert len(un) == 60 * per_shift
+    assert len(np.unique(un[:, 0])) == len(un)
+    for c in range(3):
+        assert abs(un[:, c].mean()) < 5 * uth / math.sqrt(len(un))
+        assert abs(un[:, c].std() / uth - 1.0) < 0.05
+
+
 # --------------------------------------------------------------------------
 # 2D cylindrically symmetric r-z geometry (Sec. 3.3)
 # --------------------------------------------------------------------------
