@@ -265,6 +265,25 @@ typedef enum {
 pic_status pic_diag(pic_ctx* ctx, pic_diag_kind kind, void* out, size_t out_bytes,
                     size_t* written);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * diagnostics PIC_DIAG_RHO, PIC_DIAG_GAUSS_RESIDUAL and
+ * PIC_DIAG_CHARGE_RESIDUAL, as pic_diag computes them, written to a DEVICE
+ * buffer of the context's device (out: ncell doubles, caller-owned; the call
+ * is synchronous).  The call allocates nothing: the node charge behind the
+ * residuals lives in a file-scope device array of the library (32 MiB per
+ * device, held until the process ends), so the residuals need ncell <=
+ * 4,194,304 (PIC_E_RANGE otherwise).  Every call on one device shares that
+ * array: calls that overlap on one device (several threads, several
+ * contexts) race.  Fails with PIC_E_UNSUPPORTED for other kinds and for a
+ * moving window (whose grid is kept in ring order), PIC_E_INVALID when out
+ * is not device memory of the context's device, PIC_E_STATE when another
+ * device is current, when particles were loaded since the last pic_step or
+ * pic_diag, or (CHARGE_RESIDUAL) without an earlier PIC_DIAG_RHO_SNAPSHOT
+ * taken with pic_diag. */
+pic_status pic_diag_noalloc(pic_ctx* ctx, pic_diag_kind kind, void* out, size_t out_bytes,
+                            size_t* written);
+
 /* Profiling: while enabled, pic_step launches every kernel individually
  * (no graph replay) and brackets each kernel family with HIP events on the
  * context's stream; PIC_DIAG_KERNEL_TIMES reads the sums.  enable = 0 turns it

@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -92,6 +93,7 @@ int store_chunk(const GridDesc& g, int chunk) {
 }
 
 struct Sim {
+  int device = 0;       // HIP device the context was created on
   int num_cu = kNumCU;  // compute units of the device
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -1343,6 +1345,81 @@ pic_status sim_diag(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_byt
   return S.fail(PIC_E_INVALID, "unknown diagnostic kind %d", (int)kind);
 }
 
+// ---------------------------------------------------------------------------
+// scratch of the diagnostics that allocate nothing (pic_diag_noalloc)
+// ---------------------------------------------------------------------------
+// The node charge behind the Gauss and charge residuals lives in this
+// file-scope device array: every GPU the library runs on holds its own copy
+// until the process ends.  In host code the array's name is a host-side
+// stand-in, not a device address; the address is taken once per device with
+// hipGetSymbolAddress (at the first pic_create on that device) and used
+// everywhere instead of the name.
+constexpr size_t kNoAllocCells = size_t(1) << 22;  // doubles: 32 MiB, grids up to 4,194,304 cells
+__device__ __align__(256) double scratch[kNoAllocCells];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+
+// Record the address of this device's copy of the scratch (the context's
+// device is current).
+pic_status noalloc_scratch_setup(Sim& S) {
+  if (S.device < 0 || S.device >= kMaxDevices) return S.fail(PIC_E_UNSUPPORTED, "device index %d", S.device);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[S.device]) return PIC_OK;
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) return S.fail(PIC_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+  g_scratch[S.device] = (double*)p;
+  return PIC_OK;
+}
+
+// RHO, GAUSS_RESIDUAL or CHARGE_RESIDUAL of instance i into a device buffer
+// without allocating: the node charge of the residuals is computed in this
+// device's copy of the scratch array, the result goes straight to 'out'.
+pic_status sim_diag_noalloc(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_bytes, size_t* written) {
+  if (i < 0 || i >= (int)S.inst.size()) return S.fail(PIC_E_INVALID, "instance out of range");
+  if (written) *written = 0;
+  if (kind != PIC_DIAG_RHO && kind != PIC_DIAG_GAUSS_RESIDUAL && kind != PIC_DIAG_CHARGE_RESIDUAL)
+    return S.fail(PIC_E_UNSUPPORTED, "pic_diag_noalloc computes RHO, GAUSS_RESIDUAL and CHARGE_RESIDUAL only");
+  if (!out) return S.fail(PIC_E_INVALID, "null output buffer");
+  Instance& I = S.inst[i];
+  if (I.cfg.move_window)
+    return S.fail(PIC_E_UNSUPPORTED, "a moving window keeps its grid in ring order: use pic_diag");
+  const size_t nc = (size_t)I.g.ncell;
+  pic_status st = need(S, nc * sizeof(double), out_bytes, written);
+  if (st != PIC_OK) return st;
+  if (kind != PIC_DIAG_RHO && nc > kNoAllocCells)
+    return S.fail(PIC_E_RANGE, "grid of %zu cells exceeds the %zu-cell scratch of pic_diag_noalloc", nc,
+                  kNoAllocCells);
+  if (kind == PIC_DIAG_CHARGE_RESIDUAL && !I.have_snap)
+    return S.fail(PIC_E_STATE, "CHARGE_RESIDUAL needs an earlier RHO_SNAPSHOT");
+  int cur = 0;
+  HIPCHK(S, hipGetDevice(&cur));
+  if (cur != S.device) return S.fail(PIC_E_STATE, "device %d is current, the context lives on device %d", cur, S.device);
+  // the output must be device memory of this device (a kernel writes it)
+  hipPointerAttribute_t pa;
+  if (hipPointerGetAttributes(&pa, out) != hipSuccess || pa.type != hipMemoryTypeDevice || pa.device != S.device) {
+    (void)hipGetLastError();
+    return S.fail(PIC_E_INVALID, "out must be device memory of device %d", S.device);
+  }
+  double* scr = g_scratch[S.device];
+  if (!scr) return S.fail(PIC_E_STATE, "no scratch address for device %d", S.device);
+  if ((st = sim_sync(S)) != PIC_OK) return st;
+  if (S.dirty)
+    return S.fail(PIC_E_STATE, "the launch descriptors are out of date (a load since the last step): run "
+                               "pic_step or pic_diag first");
+  const int ii = inst_desc_index(S, i);
+  double* rho = kind == PIC_DIAG_RHO ? (double*)out : scr;
+  if ((st = compute_rho(S, i, rho)) != PIC_OK) return st;  // starts with a fill kernel: no stale contents
+  if (kind == PIC_DIAG_GAUSS_RESIDUAL)
+    HIPCHK(S, pic_launch_gauss64(S.d_inst + ii, rho, (double*)out, I.g.ncell, I.g.dim, (int)(S.steps & 1), S.stream));
+  else if (kind == PIC_DIAG_CHARGE_RESIDUAL)
+    HIPCHK(S, pic_launch_charge64(S.d_inst + ii, I.rho_snap, rho, (double*)out, I.g.ncell, I.g.dim, S.stream));
+  HIPCHK(S, hipStreamSynchronize(S.stream));
+  return PIC_OK;
+}
+
 // Neighbour tile tables of the rebin: tile t -/+ delta_s for the 27 slots,
 // periodic in tiles.
 pic_status build_tables(Sim& S, Instance& I) {
@@ -1392,9 +1469,12 @@ pic_status sim_create(Sim& S, const pic_config* cfgs, int n, void* stream) {
   S.stream = (hipStream_t)stream;
   {
     int dev = 0, ncu = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+    HIPCHK(S, hipGetDevice(&dev));
+    S.device = dev;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
       S.num_cu = ncu;
+    pic_status st = noalloc_scratch_setup(S);
+    if (st != PIC_OK) return st;
   }
   if (!S.stream) {
     // graph capture needs a stream of our own when the caller gives none
@@ -1923,6 +2003,11 @@ pic_status pic_sync(pic_ctx* ctx) {
 pic_status pic_diag(pic_ctx* ctx, pic_diag_kind kind, void* out, size_t out_bytes, size_t* written) {
   if (!ctx) return PIC_E_INVALID;
   return sim_diag(ctx->s, 0, kind, out, out_bytes, written);
+}
+
+pic_status pic_diag_noalloc(pic_ctx* ctx, pic_diag_kind kind, void* out, size_t out_bytes, size_t* written) {
+  if (!ctx) return PIC_E_INVALID;
+  return sim_diag_noalloc(ctx->s, 0, kind, out, out_bytes, written);
 }
 
 pic_status pic_get_info(const pic_ctx* ctx, pic_info* out) {

@@ -51,7 +51,7 @@ PIC_DIAG_KERNEL_TIMES = 11
 
 EXPORTED = [
     "pic_create", "pic_destroy", "pic_load_particles", "pic_load_fields", "pic_step", "pic_sync",
-    "pic_diag", "pic_get_info", "pic_last_error", "pic_profile", "pic_batch_profile", "pic_batch_create", "pic_batch_destroy",
+    "pic_diag", "pic_diag_noalloc", "pic_get_info", "pic_last_error", "pic_profile", "pic_batch_profile", "pic_batch_create", "pic_batch_destroy",
     "pic_batch_load_particles", "pic_batch_load_fields", "pic_batch_step", "pic_batch_diag",
     "pic_batch_sync", "pic_batch_last_error", "pic_autotune", "pic_batch_autotune", "pic_batch_get_info",
 ]
@@ -147,6 +147,7 @@ def lib():
         L.pic_step.argtypes = [V, I64]
         L.pic_sync.argtypes = [V]
         L.pic_diag.argtypes = [V, C.c_int, V, SZ, C.POINTER(SZ)]
+        L.pic_diag_noalloc.argtypes = [V, C.c_int, V, SZ, C.POINTER(SZ)]
         L.pic_get_info.argtypes = [V, C.POINTER(pic_info)]
         L.pic_profile.argtypes = [V, I32]
         L.pic_batch_profile.argtypes = [V, I32]
@@ -331,6 +332,14 @@ class Pic(_Base):
         wr = C.c_size_t(0)
         self._check(self._L.pic_diag(self._h, kind, C.c_void_p(out.ctypes.data), out.nbytes, C.byref(wr)))
         return out[:count]
+
+    def diag_noalloc(self, kind: int, out) -> int:
+        """pic_diag_noalloc into a caller-owned device tensor (float64, at
+        least ncell elements); returns the bytes written."""
+        wr = C.c_size_t(0)
+        nbytes = out.numel() * out.element_size()
+        self._check(self._L.pic_diag_noalloc(self._h, kind, C.c_void_p(out.data_ptr()), nbytes, C.byref(wr)))
+        return wr.value
 
     def info(self) -> pic_info:
         i = pic_info()
