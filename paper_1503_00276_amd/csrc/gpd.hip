@@ -1117,6 +1117,115 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
 
 constexpr int kSplitR = 3;  // particles per thread per work item
 
+// LDS the re-interleave below needs: class counts, and one occupancy mask
+// and one start per level (at most one level per particle of the item)
+constexpr size_t kInterleaveLds = 64 * sizeof(int) + (size_t)kSplitR * kBlock * (sizeof(unsigned long long) + sizeof(int));
+
+// After the step, the particles of a work item are rewritten inside the
+// item's range in cell-interleaved order: the cells of the tile fall into
+// 64 classes (local linear index mod 64, x fastest), and the order is the
+// first particle of every class in class order, then the second of every
+// class, and so on.  The lanes of a wavefront then hold particles of
+// (nearly) 64 different cells, so the next step's LDS gathers and current
+// adds spread over the banks and rarely hit one address together; without
+// it the loaded order decays as particles change cells, and the kernel
+// slows by about a third.  Among particles of one class the order is that
+// of the LDS atomics (not reproducible), which only permutes storage: every
+// particle's own arithmetic, the item's membership and its fixed-point unit
+// are unchanged, and the int64 current is order-free.  The new state was
+// written by the same thread in phase A and is read back here.
+__device__ __forceinline__ void reinterleave_item(const StoreDesc& S, int set, const Item it, float* smem) {
+  constexpr int R = kSplitR;
+  const GridDesc& g = S.g;
+  int tc[3], org[3], ext[3];
+  pic_tile_coords(g, it.tile, tc);
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    org[d] = tc[d] * g.tile[d];
+    ext[d] = min(g.tile[d], g.nx[d] - org[d]);
+  }
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;
+  int* s_n = (int*)smem;                                                    // [64]
+  unsigned long long* s_m = (unsigned long long*)(smem + 64);               // [R * nthr]
+  int* s_l = (int*)(s_m + R * kBlock);                                      // [R * nthr]
+  gint* __restrict__ cellp = (gint*)S.cell[set];
+  gfloat* __restrict__ ep0 = (gfloat*)S.eps[set][0];
+  gfloat* __restrict__ ep1 = (gfloat*)S.eps[set][1];
+  gfloat* __restrict__ ep2 = (gfloat*)S.eps[set][2];
+  gfloat* __restrict__ up0 = (gfloat*)S.u[set][0];
+  gfloat* __restrict__ up1 = (gfloat*)S.u[set][1];
+  gfloat* __restrict__ up2 = (gfloat*)S.u[set][2];
+  gfloat* __restrict__ wp = (gfloat*)S.w[set];
+  gint* __restrict__ idp = (gint*)S.id[set];
+  if (tid < 64) s_n[tid] = 0;
+  int pc[R], pid[R], key[R], lev[R];
+  float pv[R][7];
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    const int p = it.begin + tid + r * nthr;
+    key[r] = -1;
+    if (p < it.end) {
+      pc[r] = cellp[p];
+      pv[r][0] = ep0[p];
+      pv[r][1] = ep1[p];
+      pv[r][2] = ep2[p];
+      pv[r][3] = up0[p];
+      pv[r][4] = up1[p];
+      pv[r][5] = up2[p];
+      pv[r][6] = wp[p];
+      pid[r] = idp[p];
+      int cc[3], lc[3];
+      pic_unpack(g, pc[r], cc);
+#pragma unroll
+      for (int d = 0; d < 3; d++) {
+        // a particle strays at most a tile extent outside its tile
+        int l = pic_local(cc[d], org[d], ext[d], g.nx[d]);
+        l = l < 0 ? l + ext[d] : (l >= ext[d] ? l - ext[d] : l);
+        lc[d] = l;
+      }
+      key[r] = (lc[0] + ext[0] * (lc[1] + ext[1] * lc[2])) & 63;
+    }
+  }
+  __syncthreads();  // every particle of the item is read before any is rewritten
+#pragma unroll
+  for (int r = 0; r < R; r++) lev[r] = key[r] >= 0 ? atomicAdd(&s_n[key[r]], 1) : 0;
+  __syncthreads();
+  if (tid < 64) {
+    // level k holds the classes with more than k particles: its occupancy
+    // mask and its start in the item
+    const int n = s_n[tid];
+    int top = n;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) top = max(top, __shfl_xor(top, off));
+    int acc = 0;
+    for (int k = 0; k < top; k++) {
+      const unsigned long long m = __ballot(n > k);
+      if (tid == 0) {
+        s_m[k] = m;
+        s_l[k] = acc;
+      }
+      acc += (int)__popcll(m);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    if (key[r] < 0) continue;
+    const int q = it.begin + s_l[lev[r]] + (int)__popcll(s_m[lev[r]] & ((1ull << key[r]) - 1ull));
+    cellp[q] = pc[r];
+    ep0[q] = pv[r][0];
+    ep1[q] = pv[r][1];
+    ep2[q] = pv[r][2];
+    up0[q] = pv[r][3];
+    up1[q] = pv[r][4];
+    up2[q] = pv[r][5];
+    wp[q] = pv[r][6];
+    idp[q] = pid[r];
+  }
+  __syncthreads();
+}
+
 // FIXED: the LDS strides are the 12-node rows and 144-node planes that 4x4xN
 // tiles take (every shape order, stray bound 1), as compile-time constants,
 // so that the taps and adds address LDS through instruction offsets.
@@ -1484,6 +1593,7 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
     }
   }
   __syncthreads();
+  reinterleave_item(S, set, it, smem);
 }
 
 template <int DIM, int ORDER, int MODE>
@@ -1545,11 +1655,13 @@ __device__ __forceinline__ void gpd_body(const StoreDesc* __restrict__ stores, i
 // five waves per SIMD (96 VGPRs, no spills): where the LDS of a tile allows
 // five workgroups per CU this is up to 8 % faster (16x8 tiles, the batched
 // parameter scan); where LDS allows only four (32x8 tiles late in a sort
-// cycle) it changes nothing.  The other variants would spill; they keep the
-// compiler's choice.
+// cycle) it changes nothing.  The two-phase 3D kernels are held to four
+// waves (128 VGPRs; their LDS allows four workgroups of 4x4x4 tiles), except
+// the cubic one with runtime strides, which would spill there and takes
+// three.  The other variants would spill; they keep the compiler's choice.
 template <int DIM, int ORDER, int MODE>
 __global__ void __launch_bounds__(kBlock)
-    __attribute__((amdgpu_waves_per_eu(DIM == 2 && ORDER <= 2 && MODE == 0 ? 5 : (MODE >= 4 ? 4 : 1)))) gpd_kernel(const StoreDesc* __restrict__ stores, int nstores, int jp,
+    __attribute__((amdgpu_waves_per_eu(DIM == 2 && ORDER <= 2 && MODE == 0 ? 5 : (MODE == 4 && ORDER == 3 ? 3 : (MODE >= 4 ? 4 : 1))))) gpd_kernel(const StoreDesc* __restrict__ stores, int nstores, int jp,
                                                      int kstep) {
   gpd_body<DIM, ORDER, MODE>(stores, nstores, jp, kstep);
 }
@@ -1669,7 +1781,8 @@ static size_t split_lds_bytes(const GridDesc& g0) {
   pic_gpd_split_strides(g);
   const size_t f2 = (size_t)(g.tile[2] + 2 * g.slk[2] + g.fa + g.fb);
   const size_t j2 = (size_t)(g.tile[2] + 2 * g.slk[2] + g.ja + g.jb);
-  return std::max(6 * (size_t)g.fs01 * f2 * sizeof(float), 3 * (size_t)g.js01 * j2 * sizeof(unsigned long long));
+  return std::max(std::max(6 * (size_t)g.fs01 * f2 * sizeof(float), 3 * (size_t)g.js01 * j2 * sizeof(unsigned long long)),
+                  kInterleaveLds);
 }
 
 size_t pic_gpd_lds_bytes(const GridDesc& g) {
