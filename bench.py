@@ -182,6 +182,32 @@ def timed_steps(sim, stream, steps):
     return max(wall, ev0.elapsed_time(ev1) / 1000.0)
 
 
+def _source_sha256():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ["gpd.hip", "pic_dev.h"]:
+        with open(os.path.join(ROOT, "paper_1503_00276_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def batched_traffic(ninst, infos, step_s):
+    """Counter-measured HBM traffic (GB/s) of the batched particle launches,
+    from the committed record of the same source and the same autotuned
+    layout (every instance's tile and the sort interval), else None."""
+    path = os.path.join(ROOT, "profiles", f"gpd_2d3v_thermal_scan_{ninst}_instances_counters.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    layout = {"sort_interval": int(infos[0].sort_interval), "tiles": [list(i.tile)[:2] for i in infos],
+              "chunks": [int(i.chunk) for i in infos]}
+    if rec.get("source_sha256") != _source_sha256() or rec.get("layout") != layout:
+        return None
+    kib = rec["fetch_kib_per_step"] * rec["fetch_scale"] + rec["write_kib_per_step"] * rec["write_scale"]
+    return kib * 1024.0 / step_s / 1e9
+
+
 def run_batched(args, pic, stream):
     """The batched scan against the same instances run plain one after another,
     each plain run with the layout the batch's autotuner gave that instance."""
@@ -216,10 +242,18 @@ def run_batched(args, pic, stream):
     infos = [batch.info(k) for k in range(len(wls))]
     batch.close()
     abytes = sum(algorithmic_bytes(wl.n, 2, wl.ncell) for wl in wls)
+    # one launch per shape order and step: the per-step traffic of all of
+    # them against the per-launch average time times the launches per step
+    nlaunch = len({wl.order for wl in wls})
+    traffic = batched_traffic(len(wls), infos, gpd_avg_s * nlaunch)
+    if args.batch_layout_out:
+        with open(args.batch_layout_out, "w") as f:
+            json.dump({"sort_interval": int(infos[0].sort_interval), "tiles": [list(i.tile)[:2] for i in infos],
+                       "chunks": [int(i.chunk) for i in infos]}, f)
 
     log("batched leg: the same instances plain, one after another")
     t_plain = 0.0
-    for k, wl in enumerate(wls):
+    for k, wl in enumerate(wls if not args.batch_no_plain else []):
         inf = infos[k]
         cfg = pic.Config(ndim=2, nx=wl.nx, dx=wl.dx, dt=wl.dt, shape_order=wl.order, ion_density=wl.ion_density,
                          tile=tuple(inf.tile), sort_interval=inf.sort_interval, chunk=inf.chunk)
@@ -230,7 +264,7 @@ def run_batched(args, pic, stream):
         t_plain += timed_steps(sim, stream, K)
         sim.close()
     v_batch = ntot * K / t_batch
-    v_plain = ntot * K / t_plain
+    v_plain = ntot * K / t_plain if t_plain > 0 else float("nan")
     return {
         "workload": f"2d3v_thermal_scan_{len(wls)}_instances",
         "instances": len(wls),
@@ -250,8 +284,9 @@ def run_batched(args, pic, stream):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": abytes / gpd_avg_s / 1e9 / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
             "kernel": "gpd_kernel, all instances in one launch per shape order",
+            "launches_per_step": nlaunch,
             "kernel_avg_us": gpd_avg_s * 1e6,
             "kernel_pushes_per_s": ntot / gpd_avg_s,
         },
@@ -272,17 +307,11 @@ def counter_record(wl, info):
     workload and layout (FETCH_SIZE, WRITE_SIZE and SQ_INSTS_VALU per
     dispatch), or None when there is none or the kernel's source changed
     since the counters were taken."""
-    import hashlib
-
     path = os.path.join(ROOT, "profiles", f"gpd_{wl.name}_counters.json")
     if not os.path.exists(path):
         return None, None
     rec = json.load(open(path))
-    h = hashlib.sha256()
-    for f in ["gpd.hip", "pic_dev.h"]:
-        with open(os.path.join(ROOT, "paper_1503_00276_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    if rec.get("source_sha256") != h.hexdigest() or rec.get("workload_name") != wl.name:
+    if rec.get("source_sha256") != _source_sha256() or rec.get("workload_name") != wl.name:
         return rec, None
     for e in rec.get("layouts", []):
         if (list(e["tile"]) == list(info.tile)[:wl.ndim] and e["sort_interval"] == info.sort_interval
@@ -431,6 +460,10 @@ def main():
                     help="run only the batched leg and print its record (for profiling)")
     ap.add_argument("--batch-instances", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--batch-no-plain", action="store_true",
+                    help="skip the plain one-after-another runs of the batched leg (counter passes)")
+    ap.add_argument("--batch-layout-out", default="",
+                    help="write the batched leg's autotuned layout (JSON) to this file (counter records)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -447,6 +480,15 @@ def main():
     assert torch.cuda.is_available(), "no GPU visible"
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()  # a non-default stream so the library can capture graphs on it
+    if args.calib_copy_mib > 0:
+        # a plain device copy of known size: the counters' calibration
+        n = args.calib_copy_mib * 1024 * 1024 // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     if args.only_batched:
         print(json.dumps(run_batched(args, pic, stream)), flush=True)
         return
@@ -458,15 +500,6 @@ def main():
         layout = DEFAULT_LAYOUT.get(args.workload)
     head = plain_leg(args, pic, stream, args.workload, args.steps, layout,
                      tune=args.tune_headline or (layout is None and args.workload not in DEFAULT_LAYOUT))
-
-    if args.calib_copy_mib > 0:
-        n = args.calib_copy_mib * 1024 * 1024 // 4
-        a = torch.ones(n, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
 
     lwfa = None
     if not args.no_lwfa and args.workload != "lwfa2d":

@@ -16,6 +16,7 @@ namespace {
 constexpr int kBlock = 256;
 
 typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) unsigned int guint;
 
 // Tile of cells one workgroup advances (256 cells, one per thread).
 template <int DIM> struct YeeTile;
@@ -44,6 +45,40 @@ __device__ __forceinline__ int wrap1(int v, int n) {
 
 // WIN: compiled with the moving-window terms (launched for groups that hold a
 // moving window).
+// The fixed point of this step's current, per store whose particles take
+// the one-phase fused kernel with FP32 accumulation (Cartesian).  A
+// contribution of particle p to one node is at most |w_p| |v_p| (the charge
+// fraction that crosses a face in a step is at most the displacement in
+// cells; the transverse weight is at most one), and the Boris step changes
+// |u| by at most |q/m| dt |E| at the particle, where a gathered E_c is a
+// convex combination of node values: |E| <= sqrt(3) max|E_c| + |E_0|.  The
+// store keeps umax, a bound on |u| at the start of the step, and the
+// instance a running bound on |E_c| (set at a field load, raised by the Yee
+// step), so V = max|w| min(1, umax + kick) bounds every contribution of the
+// step, and the unit 2^-e with 2^e V 1.0001 < 2^31 keeps each inside an
+// int32: it follows the plasma's speed rather than c.  umax then advances
+// by the kick for the next step.  The int64 mode keeps the instance's unit
+// (its sums are exact in one unit), and so do r-z (whose field step keeps no
+// bound) and the two-phase 3D kernel (which takes a unit per work item).
+__global__ void current_units(StoreDesc* __restrict__ stores, int nstores) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nstores) return;
+  StoreDesc& D = stores[k];
+  const GridDesc& g = D.g;
+  if (g.acc_mode == 2 || g.cyl || pic_gpd_split(g)) return;
+  const float em = *(const gfloat*)D.emax;
+  const float e0n = sqrtf(g.e0[0] * g.e0[0] + g.e0[1] * g.e0[1] + g.e0[2] * g.e0[2]);
+  const float kick = fabsf(D.qm) * g.dt * (1.7320509f * em + e0n) * 1.0001f;
+  const float um = (D.ctl->umax + kick) * 1.000001f;
+  D.ctl->umax = um;
+  const float V = D.wmax * fminf(1.0f, um * 1.0001f);
+  int ex = 0;
+  (void)frexpf(V * 1.0001f, &ex);
+  const int e = V > 0.0f ? min(100, max(-100, 31 - ex)) : 100;
+  D.g.jscale = ldexpf(1.0f, e);
+  D.g.jinv = ldexpf(1.0f, -e);
+}
+
 template <int DIM, bool WIN>
 __global__ void __launch_bounds__(kBlock) yee_step(const InstDesc* __restrict__ inst, int par) {
   using T = YeeTile<DIM>;
@@ -223,8 +258,12 @@ __global__ void __launch_bounds__(kBlock) yee_step(const InstDesc* __restrict__ 
           }
         }
     __syncthreads();
-    // B' on the tile, and write E', B' back
+    // B' on the tile, and write E', B' back; the largest |E'_c| written
+    // raises the instance's running field bound (read by the particle
+    // kernel for its current unit)
     gfloat* Fw = (gfloat*)I.F[1 - par];
+    float em = 0.0f;
+    const float emax0 = *(const gfloat*)I.emax;
     for (int z = zoff + (DIM == 3 ? tz : 0); z <= (DIM == 3 ? e2 : 0); z += T::Z)
       for (int y = 1 + ty; y <= e1; y += T::Y)
         for (int x = 1 + tx; x <= e0; x += T::X) {
@@ -250,7 +289,14 @@ __global__ void __launch_bounds__(kBlock) yee_step(const InstDesc* __restrict__ 
           Fw[gi] = sE[0][c] * keep;
           Fw[nc + gi] = sE[1][c] * keep;
           Fw[2 * nc + gi] = sE[2][c] * keep;
+          em = fmaxf(em, fmaxf(fabsf(sE[0][c]), fmaxf(fabsf(sE[1][c]), fabsf(sE[2][c]))));
         }
+    if (__ballot(em > emax0)) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) em = fmaxf(em, __shfl_xor(em, off));
+      if ((threadIdx.x & 63) == 0)
+        __hip_atomic_fetch_max((guint*)I.emax, __float_as_uint(em), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 
@@ -599,6 +645,11 @@ int pic_yee_tiles(int dim, const int nx[3]) {
     return ((nx[0] + YeeTile<2>::X - 1) / YeeTile<2>::X) * ((nx[1] + YeeTile<2>::Y - 1) / YeeTile<2>::Y);
   return ((nx[0] + YeeTile<3>::X - 1) / YeeTile<3>::X) * ((nx[1] + YeeTile<3>::Y - 1) / YeeTile<3>::Y) *
          ((nx[2] + YeeTile<3>::Z - 1) / YeeTile<3>::Z);
+}
+
+hipError_t pic_launch_current_units(StoreDesc* d_stores, int nstores, hipStream_t st) {
+  hipLaunchKernelGGL(current_units, dim3((nstores + 63) / 64), dim3(64), 0, st, d_stores, nstores);
+  return hipGetLastError();
 }
 
 hipError_t pic_launch_yee_step(const InstDesc* d_inst, int ninst, int max_tiles, int dim, bool cart, bool cyl,

@@ -65,6 +65,9 @@ struct StoreCtl {
                     // every k-th check (nchecks % k == 0), flagged or not
   int np;           // particles in the current set after the last rebin (moving window)
   int sorted;       // 1: every particle sits in its own tile (loaded, or re-sorted at the last check)
+  float umax;       // bound on |u| of the store's particles at the start of the step: set at
+                    // a load (with the largest thermal momentum a moving window can inject),
+                    // raised at every step by the largest kick it can give (see gpd_body)
 };
 
 __host__ __device__ inline int pic_cur(const StoreCtl& c) { return c.cur ^ c.pending; }
@@ -101,6 +104,7 @@ struct Item {
 struct StoreDesc {
   GridDesc g;
   float qm;                  // charge-to-mass ratio q/m = 1/rqm
+  float wmax;                // max |w| over the store's particles (rounded up)
   int np;                    // particles stored
   int chunk;                 // maximum particles per work item
   int max_items;
@@ -133,6 +137,7 @@ struct StoreDesc {
   const int* nsrc;           // [ntiles][27] tile - delta_s (periodic), per instance
   const int* ndst;           // [ntiles][27] tile + delta_s (periodic), per instance
   StoreCtl* ctl;
+  const float* emax;         // the instance's running bound on |E_c| (see InstDesc)
 };
 
 // One instance (for the field kernels).
@@ -152,6 +157,8 @@ struct InstDesc {
   float* Jsm[2];
   WinCtl* win;               // moving window state (null without a window)
   int win_inject;            // moving window: particles injected per shift
+  float* emax;               // running bound on |E_c| over the grid (Cartesian): set at a field
+                             // load, raised by the Yee step, never lowered
 };
 
 // ---------------------------------------------------------------------------

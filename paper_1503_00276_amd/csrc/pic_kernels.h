@@ -37,6 +37,9 @@ hipError_t pic_launch_smooth_pass(const InstDesc* d_inst, int ninst, int max_nce
 // cart / cyl: the group holds Cartesian / r-z instances (each kernel skips the
 // others); window: some instance has a moving window (selects the variant
 // with the window terms)
+// Per store: this step's fixed point of the one-phase kernels' FP32 current
+// (from the store's bound on |u| and the instance's bound on |E_c|).
+hipError_t pic_launch_current_units(StoreDesc* d_stores, int nstores, hipStream_t st);
 hipError_t pic_launch_yee_step(const InstDesc* d_inst, int ninst, int max_tiles, int dim, bool cart, bool cyl,
                                bool window, int parity, hipStream_t st);
 

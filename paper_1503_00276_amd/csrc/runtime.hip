@@ -53,6 +53,7 @@ struct Instance {
   float* Jout = nullptr;
   float* Jsm[2] = {nullptr, nullptr};  // smoothing buffers (only when smoothing is on)
   WinCtl* win = nullptr;               // moving window state (device)
+  float* emax = nullptr;               // running bound on |E_c| (device, see InstDesc)
   int* nsrc = nullptr;  // neighbour tile tables of the rebin
   int* ndst = nullptr;
   double wmax[PIC_MAX_SPECIES] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -69,6 +70,7 @@ struct Group {
   int sm_max[3];  // most smoothing passes of any instance, per axis
   int inject_max; // moving window: most particles a store injects per shift
   bool window;    // some instance has a moving window
+  bool units = false;  // stores: some store takes a per-step current unit (current_units)
   int mode = 0;   // stores: boundary logic of the fused kernel (0 periodic, 1 moving window, 2 r-z)
   int resident = 1;  // stores: fused-kernel workgroups resident per CU (the grid is one full wave of them)
   // stores, per step of a sort cycle: the LDS that step stages (its halo
@@ -361,8 +363,12 @@ void set_current_scale(Instance& I) {
   e = std::max(-60, std::min(60, e));
   I.g.jscale = std::ldexp(1.0f, e);
   I.g.jinv = std::ldexp(1.0f, -e);
-  for (Species& sp : I.sp)
-    if (sp.used) sp.desc.g = I.g;
+  for (int s = 0; s < PIC_MAX_SPECIES; s++) {
+    Species& sp = I.sp[s];
+    if (!sp.used) continue;
+    sp.desc.g = I.g;
+    sp.desc.wmax = std::nextafter((float)I.wmax[s], INFINITY);  // the one-phase kernels' per-item unit
+  }
 }
 
 // Allocate (or grow) a species store for 'cap' particles.
@@ -408,6 +414,7 @@ pic_status alloc_species(Sim& S, Instance& I, Species& sp, int64_t cap, int chun
   d.ndst = I.ndst;
   d.cap = (int)cap;
   d.win = I.win;
+  d.emax = I.emax;
   StoreCtl z{};
   HIPCHK(S, hipMemcpy(sp.ctl, &z, sizeof z, hipMemcpyHostToDevice));
   sp.cap = cap;
@@ -446,6 +453,7 @@ pic_status refresh_descriptors(Sim& S) {
           gr.max_blocks += (I.g.ntiles + PIC_REBIN_TILES - 1) / PIC_REBIN_TILES;
           gr.lds = std::max(gr.lds, pic_gpd_lds_bytes(I.g));
           if (I.g.window) gr.window = true;
+          if (I.g.acc_mode != PIC_ACC_FIXED64 && !I.g.cyl && !pic_gpd_split(I.g)) gr.units = true;
           gr.inject_max = std::max(gr.inject_max, sp.desc.inj_ppc[0] * sp.desc.inj_ppc[1] * sp.desc.inj_ppc[2] *
                                                       (I.g.ncell / I.g.nx[0]));
         }
@@ -500,6 +508,7 @@ pic_status refresh_descriptors(Sim& S) {
       id.Jsm[0] = I.Jsm[0];
       id.Jsm[1] = I.Jsm[1];
       id.win = I.win;
+      id.emax = I.emax;
       if (I.cfg.move_window) {
         int ppc = 1;
         for (int a = 0; a < I.g.dim; a++) ppc *= I.cfg.inject_ppc[a];
@@ -616,6 +625,8 @@ pic_status launch_steps(Sim& S, int64_t first, int nsteps, bool end_with_check, 
       p1 = take_event(S);
       if (!p0 || !p1) p0 = p1 = nullptr;
     }
+    for (const Group& gr : S.sgroups)
+      if (gr.units) HIPCHK(S, pic_launch_current_units(S.d_stores + gr.first, gr.count, S.stream));
     for (size_t q = 0; q < S.sgroups.size(); q++) {
       const Group& gr = S.sgroups[q];
       // one full wave of resident workgroups: a partial second wave would
@@ -871,6 +882,12 @@ pic_status upload_bins(Sim& S, Species& sp, const Binned& B) {
   c.n_items[0] = (int)B.items.size();
   c.n_items[1] = 0;
   c.sorted = 1;  // binned exactly: every particle in its own tile
+  // the one-phase kernels' bound on |u| covers every particle uploaded
+  double um = 0.0;
+  for (size_t q = 0; q < n; q++)
+    um = std::max(um, std::sqrt((double)o.u[0][q] * o.u[0][q] + (double)o.u[1][q] * o.u[1][q] +
+                                (double)o.u[2][q] * o.u[2][q]));
+  c.umax = std::max(c.umax, std::nextafter((float)(um * (1.0 + 1e-6)), INFINITY));
   HIPCHK(S, hipMemcpy(sp.ctl, &c, sizeof c, hipMemcpyHostToDevice));
   sp.np = (int64_t)n;
   sp.desc.np = (int)n;
@@ -1029,6 +1046,11 @@ pic_status sim_load(Sim& S, int inst, int32_t species, double rqm, int64_t n, co
     StoreCtl c{};
     HIPCHK(S, hipMemcpy(&c, sp.ctl, sizeof c, hipMemcpyDeviceToHost));
     c.np = (int)sp.np;
+    // the bound on |u| also covers what a thermal window can inject (a
+    // Box-Muller deviate from 53-bit uniforms is at most sqrt(2 * 53 ln 2) =
+    // 8.5717 per component)
+    if (win && species == 0 && I.cfg.inject_uth > 0.0)
+      c.umax = std::max(c.umax, (float)(8.5718 * std::sqrt(3.0) * I.cfg.inject_uth * (1.0 + 1e-6)));
     HIPCHK(S, hipMemcpy(sp.ctl, &c, sizeof c, hipMemcpyHostToDevice));
   }
   return st;
@@ -1083,13 +1105,19 @@ pic_status sim_load_fields(Sim& S, int inst, const double* e, const double* b, u
     }
   }
   std::vector<float> f(2 * n);
+  float em = 0.0f;
   for (size_t i = 0; i < n; i++) {
     if (!std::isfinite(he[i]) || !std::isfinite(hb[i])) return S.fail(PIC_E_RANGE, "non-finite field value");
     f[i] = (float)he[i];
     f[n + i] = (float)hb[i];
+    em = std::max(em, std::fabs(f[i]));
   }
   HIPCHK(S, hipStreamSynchronize(S.stream));
   HIPCHK(S, hipMemcpy(I.F[S.steps & 1], f.data(), 2 * n * sizeof(float), hipMemcpyHostToDevice));
+  // the running field bound covers the loaded E
+  float em0 = 0.0f;
+  HIPCHK(S, hipMemcpy(&em0, I.emax, sizeof em0, hipMemcpyDeviceToHost));
+  if (em > em0) HIPCHK(S, hipMemcpy(I.emax, &em, sizeof em, hipMemcpyHostToDevice));
   return PIC_OK;
 }
 
@@ -1497,6 +1525,8 @@ pic_status sim_create(Sim& S, const pic_config* cfgs, int n, void* stream) {
     }
     if ((st = build_tables(S, I)) != PIC_OK) return st;
     if (hipMalloc(&I.Jout, 3 * nc * sizeof(float)) != hipSuccess) return S.fail(PIC_E_NOMEM, "current allocation failed");
+    if (hipMalloc(&I.emax, sizeof(float)) != hipSuccess) return S.fail(PIC_E_NOMEM, "field bound allocation failed");
+    HIPCHK(S, hipMemset(I.emax, 0, sizeof(float)));
     if (I.cfg.move_window) {
       if (hipMalloc(&I.win, sizeof(WinCtl)) != hipSuccess) return S.fail(PIC_E_NOMEM, "window state allocation failed");
       HIPCHK(S, hipMemset(I.win, 0, sizeof(WinCtl)));
@@ -1560,6 +1590,7 @@ void sim_destroy(Sim& S) {
     for (int k = 0; k < 2; k++)
       if (I.Jsm[k]) (void)hipFree(I.Jsm[k]);
     if (I.win) (void)hipFree(I.win);
+    if (I.emax) (void)hipFree(I.emax);
     if (I.nsrc) (void)hipFree(I.nsrc);
     if (I.ndst) (void)hipFree(I.ndst);
     if (I.rho_snap) (void)hipFree(I.rho_snap);

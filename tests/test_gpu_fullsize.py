@@ -161,6 +161,46 @@ def test_cubic3d_subrun_full_parity(orc):
     sim.close()
 
 
+def _golden_energy():
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "cubic3d_64_energy.txt")
+    rows = [line.split() for line in open(path) if line.strip() and not line.startswith("#")]
+    return np.array([[float(v) for v in r[1:]] for r in rows])
+
+
+def test_cubic3d_subrun_energy_history_in_bench_layout():
+    """Workload 5's 64^3 sub-run in the benchmark's layout of the full
+    workload (4x4x4 tiles, sort interval 1, chunk 512): the field and
+    kinetic energies of 100 FP32 steps against the FP64 oracle's history
+    (tests/golden/cubic3d_64_energy.txt, written by make_cubic_sub_energy.py
+    from the oracle alone).  W_E and W_B grow from the thermal noise and
+    are compared within 1 % of their own value from step 5 on; W_K moves by
+    about 1 % over the run, and its change is compared within 1 %."""
+    from paper_1503_00276_amd import workloads as W
+
+    pic = _pic()
+    ref = _golden_energy()
+    assert ref.shape == (100, 3)
+    wl = W.workload5_sub()
+    cfg, sim = _sim(pic, wl, tile=(4, 4, 4), sort_interval=1, chunk=512)
+    gpu = []
+    for n in range(100):
+        sim.step(1)
+        en = sim.energy()
+        gpu.append((en[0], en[1], en[2]))
+    gpu = np.array(gpu)
+    print("W_E", gpu[[4, 49, 99], 0], ref[[4, 49, 99], 0], flush=True)
+    print("W_B", gpu[[4, 49, 99], 1], ref[[4, 49, 99], 1], flush=True)
+    print("W_K", gpu[[4, 49, 99], 2], ref[[4, 49, 99], 2], flush=True)
+    assert np.abs(gpu[4:, 0] / ref[4:, 0] - 1).max() <= 1e-2
+    assert np.abs(gpu[4:, 1] / ref[4:, 1] - 1).max() <= 1e-2
+    dk = np.abs(ref[:, 2] - ref[0, 2]).max()
+    assert np.abs(gpu[:, 2] - ref[:, 2]).max() <= 1e-2 * dk + 1e-6 * ref[:, 2].max()
+    assert sim.counts()[0] == 100
+    sim.close()
+
+
 def test_cubic3d_full_size_sampled_parity(orc):
     """Workload 5 at full size (134,217,728 electrons, 512x256x256, cubic)."""
     from paper_1503_00276_amd import workloads as W

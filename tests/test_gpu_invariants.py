@@ -40,19 +40,6 @@ def _pic():
     return pic
 
 
-def _drift_j_tol(ndim, speed):
-    """The periodic 3D kernel takes its fixed point per work item from the
-    item's fastest particle, so its current keeps J_TOL at any speed.  The 2D
-    kernels take one unit per instance, 2^-31 max|w| (a contribution is at
-    most |w| |v| < |w| c): a particle at 1e-4 c splits |w| 1e-4 over a few
-    dozen node contributions of ~2^13 units each, so a node's rounding is a
-    few parts in 10^5 of the current at that speed (1.1-1.8e-5 measured).
-    At 1e-3 c and above the 2D current is within J_TOL."""
-    if ndim == 2 and speed < 1e-3:
-        return 3e-5
-    return J_TOL
-
-
 @pytest.mark.parametrize("speed", [1e-4, 1e-3])
 @pytest.mark.parametrize("ndim,order", [(2, 1), (2, 2), (2, 3), (3, 1), (3, 2), (3, 3)])
 def test_slow_coherent_drift_current(orc, ndim, order, speed):
@@ -96,7 +83,7 @@ def test_slow_coherent_drift_current(orc, ndim, order, speed):
         # rounding of the offsets
         mv = periodic_dx(x1, x0, L) - (u1[:, :ndim] / np.sqrt(1.0 + (u1 ** 2).sum(axis=1))[:, None]) * cfg.dt
         print(k, "J", err, "move", np.abs(mv / np.asarray(dx)).max(), flush=True)
-        assert err <= _drift_j_tol(ndim, speed)
+        assert err <= J_TOL
         assert np.abs(mv / np.asarray(dx)).max() <= POS_TOL
     sim.close()
 
