@@ -6,9 +6,12 @@ charge-conserving deposit of one particle), whole step included (the Yee
 field solve and the rebin checks run inside the timed region), inputs already
 resident in HBM.  Headline workload (default): the 3D3V uniform thermal
 plasma of 512x256x256 cells, 134,217,728 electrons, cubic shape, timed after
-100 untimed steps in the layout the autotuner picks for it.  Further legs:
-the 2D3V laser wakefield (1024x256 cells, 2,097,152 electrons, quadratic,
-autotuned in the run), the batched scan (64 independent 2D thermal instances
+100 untimed steps in the layout the autotuner picked for it (4x4x4 tiles,
+sort interval 1, chunk 512).  Further legs: the 2D3V laser wakefield
+(1024x256 cells, 2,097,152 electrons, quadratic, 32x8 tiles, sort interval
+6, chunk 1024: the autotuner's usual pick, fixed so that the parity tests
+and the counter records cover exactly the timed layout; --workload lwfa2d
+autotunes it in the run), the batched scan (64 independent 2D thermal instances
 of uneven grids and particle counts advanced by the batched step) against the
 same instances run plain one after another, and the FP64 CPU oracle on the
 host's cores.  Prints one JSON line.
@@ -208,14 +211,22 @@ def batched_traffic(ninst, infos, step_s):
     return kib * 1024.0 / step_s / 1e9
 
 
+# Layout of the batched leg unless --batch-tune: the library's tile for each
+# instance, with the sort interval and chunk the batch autotuner picked for
+# this scan (fixed so that runs, parity tests and the counter record agree).
+BATCH_LAYOUT = {"sort_interval": 3, "chunk": 2048}
+
+
 def run_batched(args, pic, stream):
     """The batched scan against the same instances run plain one after another,
-    each plain run with the layout the batch's autotuner gave that instance."""
+    each plain run with the layout the batch gave that instance."""
     from paper_1503_00276_amd import workloads as W
 
     log(f"batched leg: generating {args.batch_instances} instances")
     wls = W.workload4(ninst=args.batch_instances, steps=args.batch_steps)
-    cfgs = [pic.Config(ndim=2, nx=wl.nx, dx=wl.dx, dt=wl.dt, shape_order=wl.order, ion_density=wl.ion_density)
+    lay = {} if args.batch_tune else BATCH_LAYOUT
+    cfgs = [pic.Config(ndim=2, nx=wl.nx, dx=wl.dx, dt=wl.dt, shape_order=wl.order, ion_density=wl.ion_density,
+                       sort_interval=lay.get("sort_interval", 0), chunk=lay.get("chunk", 0))
             for wl in wls]
     ntot = sum(wl.n for wl in wls)
     batch = pic.PicBatch(cfgs, stream=stream)
@@ -225,7 +236,7 @@ def run_batched(args, pic, stream):
     batch.step(args.warmup)
     batch.sync()
     tune = None
-    if args.tune_steps > 0:
+    if args.batch_tune and args.tune_steps > 0:
         log("batched leg: autotune")
         tune = batch.autotune(trial_steps=args.tune_steps)
         batch.step(args.warmup)
@@ -277,18 +288,19 @@ def run_batched(args, pic, stream):
         "plain_ms_per_step": t_plain * 1000.0 / K,
         "batched_over_plain": v_batch / v_plain,
         "autotune": tune,
+        "layout_from": "autotuned in this run" if tune else "fixed: library tiles, sort interval 3, chunk 2048",
         "sort_interval": int(infos[0].sort_interval),
         "roofline": {
             "bound": "hbm",
-            "achieved": abytes / gpd_avg_s / 1e9,
+            "achieved": abytes / (gpd_avg_s * nlaunch) / 1e9,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": abytes / gpd_avg_s / 1e9 / HBM_PEAK_GBS,
+            "frac": abytes / (gpd_avg_s * nlaunch) / 1e9 / HBM_PEAK_GBS,
             "traffic": traffic,
             "kernel": "gpd_kernel, all instances in one launch per shape order",
             "launches_per_step": nlaunch,
             "kernel_avg_us": gpd_avg_s * 1e6,
-            "kernel_pushes_per_s": ntot / gpd_avg_s,
+            "kernel_pushes_per_s": ntot / (gpd_avg_s * nlaunch),
         },
     }
 
@@ -299,6 +311,7 @@ def run_batched(args, pic, stream):
 # minutes.  --tune-headline runs the search instead.
 DEFAULT_LAYOUT = {
     "cubic3d": {"tile": [4, 4, 4], "sort_interval": 1, "chunk": 512},
+    "lwfa2d": {"tile": [32, 8], "sort_interval": 6, "chunk": 1024},
 }
 
 
@@ -460,6 +473,8 @@ def main():
                     help="run only the batched leg and print its record (for profiling)")
     ap.add_argument("--batch-instances", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--batch-tune", action="store_true",
+                    help="run the batch autotuner instead of the fixed batched layout")
     ap.add_argument("--batch-no-plain", action="store_true",
                     help="skip the plain one-after-another runs of the batched leg (counter passes)")
     ap.add_argument("--batch-layout-out", default="",
@@ -503,7 +518,7 @@ def main():
 
     lwfa = None
     if not args.no_lwfa and args.workload != "lwfa2d":
-        lwfa = plain_leg(args, pic, stream, "lwfa2d", args.lwfa_steps, None, tune=True)
+        lwfa = plain_leg(args, pic, stream, "lwfa2d", args.lwfa_steps, DEFAULT_LAYOUT["lwfa2d"], tune=False)
     batched = None
     if not args.no_batched:
         batched = run_batched(args, pic, stream)

@@ -103,14 +103,15 @@ def test_thermal_64x64_full_parity_and_energy_history(orc):
     sim.close()
 
 
-@pytest.mark.parametrize("layout", [None, (32, 8, 8, 1024)], ids=["autotuned", "32x8_si8_chunk1024"])
+@pytest.mark.parametrize("layout", [None, (32, 8, 8, 1024, 45), (32, 8, 6, 1024, 112)],
+                         ids=["autotuned", "32x8_si8_chunk1024", "bench_32x8_si6_chunk1024"])
 def test_lwfa_full_size_parity_in_bench_layout(orc, layout):
     """Workload 2 (2,097,152 electrons, quadratic, laser): the autotuned
-    layout, or the layout the benchmark's autotuner settles on (32x8 tiles,
-    sort interval 8, chunk 1024); 40-45 steps into the run (the wake has
-    formed, particles cross cells and tiles, rebins have run), then every
-    particle, current and field value for two steps (late in a sort cycle
-    for the fixed layout, where the staged halo is widest)."""
+    layout, a fixed 32x8 layout with sort interval 8, and the benchmark's
+    layout (32x8 tiles, sort interval 6, chunk 1024) at the benchmark's
+    state (it times from step 111 on: steps 113 and 114 are the last two of
+    a sort cycle, where the staged halo is widest); then every particle,
+    current and field value for two steps."""
     from paper_1503_00276_amd import workloads as W
 
     pic = _pic()
@@ -122,7 +123,7 @@ def test_lwfa_full_size_parity_in_bench_layout(orc, layout):
     else:
         cfg, sim = _sim(pic, wl, tile=layout[:2], sort_interval=layout[2], chunk=layout[3])
         tune = None
-        nsteps = 45  # the next two steps are steps 5 and 6 of an 8-step cycle
+        nsteps = layout[4]
     info = sim.info()
     print("layout", list(info.tile), info.sort_interval, info.chunk, tune, flush=True)
     sim.step(nsteps)
@@ -201,35 +202,53 @@ def test_cubic3d_subrun_energy_history_in_bench_layout():
     sim.close()
 
 
-def test_cubic3d_full_size_sampled_parity(orc):
-    """Workload 5 at full size (134,217,728 electrons, 512x256x256, cubic)."""
+@pytest.mark.parametrize("layout", [None, (4, 4, 4, 1, 512)], ids=["defaults", "bench_4x4x4_si1_chunk512"])
+def test_cubic3d_full_size_sampled_parity(orc, layout):
+    """Workload 5 at full size (134,217,728 electrons, 512x256x256, cubic):
+    with the library's defaults two steps in, and in the benchmark's layout
+    (4x4x4 tiles, sort interval 1, chunk 512) at the benchmark's state (it
+    times from step 111 on, after the work items have been re-interleaved
+    and particles have strayed from their tiles for a hundred steps)."""
     from paper_1503_00276_amd import workloads as W
 
     pic = _pic()
     wl = W.workload5()
-    cfg, sim = _sim(pic, wl)
+    if layout is None:
+        cfg, sim = _sim(pic, wl)
+        nsteps = 2
+    else:
+        cfg, sim = _sim(pic, wl, tile=layout[:3], sort_interval=layout[3], chunk=layout[4])
+        nsteps = 111
     del wl
-    sim.step(2)
-    _check(sampled_step_parity(orc, sim, cfg, 20000, (200, 100, 100), (216, 116, 116)), "cfg5 full")
+    sim.step(nsteps)
+    print("layout", list(sim.info().tile), sim.info().sort_interval, sim.info().chunk, flush=True)
+    _check(sampled_step_parity(orc, sim, cfg, 20000, (200, 100, 100), (216, 116, 116)), f"cfg5 full, step {nsteps + 1}")
     sim.close()
 
 
-def test_batched_scan_parity():
-    """Workload 4 (64 instances, 62 M particles) as the benchmark runs it
-    (autotuned batch): every particle of the four smallest instances and a
-    sample of two large ones, one step each, against the oracle."""
+@pytest.mark.parametrize("tuned", [False, True], ids=["bench_layout", "autotuned"])
+def test_batched_scan_parity(tuned):
+    """Workload 4 (64 instances, 62 M particles) in the benchmark's batched
+    layout (the library's tiles, sort interval 3, chunk 2048) at the state it
+    times from (after 10 steps), and autotuned: every particle of the four
+    smallest instances and a sample of two large ones, one step each,
+    against the oracle."""
     import oracle as orc
     from paper_1503_00276_amd import workloads as W
 
     pic = _pic()
     wls = W.workload4()
-    cfgs = [pic.Config(ndim=2, nx=wl.nx, dx=wl.dx, dt=wl.dt, shape_order=wl.order, ion_density=wl.ion_density)
+    lay = {} if tuned else {"sort_interval": 3, "chunk": 2048}
+    cfgs = [pic.Config(ndim=2, nx=wl.nx, dx=wl.dx, dt=wl.dt, shape_order=wl.order, ion_density=wl.ion_density, **lay)
             for wl in wls]
     batch = pic.PicBatch(cfgs)
     for k, wl in enumerate(wls):
         batch.load_particles(k, wl.x, wl.u, wl.w, rqm=wl.rqm)
-    batch.autotune(trial_steps=4)
-    batch.step(5)
+    if tuned:
+        batch.autotune(trial_steps=4)
+        batch.step(5)
+    else:
+        batch.step(10)
     sizes = np.array([wl.n for wl in wls])
     pick = list(np.argsort(sizes)[:4]) + list(np.argsort(sizes)[-2:])
     states = {}
