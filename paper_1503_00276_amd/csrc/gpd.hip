@@ -1121,73 +1121,31 @@ constexpr int kSplitR = 3;  // particles per thread per work item
 // and one start per level (at most one level per particle of the item)
 constexpr size_t kInterleaveLds = 64 * sizeof(int) + (size_t)kSplitR * kBlock * (sizeof(unsigned long long) + sizeof(int));
 
-// After the step, the particles of a work item are rewritten inside the
-// item's range in cell-interleaved order: the cells of the tile fall into
-// 64 classes (local linear index mod 64, x fastest), and the order is the
-// first particle of every class in class order, then the second of every
-// class, and so on.  The lanes of a wavefront then hold particles of
-// (nearly) 64 different cells, so the next step's LDS gathers and current
-// adds spread over the banks and rarely hit one address together; without
-// it the loaded order decays as particles change cells, and the kernel
-// slows by about a third.  Among particles of one class the order is that
-// of the LDS atomics (not reproducible), which only permutes storage: every
-// particle's own arithmetic, the item's membership and its fixed-point unit
-// are unchanged, and the int64 current is order-free.  The new state was
-// written by the same thread in phase A and is read back here.
-__device__ __forceinline__ void reinterleave_item(const StoreDesc& S, int set, const Item it, float* smem) {
+// The particles of a work item are stored after the step inside the item's
+// range in cell-interleaved order: the cells of the tile fall into 64
+// classes (local linear index mod 64, x fastest), and the order is the first
+// particle of every class in class order, then the second of every class,
+// and so on.  The lanes of a wavefront then hold particles of (nearly) 64
+// different cells, so the next step's LDS gathers and current adds spread
+// over the banks and rarely hit one address together; without it the loaded
+// order decays as particles change cells, and the kernel slows by about a
+// third.  Among particles of one class the order is that of the LDS atomics
+// (not reproducible), which only permutes storage: every particle's own
+// arithmetic, the item's membership and its fixed-point unit are unchanged,
+// and the int64 current is order-free.
+//
+// interleave_slots: key[r] is the class of the thread's r-th particle (-1:
+// none); on return pos[r] is its slot in the item.  smem is free LDS of at
+// least kInterleaveLds bytes; every thread of the workgroup calls it.
+__device__ __forceinline__ void interleave_slots(const int (&key)[kSplitR], int (&pos)[kSplitR], float* smem) {
   constexpr int R = kSplitR;
-  const GridDesc& g = S.g;
-  int tc[3], org[3], ext[3];
-  pic_tile_coords(g, it.tile, tc);
-#pragma unroll
-  for (int d = 0; d < 3; d++) {
-    org[d] = tc[d] * g.tile[d];
-    ext[d] = min(g.tile[d], g.nx[d] - org[d]);
-  }
   const int tid = threadIdx.x;
-  const int nthr = blockDim.x;
-  int* s_n = (int*)smem;                                                    // [64]
-  unsigned long long* s_m = (unsigned long long*)(smem + 64);               // [R * nthr]
-  int* s_l = (int*)(s_m + R * kBlock);                                      // [R * nthr]
-  gint* __restrict__ cellp = (gint*)S.cell[set];
-  gfloat* __restrict__ ep0 = (gfloat*)S.eps[set][0];
-  gfloat* __restrict__ ep1 = (gfloat*)S.eps[set][1];
-  gfloat* __restrict__ ep2 = (gfloat*)S.eps[set][2];
-  gfloat* __restrict__ up0 = (gfloat*)S.u[set][0];
-  gfloat* __restrict__ up1 = (gfloat*)S.u[set][1];
-  gfloat* __restrict__ up2 = (gfloat*)S.u[set][2];
-  gfloat* __restrict__ wp = (gfloat*)S.w[set];
-  gint* __restrict__ idp = (gint*)S.id[set];
+  int* s_n = (int*)smem;                                      // [64]
+  unsigned long long* s_m = (unsigned long long*)(smem + 64); // [R * kBlock]
+  int* s_l = (int*)(s_m + R * kBlock);                        // [R * kBlock]
   if (tid < 64) s_n[tid] = 0;
-  int pc[R], pid[R], key[R], lev[R];
-  float pv[R][7];
-#pragma unroll
-  for (int r = 0; r < R; r++) {
-    const int p = it.begin + tid + r * nthr;
-    key[r] = -1;
-    if (p < it.end) {
-      pc[r] = cellp[p];
-      pv[r][0] = ep0[p];
-      pv[r][1] = ep1[p];
-      pv[r][2] = ep2[p];
-      pv[r][3] = up0[p];
-      pv[r][4] = up1[p];
-      pv[r][5] = up2[p];
-      pv[r][6] = wp[p];
-      pid[r] = idp[p];
-      int cc[3], lc[3];
-      pic_unpack(g, pc[r], cc);
-#pragma unroll
-      for (int d = 0; d < 3; d++) {
-        // a particle strays at most a tile extent outside its tile
-        int l = pic_local(cc[d], org[d], ext[d], g.nx[d]);
-        l = l < 0 ? l + ext[d] : (l >= ext[d] ? l - ext[d] : l);
-        lc[d] = l;
-      }
-      key[r] = (lc[0] + ext[0] * (lc[1] + ext[1] * lc[2])) & 63;
-    }
-  }
-  __syncthreads();  // every particle of the item is read before any is rewritten
+  __syncthreads();
+  int lev[R];
 #pragma unroll
   for (int r = 0; r < R; r++) lev[r] = key[r] >= 0 ? atomicAdd(&s_n[key[r]], 1) : 0;
   __syncthreads();
@@ -1210,20 +1168,9 @@ __device__ __forceinline__ void reinterleave_item(const StoreDesc& S, int set, c
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < R; r++) {
-    if (key[r] < 0) continue;
-    const int q = it.begin + s_l[lev[r]] + (int)__popcll(s_m[lev[r]] & ((1ull << key[r]) - 1ull));
-    cellp[q] = pc[r];
-    ep0[q] = pv[r][0];
-    ep1[q] = pv[r][1];
-    ep2[q] = pv[r][2];
-    up0[q] = pv[r][3];
-    up1[q] = pv[r][4];
-    up2[q] = pv[r][5];
-    wp[q] = pv[r][6];
-    idp[q] = pid[r];
-  }
-  __syncthreads();
+  for (int r = 0; r < R; r++)
+    pos[r] = key[r] >= 0 ? s_l[lev[r]] + (int)__popcll(s_m[lev[r]] & ((1ull << key[r]) - 1ull)) : -1;
+  __syncthreads();  // the tables are read before the LDS is reused
 }
 
 // FIXED: the LDS strides are the 12-node rows and 144-node planes that 4x4xN
@@ -1248,7 +1195,8 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
   gfloat* __restrict__ up0 = (gfloat*)S.u[set][0];
   gfloat* __restrict__ up1 = (gfloat*)S.u[set][1];
   gfloat* __restrict__ up2 = (gfloat*)S.u[set][2];
-  const gfloat* __restrict__ wp = (const gfloat*)S.w[set];
+  gfloat* __restrict__ wp = (gfloat*)S.w[set];
+  gint* __restrict__ idp = (gint*)S.id[set];
 
   int tc[3];
   pic_tile_coords(g, it.tile, tc);
@@ -1277,12 +1225,13 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
   acc_t* sJ = (acc_t*)smem;    // phase B: [3][jpl]
 
   // this thread's particles: requested before the fields are staged
-  int pc[R];
+  int pc[R], pid[R];
   float pe[R][3], pu[R][3], pw[R];
 #pragma unroll
   for (int r = 0; r < R; r++) {
     const int p = it.begin + tid + r * nthr;
     pc[r] = -1;
+    pid[r] = 0;
     pe[r][0] = pe[r][1] = pe[r][2] = 0.0f;
     pu[r][0] = pu[r][1] = pu[r][2] = 0.0f;
     pw[r] = 0.0f;
@@ -1295,6 +1244,7 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
       pu[r][1] = up1[p];
       pu[r][2] = up2[p];
       pw[r] = wp[p];
+      pid[r] = idp[p];
     }
   }
 
@@ -1340,17 +1290,21 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
   bool strayed = false, bad = false;
   float bmax = 0.0f;
   // kept for the deposit: old and new offsets, the move, the weight and the
-  // old cell in current-region coordinates (-1: no particle)
-  float se0[R][3], sen[R][3], swq[R];
-  int smv[R], sjc[R];
+  // old cell in current-region coordinates (-1: nothing to deposit); kept
+  // for the interleaved store: the new cell, its class (-1: no particle) and
+  // the new momentum
+  float se0[R][3], sen[R][3], swq[R], snu[R][3];
+  int smv[R], sjc[R], sncell[R], skey[R];
 #pragma unroll
   for (int r = 0; r < R; r++) {
     const int p = it.begin + tid + r * nthr;
     smv[r] = 0;
     sjc[r] = -1;
+    skey[r] = -1;
+    sncell[r] = 0;
     swq[r] = 0.0f;
 #pragma unroll
-    for (int d = 0; d < 3; d++) se0[r][d] = sen[r][d] = 0.0f;
+    for (int d = 0; d < 3; d++) se0[r][d] = sen[r][d] = snu[r][d] = 0.0f;
     int dd[3] = {0, 0, 0};
     bool live = p < it.end;
     if (live) {
@@ -1451,8 +1405,8 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
         en[d] = rr;
         mv[d] = c;
       }
-      // ---- store the new state
-      int nc[3];
+      // ---- the new state (stored after the item's interleaved slots are known)
+      int nc[3], lk[3];
 #pragma unroll
       for (int d = 0; d < 3; d++) {
         nc[d] = cc[d] + mv[d];
@@ -1461,22 +1415,20 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
         const int ln = pic_local(nc[d], org[d], ext[d], g.nx[d]);
         strayed = strayed || ln < -g.flag_slack || ln >= ext[d] + g.flag_slack;
         dd[d] = ln < 0 ? -1 : (ln >= ext[d] ? 1 : 0);
+        // cell class: a particle strays at most a tile extent outside its tile
+        lk[d] = ln < 0 ? ln + ext[d] : (ln >= ext[d] ? ln - ext[d] : ln);
+        sen[r][d] = en[d];
       }
-      cellp[p] = pic_pack(g, nc[0], nc[1], nc[2]);
-      ep0[p] = en[0];
-      ep1[p] = en[1];
-      ep2[p] = en[2];
-      up0[p] = ux;
-      up1[p] = uy;
-      up2[p] = uz;
+      sncell[r] = pic_pack(g, nc[0], nc[1], nc[2]);
+      skey[r] = (lk[0] + ext[0] * (lk[1] + ext[1] * lk[2])) & 63;
+      snu[r][0] = ux;
+      snu[r][1] = uy;
+      snu[r][2] = uz;
       // ---- what the deposit needs
       const bool moved = mv[0] != 0 || mv[1] != 0 || mv[2] != 0 || en[0] != e[0] || en[1] != e[1] || en[2] != e[2];
       if (moved) {
 #pragma unroll
-        for (int d = 0; d < 3; d++) {
-          se0[r][d] = e[d];
-          sen[r][d] = en[d];
-        }
+        for (int d = 0; d < 3; d++) se0[r][d] = e[d];
         smv[r] = (mv[0] + 1) | ((mv[1] + 1) << 2) | ((mv[2] + 1) << 4);
         sjc[r] = (jlo[2] + l[2]) * js01 + (jlo[1] + l[1]) * js0 + jlo[0] + l[0];
         swq[r] = pw[r];
@@ -1510,7 +1462,26 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
   const int e_item = __builtin_amdgcn_readfirstlane(g.acc_mode == 2 ? eg - 1 : item_exponent(btop));
   const float Q = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(ldexpf(1.0f, e_item))));
 
-  // 3. clear the current tile (over the staged fields)
+  // 3. store the new state at the item's interleaved slots (the LDS of the
+  // staged fields is free), then clear the current tile over it
+  {
+    int pos[R];
+    interleave_slots(skey, pos, smem);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      if (pos[r] < 0) continue;
+      const int q = it.begin + pos[r];
+      cellp[q] = sncell[r];
+      ep0[q] = sen[r][0];
+      ep1[q] = sen[r][1];
+      ep2[q] = sen[r][2];
+      up0[q] = snu[r][0];
+      up1[q] = snu[r][1];
+      up2[q] = snu[r][2];
+      wp[q] = pw[r];
+      idp[q] = pid[r];
+    }
+  }
   for (int idx = tid; idx < 3 * jpl; idx += nthr) sJ[idx] = 0ull;
   if (tid == 0) {
     if (any_strayed) S.ctl->flag = 1;
@@ -1593,7 +1564,6 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
     }
   }
   __syncthreads();
-  reinterleave_item(S, set, it, smem);
 }
 
 template <int DIM, int ORDER, int MODE>
