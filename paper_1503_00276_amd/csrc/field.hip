@@ -300,6 +300,201 @@ __global__ void __launch_bounds__(kBlock) yee_step(const InstDesc* __restrict__ 
   }
 }
 
+// The periodic 3D field step marching along z.  A workgroup owns a 32x8
+// column of cells in x-y and a run of kMarchZ planes, and keeps a rolling
+// window of planes in LDS: E at z+1 and z+2, Bh at z and z+1, E' at z and
+// z+1.  Each plane of E, B and J is read once per column (plus the x-y halo
+// and two planes at the start of a run), instead of once per 16x4x4 tile
+// with a halo on every face.  The arithmetic is that of yee_step, term by
+// term, so the two agree bitwise:
+//   Bh(z+1) = B(z+1) - (dt/2) curl+ E        (E at z+1, and z+2 for d/dz)
+//   E'(z+1) = E(z+1) + dt (curl- Bh - J)      (Bh at z+1, and z for d/dz)
+//   B'(z)   = Bh(z) - (dt/2) curl+ E'         (E' at z, and z+1 for d/dz)
+// x-y indices are region-relative with the origin one node below the column
+// (E region 35x11, B region 34x10); E' is formed on nodes 1..e+1, B' on the
+// column's own nodes 1..e.
+struct MarchTile { static constexpr int X = 32, Y = 8; };
+constexpr int kMarchZ = 32;
+constexpr int kMarchE = (MarchTile::X + 3) * (MarchTile::Y + 3);
+constexpr int kMarchB = (MarchTile::X + 2) * (MarchTile::Y + 2);
+
+__global__ void __launch_bounds__(kBlock) yee_march3(const InstDesc* __restrict__ inst, int par) {
+  __shared__ float sE[2][3][kMarchE];
+  __shared__ float sBh[2][3][kMarchB];
+  __shared__ float sEp[2][3][kMarchE];
+  const InstDesc& I = inst[blockIdx.y];
+  const GridDesc& g = I.g;
+  if (g.cyl || g.window) return;  // launched for periodic Cartesian groups only
+  const int n0 = g.nx[0], n1 = g.nx[1], n2 = g.nx[2];
+  const int ntx = (n0 + MarchTile::X - 1) / MarchTile::X;
+  const int nty = (n1 + MarchTile::Y - 1) / MarchTile::Y;
+  const int ntz = (n2 + kMarchZ - 1) / kMarchZ;
+  const int tile = blockIdx.x;
+  if (tile >= ntx * nty * ntz) return;
+  const int tid = threadIdx.x;
+  const int o0 = (tile % ntx) * MarchTile::X;
+  const int o1 = ((tile / ntx) % nty) * MarchTile::Y;
+  const int z0 = (tile / (ntx * nty)) * kMarchZ;
+  const int z1 = min(z0 + kMarchZ, n2);
+  const int e0 = min(MarchTile::X, n0 - o0), e1 = min(MarchTile::Y, n1 - o1);
+  const int EX = e0 + 3, EY = e1 + 3, BX = e0 + 2, BY = e1 + 2;
+  const int EN = EX * EY, BN = BX * BY, PX = e0 + 1, PN = PX * (e1 + 1);
+  const size_t nc = (size_t)g.ncell;
+  const size_t pl = (size_t)n0 * n1;
+  const float h = 0.5f * g.dt, dt = g.dt;
+  const float r0 = g.rdx[0], r1 = g.rdx[1], r2 = g.rdx[2];
+  const gfloat* F = (const gfloat*)I.F[par];
+  gfloat* Fw = (gfloat*)I.F[1 - par];
+  const int jp = par, jn = 1 - par;
+  const double jinv = (double)g.jinv;
+  auto col = [&](int x, int y) {  // x-y offset of region node (x, y)
+    return (size_t)wrap1(o0 - 1 + x, n0) + (size_t)n0 * wrap1(o1 - 1 + y, n1);
+  };
+  auto zoff = [&](int z) { return (size_t)wrap1(z, n2) * pl; };
+  // E of plane z on the E region into buffer b
+  auto load_e = [&](int z, int b) {
+    const size_t zo = zoff(z);
+    for (int q = tid; q < EN; q += kBlock) {
+      const size_t gi = zo + col(q % EX, q / EX);
+      sE[b][0][q] = F[gi];
+      sE[b][1][q] = F[nc + gi];
+      sE[b][2][q] = F[2 * nc + gi];
+    }
+  };
+  // Bh of plane z on the B region into buffer z & 1: E of z in buffer a, of z+1 in c
+  auto make_bh = [&](int z, int a, int c) {
+    const size_t zo = zoff(z);
+    const int hb = z & 1;
+    for (int q = tid; q < BN; q += kBlock) {
+      const int x = q % BX, y = q / BX;
+      const int ce = x + EX * y;
+      const size_t gi = zo + col(x, y);
+      const float d2E3 = (sE[a][2][ce + EX] - sE[a][2][ce]) * r1;
+      const float d1E3 = (sE[a][2][ce + 1] - sE[a][2][ce]) * r0;
+      const float d1E2 = (sE[a][1][ce + 1] - sE[a][1][ce]) * r0;
+      const float d2E1 = (sE[a][0][ce + EX] - sE[a][0][ce]) * r1;
+      const float d3E2 = (sE[c][1][ce] - sE[a][1][ce]) * r2;
+      const float d3E1 = (sE[c][0][ce] - sE[a][0][ce]) * r2;
+      float b1 = F[3 * nc + gi], b2 = F[4 * nc + gi], b3 = F[5 * nc + gi];
+      b1 -= h * (d2E3 - d3E2);
+      b2 -= h * (d3E1 - d1E3);
+      b3 -= h * (d1E2 - d2E1);
+      sBh[hb][0][q] = b1;
+      sBh[hb][1][q] = b2;
+      sBh[hb][2][q] = b3;
+    }
+  };
+  // E' of plane z on nodes 1..e+1 into buffer z & 1 (E of z in buffer a);
+  // on the column's own cells of a plane of this run, Jout and the clear
+  auto make_ep = [&](int z, int a) {
+    const size_t zo = zoff(z);
+    const int hb = z & 1, hm = (z - 1) & 1, eb = z & 1;
+    const bool own = z >= z0 && z < z1;
+    for (int q = tid; q < PN; q += kBlock) {
+      const int x = 1 + q % PX, y = 1 + q / PX;
+      const int ce = x + EX * y, cb = x + BX * y;
+      const size_t gi = zo + col(x, y);
+      float J1, J2, J3;
+      if (I.sm_npass > 0) {
+        const gfloat* Js = (const gfloat*)I.Jsm[(I.sm_npass - 1) & 1];
+        J1 = Js[gi];
+        J2 = Js[nc + gi];
+        J3 = Js[2 * nc + gi];
+      } else if (g.acc_mode == 2) {
+        J1 = (float)((double)(long long)I.J64[jp][gi] * jinv);
+        J2 = (float)((double)(long long)I.J64[jp][nc + gi] * jinv);
+        J3 = (float)((double)(long long)I.J64[jp][2 * nc + gi] * jinv);
+      } else {
+        const gfloat* Ja = (const gfloat*)I.Jacc[jp];
+        J1 = Ja[gi];
+        J2 = Ja[nc + gi];
+        J3 = Ja[2 * nc + gi];
+      }
+      const float d2B3 = (sBh[hb][2][cb] - sBh[hb][2][cb - BX]) * r1;
+      const float d1B3 = (sBh[hb][2][cb] - sBh[hb][2][cb - 1]) * r0;
+      const float d1B2 = (sBh[hb][1][cb] - sBh[hb][1][cb - 1]) * r0;
+      const float d2B1 = (sBh[hb][0][cb] - sBh[hb][0][cb - BX]) * r1;
+      const float d3B2 = (sBh[hb][1][cb] - sBh[hm][1][cb]) * r2;
+      const float d3B1 = (sBh[hb][0][cb] - sBh[hm][0][cb]) * r2;
+      float v1 = sE[a][0][ce], v2 = sE[a][1][ce], v3 = sE[a][2][ce];
+      v1 += dt * ((d2B3 - d3B2) - J1);
+      v2 += dt * ((d3B1 - d1B3) - J2);
+      v3 += dt * ((d1B2 - d2B1) - J3);
+      sEp[eb][0][ce] = v1;
+      sEp[eb][1][ce] = v2;
+      sEp[eb][2][ce] = v3;
+      if (own && x <= e0 && y <= e1) {
+        gfloat* Jo = (gfloat*)I.Jout;
+        Jo[gi] = J1;
+        Jo[nc + gi] = J2;
+        Jo[2 * nc + gi] = J3;
+        if (g.acc_mode == 2) {
+          I.J64[jn][gi] = 0ull;
+          I.J64[jn][nc + gi] = 0ull;
+          I.J64[jn][2 * nc + gi] = 0ull;
+        } else {
+          gfloat* Jz = (gfloat*)I.Jacc[jn];
+          Jz[gi] = 0.0f;
+          Jz[nc + gi] = 0.0f;
+          Jz[2 * nc + gi] = 0.0f;
+        }
+      }
+    }
+  };
+
+  // prologue: Bh(z0-1), Bh(z0), E'(z0)
+  load_e(z0 - 1, (z0 - 1) & 1);
+  load_e(z0, z0 & 1);
+  __syncthreads();
+  make_bh(z0 - 1, (z0 - 1) & 1, z0 & 1);
+  __syncthreads();
+  load_e(z0 + 1, (z0 + 1) & 1);  // over E(z0-1)
+  __syncthreads();
+  make_bh(z0, z0 & 1, (z0 + 1) & 1);
+  __syncthreads();
+  make_ep(z0, z0 & 1);
+  __syncthreads();
+  float em = 0.0f;
+  const int tx = tid % MarchTile::X, ty = tid / MarchTile::X;
+  for (int z = z0; z < z1; z++) {
+    // E(z+2) over E(z), which E'(z) no longer needs
+    load_e(z + 2, z & 1);
+    __syncthreads();
+    make_bh(z + 1, (z + 1) & 1, z & 1);
+    __syncthreads();
+    make_ep(z + 1, (z + 1) & 1);
+    __syncthreads();
+    // B'(z) on the column's cells, and E'(z), B'(z) written out
+    if (tx < e0 && ty < e1) {
+      const int x = 1 + tx, y = 1 + ty;
+      const int c = x + EX * y, cb = x + BX * y;
+      const int a = z & 1, b = (z + 1) & 1;
+      const float d2E3 = (sEp[a][2][c + EX] - sEp[a][2][c]) * r1;
+      const float d1E3 = (sEp[a][2][c + 1] - sEp[a][2][c]) * r0;
+      const float d1E2 = (sEp[a][1][c + 1] - sEp[a][1][c]) * r0;
+      const float d2E1 = (sEp[a][0][c + EX] - sEp[a][0][c]) * r1;
+      const float d3E2 = (sEp[b][1][c] - sEp[a][1][c]) * r2;
+      const float d3E1 = (sEp[b][0][c] - sEp[a][0][c]) * r2;
+      const size_t gi = zoff(z) + col(x, y);
+      Fw[3 * nc + gi] = sBh[a][0][cb] - h * (d2E3 - d3E2);
+      Fw[4 * nc + gi] = sBh[a][1][cb] - h * (d3E1 - d1E3);
+      Fw[5 * nc + gi] = sBh[a][2][cb] - h * (d1E2 - d2E1);
+      Fw[gi] = sEp[a][0][c];
+      Fw[nc + gi] = sEp[a][1][c];
+      Fw[2 * nc + gi] = sEp[a][2][c];
+      em = fmaxf(em, fmaxf(fabsf(sEp[a][0][c]), fmaxf(fabsf(sEp[a][1][c]), fabsf(sEp[a][2][c]))));
+    }
+  }
+  // the largest |E'_c| written raises the instance's running field bound
+  const float emax0 = *(const gfloat*)I.emax;
+  if (__ballot(em > emax0)) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) em = fmaxf(em, __shfl_xor(em, off));
+    if ((tid & 63) == 0)
+      __hip_atomic_fetch_max((guint*)I.emax, __float_as_uint(em), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 // The r-z field step (Sec. 3.3, Eqs. 2d-field-solve-cyl and
 // 2d-field-solve-cyl-b1-axis) on the 2D tiles, in the three parts of
 // yee_step.  E_z, E_theta, B_r (components 0, 2, 4) sit on whole rows at
@@ -643,8 +838,12 @@ hipError_t pic_launch_smooth_pass(const InstDesc* d_inst, int ninst, int max_nce
 int pic_yee_tiles(int dim, const int nx[3]) {
   if (dim == 2)
     return ((nx[0] + YeeTile<2>::X - 1) / YeeTile<2>::X) * ((nx[1] + YeeTile<2>::Y - 1) / YeeTile<2>::Y);
-  return ((nx[0] + YeeTile<3>::X - 1) / YeeTile<3>::X) * ((nx[1] + YeeTile<3>::Y - 1) / YeeTile<3>::Y) *
-         ((nx[2] + YeeTile<3>::Z - 1) / YeeTile<3>::Z);
+  // the larger of the tile counts of yee_step (moving windows) and yee_march3
+  const int t = ((nx[0] + YeeTile<3>::X - 1) / YeeTile<3>::X) * ((nx[1] + YeeTile<3>::Y - 1) / YeeTile<3>::Y) *
+                ((nx[2] + YeeTile<3>::Z - 1) / YeeTile<3>::Z);
+  const int m = ((nx[0] + MarchTile::X - 1) / MarchTile::X) * ((nx[1] + MarchTile::Y - 1) / MarchTile::Y) *
+                ((nx[2] + kMarchZ - 1) / kMarchZ);
+  return t > m ? t : m;
 }
 
 hipError_t pic_launch_current_units(StoreDesc* d_stores, int nstores, hipStream_t st) {
@@ -662,7 +861,7 @@ hipError_t pic_launch_yee_step(const InstDesc* d_inst, int ninst, int max_tiles,
   } else if (window) {
     hipLaunchKernelGGL((yee_step<3, true>), grid, dim3(kBlock), 0, st, d_inst, parity);
   } else {
-    hipLaunchKernelGGL((yee_step<3, false>), grid, dim3(kBlock), 0, st, d_inst, parity);
+    hipLaunchKernelGGL(yee_march3, grid, dim3(kBlock), 0, st, d_inst, parity);
   }
   return hipGetLastError();
 }
