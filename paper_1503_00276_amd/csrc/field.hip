@@ -351,31 +351,91 @@ __global__ void __launch_bounds__(kBlock) yee_march3(const InstDesc* __restrict_
     return (size_t)wrap1(o0 - 1 + x, n0) + (size_t)n0 * wrap1(o1 - 1 + y, n1);
   };
   auto zoff = [&](int z) { return (size_t)wrap1(z, n2) * pl; };
-  // E of plane z on the E region into buffer b
-  auto load_e = [&](int z, int b) {
+  // A plane's global reads are issued together into registers (each thread
+  // holds at most two nodes of each region), so a plane waits for one memory
+  // latency rather than one per sub-update.
+  // E of plane z on the E region
+  auto get_e = [&](int z, float (&v)[2][3]) {
     const size_t zo = zoff(z);
-    for (int q = tid; q < EN; q += kBlock) {
-      const size_t gi = zo + col(q % EX, q / EX);
-      sE[b][0][q] = F[gi];
-      sE[b][1][q] = F[nc + gi];
-      sE[b][2][q] = F[2 * nc + gi];
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+      const int q = tid + k * kBlock;
+      if (q < EN) {
+        const size_t gi = zo + col(q % EX, q / EX);
+        v[k][0] = F[gi];
+        v[k][1] = F[nc + gi];
+        v[k][2] = F[2 * nc + gi];
+      }
     }
   };
-  // Bh of plane z on the B region into buffer z & 1: E of z in buffer a, of z+1 in c
-  auto make_bh = [&](int z, int a, int c) {
+  auto put_e = [&](int b, const float (&v)[2][3]) {
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+      const int q = tid + k * kBlock;
+      if (q < EN) {
+        sE[b][0][q] = v[k][0];
+        sE[b][1][q] = v[k][1];
+        sE[b][2][q] = v[k][2];
+      }
+    }
+  };
+  // B of plane z on the B region
+  auto get_b = [&](int z, float (&v)[2][3]) {
     const size_t zo = zoff(z);
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+      const int q = tid + k * kBlock;
+      if (q < BN) {
+        const size_t gi = zo + col(q % BX, q / BX);
+        v[k][0] = F[3 * nc + gi];
+        v[k][1] = F[4 * nc + gi];
+        v[k][2] = F[5 * nc + gi];
+      }
+    }
+  };
+  // J of plane z on the E' nodes 1..e+1
+  auto get_j = [&](int z, float (&v)[2][3]) {
+    const size_t zo = zoff(z);
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+      const int q = tid + k * kBlock;
+      if (q < PN) {
+        const size_t gi = zo + col(1 + q % PX, 1 + q / PX);
+        if (I.sm_npass > 0) {
+          const gfloat* Js = (const gfloat*)I.Jsm[(I.sm_npass - 1) & 1];
+          v[k][0] = Js[gi];
+          v[k][1] = Js[nc + gi];
+          v[k][2] = Js[2 * nc + gi];
+        } else if (g.acc_mode == 2) {
+          v[k][0] = (float)((double)(long long)I.J64[jp][gi] * jinv);
+          v[k][1] = (float)((double)(long long)I.J64[jp][nc + gi] * jinv);
+          v[k][2] = (float)((double)(long long)I.J64[jp][2 * nc + gi] * jinv);
+        } else {
+          const gfloat* Ja = (const gfloat*)I.Jacc[jp];
+          v[k][0] = Ja[gi];
+          v[k][1] = Ja[nc + gi];
+          v[k][2] = Ja[2 * nc + gi];
+        }
+      }
+    }
+  };
+  // Bh of plane z on the B region into buffer z & 1: E of z in buffer a, of
+  // z+1 in c, B of z in v
+  auto make_bh = [&](int z, int a, int c, const float (&v)[2][3]) {
     const int hb = z & 1;
-    for (int q = tid; q < BN; q += kBlock) {
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+      const int q = tid + k * kBlock;
+      if (q >= BN) continue;
       const int x = q % BX, y = q / BX;
       const int ce = x + EX * y;
-      const size_t gi = zo + col(x, y);
       const float d2E3 = (sE[a][2][ce + EX] - sE[a][2][ce]) * r1;
       const float d1E3 = (sE[a][2][ce + 1] - sE[a][2][ce]) * r0;
       const float d1E2 = (sE[a][1][ce + 1] - sE[a][1][ce]) * r0;
       const float d2E1 = (sE[a][0][ce + EX] - sE[a][0][ce]) * r1;
       const float d3E2 = (sE[c][1][ce] - sE[a][1][ce]) * r2;
       const float d3E1 = (sE[c][0][ce] - sE[a][0][ce]) * r2;
-      float b1 = F[3 * nc + gi], b2 = F[4 * nc + gi], b3 = F[5 * nc + gi];
+      float b1 = v[k][0], b2 = v[k][1], b3 = v[k][2];
       b1 -= h * (d2E3 - d3E2);
       b2 -= h * (d3E1 - d1E3);
       b3 -= h * (d1E2 - d2E1);
@@ -384,32 +444,20 @@ __global__ void __launch_bounds__(kBlock) yee_march3(const InstDesc* __restrict_
       sBh[hb][2][q] = b3;
     }
   };
-  // E' of plane z on nodes 1..e+1 into buffer z & 1 (E of z in buffer a);
-  // on the column's own cells of a plane of this run, Jout and the clear
-  auto make_ep = [&](int z, int a) {
+  // E' of plane z on nodes 1..e+1 into buffer z & 1 (E of z in buffer a, J
+  // of z in v); on the column's own cells of a plane of this run, Jout and
+  // the clear of the other accumulator
+  auto make_ep = [&](int z, int a, const float (&v)[2][3]) {
     const size_t zo = zoff(z);
     const int hb = z & 1, hm = (z - 1) & 1, eb = z & 1;
     const bool own = z >= z0 && z < z1;
-    for (int q = tid; q < PN; q += kBlock) {
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+      const int q = tid + k * kBlock;
+      if (q >= PN) continue;
       const int x = 1 + q % PX, y = 1 + q / PX;
       const int ce = x + EX * y, cb = x + BX * y;
-      const size_t gi = zo + col(x, y);
-      float J1, J2, J3;
-      if (I.sm_npass > 0) {
-        const gfloat* Js = (const gfloat*)I.Jsm[(I.sm_npass - 1) & 1];
-        J1 = Js[gi];
-        J2 = Js[nc + gi];
-        J3 = Js[2 * nc + gi];
-      } else if (g.acc_mode == 2) {
-        J1 = (float)((double)(long long)I.J64[jp][gi] * jinv);
-        J2 = (float)((double)(long long)I.J64[jp][nc + gi] * jinv);
-        J3 = (float)((double)(long long)I.J64[jp][2 * nc + gi] * jinv);
-      } else {
-        const gfloat* Ja = (const gfloat*)I.Jacc[jp];
-        J1 = Ja[gi];
-        J2 = Ja[nc + gi];
-        J3 = Ja[2 * nc + gi];
-      }
+      const float J1 = v[k][0], J2 = v[k][1], J3 = v[k][2];
       const float d2B3 = (sBh[hb][2][cb] - sBh[hb][2][cb - BX]) * r1;
       const float d1B3 = (sBh[hb][2][cb] - sBh[hb][2][cb - 1]) * r0;
       const float d1B2 = (sBh[hb][1][cb] - sBh[hb][1][cb - 1]) * r0;
@@ -424,6 +472,7 @@ __global__ void __launch_bounds__(kBlock) yee_march3(const InstDesc* __restrict_
       sEp[eb][1][ce] = v2;
       sEp[eb][2][ce] = v3;
       if (own && x <= e0 && y <= e1) {
+        const size_t gi = zo + col(x, y);
         gfloat* Jo = (gfloat*)I.Jout;
         Jo[gi] = J1;
         Jo[nc + gi] = J2;
@@ -443,26 +492,39 @@ __global__ void __launch_bounds__(kBlock) yee_march3(const InstDesc* __restrict_
   };
 
   // prologue: Bh(z0-1), Bh(z0), E'(z0)
-  load_e(z0 - 1, (z0 - 1) & 1);
-  load_e(z0, z0 & 1);
-  __syncthreads();
-  make_bh(z0 - 1, (z0 - 1) & 1, z0 & 1);
-  __syncthreads();
-  load_e(z0 + 1, (z0 + 1) & 1);  // over E(z0-1)
-  __syncthreads();
-  make_bh(z0, z0 & 1, (z0 + 1) & 1);
-  __syncthreads();
-  make_ep(z0, z0 & 1);
-  __syncthreads();
+  float ev[2][3], bv[2][3], jv[2][3];
+  {
+    float ew[2][3], bw[2][3];
+    get_e(z0 - 1, ev);
+    get_e(z0, ew);
+    get_b(z0 - 1, bv);
+    get_b(z0, bw);
+    get_j(z0, jv);
+    put_e((z0 - 1) & 1, ev);
+    put_e(z0 & 1, ew);
+    get_e(z0 + 1, ev);
+    __syncthreads();
+    make_bh(z0 - 1, (z0 - 1) & 1, z0 & 1, bv);
+    __syncthreads();
+    put_e((z0 + 1) & 1, ev);  // over E(z0-1)
+    __syncthreads();
+    make_bh(z0, z0 & 1, (z0 + 1) & 1, bw);
+    __syncthreads();
+    make_ep(z0, z0 & 1, jv);
+    __syncthreads();
+  }
   float em = 0.0f;
   const int tx = tid % MarchTile::X, ty = tid / MarchTile::X;
   for (int z = z0; z < z1; z++) {
+    get_e(z + 2, ev);
+    get_b(z + 1, bv);
+    get_j(z + 1, jv);
     // E(z+2) over E(z), which E'(z) no longer needs
-    load_e(z + 2, z & 1);
+    put_e(z & 1, ev);
     __syncthreads();
-    make_bh(z + 1, (z + 1) & 1, z & 1);
+    make_bh(z + 1, (z + 1) & 1, z & 1, bv);
     __syncthreads();
-    make_ep(z + 1, (z + 1) & 1);
+    make_ep(z + 1, (z + 1) & 1, jv);
     __syncthreads();
     // B'(z) on the column's cells, and E'(z), B'(z) written out
     if (tx < e0 && ty < e1) {
