@@ -515,16 +515,31 @@ __global__ void __launch_bounds__(kBlock) yee_march3(const InstDesc* __restrict_
   }
   float em = 0.0f;
   const int tx = tid % MarchTile::X, ty = tid / MarchTile::X;
+  // the reads of a plane are issued one plane ahead, so they are in flight
+  // while the previous plane is computed
+  get_e(z0 + 2, ev);
+  get_b(z0 + 1, bv);
+  get_j(z0 + 1, jv);
   for (int z = z0; z < z1; z++) {
-    get_e(z + 2, ev);
-    get_b(z + 1, bv);
-    get_j(z + 1, jv);
     // E(z+2) over E(z), which E'(z) no longer needs
     put_e(z & 1, ev);
+    float bc[2][3], jc[2][3];
+#pragma unroll
+    for (int k = 0; k < 2; k++)
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        bc[k][c] = bv[k][c];
+        jc[k][c] = jv[k][c];
+      }
+    if (z + 1 < z1) {
+      get_e(z + 3, ev);
+      get_b(z + 2, bv);
+      get_j(z + 2, jv);
+    }
     __syncthreads();
-    make_bh(z + 1, (z + 1) & 1, z & 1, bv);
+    make_bh(z + 1, (z + 1) & 1, z & 1, bc);
     __syncthreads();
-    make_ep(z + 1, (z + 1) & 1, jv);
+    make_ep(z + 1, (z + 1) & 1, jc);
     __syncthreads();
     // B'(z) on the column's cells, and E'(z), B'(z) written out
     if (tx < e0 && ty < e1) {
