@@ -17,6 +17,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "pic_dev.h"
 #include "pic_kernels.h"
@@ -248,6 +249,11 @@ __device__ __forceinline__ void lds_add_any(acc_t* p, float v) {
   __hip_atomic_fetch_add(p, (acc_t)(long long)cvt_rpi(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// The same on a 32-bit tile (two's complement sums in an unsigned word).
+__device__ __forceinline__ void lds_add_any(unsigned* p, float v) {
+  __hip_atomic_fetch_add(p, (unsigned)cvt_rpi(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Fixed point of one work item's int64 current tile: Q = 2^e with Q b < 2^29
 // for a bound b on any single contribution (a factor 2 to spare for the FP32
 // rounding of the shape differences), so that every contribution converts
@@ -256,6 +262,17 @@ __device__ __forceinline__ int item_exponent(float b) {
   int ex = 0;
   (void)frexpf(b, &ex);
   return b > 0.0f ? min(100, max(-100, 29 - ex)) : 0;
+}
+
+// The same for a 32-bit tile summing at most n contributions per node:
+// Q = 2^e with Q n b (1 + 2^-16) < 2^31.  FP32 rounding lets a contribution
+// exceed its bound b by a few tens of ulps (under 2^-19 relative), and the
+// rounding to the unit adds at most 1/2, so a node's sum of n of them stays
+// below 2^31 - 2^14 in magnitude.
+__device__ __forceinline__ int item_exponent32(float b, int n) {
+  int ex = 0;
+  (void)frexpf((float)n * b * 1.0000153f, &ex);  // n b (1 + 2^-16) < 2^ex
+  return b > 0.0f ? min(100, max(-100, 31 - ex)) : 0;
 }
 
 // An int64 node sum times its unit, as FP32.  The low word is taken signed
@@ -468,7 +485,10 @@ __device__ __forceinline__ void dep3_comp(Acc* J, int cb, const int st[3], const
 // MODE selects the boundary logic compiled into the kernel: 0 periodic,
 // 1 moving window along x1 (a launch whose stores include a moving window),
 // 2 the 2D r-z geometry (x1 = z, x2 = r), 3 both.  Without it the code is
-// absent.
+// absent.  Modes 4-6 are the two-phase periodic 3D kernel (process_item3):
+// 4 with an int64 current tile (the deterministic int64 accumulation), 5 and
+// 6 with a 32-bit tile, 5 for the LDS strides of 4x4xN tiles as constants,
+// 6 for strides read at run time.
 // kstep: steps done since the last rebin check (0 for the first step of a
 // sort cycle).
 template <int DIM, int ORDER, int MODE>
@@ -1098,7 +1118,7 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
 //
 // Phase A stages E and B of the tile and pushes every particle of the item
 // (up to kSplitR per thread), keeping what the deposit needs in registers.
-// Phase B clears the int64 current tile in the same LDS and deposits into it.
+// Phase B clears the integer current tile in the same LDS and deposits into it.
 // Field tile and current tile never coexist, so a workgroup needs the larger
 // of the two instead of their sum, and more workgroups share a CU.  The
 // regions carry only the guards the shapes reach (see the host's region
@@ -1114,6 +1134,15 @@ __device__ void process_item(const StoreDesc& S, int cur, const Item it, int ii,
 // FP32 rounding of the shape differences) and the int64 sums are exact; the
 // rounding unit follows the item's fastest particle instead of the speed of
 // light, so a slow or cold plasma keeps its relative precision.
+//
+// The tile is 32-bit (Acc = unsigned) unless the instance sums its current
+// deterministically in int64.  A node gets at most one contribution per
+// particle of the item, so Q max_p |w_p| |v_p| n < 2^31 (with a small margin
+// for rounding) for an item of n particles keeps the int32 sums exact
+// (item_exponent32): the unit is about 2^-31 n of the largest contribution,
+// 2^-23 for the 256 particles of a 4x4x4 tile at four per cell, the FP32
+// rounding of one such contribution.  A 32-bit tile halves the LDS lane
+// traffic of the adds and drops the sign extension of each one.
 
 constexpr int kSplitR = 3;  // particles per thread per work item
 
@@ -1176,9 +1205,10 @@ __device__ __forceinline__ void interleave_slots(const int (&key)[kSplitR], int 
 // FIXED: the LDS strides are the 12-node rows and 144-node planes that 4x4xN
 // tiles take (every shape order, stray bound 1), as compile-time constants,
 // so that the taps and adds address LDS through instruction offsets.
-template <int ORDER, bool FIXED>
+template <int ORDER, bool FIXED, typename Acc>
 __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii, int jp, int kstep, float* smem,
                               int* scnt, float* sred) {
+  constexpr bool kWide = sizeof(Acc) == 8;
   constexpr int NG = ORDER + 1;  // gather taps per axis
   constexpr int K = ORDER + 1;   // deposit core per axis
   constexpr int W = ORDER + 2;   // deposit window per axis
@@ -1222,7 +1252,7 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
   const int fpl = fs01 * FR[2];  // one field component
   const int jpl = js01 * JR[2];  // one current component
   float* sF = smem;            // phase A: [6][fpl]
-  acc_t* sJ = (acc_t*)smem;    // phase B: [3][jpl]
+  Acc* sJ = (Acc*)smem;        // phase B: [3][jpl]
 
   // this thread's particles: requested before the fields are staged
   int pc[R], pid[R];
@@ -1459,7 +1489,8 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
   // (the int64 mode: the instance's own fixed point, as in the one-phase kernel)
   int eg = 0;
   (void)frexpf(g.jscale, &eg);  // jscale = 2^(eg-1)
-  const int e_item = __builtin_amdgcn_readfirstlane(g.acc_mode == 2 ? eg - 1 : item_exponent(btop));
+  const int e_item = __builtin_amdgcn_readfirstlane(
+      kWide ? (g.acc_mode == 2 ? eg - 1 : item_exponent(btop)) : item_exponent32(btop, it.end - it.begin));
   const float Q = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(ldexpf(1.0f, e_item))));
 
   // 3. store the new state at the item's interleaved slots (the LDS of the
@@ -1482,7 +1513,7 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
       idp[q] = pid[r];
     }
   }
-  for (int idx = tid; idx < 3 * jpl; idx += nthr) sJ[idx] = 0ull;
+  for (int idx = tid; idx < 3 * jpl; idx += nthr) sJ[idx] = (Acc)0;
   if (tid == 0) {
     if (any_strayed) S.ctl->flag = 1;
     if (any_bad) S.ctl->bad = 1;
@@ -1540,8 +1571,7 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
   __syncthreads();
 
   // 5. fold the tile into the global current (periodic wrap); the int64 mode
-  // converts the item's units to the instance's fixed point exactly (a left
-  // shift) or rounds to it (a right shift), so its sums stay order-free
+  // sums in the instance's own fixed point, so its global sums stay order-free
   const float qinv = ldexpf(1.0f, -e_item);
   BoxWalk bj(tid, nthr, JR);
   for (int idx = tid; idx < jn; idx += nthr, bj.advance(JR)) {
@@ -1552,14 +1582,21 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
     const int lj = bj.x + bj.y * js0 + bj.z * js01;
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-      const long long q = (long long)sJ[c * jpl + lj];
-      if (q != 0) {
-        if (g.acc_mode == 2) {
-          atomicAdd(S.J64[jp] + (size_t)c * ncell + gidx, (acc_t)q);
-        } else {
-          __builtin_amdgcn_global_atomic_fadd_f32((gfloat*)S.Jacc[jp] + (size_t)c * ncell + gidx,
-                                                  item_sum_f32(q, qinv));
+      if constexpr (kWide) {
+        const long long q = (long long)sJ[c * jpl + lj];
+        if (q != 0) {
+          if (g.acc_mode == 2) {
+            atomicAdd(S.J64[jp] + (size_t)c * ncell + gidx, (acc_t)q);
+          } else {
+            __builtin_amdgcn_global_atomic_fadd_f32((gfloat*)S.Jacc[jp] + (size_t)c * ncell + gidx,
+                                                    item_sum_f32(q, qinv));
+          }
         }
+      } else {
+        // one rounding, as for the int64 sums
+        const int q = (int)sJ[c * jpl + lj];
+        if (q != 0)
+          __builtin_amdgcn_global_atomic_fadd_f32((gfloat*)S.Jacc[jp] + (size_t)c * ncell + gidx, (float)q * qinv);
       }
     }
   }
@@ -1614,7 +1651,8 @@ __device__ __forceinline__ void gpd_body(const StoreDesc* __restrict__ stores, i
     it.begin = __builtin_amdgcn_readfirstlane(it.begin);
     it.end = __builtin_amdgcn_readfirstlane(it.end);
     if constexpr (MODE >= 4)
-      process_item3<ORDER, MODE == 5>(S, cur, it, ii, jp, kstep, smem, s_cnt, s_red);
+      process_item3<ORDER, MODE == 5, typename std::conditional<MODE == 4, acc_t, unsigned>::type>(
+          S, cur, it, ii, jp, kstep, smem, s_cnt, s_red);
     else
       process_item<DIM, ORDER, MODE>(S, cur, it, ii, jp, kstep, smem, s_cnt);
   }
@@ -1666,6 +1704,7 @@ hipError_t prepare_one(int mode, size_t lds) {
   } else {
     if (mode == 4) return prepare_mode<DIM, ORDER, 4>(lds);
     if (mode == 5) return prepare_mode<DIM, ORDER, 5>(lds);
+    if (mode == 6) return prepare_mode<DIM, ORDER, 6>(lds);
   }
   if (mode == 0) return prepare_mode<DIM, ORDER, 0>(lds);
   return hipErrorInvalidValue;
@@ -1688,6 +1727,8 @@ hipError_t launch_one(int mode, const StoreDesc* stores, int nstores, int grid, 
       launch_mode<DIM, ORDER, 4>(stores, nstores, grid, lds, jp, kstep, st, ev0, ev1);
     else if (mode == 5)
       launch_mode<DIM, ORDER, 5>(stores, nstores, grid, lds, jp, kstep, st, ev0, ev1);
+    else if (mode == 6)
+      launch_mode<DIM, ORDER, 6>(stores, nstores, grid, lds, jp, kstep, st, ev0, ev1);
     else
       return hipErrorInvalidValue;
   }
@@ -1744,15 +1785,16 @@ void pic_gpd_split_strides(GridDesc& g) {
                     g.js01);
 }
 
-// LDS of the two-phase kernel: six field planes or three int64 current
-// planes over the padded strides of the largest region of a sort cycle.
+// LDS of the two-phase kernel: six field planes or three current planes
+// (int64 for the deterministic accumulation, else 32-bit) over the padded
+// strides of the largest region of a sort cycle.
 static size_t split_lds_bytes(const GridDesc& g0) {
   GridDesc g = g0;
   pic_gpd_split_strides(g);
   const size_t f2 = (size_t)(g.tile[2] + 2 * g.slk[2] + g.fa + g.fb);
   const size_t j2 = (size_t)(g.tile[2] + 2 * g.slk[2] + g.ja + g.jb);
-  return std::max(std::max(6 * (size_t)g.fs01 * f2 * sizeof(float), 3 * (size_t)g.js01 * j2 * sizeof(unsigned long long)),
-                  kInterleaveLds);
+  const size_t jw = g.acc_mode == 2 ? sizeof(unsigned long long) : sizeof(unsigned);  // 2: int64 accumulation
+  return std::max(std::max(6 * (size_t)g.fs01 * f2 * sizeof(float), 3 * (size_t)g.js01 * j2 * jw), kInterleaveLds);
 }
 
 size_t pic_gpd_lds_bytes(const GridDesc& g) {
@@ -1808,6 +1850,7 @@ int resident_one(int mode, size_t lds) {
   } else {
     if (mode == 4) f = gpd_entry<DIM, ORDER, 4>();
     if (mode == 5) f = gpd_entry<DIM, ORDER, 5>();
+    if (mode == 6) f = gpd_entry<DIM, ORDER, 6>();
   }
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kBlock, lds) != hipSuccess) return 1;
   return n < 1 ? 1 : n;

@@ -82,9 +82,13 @@ struct Group {
 
 // Boundary logic an instance's stores need in the fused particle kernel.
 int kernel_mode(const GridDesc& g) {
-  // two-phase 3D kernel: the variant with compile-time LDS strides when the
+  // two-phase 3D kernel: int64 current tile for the deterministic int64
+  // accumulation, else a 32-bit tile, with compile-time LDS strides when the
   // box's padded strides are the ones of 4x4xN tiles
-  if (pic_gpd_split(g)) return (g.fs0 == 12 && g.fs01 == 144 && g.js0 == 12 && g.js01 == 144) ? 5 : 4;
+  if (pic_gpd_split(g)) {
+    if (g.acc_mode == PIC_ACC_FIXED64) return 4;
+    return (g.fs0 == 12 && g.fs01 == 144 && g.js0 == 12 && g.js01 == 144) ? 5 : 6;
+  }
   return g.window ? (g.cyl ? 3 : 1) : (g.cyl ? 2 : 0);
 }
 
@@ -432,7 +436,7 @@ pic_status refresh_descriptors(Sim& S) {
   S.igroups.clear();
   for (int dim = 2; dim <= 3; dim++)
     for (int order = 1; order <= 3; order++)
-      for (int mode = 0; mode <= 5; mode++) {
+      for (int mode = 0; mode <= 6; mode++) {
       Group gr{dim, order, (int)stores.size(), 0, 0, 0, 0, 0, 0, false, {0, 0, 0}, 0, false};
       gr.mode = mode;
       for (size_t i = 0; i < S.inst.size(); i++) {
