@@ -6,8 +6,8 @@ charge-conserving deposit of one particle), whole step included (the Yee
 field solve and the rebin checks run inside the timed region), inputs already
 resident in HBM.  Headline workload (default): the 3D3V uniform thermal
 plasma of 512x256x256 cells, 134,217,728 electrons, cubic shape, timed after
-100 untimed steps in the layout the autotuner picked for it (4x4x4 tiles,
-sort interval 1, chunk 512).  Further legs: the 2D3V laser wakefield
+100 untimed steps in the layout a tile sweep of that developed state found
+fastest (8x4x4 tiles, sort interval 1, chunk 768).  Further legs: the 2D3V laser wakefield
 (1024x256 cells, 2,097,152 electrons, quadratic, 32x8 tiles, sort interval
 6, chunk 1024: the autotuner's usual pick, fixed so that the parity tests
 and the counter records cover exactly the timed layout; --workload lwfa2d
@@ -306,12 +306,13 @@ def run_batched(args, pic, stream):
     }
 
 
-# Layout of the headline workload when the benchmark does not tune it: the
-# one pic_autotune picked for it (profiles/ holds the search), since a search
-# over 134 M particles re-bins them on the host for every candidate and takes
-# minutes.  --tune-headline runs the search instead.
+# Layouts timed when the benchmark does not tune them.  The headline's is the
+# fastest of a tile sweep of its developed state (a search over 134 M
+# particles re-bins them on the host for every candidate and takes minutes;
+# --tune-headline runs it instead); the laser wakefield's is the autotuner's
+# usual pick.
 DEFAULT_LAYOUT = {
-    "cubic3d": {"tile": [4, 4, 4], "sort_interval": 1, "chunk": 512},
+    "cubic3d": {"tile": [8, 4, 4], "sort_interval": 1, "chunk": 768},
     "lwfa2d": {"tile": [32, 8], "sort_interval": 6, "chunk": 1024},
 }
 
@@ -437,7 +438,7 @@ def plain_leg(args, pic, stream, name, steps, layout=None, tune=True):
             "lds_bytes": int(info.lds_bytes),
             "autotune": tuned,
             "layout_from": "autotuned in this run" if tuned else (
-                "the autotuner's pick for this workload (fixed)" if layout else "library defaults"),
+                "fixed: the fastest layout of a tile sweep of the developed state" if layout else "library defaults"),
             "rebins_done": int(counts[2]),
             "rebin_checks": int(counts[3]),
         },

@@ -170,9 +170,12 @@ def _golden_energy():
     return np.array([[float(v) for v in r[1:]] for r in rows])
 
 
-def test_cubic3d_subrun_energy_history_in_bench_layout():
+@pytest.mark.parametrize("layout", [(8, 4, 4, 1, 768), (4, 4, 4, 1, 512)],
+                         ids=["bench_8x4x4_si1_chunk768", "4x4x4_si1_chunk512"])
+def test_cubic3d_subrun_energy_history_in_bench_layout(layout):
     """Workload 5's 64^3 sub-run in the benchmark's layout of the full
-    workload (4x4x4 tiles, sort interval 1, chunk 512): the field and
+    workload (8x4x4 tiles, sort interval 1, chunk 768; and 4x4x4 tiles, the
+    fixed-stride variant of the kernel): the field and
     kinetic energies of 100 FP32 steps against the FP64 oracle's history
     (tests/golden/cubic3d_64_energy.txt, written by make_cubic_sub_energy.py
     from the oracle alone).  W_E and W_B grow from the thermal noise and
@@ -184,7 +187,7 @@ def test_cubic3d_subrun_energy_history_in_bench_layout():
     ref = _golden_energy()
     assert ref.shape == (100, 3)
     wl = W.workload5_sub()
-    cfg, sim = _sim(pic, wl, tile=(4, 4, 4), sort_interval=1, chunk=512)
+    cfg, sim = _sim(pic, wl, tile=layout[:3], sort_interval=layout[3], chunk=layout[4])
     gpu = []
     for n in range(100):
         sim.step(1)
@@ -202,11 +205,13 @@ def test_cubic3d_subrun_energy_history_in_bench_layout():
     sim.close()
 
 
-@pytest.mark.parametrize("layout", [None, (4, 4, 4, 1, 512)], ids=["defaults", "bench_4x4x4_si1_chunk512"])
+@pytest.mark.parametrize("layout", [None, (8, 4, 4, 1, 768), (4, 4, 4, 1, 512)],
+                         ids=["defaults", "bench_8x4x4_si1_chunk768", "4x4x4_si1_chunk512"])
 def test_cubic3d_full_size_sampled_parity(orc, layout):
     """Workload 5 at full size (134,217,728 electrons, 512x256x256, cubic):
     with the library's defaults two steps in, and in the benchmark's layout
-    (4x4x4 tiles, sort interval 1, chunk 512) at the benchmark's state (it
+    (8x4x4 tiles, sort interval 1, chunk 768; also 4x4x4 tiles, the
+    fixed-stride variant) at the benchmark's state (it
     times from step 111 on, after the work items have been re-interleaved
     and particles have strayed from their tiles for a hundred steps)."""
     from paper_1503_00276_amd import workloads as W
