@@ -21,6 +21,7 @@ def test_particle_kernel_dynamic_lds_is_16_byte_aligned(tmp_path):
                           stderr=subprocess.DEVNULL)
     sizes = [int(v) for v in re.findall(r"amdhsa_group_segment_fixed_size (\d+)", out.read_text())]
     # 2 dims x 3 orders x (periodic, moving window) + 3 orders x (r-z, r-z with window)
-    # + 3 orders x periodic 3D in two phases (runtime and compile-time LDS strides)
-    assert len(sizes) == 24
+    # + 3 orders x periodic 3D in two phases (int64 tile; 32-bit tile with compile-time
+    # and with runtime LDS strides)
+    assert len(sizes) == 27
     assert all(v % 16 == 0 for v in sizes), sizes
