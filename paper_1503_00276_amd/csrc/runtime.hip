@@ -114,6 +114,8 @@ struct Sim {
   bool dirty = true;
   double* d_scratch = nullptr;  // reductions
   double* d_out = nullptr;      // reduction outputs
+  void* d_diag = nullptr;       // diagnostics' device buffers, kept between calls
+  size_t diag_cap = 0;          // its size in bytes
   std::string err;
   // captured graphs: one rebin cycle (sort_interval steps ending with the
   // check), one per parity of the cycle's first step
@@ -1129,6 +1131,25 @@ pic_status sim_load_fields(Sim& S, int inst, const double* e, const double* b, u
 // diagnostics
 // ---------------------------------------------------------------------------
 
+// The diagnostics' device scratch: kept between calls and reallocated only
+// when a call needs more than any call before it, so repeated diagnostics
+// do not allocate.  Every diagnostic synchronizes its stream before it
+// returns, so no earlier call still uses the buffer when it is replaced.
+pic_status diag_scratch(Sim& S, size_t bytes, char** p) {
+  if (bytes > S.diag_cap) {
+    if (S.d_diag) (void)hipFree(S.d_diag);
+    S.d_diag = nullptr;
+    S.diag_cap = 0;
+    HIPCHK(S, hipMalloc(&S.d_diag, bytes));
+    S.diag_cap = bytes;
+  }
+  *p = (char*)S.d_diag;
+  return PIC_OK;
+}
+
+// Bytes rounded up to a multiple of 256 (sub-buffers of the scratch).
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 pic_status need(Sim& S, size_t want, size_t out_bytes, size_t* written) {
   if (written) *written = want;
   if (out_bytes < want) return S.fail(PIC_E_RANGE, "output buffer of %zu bytes, %zu needed", out_bytes, want);
@@ -1161,13 +1182,7 @@ pic_status sim_diag(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_byt
   const int ii = inst_desc_index(S, i);
   const double V = g.dxd[0] * g.dxd[1] * (g.dim == 3 ? g.dxd[2] : 1.0);
   if (kind != PIC_DIAG_RHO_SNAPSHOT && !out) return S.fail(PIC_E_INVALID, "null output buffer");
-  std::vector<void*> tmp;
-  struct Free {
-    std::vector<void*>& v;
-    ~Free() {
-      for (void* p : v) (void)hipFree(p);
-    }
-  } fr{tmp};
+  char* scr = nullptr;
   switch (kind) {
     case PIC_DIAG_ENERGY:
     case PIC_DIAG_MOMENTUM: {
@@ -1212,14 +1227,12 @@ pic_status sim_diag(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_byt
       if ((st = need(S, want, out_bytes, written)) != PIC_OK) return st;
       if (kind == PIC_DIAG_CHARGE_RESIDUAL && !I.have_snap)
         return S.fail(PIC_E_STATE, "CHARGE_RESIDUAL needs an earlier RHO_SNAPSHOT");
-      double *rho = nullptr, *res = nullptr;
-      HIPCHK(S, hipMalloc(&rho, nc * sizeof(double)));
-      tmp.push_back(rho);
+      if ((st = diag_scratch(S, 2 * align256(nc * sizeof(double)), &scr)) != PIC_OK) return st;
+      double* rho = (double*)scr;
+      double* res = (double*)(scr + align256(nc * sizeof(double)));
       if ((st = compute_rho(S, i, rho)) != PIC_OK) return st;
       double* src = rho;
       if (kind != PIC_DIAG_RHO) {
-        HIPCHK(S, hipMalloc(&res, nc * sizeof(double)));
-        tmp.push_back(res);
         if (kind == PIC_DIAG_CHARGE_RESIDUAL)
           HIPCHK(S, pic_launch_charge64(S.d_inst + ii, I.rho_snap, rho, res, g.ncell, g.dim, S.stream));
         else
@@ -1266,16 +1279,14 @@ pic_status sim_diag(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_byt
         Species& sp = I.sp[s];
         if (!sp.used || sp.np == 0) continue;
         int k = store_desc_index(S, i, s);
-        double* dbuf = nullptr;
-        HIPCHK(S, hipMalloc(&dbuf, (size_t)sp.np * stride * sizeof(double)));
-        tmp.push_back(dbuf);
+        const size_t rb = align256((size_t)sp.np * stride * sizeof(double));
+        if ((st = diag_scratch(S, rb + align256((size_t)sp.np * sizeof(int)), &scr)) != PIC_OK) return st;
+        double* dbuf = (double*)scr;
         if (I.cfg.move_window || g.cyl) {
           // rows in storage order with their ids; sorted by id here, x1 from
           // the ring column to the lab position (moving window), x2 from the
           // cell coordinate to the radius (r-z)
-          int* dids = nullptr;
-          HIPCHK(S, hipMalloc(&dids, (size_t)sp.np * sizeof(int)));
-          tmp.push_back(dids);
+          int* dids = (int*)(scr + rb);
           HIPCHK(S, pic_launch_export_state(S.d_stores + k, (int)sp.np, dbuf, dids, S.stream));
           std::vector<double> rows((size_t)sp.np * stride);
           std::vector<int> ids(sp.np);
@@ -1321,9 +1332,8 @@ pic_status sim_diag(Sim& S, int i, pic_diag_kind kind, void* out, size_t out_byt
     case PIC_DIAG_EXPORT_CURRENT: {
       size_t ncomp = kind == PIC_DIAG_EXPORT_FIELDS ? 6 : 3;
       if ((st = need(S, ncomp * nc * sizeof(double), out_bytes, written)) != PIC_OK) return st;
-      double* dbuf = nullptr;
-      HIPCHK(S, hipMalloc(&dbuf, ncomp * nc * sizeof(double)));
-      tmp.push_back(dbuf);
+      if ((st = diag_scratch(S, ncomp * nc * sizeof(double), &scr)) != PIC_OK) return st;
+      double* dbuf = (double*)scr;
       HIPCHK(S, pic_launch_f32_to_f64(kind == PIC_DIAG_EXPORT_FIELDS ? I.F[S.steps & 1] : I.Jout, dbuf, ncomp * nc, S.stream));
       HIPCHK(S, hipMemcpyAsync(out, dbuf, ncomp * nc * sizeof(double), hipMemcpyDeviceToHost, S.stream));
       HIPCHK(S, hipStreamSynchronize(S.stream));
@@ -1603,6 +1613,7 @@ void sim_destroy(Sim& S) {
   if (S.d_inst) (void)hipFree(S.d_inst);
   if (S.d_scratch) (void)hipFree(S.d_scratch);
   if (S.d_out) (void)hipFree(S.d_out);
+  if (S.d_diag) (void)hipFree(S.d_diag);
   if (S.own_stream && S.stream) (void)hipStreamDestroy(S.stream);
 }
 
