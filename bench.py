@@ -341,11 +341,13 @@ def roofline(wl, info, gpd_avg_s):
     arithmetic bounds them, the VALU issue fraction: measured VALU wave
     instructions per launch against one wave instruction per cycle per CU
     (256 CUs at 2.4 GHz; packed FP32 is not used, so this is 78.6 TFLOP/s of
-    FMA)."""
+    FMA).  Where the record holds the LDS counters, also the share of the
+    launch the LDS is active (SQ_LDS_IDX_ACTIVE cycles per CU over the
+    launch's cycles) and the share of those cycles lost to bank conflicts."""
     bpp = bytes_per_push(wl)
     achieved = wl.n * bpp / gpd_avg_s / 1e9
     rec, e = counter_record(wl, info)
-    traffic = valu = None
+    traffic = valu = lds = None
     if e is not None:
         kib = e["fetch_kib_per_dispatch"] * rec["fetch_scale"] + e["write_kib_per_dispatch"] * rec["write_scale"]
         traffic = kib * 1024.0 / gpd_avg_s / 1e9
@@ -355,6 +357,11 @@ def roofline(wl, info, gpd_avg_s):
             valu = {"insts_per_launch": e["valu_insts_per_dispatch"], "achieved_insts_per_s": issue,
                     "peak_insts_per_s": peak, "frac": issue / peak,
                     "insts_per_push": e["valu_insts_per_dispatch"] * 64.0 / wl.n}
+        if "lds_active_cycles_per_dispatch" in e:
+            cyc = 256 * 2.4e9 * gpd_avg_s
+            lds = {"active_cycles_per_launch": e["lds_active_cycles_per_dispatch"],
+                   "active_frac": e["lds_active_cycles_per_dispatch"] / cyc,
+                   "bank_conflict_frac": e["lds_bank_conflict_cycles_per_dispatch"] / e["lds_active_cycles_per_dispatch"]}
     return {
         "bound": "hbm",
         "achieved": achieved,
@@ -367,6 +374,7 @@ def roofline(wl, info, gpd_avg_s):
         "kernel_avg_us": gpd_avg_s * 1e6,
         "kernel_pushes_per_s": wl.n / gpd_avg_s,
         "valu": valu,
+        "lds": lds,
     }
 
 
