@@ -285,13 +285,6 @@ __device__ __forceinline__ float item_sum_f32(long long q, float unit) {
   return fmaf((float)hi, 4294967296.0f, (float)lo) * unit;
 }
 
-
-
-// The tile of the two-phase 3D kernel: v is in units of the work item's own
-// fixed point (chosen so that every single contribution stays below 2^30),
-// rounded to the nearest integer and summed exactly in int64.
-
-
 // TRISTAN (Villasenor-Buneman) current of one particle for the linear shape
 // (Sec. 3.2): the straight move from offset e in the old cell by dl cells
 // (|dl| < 1 per axis) is cut where it crosses cell faces; each piece lies in
@@ -1161,7 +1154,7 @@ constexpr size_t kInterleaveLds = 64 * sizeof(int) + (size_t)kSplitR * kBlock * 
 // third.  Among particles of one class the order is that of the LDS atomics
 // (not reproducible), which only permutes storage: every particle's own
 // arithmetic, the item's membership and its fixed-point unit are unchanged,
-// and the int64 current is order-free.
+// and the integer current sums are order-free.
 //
 // interleave_slots: key[r] is the class of the thread's r-th particle (-1:
 // none); on return pos[r] is its slot in the item.  smem is free LDS of at
