@@ -481,7 +481,8 @@ __device__ __forceinline__ void dep3_comp(Acc* J, int cb, const int st[3], const
 // absent.  Modes 4-6 are the two-phase periodic 3D kernel (process_item3):
 // 4 with an int64 current tile (the deterministic int64 accumulation), 5 and
 // 6 with a 32-bit tile, 5 for the LDS strides of 4x4xN tiles as constants,
-// 6 for strides read at run time.
+// 6 for strides read at run time.  Mode 7 is the two-phase periodic 2D
+// kernel (process_item2) for FP32 accumulation with Esirkepov's deposit.
 // kstep: steps done since the last rebin check (0 for the first step of a
 // sort cycle).
 template <int DIM, int ORDER, int MODE>
@@ -1596,6 +1597,408 @@ __device__ void process_item3(const StoreDesc& S, int cur, const Item it, int ii
   __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// periodic 2D work item in two phases
+// ---------------------------------------------------------------------------
+//
+// The 2D counterpart of process_item3, for periodic Cartesian instances with
+// Esirkepov's deposit and FP32 accumulation: phase A stages E and B and
+// pushes every particle of the item (up to kSplitR2 per thread), keeping
+// what the deposit needs in registers; phase B deposits into a 32-bit
+// current tile in the same LDS, in the item's own fixed point
+// (item_exponent32: a contribution to one node is at most |w| |v|, the
+// out-of-plane one |w v_3| times a shape average at most one).  Fields and
+// current never coexist, so a workgroup needs the larger region, not their
+// sum, and no per-store unit has to be prepared before the launch.
+constexpr int kSplitR2 = 4;  // particles per thread per 2D work item
+
+template <int ORDER>
+__device__ void process_item2(const StoreDesc& S, int cur, const Item it, int ii, int jp, int kstep, float* smem,
+                              int* scnt, float* sred) {
+  constexpr int NG = ORDER + 1;  // gather taps per axis
+  constexpr int W = ORDER + 2;   // deposit window per axis
+  constexpr int K = ORDER + 1;   // deposit core per axis
+  constexpr int R = kSplitR2;
+  const GridDesc& g = S.g;
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;
+
+  const int set = cur;
+  gint* __restrict__ cellp = (gint*)S.cell[set];
+  gfloat* __restrict__ ep0 = (gfloat*)S.eps[set][0];
+  gfloat* __restrict__ ep1 = (gfloat*)S.eps[set][1];
+  gfloat* __restrict__ up0 = (gfloat*)S.u[set][0];
+  gfloat* __restrict__ up1 = (gfloat*)S.u[set][1];
+  gfloat* __restrict__ up2 = (gfloat*)S.u[set][2];
+  const gfloat* __restrict__ wp = (const gfloat*)S.w[set];
+
+  int tc[3];
+  pic_tile_coords(g, it.tile, tc);
+  // stray bound of this step (as in the one-phase kernel)
+  const int s0 = __builtin_amdgcn_readfirstlane(S.ctl->sorted) ? 0 : g.flag_slack;
+  int sl[2], org[2], ext[2], flo[2], jlo[2];
+  int FR[3] = {1, 1, 1}, JR[3] = {1, 1, 1};
+#pragma unroll
+  for (int d = 0; d < 2; d++) {
+    sl[d] = __builtin_amdgcn_readfirstlane(min(s0 + (int)ceilf((float)kstep * g.vstep[d]), g.slk[d]));
+    org[d] = tc[d] * g.tile[d];
+    ext[d] = min(g.tile[d], g.nx[d] - org[d]);
+    flo[d] = sl[d] + g.fa;
+    jlo[d] = sl[d] + g.ja;
+    FR[d] = ext[d] + 2 * sl[d] + g.fa + g.fb;
+    JR[d] = ext[d] + 2 * sl[d] + g.ja + g.jb;
+  }
+  const int fn = FR[0] * FR[1];
+  const int jn = JR[0] * JR[1];
+  float* sF = smem;                // phase A: [6][fn]
+  unsigned* sJ = (unsigned*)smem;  // phase B: [3][jn]
+
+  // this thread's particles: requested before the fields are staged
+  int pc[R];
+  float pe[R][2], pu[R][3], pw[R];
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    const int p = it.begin + tid + r * nthr;
+    pc[r] = -1;
+    pe[r][0] = pe[r][1] = 0.0f;
+    pu[r][0] = pu[r][1] = pu[r][2] = 0.0f;
+    pw[r] = 0.0f;
+    if (p < it.end) {
+      pc[r] = cellp[p];
+      pe[r][0] = ep0[p];
+      pe[r][1] = ep1[p];
+      pu[r][0] = up0[p];
+      pu[r][1] = up1[p];
+      pu[r][2] = up2[p];
+      pw[r] = wp[p];
+    }
+  }
+
+  // 1. stage E, B with periodic wrap: four nodes per thread per batch, every
+  // load of a batch in flight before its LDS writes
+  const int ncell = g.ncell;
+  {
+    const gfloat* Fg = (const gfloat*)S.F[jp];
+    BoxWalk bw(tid, nthr, FR);
+    for (int base = 0; base < fn; base += 4 * nthr) {
+      float v[4][6];
+      int gi[4];
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const int gx = wrap_fast(org[0] - flo[0] + bw.x, g.nx[0]);
+        const int gy = wrap_fast(org[1] - flo[1] + bw.y, g.nx[1]);
+        gi[q] = gx + g.nx[0] * gy;
+        bw.advance(FR);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        if (base + q * nthr + tid < fn) {
+#pragma unroll
+          for (int c = 0; c < 6; c++) v[q][c] = Fg[(size_t)c * ncell + gi[q]];
+        }
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const int li = base + q * nthr + tid;
+        if (li < fn) {
+#pragma unroll
+          for (int c = 0; c < 6; c++) sF[c * fn + li] = v[q][c];
+        }
+      }
+    }
+  }
+  if (tid < PIC_NSLOT) scnt[tid] = 0;
+  __syncthreads();
+
+  // 2. phase A: gather, Boris push, advance; store the new state
+  const float h = 0.5f * S.qm * g.dt;
+  bool strayed = false, bad = false;
+  float bmax = 0.0f;
+  // kept for the deposit: old and new offsets, the move, the old cell in
+  // current-region coordinates (-1: no particle), the weight and w v_3
+  float se0[R][2], sen[R][2], swq[R], sv3[R];
+  int smv[R], sjc[R];
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    const int p = it.begin + tid + r * nthr;
+    smv[r] = 0;
+    sjc[r] = -1;
+    swq[r] = sv3[r] = 0.0f;
+    se0[r][0] = se0[r][1] = sen[r][0] = sen[r][1] = 0.0f;
+    int dd[2] = {0, 0};
+    const bool live = p < it.end;
+    if (live) {
+      int cc[3];
+      pic_unpack(g, pc[r], cc);
+      int l[2];
+      bool ok = true;
+#pragma unroll
+      for (int d = 0; d < 2; d++) {
+        l[d] = pic_local(cc[d], org[d], ext[d], g.nx[d]);
+        ok = ok && (l[d] >= -sl[d]) && (l[d] < ext[d] + sl[d]);
+      }
+      if (!ok) {
+        // reported as a failed step; the particle is clamped into the
+        // staged region so that every access stays inside it
+        bad = true;
+#pragma unroll
+        for (int d = 0; d < 2; d++) l[d] = min(max(l[d], -sl[d]), ext[d] + sl[d] - 1);
+      }
+      const float e[2] = {pe[r][0], pe[r][1]};
+      // ---- gather: weights at offset 0 and 1/2 per axis
+      int b0[2], bh[2];
+      float w0[2][NG], wh[2][NG];
+#pragma unroll
+      for (int d = 0; d < 2; d++) {
+        gather_weights<ORDER>(e[d], false, b0[d], w0[d]);
+        gather_weights<ORDER>(e[d], true, bh[d], wh[d]);
+      }
+      const int FR0 = FR[0];
+      const int gb0 = (flo[1] + l[1] + b0[1]) * FR0 + flo[0] + l[0] + b0[0];
+      const int dgx = bh[0] - b0[0];
+      const int dgy = bh[1] == b0[1] ? 0 : (bh[1] < b0[1] ? -FR0 : FR0);
+      float Fp[6];
+#pragma unroll
+      for (int c = 0; c < 6; c++) {
+        // component c: E_c staggered half along axis c, B_c half along the others
+        const bool hx = (c < 3) ? (c == 0) : (c != 3);
+        const bool hy = (c < 3) ? (c == 1) : (c != 4);
+        const float* wx = hx ? wh[0] : w0[0];
+        const float* wy = hy ? wh[1] : w0[1];
+        const float* row = sF + c * fn + gb0 + (hx ? dgx : 0) + (hy ? dgy : 0);
+        float acc = 0.0f;
+#pragma unroll
+        for (int j = 0; j < NG; j++) {
+          float rr = 0.0f;
+#pragma unroll
+          for (int i = 0; i < NG; i++) rr += wx[i] * row[i];
+          acc += wy[j] * rr;
+          row += FR0;
+        }
+        Fp[c] = acc;
+      }
+      const float Ex = Fp[0] + g.e0[0], Ey = Fp[1] + g.e0[1], Ez = Fp[2] + g.e0[2];
+      const float Bx = Fp[3] + g.b0[0], By = Fp[4] + g.b0[1], Bz = Fp[5] + g.b0[2];
+      // ---- Boris push (Sec. 3.2, Eq. momentum-update)
+      float ux = pu[r][0], uy = pu[r][1], uz = pu[r][2];
+      const float mx = ux + h * Ex, my = uy + h * Ey, mz = uz + h * Ez;
+      const float gim = rsqrtf(1.0f + mx * mx + my * my + mz * mz);
+      const float tx = h * Bx * gim, ty = h * By * gim, tz = h * Bz * gim;
+      const float sfac = 2.0f * __builtin_amdgcn_rcpf(1.0f + tx * tx + ty * ty + tz * tz);
+      const float px = mx + (my * tz - mz * ty);
+      const float py = my + (mz * tx - mx * tz);
+      const float pz = mz + (mx * ty - my * tx);
+      const float sx_ = sfac * tx, sy_ = sfac * ty, sz_ = sfac * tz;
+      ux = mx + (py * sz_ - pz * sy_) + h * Ex;
+      uy = my + (pz * sx_ - px * sz_) + h * Ey;
+      uz = mz + (px * sy_ - py * sx_) + h * Ez;
+      // ---- advance (Eq. 2d-position-update, in-plane)
+      const float uu2 = ux * ux + uy * uy + uz * uz;
+      const float gi = rsqrtf(1.0f + uu2);
+      const float uu[2] = {ux, uy};
+      int mv[2];
+      float en[2];
+#pragma unroll
+      for (int d = 0; d < 2; d++) {
+        const float x = e[d] + g.dt * g.rdx[d] * (uu[d] * gi);
+        const float f = floorf(x);
+        int c = (int)f;
+        float rr = x - f;
+        if (rr >= 1.0f) {  // rounding edge: keep the offset in [0,1)
+          rr = 0.0f;
+          c += 1;
+        }
+        // the Courant condition keeps |move| below one cell
+        if (c > 1) {
+          c = 1;
+          rr = 0.99999994f;
+        } else if (c < -1) {
+          c = -1;
+          rr = 0.0f;
+        }
+        en[d] = rr;
+        mv[d] = c;
+      }
+      // ---- the new state
+      int nc[2];
+#pragma unroll
+      for (int d = 0; d < 2; d++) {
+        nc[d] = cc[d] + mv[d];
+        if (nc[d] < 0) nc[d] += g.nx[d];
+        if (nc[d] >= g.nx[d]) nc[d] -= g.nx[d];
+        const int ln = pic_local(nc[d], org[d], ext[d], g.nx[d]);
+        strayed = strayed || ln < -g.flag_slack || ln >= ext[d] + g.flag_slack;
+        dd[d] = ln < 0 ? -1 : (ln >= ext[d] ? 1 : 0);
+      }
+      cellp[p] = pic_pack(g, nc[0], nc[1], 0);
+      ep0[p] = en[0];
+      ep1[p] = en[1];
+      up0[p] = ux;
+      up1[p] = uy;
+      up2[p] = uz;
+      // ---- what the deposit needs
+#pragma unroll
+      for (int d = 0; d < 2; d++) {
+        se0[r][d] = e[d];
+        sen[r][d] = en[d];
+      }
+      smv[r] = (mv[0] + 1) | ((mv[1] + 1) << 2);
+      sjc[r] = (jlo[1] + l[1]) * JR[0] + jlo[0] + l[0];
+      swq[r] = pw[r];
+      sv3[r] = pw[r] * uz * gi;
+      bmax = fmaxf(bmax, fabsf(pw[r]) * (sqrtf(uu2) * gi));
+    }
+    {
+      // wave-aggregated count per rebin slot (almost every particle is in slot 13)
+      const int slt = live ? pic_slot(dd[0], dd[1], 0) : -1;
+      unsigned long long todo = __ballot(slt >= 0);
+      while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int ls = __shfl(slt, leader);
+        const unsigned long long m = __ballot(slt == ls);
+        if ((int)(threadIdx.x & 63) == leader) atomicAdd(&scnt[ls], (int)__popcll(m));
+        todo &= ~m;
+      }
+    }
+  }
+  // the item's bound on a single contribution: max of |w| |v| over its particles
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) bmax = fmaxf(bmax, __shfl_xor(bmax, off));
+  if ((tid & 63) == 0) sred[tid >> 6] = bmax;
+  const int any_strayed = __syncthreads_or(strayed ? 1 : 0);  // also: phase A done, fields dead
+  const int any_bad = __syncthreads_or(bad ? 1 : 0);
+  float btop = 0.0f;
+  for (int k = 0; k < (nthr >> 6); k++) btop = fmaxf(btop, sred[k]);
+  const int e_item = __builtin_amdgcn_readfirstlane(item_exponent32(btop, it.end - it.begin));
+  const float Q = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(ldexpf(1.0f, e_item))));
+
+  // 3. clear the current tile over the dead field tile
+  for (int idx = tid; idx < 3 * jn; idx += nthr) sJ[idx] = 0u;
+  if (tid == 0) {
+    if (any_strayed) S.ctl->flag = 1;
+    if (any_bad) S.ctl->bad = 1;
+  }
+  if (tid < PIC_NSLOT) S.cnt[ii * PIC_NSLOT + tid] = scnt[tid];
+  __syncthreads();
+
+  // 4. phase B: ISIS ordering average in Esirkepov's closed form (2D3V): the
+  // core of the old support unconditional, the extra column, row and corner
+  // under one branch each; J3 skipped by lanes without out-of-plane motion
+  unsigned* J1 = sJ;
+  unsigned* J2 = sJ + jn;
+  unsigned* J3 = sJ + 2 * jn;
+  const int RJ = JR[0];
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    if (sjc[r] < 0) continue;
+    const int mv[2] = {(smv[r] & 3) - 1, ((smv[r] >> 2) & 3) - 1};
+    int wb[2], p0[2];
+    bool wide[2];
+    float S0[2][W], D[2][W];
+#pragma unroll
+    for (int d = 0; d < 2; d++) deposit_shape<ORDER>(se0[r][d], sen[r][d], mv[d], wb[d], p0[d], wide[d], S0[d], D[d]);
+    const float q1 = -swq[r] * g.cdt[0] * Q, q2 = -swq[r] * g.cdt[1] * Q;
+    float P1[W - 1], P2[W - 1];
+    {
+      float a = 0.0f, b = 0.0f;
+#pragma unroll
+      for (int k = 0; k < W - 1; k++) {
+        a += D[0][k];
+        b += D[1][k];
+        P1[k] = q1 * a;
+        P2[k] = q2 * b;
+      }
+    }
+    const float v3 = sv3[r] * Q;
+    const bool px = p0[0] != 0, py = p0[1] != 0;
+    float Sx[K], Dx[K], Sy[K], Dy[K], Px[K - 1], Py[K - 1];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      Sx[k] = px ? S0[0][k + 1] : S0[0][k];
+      Dx[k] = px ? D[0][k + 1] : D[0][k];
+      Sy[k] = py ? S0[1][k + 1] : S0[1][k];
+      Dy[k] = py ? D[1][k + 1] : D[1][k];
+    }
+#pragma unroll
+    for (int k = 0; k < K - 1; k++) {
+      Px[k] = px ? P1[k + 1] : P1[k];
+      Py[k] = py ? P2[k + 1] : P2[k];
+    }
+    const float Sxe = px ? S0[0][0] : S0[0][K], Dxe = px ? D[0][0] : D[0][K];
+    const float Sye = py ? S0[1][0] : S0[1][K], Dye = py ? D[1][0] : D[1][K];
+    const float Pxe = wide[0] ? (px ? P1[0] : P1[K - 1]) : 0.0f;
+    const float Pye = wide[1] ? (py ? P2[0] : P2[K - 1]) : 0.0f;
+    const int exS = px ? -1 : K, exP = px ? -1 : K - 1;
+    const int cb = sjc[r] + (wb[0] + p0[0]) + (wb[1] + p0[1]) * RJ;
+    const int ey = py ? -RJ : K * RJ;
+    const int eyp = py ? -RJ : (K - 1) * RJ;
+    // y factors of J1 and J3 (S0 + D/2, S0/2 + D/3) and x factor of J2
+    float T1[K], U2[K], X2[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      T1[k] = Sy[k] + 0.5f * Dy[k];
+      U2[k] = 0.5f * Sy[k] + (1.0f / 3.0f) * Dy[k];
+      X2[k] = Sx[k] + 0.5f * Dx[k];
+    }
+    const float T1e = Sye + 0.5f * Dye, U2e = 0.5f * Sye + (1.0f / 3.0f) * Dye;
+    const float X2e = Sxe + 0.5f * Dxe;
+#pragma unroll
+    for (int j = 0; j < K; j++) {
+#pragma unroll
+      for (int i = 0; i < K - 1; i++) lds_add_any(J1 + cb + j * RJ + i, Px[i] * T1[j]);
+      if (v3 != 0.0f) {
+#pragma unroll
+        for (int i = 0; i < K; i++) lds_add_any(J3 + cb + j * RJ + i, v3 * (Sx[i] * T1[j] + Dx[i] * U2[j]));
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < K - 1; j++) {
+#pragma unroll
+      for (int i = 0; i < K; i++) lds_add_any(J2 + cb + j * RJ + i, Py[j] * X2[i]);
+    }
+    if (wide[0]) {
+#pragma unroll
+      for (int j = 0; j < K; j++) {
+        lds_add_any(J1 + cb + j * RJ + exP, Pxe * T1[j]);
+        if (v3 != 0.0f) lds_add_any(J3 + cb + j * RJ + exS, v3 * (Sxe * T1[j] + Dxe * U2[j]));
+      }
+#pragma unroll
+      for (int j = 0; j < K - 1; j++) lds_add_any(J2 + cb + j * RJ + exS, Py[j] * X2e);
+    }
+    if (wide[1]) {
+#pragma unroll
+      for (int i = 0; i < K - 1; i++) lds_add_any(J1 + cb + ey + i, Px[i] * T1e);
+#pragma unroll
+      for (int i = 0; i < K; i++) {
+        if (v3 != 0.0f) lds_add_any(J3 + cb + ey + i, v3 * (Sx[i] * T1e + Dx[i] * U2e));
+        lds_add_any(J2 + cb + eyp + i, Pye * X2[i]);
+      }
+    }
+    if (wide[0] && wide[1]) {
+      lds_add_any(J1 + cb + ey + exP, Pxe * T1e);
+      if (v3 != 0.0f) lds_add_any(J3 + cb + ey + exS, v3 * (Sxe * T1e + Dxe * U2e));
+      lds_add_any(J2 + cb + eyp + exS, Pye * X2e);
+    }
+  }
+  __syncthreads();
+
+  // 5. fold the tile into the global current (periodic wrap), one rounding
+  // of each node's sum
+  const float qinv = ldexpf(1.0f, -e_item);
+  BoxWalk bj(tid, nthr, JR);
+  for (int idx = tid; idx < jn; idx += nthr, bj.advance(JR)) {
+    const int gx = wrap_fast(org[0] - jlo[0] + bj.x, g.nx[0]);
+    const int gy = wrap_fast(org[1] - jlo[1] + bj.y, g.nx[1]);
+    const int gidx = gx + g.nx[0] * gy;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      const int q = (int)sJ[c * jn + idx];
+      if (q != 0)
+        __builtin_amdgcn_global_atomic_fadd_f32((gfloat*)S.Jacc[jp] + (size_t)c * ncell + gidx, (float)q * qinv);
+    }
+  }
+  __syncthreads();
+}
+
 template <int DIM, int ORDER, int MODE>
 __device__ __forceinline__ void gpd_body(const StoreDesc* __restrict__ stores, int nstores, int jp, int kstep) {
   // 16-byte aligned: the int64 current tile inside it takes 8-byte LDS atomics
@@ -1643,7 +2046,9 @@ __device__ __forceinline__ void gpd_body(const StoreDesc* __restrict__ stores, i
     it.tile = __builtin_amdgcn_readfirstlane(it.tile);
     it.begin = __builtin_amdgcn_readfirstlane(it.begin);
     it.end = __builtin_amdgcn_readfirstlane(it.end);
-    if constexpr (MODE >= 4)
+    if constexpr (MODE == 7)
+      process_item2<ORDER>(S, cur, it, ii, jp, kstep, smem, s_cnt, s_red);
+    else if constexpr (MODE >= 4)
       process_item3<ORDER, MODE == 5, typename std::conditional<MODE == 4, acc_t, unsigned>::type>(
           S, cur, it, ii, jp, kstep, smem, s_cnt, s_red);
     else
@@ -1694,6 +2099,7 @@ hipError_t prepare_one(int mode, size_t lds) {
   if constexpr (DIM == 2) {
     if (mode == 2) return prepare_mode<DIM, ORDER, 2>(lds);
     if (mode == 3) return prepare_mode<DIM, ORDER, 3>(lds);
+    if (mode == 7) return prepare_mode<DIM, ORDER, 7>(lds);
   } else {
     if (mode == 4) return prepare_mode<DIM, ORDER, 4>(lds);
     if (mode == 5) return prepare_mode<DIM, ORDER, 5>(lds);
@@ -1713,8 +2119,12 @@ hipError_t launch_one(int mode, const StoreDesc* stores, int nstores, int grid, 
   else if constexpr (DIM == 2) {
     if (mode == 2)
       launch_mode<DIM, ORDER, 2>(stores, nstores, grid, lds, jp, kstep, st, ev0, ev1);
-    else
+    else if (mode == 3)
       launch_mode<DIM, ORDER, 3>(stores, nstores, grid, lds, jp, kstep, st, ev0, ev1);
+    else if (mode == 7)
+      launch_mode<DIM, ORDER, 7>(stores, nstores, grid, lds, jp, kstep, st, ev0, ev1);
+    else
+      return hipErrorInvalidValue;
   } else {
     if (mode == 4)
       launch_mode<DIM, ORDER, 4>(stores, nstores, grid, lds, jp, kstep, st, ev0, ev1);
@@ -1790,6 +2200,15 @@ static size_t split_lds_bytes(const GridDesc& g0) {
   return std::max(std::max(6 * (size_t)g.fs01 * f2 * sizeof(float), 3 * (size_t)g.js01 * j2 * jw), kInterleaveLds);
 }
 
+// Whether the two-phase periodic 2D kernel (mode 7) runs a grid (the host
+// decides at set-up; see setup_grid).
+bool pic_gpd_two_phase2(const GridDesc& g) { return g.tp2 != 0; }
+
+// Its LDS: six field planes or three 32-bit current planes, whichever is larger.
+static size_t two_phase2_lds_bytes(size_t fn, size_t jn) {
+  return std::max(6 * fn, 3 * jn) * sizeof(float);
+}
+
 size_t pic_gpd_lds_bytes(const GridDesc& g) {
   size_t fn = 1, jn = 1;
   for (int d = 0; d < g.dim; d++) {
@@ -1797,6 +2216,7 @@ size_t pic_gpd_lds_bytes(const GridDesc& g) {
     jn *= (size_t)(g.tile[d] + 2 * g.slk[d] + g.ja + g.jb);
   }
   if (pic_gpd_split(g)) return split_lds_bytes(g);
+  if (pic_gpd_two_phase2(g)) return two_phase2_lds_bytes(fn, jn);
   return ((6 * fn + 1) & ~(size_t)1) * sizeof(float) + 3 * jn * sizeof(unsigned long long);
 }
 
@@ -1811,11 +2231,15 @@ size_t pic_gpd_lds_bytes_step(const GridDesc& g, int kstep) {
     jn *= (size_t)(g.tile[d] + 2 * sl + g.ja + g.jb);
   }
   if (pic_gpd_split(g)) return split_lds_bytes(g);
+  if (pic_gpd_two_phase2(g)) return two_phase2_lds_bytes(fn, jn);
   return ((6 * fn + 1) & ~(size_t)1) * sizeof(float) + 3 * jn * sizeof(unsigned long long);
 }
 
 // Particles one work item of the two-phase 3D kernel can hold.
 int pic_gpd_split_chunk() { return kSplitR * kBlock; }
+
+// Particles one work item of the two-phase 2D kernel can hold.
+int pic_gpd_two_phase2_chunk() { return kSplitR2 * kBlock; }
 
 int pic_gpd_block() { return kBlock; }
 int pic_gpd_max_group() { return kMaxGroup; }
@@ -1840,6 +2264,7 @@ int resident_one(int mode, size_t lds) {
   if constexpr (DIM == 2) {
     if (mode == 2) f = gpd_entry<DIM, ORDER, 2>();
     if (mode == 3) f = gpd_entry<DIM, ORDER, 3>();
+    if (mode == 7) f = gpd_entry<DIM, ORDER, 7>();
   } else {
     if (mode == 4) f = gpd_entry<DIM, ORDER, 4>();
     if (mode == 5) f = gpd_entry<DIM, ORDER, 5>();

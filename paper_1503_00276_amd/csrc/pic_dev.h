@@ -46,6 +46,8 @@ struct GridDesc {
   // and of a current-region row and plane, padded so that the lanes of a
   // wavefront, one particle per cell of the tile, spread over the LDS banks
   int fs0, fs01, js0, js01;
+  // 1: the two-phase periodic 2D kernel runs this grid (set by the host)
+  int tp2;
 };
 
 // Control words of one particle store.  The buffer set holding the particles

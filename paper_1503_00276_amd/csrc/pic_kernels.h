@@ -12,6 +12,10 @@ size_t pic_gpd_lds_bytes_step(const GridDesc& g, int kstep);
 int pic_gpd_block();
 // particles a work item of the two-phase 3D variant can hold (its chunk limit)
 int pic_gpd_split_chunk();
+// the two-phase periodic 2D kernel (mode 7): whether a grid takes it, and the
+// particles one of its work items can hold
+bool pic_gpd_two_phase2(const GridDesc& g);
+int pic_gpd_two_phase2_chunk();
 // padded LDS strides of the two-phase variant for g's tile and stray bound
 void pic_gpd_split_strides(GridDesc& g);
 int pic_gpd_max_group();

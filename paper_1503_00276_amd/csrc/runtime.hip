@@ -89,13 +89,18 @@ int kernel_mode(const GridDesc& g) {
     if (g.acc_mode == PIC_ACC_FIXED64) return 4;
     return (g.fs0 == 12 && g.fs01 == 144 && g.js0 == 12 && g.js01 == 144) ? 5 : 6;
   }
+  // two-phase periodic 2D kernel (FP32 accumulation, Esirkepov's deposit)
+  if (pic_gpd_two_phase2(g)) return 7;
   return g.window ? (g.cyl ? 3 : 1) : (g.cyl ? 2 : 0);
 }
 
-// Particles per work item a store of this box uses: the two-phase 3D kernel
-// holds at most pic_gpd_split_chunk() per item.
+// Particles per work item a store of this box uses: the two-phase kernels
+// hold at most pic_gpd_split_chunk() (3D) or pic_gpd_two_phase2_chunk() (2D)
+// per item.
 int store_chunk(const GridDesc& g, int chunk) {
-  return pic_gpd_split(g) ? std::min(chunk, pic_gpd_split_chunk()) : chunk;
+  if (pic_gpd_split(g)) return std::min(chunk, pic_gpd_split_chunk());
+  if (pic_gpd_two_phase2(g)) return std::min(chunk, pic_gpd_two_phase2_chunk());
+  return chunk;
 }
 
 struct Sim {
@@ -214,6 +219,14 @@ pic_status setup_grid(Sim& S, const pic_config& c, int sort_interval, GridDesc& 
     g.slack = std::max(g.slack, g.slk[d]);
   }
   region_guards(g.order, g.fa, g.fb, g.ja, g.jb);
+  // The two-phase periodic 2D kernel takes Cartesian boxes without a moving
+  // window, with Esirkepov's deposit and FP32 accumulation, whose work items
+  // fit in it (the library's chunk, or an asked-for chunk of at most what it
+  // holds); layouts with larger items keep the one-phase kernel.
+  g.tp2 = (c.ndim == 2 && !g.window && !g.cyl && g.deposit == 0 && g.acc_mode != PIC_ACC_FIXED64 &&
+           (c.chunk == 0 || c.chunk <= pic_gpd_two_phase2_chunk()))
+              ? 1
+              : 0;
   if (pic_gpd_split(g)) {
     // the two-phase kernel stages only what the shapes reach, one node less
     // above than the one-phase kernel: gather taps reach cell offsets
@@ -438,7 +451,7 @@ pic_status refresh_descriptors(Sim& S) {
   S.igroups.clear();
   for (int dim = 2; dim <= 3; dim++)
     for (int order = 1; order <= 3; order++)
-      for (int mode = 0; mode <= 6; mode++) {
+      for (int mode = 0; mode <= 7; mode++) {
       Group gr{dim, order, (int)stores.size(), 0, 0, 0, 0, 0, 0, false, {0, 0, 0}, 0, false};
       gr.mode = mode;
       for (size_t i = 0; i < S.inst.size(); i++) {
@@ -459,7 +472,8 @@ pic_status refresh_descriptors(Sim& S) {
           gr.max_blocks += (I.g.ntiles + PIC_REBIN_TILES - 1) / PIC_REBIN_TILES;
           gr.lds = std::max(gr.lds, pic_gpd_lds_bytes(I.g));
           if (I.g.window) gr.window = true;
-          if (I.g.acc_mode != PIC_ACC_FIXED64 && !I.g.cyl && !pic_gpd_split(I.g)) gr.units = true;
+          if (I.g.acc_mode != PIC_ACC_FIXED64 && !I.g.cyl && !pic_gpd_split(I.g) && !pic_gpd_two_phase2(I.g))
+            gr.units = true;
           gr.inject_max = std::max(gr.inject_max, sp.desc.inj_ppc[0] * sp.desc.inj_ppc[1] * sp.desc.inj_ppc[2] *
                                                       (I.g.ncell / I.g.nx[0]));
         }

@@ -22,6 +22,6 @@ def test_particle_kernel_dynamic_lds_is_16_byte_aligned(tmp_path):
     sizes = [int(v) for v in re.findall(r"amdhsa_group_segment_fixed_size (\d+)", out.read_text())]
     # 2 dims x 3 orders x (periodic, moving window) + 3 orders x (r-z, r-z with window)
     # + 3 orders x periodic 3D in two phases (int64 tile; 32-bit tile with compile-time
-    # and with runtime LDS strides)
-    assert len(sizes) == 27
+    # and with runtime LDS strides) + 3 orders x periodic 2D in two phases
+    assert len(sizes) == 30
     assert all(v % 16 == 0 for v in sizes), sizes
