@@ -66,13 +66,16 @@ def test_fp64_diagnostics_match_oracle(orc, ndim, order):
     assert abs(norm[1] - np.sqrt(np.mean(G_ref ** 2))) <= 1e-10 * norm[1]
 
 
-@pytest.mark.parametrize("ndim,order", [(2, 1), (2, 2), (2, 3), (3, 1), (3, 2), (3, 3)])
-def test_charge_conservation_on_gpu(ndim, order):
+@pytest.mark.parametrize("ndim,order,chunk", [(2, 1, 0), (2, 2, 0), (2, 3, 0), (3, 1, 0), (3, 2, 0), (3, 3, 0),
+                                              (2, 1, 2048), (2, 3, 2048)])
+def test_charge_conservation_on_gpu(ndim, order, chunk):
     """(rho^{n+1} - rho^n)/dt + div J = 0 for the FP32 step: the FP64 residual
-    is below 1e-6 of max|rho_e| / dt (continuity, Sec. 3.2)."""
+    is below 1e-6 of max|rho_e| / dt (continuity, Sec. 3.2).  In 2D, chunk 0
+    takes the two-phase kernel (32-bit current tile), chunk 2048 the
+    one-phase kernel (int64 tile)."""
     pic = _pic()
     nx = (24, 16) if ndim == 2 else (8, 8, 8)
-    cfg, sim = _sim(pic, ndim, nx, (0.2,) * ndim, 0.08, order, uth=0.5, tile=(4,) * ndim)
+    cfg, sim = _sim(pic, ndim, nx, (0.2,) * ndim, 0.08, order, uth=0.5, tile=(4,) * ndim, chunk=chunk)
     sim.step(2)
     rho_e = sim.rho() - 1.0
     sim.rho_snapshot()

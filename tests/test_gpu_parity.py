@@ -37,13 +37,19 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}d_o{c[4]}_{'x'.join(map(str, c[1]))}")
-def test_step_parity(orc, case):
+# 2D boxes take the two-phase kernel with the library's chunk, the one-phase
+# kernel with work items of more than 1024 particles (chunk 2048)
+STEP_CASES = [(c, 0) for c in CASES] + [(c, 2048) for c in CASES if c[0] == 2]
+
+
+@pytest.mark.parametrize("case,chunk", STEP_CASES,
+                         ids=lambda c: f"{c[0]}d_o{c[4]}_{'x'.join(map(str, c[1]))}" if isinstance(c, tuple) else f"chunk{c}")
+def test_step_parity(orc, case, chunk):
     pic = _pic()
     ndim, nx, dx, dt, order, ppc, uth, tile = case
     x, u, w = _thermal(ndim, nx, dx, ppc, uth, 11 + order + 10 * ndim)
     cfg = pic.Config(ndim=ndim, nx=nx, dx=dx, dt=dt, shape_order=order, tile=tile, sort_interval=2,
-                     ion_density=1.0)
+                     ion_density=1.0, chunk=chunk)
     sim = pic.Pic(cfg)
     sim.load_particles(x, u, w, rqm=-1.0)
     rng = np.random.default_rng(5)
