@@ -103,15 +103,16 @@ def test_thermal_64x64_full_parity_and_energy_history(orc):
     sim.close()
 
 
-@pytest.mark.parametrize("layout", [None, (32, 8, 8, 1024, 45), (32, 8, 6, 1024, 112)],
-                         ids=["autotuned", "32x8_si8_chunk1024", "bench_32x8_si6_chunk1024"])
+@pytest.mark.parametrize("layout", [None, (32, 8, 8, 1024, 45), (32, 8, 6, 1024, 112), (32, 8, 12, 1024, 118)],
+                         ids=["autotuned", "32x8_si8_chunk1024", "32x8_si6_chunk1024", "bench_32x8_si12_chunk1024"])
 def test_lwfa_full_size_parity_in_bench_layout(orc, layout):
     """Workload 2 (2,097,152 electrons, quadratic, laser): the autotuned
-    layout, a fixed 32x8 layout with sort interval 8, and the benchmark's
-    layout (32x8 tiles, sort interval 6, chunk 1024) at the benchmark's
-    state (it times from step 111 on: steps 113 and 114 are the last two of
-    a sort cycle, where the staged halo is widest); then every particle,
-    current and field value for two steps."""
+    layout, fixed 32x8 layouts with sort intervals 8 and 6, and the
+    benchmark's layout (32x8 tiles, sort interval 12, chunk 1024) at the
+    benchmark's state (it times from step 111 on; the steps compared are
+    the last two of a sort cycle, where the staged halo is widest: 113-114
+    at interval 6, 119-120 at interval 12); then every particle, current
+    and field value for two steps."""
     from paper_1503_00276_amd import workloads as W
 
     pic = _pic()
