@@ -235,7 +235,7 @@ def test_cubic3d_full_size_sampled_parity(orc, layout):
 @pytest.mark.parametrize("tuned", [False, True], ids=["bench_layout", "autotuned"])
 def test_batched_scan_parity(tuned):
     """Workload 4 (64 instances, 62 M particles) in the benchmark's batched
-    layout (the library's tiles, sort interval 3, chunk 2048) at the state it
+    layout (the library's tiles, sort interval 4, chunk 2048) at the state it
     times from (after 10 steps), and autotuned: every particle of the four
     smallest instances and a sample of two large ones, one step each,
     against the oracle."""
@@ -244,7 +244,7 @@ def test_batched_scan_parity(tuned):
 
     pic = _pic()
     wls = W.workload4()
-    lay = {} if tuned else {"sort_interval": 3, "chunk": 2048}
+    lay = {} if tuned else {"sort_interval": 4, "chunk": 2048}
     cfgs = [pic.Config(ndim=2, nx=wl.nx, dx=wl.dx, dt=wl.dt, shape_order=wl.order, ion_density=wl.ion_density, **lay)
             for wl in wls]
     batch = pic.PicBatch(cfgs)
