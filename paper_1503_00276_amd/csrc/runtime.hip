@@ -1935,7 +1935,10 @@ pic_status sim_autotune(Sim& S, pic_tune* io) {
   }
   seen.push_back(key(start_cfgs, start.si, start.chunk));
   const double ms_before = best_ms;
-  auto consider = [&](const Layout& L) -> pic_status {
+  // (out_ms, when given, receives the trial's time; 0 when the layout was
+  // not tried: invalid for some instance, or tried before)
+  auto consider = [&](const Layout& L, double* out_ms = nullptr) -> pic_status {
+    if (out_ms) *out_ms = 0.0;
     std::vector<pic_config> c;
     if (layout_configs(S, L, c) != PIC_OK) return PIC_OK;  // not valid for some instance: skip
     std::vector<int> k = key(c, L.si, L.chunk);
@@ -1945,6 +1948,7 @@ pic_status sim_autotune(Sim& S, pic_tune* io) {
     double ms = 0.0;
     pic_status r = trial(L, c, &ms);
     if (r != PIC_OK) return r;
+    if (out_ms) *out_ms = ms;
     // a candidate must beat the best so far by 2% (timing noise of a short
     // trial), which keeps the choice stable from run to run
     if (ms < 0.98 * best_ms) {
@@ -1956,11 +1960,12 @@ pic_status sim_autotune(Sim& S, pic_tune* io) {
   };
   static const int kPpt[] = {256, 512, 1024, 2048, 4096, 8192};
   static const int kAspect[] = {1, 2, 4, 8};
-  static const int kSi[] = {1, 2, 3, 4, 6, 8};
+  static const int kSi[] = {1, 2, 3, 4, 6, 8, 12};
   // chunks above 2048 are left out: a tile whose density grows several-fold
   // later in a run (wakes, beams) would become one long item, a tail no trial
   // on the loaded state can see
   static const int kChunk[] = {512, 1024, 2048};
+  std::vector<std::pair<double, Layout>> tiles_tried;  // first round's tile trials by time
   for (int round = 0; round < 2 && st == PIC_OK; round++) {
     if (what & PIC_TUNE_TILE)
       for (int p : kPpt) {
@@ -1968,16 +1973,37 @@ pic_status sim_autotune(Sim& S, pic_tune* io) {
           Layout L = best;
           L.ppt = p;
           L.aspect = a;
-          if ((st = consider(L)) != PIC_OK) break;
+          double ms = 0.0;
+          if ((st = consider(L, &ms)) != PIC_OK) break;
+          if (round == 0 && ms > 0.0) tiles_tried.push_back({ms, L});
         }
         if (st != PIC_OK) break;
       }
-    if (st == PIC_OK && (what & PIC_TUNE_SORT) && round == 0)
+    if (st == PIC_OK && (what & PIC_TUNE_SORT) && round == 0) {
       for (int si : kSi) {
         Layout L = best;
         L.si = si;
         if ((st = consider(L)) != PIC_OK) break;
       }
+      // Tile and sort interval interact: a longer cycle needs a wider halo,
+      // which a longer tile carries at a smaller share of its work, so the
+      // next three fastest tiles of the tile search get an interval search
+      // of their own.
+      std::sort(tiles_tried.begin(), tiles_tried.end(),
+                [](const std::pair<double, Layout>& a, const std::pair<double, Layout>& b) { return a.first < b.first; });
+      int extra = 0;
+      for (size_t q = 0; q < tiles_tried.size() && extra < 3 && st == PIC_OK; q++) {
+        const Layout& T = tiles_tried[q].second;
+        if (T.ppt == best.ppt && T.aspect == best.aspect) continue;
+        extra++;
+        for (int si : kSi) {
+          Layout L = T;
+          L.si = si;
+          L.chunk = best.chunk;
+          if ((st = consider(L)) != PIC_OK) break;
+        }
+      }
+    }
     if (st == PIC_OK && (what & PIC_TUNE_CHUNK) && round == 0)
       for (int ch : kChunk) {
         Layout L = best;
