@@ -64,9 +64,15 @@ typedef enum {
 } pic_status;
 
 /* Accumulation of the current.  Every particle's FP32 contribution is
- * rounded to an integer multiple of a power-of-two unit (2^-30 of the largest
- * possible single contribution, max|w| * max(dx/dt, 1)) and the contributions
- * of a tile are summed exactly in int64 in LDS. */
+ * rounded to an integer multiple of a power-of-two unit and the
+ * contributions of a tile are summed exactly in integers in LDS.  The unit
+ * follows a bound on a single contribution |w| |v|: the work item's largest
+ * in the two-phase kernels (periodic 3D; periodic 2D with items of at most
+ * 1024 particles), whose 32-bit tile sums hold n such contributions
+ * (unit about n 2^-31 of the bound for an item of n particles); a per-step
+ * bound of the species in the other kernels, whose tile sums are int64
+ * (unit 2^-31 of the bound); the instance's 2^-31 max|w| with
+ * PIC_ACC_FIXED64. */
 enum {
   PIC_ACC_FP32 = 0,        /* exact tile sums, folded into the FP32 current
                               with FP32 global atomic adds */
@@ -98,7 +104,10 @@ typedef struct {
   int32_t sort_interval; /* steps between rebin checks; 0 = a default from the
                             Courant number (searched by pic_autotune) */
   int32_t chunk;         /* maximum particles one workgroup takes from a tile;
-                            0 = 2048 (searched by pic_autotune) */
+                            0 = 2048 (searched by pic_autotune); capped at
+                            768 in periodic 3D boxes, and at 1024 in periodic
+                            2D ones with FP32 accumulation unless it is asked
+                            above 1024 (then the one-phase kernel runs) */
   int32_t accumulator;   /* PIC_ACC_* */
   int32_t deposit;       /* PIC_DEPOSIT_*: which charge-conserving current */
   /* Smoothing of the current before the field solve (App. A, current
