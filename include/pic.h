@@ -76,8 +76,8 @@ typedef enum {
 enum {
   PIC_ACC_FP32 = 0,        /* exact tile sums, folded into the FP32 current
                               with FP32 global atomic adds */
-  PIC_ACC_COMPENSATED = 1, /* same as PIC_ACC_FP32: the exact int64 tile sum
-                              is the compensated accumulation */
+  PIC_ACC_COMPENSATED = 1, /* same as PIC_ACC_FP32: the exact integer tile
+                              sum is the compensated accumulation */
   PIC_ACC_FIXED64 = 2      /* tiles folded in int64 too: the current is
                               independent of the order of the adds (bitwise
                               reproducible), converted to FP32 once per step */
