@@ -25,3 +25,25 @@ def test_particle_kernel_dynamic_lds_is_16_byte_aligned(tmp_path):
     # and with runtime LDS strides) + 3 orders x periodic 2D in two phases
     assert len(sizes) == 30
     assert all(v % 16 == 0 for v in sizes), sizes
+
+
+def test_counter_records_match_the_kernel_source():
+    """The committed rocprofv3 counter records (profiles/*_counters.json) were
+    taken on the particle kernel's current source: bench.py reports their
+    traffic only when the SHA-256 of gpd.hip + pic_dev.h matches, so a stale
+    record would leave the measured traffic out silently."""
+    import glob
+    import hashlib
+    import json
+
+    h = hashlib.sha256()
+    for fn in ("gpd.hip", "pic_dev.h"):
+        with open(os.path.join(CSRC, fn), "rb") as f:
+            h.update(f.read())
+    recs = glob.glob(os.path.join(ROOT, "profiles", "*_counters.json"))
+    assert recs
+    for p in recs:
+        with open(p) as f:
+            rec = json.load(f)
+        assert rec["source_sha256"] == h.hexdigest(), os.path.basename(p)
+        assert rec["fetch_scale"] > 0 and rec["write_scale"] > 0
