@@ -2004,12 +2004,22 @@ pic_status sim_autotune(Sim& S, pic_tune* io) {
         }
       }
     }
-    if (st == PIC_OK && (what & PIC_TUNE_CHUNK) && round == 0)
+    if (st == PIC_OK && (what & PIC_TUNE_CHUNK) && round == 0) {
+      const int chunk0 = best.chunk;
       for (int ch : kChunk) {
         Layout L = best;
         L.chunk = ch;
         if ((st = consider(L)) != PIC_OK) break;
       }
+      // a new chunk can change the kernel (2D items of more than 1024
+      // particles take the one-phase kernel) and with it the best interval
+      if (st == PIC_OK && (what & PIC_TUNE_SORT) && best.chunk != chunk0)
+        for (int si : kSi) {
+          Layout L = best;
+          L.si = si;
+          if ((st = consider(L)) != PIC_OK) break;
+        }
+    }
     if (!(what & PIC_TUNE_TILE)) break;
   }
   if (st != PIC_OK) {
